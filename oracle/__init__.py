@@ -1,0 +1,246 @@
+"""CPU oracle for the level-set restricted geodesic Voronoi pipeline.
+
+TEST INFRASTRUCTURE ONLY.  This package is the plain reference the GPU library
+is checked against.  Only the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import it; the GPU library never imports it and it
+imports nothing from the GPU library.
+
+The arithmetic lives in ``lsrvt_oracle.c`` (plain C, double precision, exact
+integers for the site update); this module only marshals numpy arrays through
+ctypes.  Each function cites the passage of the paper it follows:
+
+* :func:`bands`       -- Sec. 3.1, isoband definition B_{a,b} = {a < f <= b}
+* :func:`components`  -- Sec. 3.1, connected components of each isoband,
+  numbered by (band, smallest member index) as in the hierarchical layout of
+  Sec. 3.2.4 / Fig. 5
+* :func:`vt`          -- Eq. 1, restricted geodesic Voronoi regions (hop
+  distance in the restricted 6-neighbour graph, ties to the lower site id)
+* :func:`update`      -- Sec. 3.1 "Centroids", weighted centre of mass moved
+  to the nearest in-region voxel
+* :func:`cvt`         -- Algorithm 1 with a fixed number of updates
+* :func:`stats`       -- Sec. 3.3 "Aggregation": per-unit moments, extrema,
+  histograms and covariance, computed directly per unit in double precision
+* :func:`chan_merge`  -- pairwise merge of (n, mean, M2, C) summaries, used by
+  the tests to check that merged cell statistics equal the direct ones
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lsrvt_oracle.c")
+_LIB = os.path.join(_HERE, "liblsrvt_oracle.so")
+
+NONE_ID = 0xFFFFFFFF
+OK, EINVAL, ENAN, ENOMEM, ELIMIT = 0, 1, 2, 3, 4
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no fused multiply-add contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+             "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64, u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        lib.oracle_bands.argtypes = [P, i64, P, i32, P]
+        lib.oracle_components.argtypes = [P, i32, i32, i32, i32, P, P, P, P, P, P]
+        lib.oracle_vt.argtypes = [P, i32, i32, i32, P, u32, P, P]
+        lib.oracle_vt_unpruned.argtypes = [P, i32, i32, i32, P, u32, P, P]
+        lib.oracle_update.argtypes = [P, i32, i32, i32, P, P, u32, P]
+        lib.oracle_cvt.argtypes = [P, i32, i32, i32, P, u32, P, i32, P, P, P, P]
+        lib.oracle_stats.argtypes = [P, i64, u32, P, i32, P, i32, P, P, P, P, P, P, P]
+        for f in (lib.oracle_bands, lib.oracle_components, lib.oracle_vt, lib.oracle_vt_unpruned,
+                  lib.oracle_update, lib.oracle_cvt, lib.oracle_stats):
+            f.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dims(shape):
+    nz, ny, nx = (int(s) for s in shape)
+    return nx, ny, nz
+
+
+def _check(code, what):
+    if code != OK:
+        raise OracleError(code, what)
+
+
+# --------------------------------------------------------------------------
+def bands(field: np.ndarray, iso) -> np.ndarray:
+    """Band index #{i : iso_i < f(v)} per voxel (Sec. 3.1).  Raises on NaN."""
+    f = np.ascontiguousarray(field, dtype=np.float32)
+    iso = np.ascontiguousarray(iso, dtype=np.float32)
+    out = np.empty(f.shape, dtype=np.uint8)
+    _check(_load().oracle_bands(_ptr(f), f.size, _ptr(iso), len(iso), _ptr(out)), "bands")
+    return out
+
+
+@dataclass
+class Components:
+    comp: np.ndarray        # uint32[nz, ny, nx]
+    n_comp: int
+    comp_band: np.ndarray   # uint8[n_comp]
+    comp_size: np.ndarray   # uint64[n_comp]
+    comp_first: np.ndarray  # uint32[n_comp]
+    band_offset: np.ndarray  # uint32[n_bands + 1]
+
+
+def components(band: np.ndarray, n_bands: int) -> Components:
+    """6-connected components of each isoband, numbered by (band, min index)."""
+    b = np.ascontiguousarray(band, dtype=np.uint8)
+    nx, ny, nz = _dims(b.shape)
+    n = b.size
+    comp = np.empty(b.shape, dtype=np.uint32)
+    ncomp = np.zeros(1, dtype=np.uint32)
+    cb = np.empty(n, dtype=np.uint8)
+    cs = np.empty(n, dtype=np.uint64)
+    cf = np.empty(n, dtype=np.uint32)
+    bo = np.empty(n_bands + 1, dtype=np.uint32)
+    _check(_load().oracle_components(_ptr(b), nx, ny, nz, n_bands, _ptr(comp), _ptr(ncomp),
+                                     _ptr(cb), _ptr(cs), _ptr(cf), _ptr(bo)), "components")
+    k = int(ncomp[0])
+    return Components(comp, k, cb[:k].copy(), cs[:k].copy(), cf[:k].copy(), bo)
+
+
+def vt(comp: np.ndarray, sites, pruned: bool = True, return_dist: bool = False):
+    """Restricted geodesic Voronoi regions of Eq. 1 (hop metric, id tie-break)."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32)
+    s = np.ascontiguousarray(sites, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    cell = np.empty(c.shape, dtype=np.uint32)
+    dist = np.empty(c.shape, dtype=np.uint32)
+    fn = _load().oracle_vt if pruned else _load().oracle_vt_unpruned
+    _check(fn(_ptr(c), nx, ny, nz, _ptr(s), len(s), _ptr(cell), _ptr(dist)), "vt")
+    return (cell, dist) if return_dist else cell
+
+
+def update(cell: np.ndarray, sites, weights=None):
+    """One site update: exact weighted centroid snapped to the nearest in-cell voxel.
+
+    Returns (new_sites, ds) where ds[s] is the Euclidean move of site s."""
+    c = np.ascontiguousarray(cell, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    s = np.array(sites, dtype=np.uint32, copy=True)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint16)
+    ds = np.zeros(len(s), dtype=np.float64)
+    _check(_load().oracle_update(_ptr(c), nx, ny, nz, _ptr(w), _ptr(s), len(s), _ptr(ds)), "update")
+    return s, ds
+
+
+@dataclass
+class CVTResult:
+    cell: np.ndarray       # uint32[nz, ny, nx]
+    sites: np.ndarray      # uint32[S]
+    site_comp: np.ndarray  # uint32[S]
+    mean_ds: np.ndarray    # float64[iters]
+
+
+def cvt(comp: np.ndarray, seeds, weights=None, iters: int = 0) -> CVTResult:
+    """Algorithm 1 with a fixed number of updates: T x (VT + update) + final VT."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint16)
+    cell = np.empty(c.shape, dtype=np.uint32)
+    sites = np.empty(len(sd), dtype=np.uint32)
+    sc = np.empty(len(sd), dtype=np.uint32)
+    mds = np.zeros(max(iters, 0), dtype=np.float64)
+    _check(_load().oracle_cvt(_ptr(c), nx, ny, nz, _ptr(sd), len(sd), _ptr(w), int(iters),
+                              _ptr(cell), _ptr(sites), _ptr(sc), _ptr(mds) if iters > 0 else None), "cvt")
+    return CVTResult(cell, sites, sc, mds)
+
+
+@dataclass
+class Stats:
+    n: np.ndarray      # uint64[U]
+    mean: np.ndarray   # float64[U, m]
+    m2: np.ndarray     # float64[U, m]   (population variance = m2 / n)
+    vmin: np.ndarray   # float32[U, m]
+    vmax: np.ndarray   # float32[U, m]
+    hist: np.ndarray | None  # uint32[U, m, B]
+    cov: np.ndarray | None   # float64[U, m(m+1)/2]  co-moments, packed upper triangle
+
+    @property
+    def var(self):
+        with np.errstate(invalid="ignore", divide="ignore"):
+            return np.where(self.n[:, None] > 0, self.m2 / np.maximum(self.n, 1)[:, None], 0.0)
+
+
+def stats(unit: np.ndarray, n_units: int, variables: np.ndarray, edges=None, cov: bool = False) -> Stats:
+    """Direct two-pass FP64 statistics of each unit (Sec. 3.3 "Aggregation").
+
+    ``unit`` holds a unit id per voxel (NONE_ID = skip); ``variables`` is
+    [m, ...] with the spatial shape of ``unit``; ``edges`` is [m, B+1]."""
+    u = np.ascontiguousarray(unit, dtype=np.uint32).reshape(-1)
+    m = variables.shape[0]
+    x = np.ascontiguousarray(variables, dtype=np.float32).reshape(m, -1)
+    n = u.size
+    e = None if edges is None else np.ascontiguousarray(edges, dtype=np.float32)
+    nb = 0 if e is None else e.shape[1] - 1
+    U = int(n_units)
+    cnt = np.empty(U, dtype=np.uint64)
+    mean = np.empty((U, m), dtype=np.float64)
+    m2 = np.empty((U, m), dtype=np.float64)
+    vmin = np.empty((U, m), dtype=np.float32)
+    vmax = np.empty((U, m), dtype=np.float32)
+    hist = np.empty((U, m, nb), dtype=np.uint32) if e is not None else None
+    P = m * (m + 1) // 2
+    cv = np.empty((U, P), dtype=np.float64) if cov else None
+    _check(_load().oracle_stats(_ptr(u), n, U, _ptr(x), m, _ptr(e), nb, _ptr(cnt), _ptr(mean), _ptr(m2),
+                                _ptr(vmin), _ptr(vmax), _ptr(hist), _ptr(cv)), "stats")
+    return Stats(cnt, mean, m2, vmin, vmax, hist, cv)
+
+
+def chan_merge(n_a, mean_a, m2_a, cov_a, n_b, mean_b, m2_b, cov_b):
+    """Pairwise merge of two (n, mean, M2, co-moment) summaries (Chan et al.).
+
+    n = n_a + n_b, delta = mean_b - mean_a, mean = mean_a + delta n_b / n,
+    M2 = M2_a + M2_b + delta^2 n_a n_b / n, C_jk = C_a + C_b + delta_j delta_k n_a n_b / n."""
+    n = n_a + n_b
+    if n == 0:
+        return 0, np.zeros_like(mean_a), np.zeros_like(m2_a), None if cov_a is None else np.zeros_like(cov_a)
+    if n_a == 0:
+        return n_b, mean_b.copy(), m2_b.copy(), None if cov_b is None else cov_b.copy()
+    if n_b == 0:
+        return n_a, mean_a.copy(), m2_a.copy(), None if cov_a is None else cov_a.copy()
+    delta = mean_b - mean_a
+    f = float(n_a) * float(n_b) / float(n)
+    mean = mean_a + delta * (float(n_b) / float(n))
+    m2 = m2_a + m2_b + delta * delta * f
+    cv = None
+    if cov_a is not None:
+        m = len(mean_a)
+        dd = np.concatenate([delta[j] * delta[j:] for j in range(m)])
+        cv = cov_a + cov_b + dd * f
+    return n, mean, m2, cv
