@@ -1,0 +1,240 @@
+/*
+ * lsrvt.h -- C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of the level-set restricted geodesic Voronoi tessellation of Neuroth
+ * et al., "Level Set Restricted Voronoi Tessellation for Large scale Spatial
+ * Statistical Analysis":
+ *
+ *   field --(isobands)--> band --(components)--> comp
+ *         --(Lloyd loop of restricted geodesic Voronoi passes)--> cell, sites
+ *         --(aggregate)--> per-cell / per-component / per-band statistics
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Volumes are C-order [nz][ny][nx]; voxel (x, y, z) has linear index
+ *    i = x + nx*(y + ny*z).  Limits: every extent in 1..32767 and
+ *    N = nx*ny*nz <= 2^31 - 1 (LSRVT_ELIMIT otherwise).
+ *  - d_* arguments are device pointers owned by the caller; h_* are host
+ *    pointers.  The library never allocates device memory: scratch space is
+ *    the caller's d_work buffer, sized by the matching *_workspace query, and
+ *    must be 256-byte aligned.  A buffer that is too small returns
+ *    LSRVT_EWORKSPACE before anything is launched.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it; calls return once the work is enqueued, except where a call says
+ *    it synchronises the stream.
+ *  - Arguments are validated on the host before any launch.  Validation that
+ *    needs device data (a seed index out of range) is reported by the calls
+ *    that synchronise.  Device or launch failures return LSRVT_EDEVICE.
+ *  - Labels, sites, counts, minima, maxima and histograms are bit-exact and
+ *    independent of scheduling; floating-point statistics use a fixed
+ *    reduction order, so repeated calls give bit-identical results.
+ *  - Calls on distinct streams with distinct workspaces may run concurrently.
+ */
+#ifndef LSRVT_H
+#define LSRVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t nx, ny, nz;
+} lsrvt_dims;
+
+enum {
+  LSRVT_OK = 0,
+  LSRVT_EINVAL = 1,     /* bad argument (dims, isovalues, iters, seed index, sizes) */
+  LSRVT_ENAN = 2,       /* the field holds a NaN; band labels are unspecified */
+  LSRVT_ECAPACITY = 3,  /* an output table is smaller than the number of entries */
+  LSRVT_EWORKSPACE = 4, /* d_work is NULL, misaligned or smaller than required */
+  LSRVT_ELIMIT = 5,     /* volume beyond the size limits above */
+  LSRVT_EDEVICE = 6     /* a HIP runtime or launch error */
+};
+
+/* Label of a voxel whose component holds no site (restricted Voronoi pass). */
+#define LSRVT_NONE 0xFFFFFFFFu
+
+/* Flags for lsrvt_aggregate. */
+#define LSRVT_STATS_HIST 1u /* fill the histograms (needs d_edges, n_bins >= 1) */
+#define LSRVT_STATS_COV 2u  /* fill the co-moment (covariance) arrays */
+
+/* Human-readable name of a status code (static string). */
+const char *lsrvt_status_string(int32_t status);
+
+/* Library ABI version (major * 10000 + minor * 100 + patch). */
+int32_t lsrvt_version(void);
+
+/* ------------------------------------------------------------------------
+ * Isoband classification (Sec. 3.1, the isoband definition
+ * B_{a,b} = { v : a < f(v) <= b }).
+ *
+ * band[i] = #{ k : h_iso[k] < d_field[i] }, i.e. the number of isovalues
+ * strictly below the value, so a value equal to an isovalue joins the lower
+ * band and the two outer half-open bands are included (n_iso + 1 bands).
+ *   d_field  float32[N]           input field (+-inf classify normally)
+ *   h_iso    float32[n_iso]       strictly increasing, finite; 0 <= n_iso <= 254
+ *   d_band   uint8[N]             output band per voxel
+ *   d_status uint32[1] or NULL    cleared, then bit 0 is set if any value is NaN
+ * Errors: EINVAL (isovalues not strictly increasing / not finite, n_iso out of
+ * range, NULL pointers), ELIMIT.  A NaN is reported only through d_status.
+ * Needs no workspace.
+ */
+int32_t lsrvt_isobands(const float *d_field, lsrvt_dims dims, const float *h_iso, int32_t n_iso,
+                       uint8_t *d_band, uint32_t *d_status, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Connected components of every isoband (Sec. 3.1: an isoband is the union
+ * of components no voxel of which is adjacent to a voxel of another), with
+ * 6-connectivity: face neighbours with equal band are joined.
+ *
+ * Components are numbered in the hierarchical order of the paper's
+ * structured layout (Sec. 3.2.4, Fig. 5): by band, then by the smallest
+ * linear index of their voxels.
+ *   d_band         uint8[N]        band per voxel, every value < n_bands
+ *   n_bands        1..255
+ *   d_comp         uint32[N]       output component id per voxel
+ *   cap_comp       capacity of the four tables below
+ *   d_comp_band    uint8[cap_comp]   band of each component
+ *   d_comp_size    uint64[cap_comp]  voxel count of each component
+ *   d_comp_first   uint32[cap_comp]  smallest linear index in each component
+ *   d_band_offset  uint32[n_bands+1] components of band b are
+ *                                    [band_offset[b], band_offset[b+1])
+ *   h_n_comp       output: number of components
+ * Synchronises the stream once (to learn the component count).  If the count
+ * exceeds cap_comp, d_comp and *h_n_comp are valid, the tables are not
+ * written and LSRVT_ECAPACITY is returned.  A band value >= n_bands gives
+ * unspecified labels (it is not checked on the device).
+ * Workspace: lsrvt_components_workspace(dims, n_bands).
+ */
+size_t lsrvt_components_workspace(lsrvt_dims dims, int32_t n_bands);
+int32_t lsrvt_components(const uint8_t *d_band, lsrvt_dims dims, int32_t n_bands, uint32_t *d_comp,
+                         uint32_t cap_comp, uint8_t *d_comp_band, uint64_t *d_comp_size,
+                         uint32_t *d_comp_first, uint32_t *d_band_offset, uint32_t *h_n_comp,
+                         void *d_work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * One restricted geodesic Voronoi pass (Eq. 1).  The graph geodesic is the
+ * hop count in the 6-neighbour graph whose edges join voxels of equal band
+ * (which, for searches started inside a component, is the graph of that
+ * component); a voxel belongs to the site s of its component that minimises
+ * (hop distance, s), so ties go to the lower site id.
+ *   d_band    uint8[N]           band per voxel
+ *   d_sites   uint32[n_sites]    site voxels (linear indices); id = position
+ *   d_cell    uint32[N]          output site id per voxel, LSRVT_NONE when the
+ *                                voxel's component holds no site
+ * Co-located sites: the lowest id owns the voxel, higher ids get empty cells.
+ * Synchronises the stream (to detect convergence).  EINVAL if a site index
+ * is >= N.  Workspace: lsrvt_cvt_workspace(dims, n_sites, 0).
+ */
+int32_t lsrvt_vt(const uint8_t *d_band, lsrvt_dims dims, const uint32_t *d_sites, uint32_t n_sites,
+                 uint32_t *d_cell, void *d_work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * One site update (Sec. 3.1, "Centroids or Centers of Mass"; Sec. 3.2.3).
+ * For each site s: M = sum of weights over its cell and S_a = sum w * a(v)
+ * for a in {x, y, z}, exactly in uint64.  If M = 0 the site stays; otherwise
+ * it moves to the voxel v of its cell minimising sum_a (M a(v) - S_a)^2
+ * (the voxel nearest the weighted centre of mass, compared exactly), ties to
+ * the lower linear index.
+ *   d_cell     uint32[N]        cells from lsrvt_vt
+ *   d_weights  uint16[N] or NULL (NULL = weight 1 everywhere)
+ *   d_sites    uint32[n_sites]  in: current sites; out: moved sites
+ *   d_ds       float64[n_sites] or NULL: Euclidean move of each site (voxels)
+ * Does not synchronise.  Workspace: lsrvt_cvt_workspace(dims, n_sites, 0).
+ */
+int32_t lsrvt_update(const uint32_t *d_cell, lsrvt_dims dims, const uint16_t *d_weights,
+                     uint32_t *d_sites, uint32_t n_sites, double *d_ds, void *d_work,
+                     size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * The Lloyd loop of Algorithm 1 with a fixed number of updates:
+ * sites_0 = seeds; for t < iters: cells_t = VT(sites_t),
+ * sites_{t+1} = update(cells_t); the output cells are VT(sites_iters).
+ * (iters + 1 Voronoi passes and iters updates; iters = 0 is the Voronoi
+ * tessellation of the seeds.)
+ *   d_band, d_comp   band and component id per voxel (lsrvt_components)
+ *   d_seeds          uint32[n_sites] initial site voxels; id = position
+ *   d_weights        uint16[N] or NULL (uniform)
+ *   d_cell           uint32[N] output cells of the final pass
+ *   d_sites          uint32[n_sites] output final sites (may alias d_seeds)
+ *   d_site_comp      uint32[n_sites] output component of each seed
+ *   h_mean_ds        float64[iters] or NULL: mean Euclidean site move of
+ *                    each update, in voxel units
+ * Synchronises the stream.  Errors: EINVAL (iters < 0, a seed >= N).
+ * Workspace: lsrvt_cvt_workspace(dims, n_sites, iters).
+ */
+size_t lsrvt_cvt_workspace(lsrvt_dims dims, uint32_t n_sites, int32_t iters);
+int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrvt_dims dims,
+                  const uint32_t *d_seeds, uint32_t n_sites, const uint16_t *d_weights, int32_t iters,
+                  uint32_t *d_cell, uint32_t *d_sites, uint32_t *d_site_comp, double *h_mean_ds,
+                  void *d_work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Statistics of every cell, merged up the hierarchy cell -> component ->
+ * band (Sec. 3.3, "Aggregation"; the hierarchy of Sec. 3.2.4 / Fig. 5).
+ *
+ * For every unit and variable j: the voxel count n, the mean, the centred
+ * sum of squares M2 = sum (x - mean)^2 (population variance = M2 / n), the
+ * minimum and maximum, a histogram over caller-given edges, and the centred
+ * co-moments C_jk = sum (x_j - mean_j)(x_k - mean_k), j <= k, packed
+ * row-major over the upper triangle (m(m+1)/2 entries, C_jj = M2_j).
+ * Statistics are unweighted.  Histogram bin of x: the number of interior
+ * edges e_1..e_{B-1} that are <= x (below e_0 -> bin 0, >= e_B -> bin B-1).
+ * Cells accumulate in float32 with compensated (error-free two-sum) sums of
+ * values shifted by the value at the cell's site; the cell -> component ->
+ * band merges are pairwise (Chan et al.) in float64, in a fixed order (cells
+ * by site id within a component, components by id within a band).
+ * Units with n = 0: mean = M2 = C = 0, min = +inf, max = -inf, hist = 0.
+ * Variables must be finite.
+ *
+ * Output arrays (all device, caller-allocated; U = number of units):
+ *   n [U] uint64; mean, m2 [U][m]; vmin, vmax [U][m] float32;
+ *   hist [U][m][B] uint32 (or NULL); cov [U][m(m+1)/2] (or NULL).
+ * Cell level uses float32 mean/m2/cov, components and bands float64.
+ *
+ *   d_cell        uint32[N]        cells (LSRVT_NONE voxels are skipped)
+ *   d_sites       uint32[n_sites]  site voxels (the shift reference)
+ *   d_site_comp   uint32[n_sites]  component of each site
+ *   d_comp_band   uint8[n_comp]    band of each component
+ *   d_vars        float32[m][N]    the variables, one volume after another
+ *   d_edges       float32[m][B+1]  increasing edges (needed with HIST)
+ *   flags         LSRVT_STATS_HIST | LSRVT_STATS_COV
+ * Does not synchronise.  Errors: EINVAL (m < 1 or > 32, B < 1 with HIST,
+ * NULL output arrays that the flags require).
+ * Workspace: lsrvt_aggregate_workspace(...).
+ */
+typedef struct {
+  uint64_t *n;
+  float *mean;
+  float *m2;
+  float *vmin;
+  float *vmax;
+  uint32_t *hist;
+  float *cov;
+} lsrvt_cell_stats;
+
+typedef struct {
+  uint64_t *n;
+  double *mean;
+  double *m2;
+  float *vmin;
+  float *vmax;
+  uint32_t *hist;
+  double *cov;
+} lsrvt_group_stats;
+
+size_t lsrvt_aggregate_workspace(lsrvt_dims dims, uint32_t n_sites, uint32_t n_comp, int32_t n_bands,
+                                 int32_t n_vars, int32_t n_bins, uint32_t flags);
+int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t *d_sites,
+                        const uint32_t *d_site_comp, uint32_t n_sites, const uint8_t *d_comp_band,
+                        uint32_t n_comp, int32_t n_bands, const float *d_vars, int32_t n_vars,
+                        const float *d_edges, int32_t n_bins, uint32_t flags,
+                        const lsrvt_cell_stats *cell, const lsrvt_group_stats *comp,
+                        const lsrvt_group_stats *band, void *d_work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSRVT_H */

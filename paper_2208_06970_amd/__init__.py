@@ -1,0 +1,369 @@
+"""Python binding of the gfx950 LSRVT library (``liblsrvt.so``).
+
+Argument marshalling only: every function below has the name of the C entry
+point it wraps (``include/lsrvt.h``), takes torch tensors that live on the GPU
+(torch provides device memory and streams, nothing else), and calls the HIP
+library through ctypes.  There is no CPU fallback: importing the functions
+without a built library raises ``LsrvtError``.
+
+The pipeline (Neuroth et al., "Level Set Restricted Voronoi Tessellation"):
+
+* :func:`lsrvt_isobands`   Sec. 3.1, isoband per voxel
+* :func:`lsrvt_components` Sec. 3.1, 6-connected components per isoband
+* :func:`lsrvt_vt`         Eq. 1, one restricted geodesic Voronoi pass
+* :func:`lsrvt_update`     Sec. 3.1 centroid, one snapped site update
+* :func:`lsrvt_cvt`        Algorithm 1 with a fixed number of updates
+* :func:`lsrvt_aggregate`  Sec. 3.3 aggregation, cell -> component -> band
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsrvt.so")
+
+OK, EINVAL, ENAN, ECAPACITY, EWORKSPACE, ELIMIT, EDEVICE = range(7)
+NONE_ID = 0xFFFFFFFF
+STATS_HIST = 1
+STATS_COV = 2
+
+EXPORTS = (
+    "lsrvt_status_string", "lsrvt_version", "lsrvt_isobands", "lsrvt_components_workspace",
+    "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
+    "lsrvt_aggregate_workspace", "lsrvt_aggregate",
+)
+
+
+class LsrvtError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        msg = f"{what}: status {code}"
+        if code >= 0:
+            try:
+                msg += f" ({_lib().lsrvt_status_string(code).decode()})"
+            except Exception:  # pragma: no cover
+                pass
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+        self.code = code
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class CellStatsC(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov")]
+
+
+class GroupStatsC(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov")]
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise LsrvtError(-1, "load", f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, S = ctypes.c_void_p, ctypes.c_size_t
+        i32, u32 = ctypes.c_int32, ctypes.c_uint32
+        lib.lsrvt_status_string.argtypes = [i32]
+        lib.lsrvt_status_string.restype = ctypes.c_char_p
+        lib.lsrvt_version.restype = i32
+        lib.lsrvt_isobands.argtypes = [P, Dims, P, i32, P, P, P]
+        lib.lsrvt_components_workspace.argtypes = [Dims, i32]
+        lib.lsrvt_components_workspace.restype = S
+        lib.lsrvt_components.argtypes = [P, Dims, i32, P, u32, P, P, P, P, P, P, S, P]
+        lib.lsrvt_vt.argtypes = [P, Dims, P, u32, P, P, S, P]
+        lib.lsrvt_update.argtypes = [P, Dims, P, P, u32, P, P, S, P]
+        lib.lsrvt_cvt_workspace.argtypes = [Dims, u32, i32]
+        lib.lsrvt_cvt_workspace.restype = S
+        lib.lsrvt_cvt.argtypes = [P, P, Dims, P, u32, P, i32, P, P, P, P, P, S, P]
+        lib.lsrvt_aggregate_workspace.argtypes = [Dims, u32, u32, i32, i32, i32, u32]
+        lib.lsrvt_aggregate_workspace.restype = S
+        lib.lsrvt_aggregate.argtypes = [P, Dims, P, P, u32, P, u32, i32, P, i32, P, i32, u32,
+                                        ctypes.POINTER(CellStatsC), ctypes.POINTER(GroupStatsC),
+                                        ctypes.POINTER(GroupStatsC), P, S, P]
+        for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
+                     "lsrvt_aggregate"):
+            getattr(lib, name).restype = i32
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes library (raises if it is not built)."""
+    return _lib()
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dims(shape) -> Dims:
+    nz, ny, nx = (int(v) for v in shape)
+    return Dims(nx, ny, nz)
+
+
+def _need(t, dtype, what):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise LsrvtError(EINVAL, what, "expected a CUDA tensor")
+    if t.dtype != dtype:
+        raise LsrvtError(EINVAL, what, f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise LsrvtError(EINVAL, what, "expected a contiguous tensor")
+    return t
+
+
+def _check(code, what):
+    if code != OK:
+        raise LsrvtError(int(code), what)
+
+
+class Workspace:
+    """A growable, 256-byte-aligned device scratch buffer owned by the caller."""
+
+    def __init__(self, device=None):
+        self.device = device
+        self.buf = None
+        self.bytes = 0
+
+    def get(self, nbytes: int):
+        torch = _torch()
+        nbytes = int(nbytes)
+        if self.buf is None or self.bytes < nbytes:
+            self.buf = torch.empty(nbytes + 512, dtype=torch.uint8, device=self.device or "cuda")
+            self.bytes = nbytes
+        base = self.buf.data_ptr()
+        off = (-base) % 256
+        return ctypes.c_void_p(base + off), nbytes
+
+
+_default_ws = {}
+
+
+def _ws(ws):
+    if ws is not None:
+        return ws
+    torch = _torch()
+    dev = torch.cuda.current_device()
+    if dev not in _default_ws:
+        _default_ws[dev] = Workspace(f"cuda:{dev}")
+    return _default_ws[dev]
+
+
+# --------------------------------------------------------------------------
+# entry points
+def lsrvt_isobands(field, iso, band=None, status=None, stream=None):
+    """Isoband per voxel: #{k : iso[k] < f} (Sec. 3.1).  Returns (band, status)."""
+    torch = _torch()
+    _need(field, torch.float32, "lsrvt_isobands")
+    iso = np.ascontiguousarray(np.asarray(iso, dtype=np.float32))
+    if band is None:
+        band = torch.empty(field.shape, dtype=torch.uint8, device=field.device)
+    if status is None:
+        status = torch.zeros(1, dtype=torch.int32, device=field.device)
+    code = _lib().lsrvt_isobands(_ptr(field), _dims(field.shape), iso.ctypes.data_as(ctypes.c_void_p), len(iso),
+                                 _ptr(band), _ptr(status), _stream(stream))
+    _check(code, "lsrvt_isobands")
+    return band, status
+
+
+@dataclass
+class Components:
+    comp: "object"
+    n_comp: int
+    comp_band: "object"
+    comp_size: "object"
+    comp_first: "object"
+    band_offset: "object"
+
+
+def lsrvt_components(band, n_bands: int, comp=None, cap_comp: int | None = None, ws: Workspace | None = None,
+                     stream=None) -> Components:
+    """6-connected components per band, numbered by (band, min index) (Sec. 3.1)."""
+    torch = _torch()
+    _need(band, torch.uint8, "lsrvt_components")
+    dev = band.device
+    lib = _lib()
+    dims = _dims(band.shape)
+    if comp is None:
+        comp = torch.empty(band.shape, dtype=torch.int32, device=dev)
+    cap = int(cap_comp) if cap_comp is not None else max(1024, band.numel() // 64)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_components_workspace(dims, n_bands))
+    bo = torch.empty(n_bands + 1, dtype=torch.int32, device=dev)
+    ncomp = ctypes.c_uint32(0)
+    while True:
+        cb = torch.empty(cap, dtype=torch.uint8, device=dev)
+        cs = torch.empty(cap, dtype=torch.int64, device=dev)
+        cf = torch.empty(cap, dtype=torch.int32, device=dev)
+        code = lib.lsrvt_components(_ptr(band), dims, n_bands, _ptr(comp), cap, _ptr(cb), _ptr(cs), _ptr(cf),
+                                    _ptr(bo), ctypes.byref(ncomp), wptr, wbytes, _stream(stream))
+        if code == ECAPACITY:
+            cap = int(ncomp.value)
+            continue
+        _check(code, "lsrvt_components")
+        break
+    k = int(ncomp.value)
+    return Components(comp, k, cb[:k], cs[:k], cf[:k], bo)
+
+
+def lsrvt_vt(band, sites, cell=None, ws: Workspace | None = None, stream=None):
+    """One restricted geodesic Voronoi pass (Eq. 1, hop metric, id tie-break)."""
+    torch = _torch()
+    _need(band, torch.uint8, "lsrvt_vt")
+    _need(sites, torch.int32, "lsrvt_vt")
+    lib = _lib()
+    dims = _dims(band.shape)
+    if cell is None:
+        cell = torch.empty(band.shape, dtype=torch.int32, device=band.device)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_cvt_workspace(dims, sites.numel(), 0))
+    code = lib.lsrvt_vt(_ptr(band), dims, _ptr(sites), sites.numel(), _ptr(cell), wptr, wbytes, _stream(stream))
+    _check(code, "lsrvt_vt")
+    return cell
+
+
+def lsrvt_update(cell, sites, weights=None, ds=None, ws: Workspace | None = None, stream=None):
+    """One snapped centroid update of ``sites`` in place; returns (sites, ds)."""
+    torch = _torch()
+    _need(cell, torch.int32, "lsrvt_update")
+    _need(sites, torch.int32, "lsrvt_update")
+    if weights is not None:
+        _need(weights, torch.int16, "lsrvt_update")
+    lib = _lib()
+    dims = _dims(cell.shape)
+    if ds is None:
+        ds = torch.empty(sites.numel(), dtype=torch.float64, device=cell.device)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_cvt_workspace(dims, sites.numel(), 0))
+    code = lib.lsrvt_update(_ptr(cell), dims, _ptr(weights), _ptr(sites), sites.numel(), _ptr(ds), wptr, wbytes,
+                            _stream(stream))
+    _check(code, "lsrvt_update")
+    return sites, ds
+
+
+@dataclass
+class CVT:
+    cell: "object"
+    sites: "object"
+    site_comp: "object"
+    mean_ds: np.ndarray
+
+
+def lsrvt_cvt(band, comp, seeds, weights=None, iters: int = 0, cell=None, sites=None, site_comp=None,
+              ws: Workspace | None = None, stream=None, want_mean_ds: bool = True) -> CVT:
+    """Algorithm 1 with ``iters`` snapped centroid updates and a final pass."""
+    torch = _torch()
+    _need(band, torch.uint8, "lsrvt_cvt")
+    _need(comp, torch.int32, "lsrvt_cvt")
+    _need(seeds, torch.int32, "lsrvt_cvt")
+    if weights is not None:
+        _need(weights, torch.int16, "lsrvt_cvt")
+    lib = _lib()
+    dims = _dims(band.shape)
+    dev = band.device
+    S = seeds.numel()
+    if cell is None:
+        cell = torch.empty(band.shape, dtype=torch.int32, device=dev)
+    if sites is None:
+        sites = torch.empty(S, dtype=torch.int32, device=dev)
+    if site_comp is None:
+        site_comp = torch.empty(S, dtype=torch.int32, device=dev)
+    mds = np.zeros(max(int(iters), 1), dtype=np.float64)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_cvt_workspace(dims, S, max(int(iters), 0)))
+    code = lib.lsrvt_cvt(_ptr(band), _ptr(comp), dims, _ptr(seeds), S, _ptr(weights), int(iters), _ptr(cell),
+                         _ptr(sites), _ptr(site_comp),
+                         mds.ctypes.data_as(ctypes.c_void_p) if want_mean_ds else None, wptr, wbytes,
+                         _stream(stream))
+    _check(code, "lsrvt_cvt")
+    return CVT(cell, sites, site_comp, mds[:max(int(iters), 0)])
+
+
+@dataclass
+class LevelStats:
+    n: "object"
+    mean: "object"
+    m2: "object"
+    vmin: "object"
+    vmax: "object"
+    hist: "object"
+    cov: "object"
+
+
+def _alloc_level(U, m, B, hist, cov, fdt, dev):
+    torch = _torch()
+    P = m * (m + 1) // 2
+    return LevelStats(
+        torch.empty(U, dtype=torch.int64, device=dev),
+        torch.empty((U, m), dtype=fdt, device=dev),
+        torch.empty((U, m), dtype=fdt, device=dev),
+        torch.empty((U, m), dtype=torch.float32, device=dev),
+        torch.empty((U, m), dtype=torch.float32, device=dev),
+        torch.empty((U, m, B), dtype=torch.int32, device=dev) if hist else None,
+        torch.empty((U, P), dtype=fdt, device=dev) if cov else None,
+    )
+
+
+def _cstruct(cls, L):
+    return cls(*(None if getattr(L, k) is None else getattr(L, k).data_ptr()
+                 for k in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov")))
+
+
+def lsrvt_aggregate(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int, variables, edges=None,
+                    cov: bool = False, ws: Workspace | None = None, stream=None, out=None):
+    """Per-cell FP32 compensated statistics merged (FP64, Chan) to components and bands.
+
+    Returns (cell_stats, comp_stats, band_stats) as :class:`LevelStats`."""
+    torch = _torch()
+    _need(cell, torch.int32, "lsrvt_aggregate")
+    _need(sites, torch.int32, "lsrvt_aggregate")
+    _need(site_comp, torch.int32, "lsrvt_aggregate")
+    _need(comp_band, torch.uint8, "lsrvt_aggregate")
+    _need(variables, torch.float32, "lsrvt_aggregate")
+    if edges is not None:
+        _need(edges, torch.float32, "lsrvt_aggregate")
+    lib = _lib()
+    dims = _dims(cell.shape)
+    dev = cell.device
+    m = int(variables.shape[0])
+    B = 0 if edges is None else int(edges.shape[1]) - 1
+    flags = (STATS_HIST if edges is not None else 0) | (STATS_COV if cov else 0)
+    S = sites.numel()
+    if out is None:
+        out = (_alloc_level(S, m, B, edges is not None, cov, torch.float32, dev),
+               _alloc_level(n_comp, m, B, edges is not None, cov, torch.float64, dev),
+               _alloc_level(n_bands, m, B, edges is not None, cov, torch.float64, dev))
+    cs, gs, bs = out
+    c_cell, c_comp, c_band = _cstruct(CellStatsC, cs), _cstruct(GroupStatsC, gs), _cstruct(GroupStatsC, bs)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_aggregate_workspace(dims, S, n_comp, n_bands, m, B, flags))
+    code = lib.lsrvt_aggregate(_ptr(cell), dims, _ptr(sites), _ptr(site_comp), S, _ptr(comp_band), n_comp, n_bands,
+                               _ptr(variables), m, _ptr(edges), B, flags, ctypes.byref(c_cell), ctypes.byref(c_comp),
+                               ctypes.byref(c_band), wptr, wbytes, _stream(stream))
+    _check(code, "lsrvt_aggregate")
+    return out

@@ -111,8 +111,12 @@ def quantile_isovalues(f: np.ndarray, qs) -> np.ndarray:
 
 def gradient_weight(f: np.ndarray) -> np.ndarray:
     """Saliency weight max(1, round(65535 |grad f| / max |grad f|)) as uint16."""
-    g = np.gradient(f.astype(np.float64))
-    mag = np.sqrt(g[0] ** 2 + g[1] ** 2 + g[2] ** 2)
+    f64 = f.astype(np.float64)
+    mag2 = np.zeros(f.shape, dtype=np.float64)
+    for axis in range(f.ndim):
+        if f.shape[axis] >= 2:          # an axis of length 1 has no gradient
+            mag2 += np.gradient(f64, axis=axis) ** 2
+    mag = np.sqrt(mag2)
     gmax = mag.max()
     if gmax <= 0:
         return np.ones(f.shape, dtype=np.uint16)

@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/lsrvt.h; host-side validation runs without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2208_06970_amd as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsrvt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsrvt_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        from paper_2208_06970_amd import build
+        build.build()
+    return L.library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS)
+
+
+def test_status_strings_and_version(lib):
+    assert lib.lsrvt_status_string(0) == b"ok"
+    assert b"NaN" in lib.lsrvt_status_string(2)
+    assert lib.lsrvt_status_string(99) == b"unknown status"
+    assert lib.lsrvt_version() >= 100
+
+
+def test_host_validation_without_gpu(lib):
+    bad = L.Dims(0, 4, 4)
+    huge = L.Dims(32768, 1, 1)
+    big = L.Dims(32767, 32767, 4)
+    nul = ctypes.c_void_p(0)
+    iso = (ctypes.c_float * 2)(1.0, 1.0)
+    fake = ctypes.c_void_p(4096)
+    assert lib.lsrvt_isobands(fake, bad, iso, 1, fake, nul, nul) == L.EINVAL
+    assert lib.lsrvt_isobands(fake, huge, iso, 1, fake, nul, nul) == L.ELIMIT
+    assert lib.lsrvt_isobands(fake, big, iso, 1, fake, nul, nul) == L.ELIMIT
+    assert lib.lsrvt_isobands(fake, L.Dims(4, 4, 4), iso, 2, fake, nul, nul) == L.EINVAL  # not increasing
+    assert lib.lsrvt_isobands(fake, L.Dims(4, 4, 4), iso, 255, fake, nul, nul) == L.EINVAL
+    d = L.Dims(64, 64, 64)
+    assert lib.lsrvt_components_workspace(d, 5) > 64 ** 3 * 4
+    assert lib.lsrvt_cvt_workspace(d, 1000, 10) > 0
+    assert lib.lsrvt_aggregate_workspace(d, 1000, 100, 5, 3, 16, 3) > 0
+    # a workspace that is too small is refused before any launch
+    assert lib.lsrvt_components(fake, d, 5, fake, 10, fake, fake, fake, fake, ctypes.byref(ctypes.c_uint32()),
+                                fake, 16, nul) == L.EWORKSPACE
+    assert lib.lsrvt_cvt(fake, fake, d, fake, 10, nul, -1, fake, fake, fake, nul, fake, 1 << 30, nul) == L.EINVAL
+    assert lib.lsrvt_vt(fake, d, fake, 10, fake, fake, 16, nul) == L.EWORKSPACE
