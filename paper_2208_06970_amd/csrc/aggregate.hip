@@ -1,6 +1,909 @@
-// placeholder, replaced below
+// Statistics of every cell, merged cell -> component -> band (Sec. 3.3,
+// "Aggregation"; the hierarchy of Sec. 3.2.4 / Fig. 5).
+//
+// Pipeline:
+//  1. one pass over the cells: voxel count and bounding box of every cell
+//     (wave-aggregated atomics along rows);
+//  2. every cell's bounding box is cut into work items of whole box rows
+//     (about kItemVoxels voxels each; giant cells get many items);
+//  3. one workgroup per item walks its rows, compacts the voxels that belong
+//     to the cell into LDS, and accumulates, per "unit", float32 sums with an
+//     error-free two-sum compensation (hi + lo) of the values shifted by the
+//     value at the cell's site: units are sum d_j and sum d_j d_k (the product
+//     error of d_j d_k is folded into lo with an FMA).  Lanes own units, so
+//     the order of every sum is fixed.  Histograms and extrema are integer /
+//     compare operations and go through LDS and then global atomics;
+//  4. per cell, the item partials are combined in item order; mean, M2 and
+//     co-moments are formed in float32 (cell outputs) and expanded to
+//     float64 for the merges;
+//  5. Chan et al.'s pairwise merge in float64: cells of a component in site
+//     id order (sites sorted by component with a stable LSD radix sort), then
+//     components of a band in component id order.  Counts, extrema and
+//     histograms merge exactly with atomics.
 #include "common.h"
-extern "C" size_t lsrvt_aggregate_workspace(lsrvt_dims, uint32_t, uint32_t, int32_t, int32_t, int32_t, uint32_t) { return 256; }
-extern "C" int32_t lsrvt_aggregate(const uint32_t *, lsrvt_dims, const uint32_t *, const uint32_t *, uint32_t, const uint8_t *,
-                        uint32_t, int32_t, const float *, int32_t, const float *, int32_t, uint32_t,
-                        const lsrvt_cell_stats *, const lsrvt_group_stats *, const lsrvt_group_stats *, void *, size_t, void *) { return LSRVT_EINVAL; }
+
+namespace lsrvt {
+
+namespace {
+
+constexpr int kAggThreads = 256;
+constexpr int kMaxVars = 32;
+constexpr int kMaxPairs = kMaxVars * (kMaxVars + 1) / 2;
+constexpr int64_t kItemVoxels = 8192;
+constexpr int kMaxHist = 8192;  // n_vars * n_bins
+
+struct Pairs {
+  uint8_t j[kMaxPairs];
+  uint8_t k[kMaxPairs];
+};
+
+struct BBox {
+  uint32_t *x0, *x1, *y0, *y1, *z0, *z1;
+};
+
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+  s = a + b;
+  float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated accumulate of x (with an exact extra error term ex) into (hi, lo).
+__device__ __forceinline__ void acc(float &hi, float &lo, float x, float ex) {
+  float s, e;
+  two_sum(hi, x, s, e);
+  hi = s;
+  lo += e + ex;
+}
+
+// ---------------------------------------------------------------------------
+// 1. counts and bounding boxes
+__global__ __launch_bounds__(kWave) void k_agg_bbox(const uint32_t *__restrict__ cell, Geom g, uint32_t S,
+                                                    unsigned long long *cnt, BBox bb) {
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  const int lane = lane_id();
+  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+    const uint32_t y = (uint32_t)(row % g.ny), z = (uint32_t)(row / g.ny);
+    const int64_t base = row * g.nx;
+    for (int x0 = 0; x0 < g.nx; x0 += kWave) {
+      int x = x0 + lane;
+      uint32_t c = x < g.nx ? cell[base + x] : kNone;
+      bool pending = c < S;
+      while (true) {
+        uint64_t act = __ballot(pending);
+        if (!act) break;
+        int leader = __ffsll((long long)act) - 1;
+        uint32_t c0 = __shfl(c, leader, kWave);
+        bool mine = pending && c == c0;
+        uint64_t mm = __ballot(mine);
+        if (lane == leader) {
+          int last = 63 - __clzll((long long)mm);
+          atomicAdd(&cnt[c0], (unsigned long long)__popcll(mm));
+          atomicMin(&bb.x0[c0], (uint32_t)(x0 + leader));
+          atomicMax(&bb.x1[c0], (uint32_t)(x0 + last));
+          atomicMin(&bb.y0[c0], y);
+          atomicMax(&bb.y1[c0], y);
+          atomicMin(&bb.z0[c0], z);
+          atomicMax(&bb.z1[c0], z);
+        }
+        pending = pending && !mine;
+      }
+    }
+  }
+}
+
+// 2. items per cell: whole bounding-box rows, about `target` voxels per item
+__global__ void k_agg_items(const unsigned long long *__restrict__ cnt, BBox bb, uint32_t S, int64_t target,
+                            uint32_t *items, uint32_t *rows_per_item) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  if (cnt[s] == 0) {
+    items[s] = 0;
+    rows_per_item[s] = 1;
+    return;
+  }
+  int64_t lx = (int64_t)bb.x1[s] - bb.x0[s] + 1;
+  int64_t rows = ((int64_t)bb.y1[s] - bb.y0[s] + 1) * ((int64_t)bb.z1[s] - bb.z0[s] + 1);
+  int64_t rpi = target / lx;
+  if (rpi < 1) rpi = 1;
+  if (rpi > rows) rpi = rows;
+  items[s] = (uint32_t)((rows + rpi - 1) / rpi);
+  rows_per_item[s] = (uint32_t)rpi;
+}
+
+// 3. per-item compensated sums
+struct CellArgs {
+  const uint32_t *cell;
+  Geom g;
+  uint32_t S;
+  const uint32_t *sites;
+  const float *vars;  // [m][N]
+  const float *edges; // [m][B+1] or null
+  int m, B, U, G, P;
+  Pairs pairs;
+  BBox bb;
+  const uint32_t *item_off;  // [S + 1]
+  const uint32_t *rows_per_item;
+  uint32_t n_items;
+  float *part_hi, *part_lo;  // [n_items][U]
+  uint32_t *hist;            // cell histograms [S][m][B] (zeroed) or null
+  uint32_t *kmin, *kmax;     // ordered keys [S][m]
+};
+
+// R = unit slots per lane: with R == 1 the U units are replicated over
+// G = 256 / U lane groups that split the voxels; with R > 1 (more units than
+// lanes) lane t owns units t, t + 256, ... and G = 1.
+template <int R>
+__global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
+  extern __shared__ uint8_t smem[];
+  const int m = A.m, B = A.B, U = A.U, G = A.G;
+  float *vals = reinterpret_cast<float *>(smem);                           // [m][256]
+  uint32_t *hist_l = reinterpret_cast<uint32_t *>(vals + m * kAggThreads);  // [m*B]
+  uint32_t *kmin_l = hist_l + m * B;                                        // [m]
+  uint32_t *kmax_l = kmin_l + m;                                            // [m]
+  float *K = reinterpret_cast<float *>(kmax_l + m);                         // [m]
+  float *ph = K + m;                                                        // [G*U]
+  float *pl = ph + G * U;                                                   // [G*U]
+  __shared__ uint32_t wcnt[4];
+  __shared__ uint32_t s_ntile;
+  const int t = threadIdx.x;
+  const int wid = t / kWave;
+  const int grp = R == 1 ? t / U : 0;
+  const Geom g = A.g;
+
+  for (uint32_t item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+    // the cell of this item: last s with item_off[s] <= item
+    uint32_t lo_s = 0, hi_s = A.S;
+    while (hi_s - lo_s > 1) {
+      uint32_t mid = (lo_s + hi_s) >> 1;
+      if (A.item_off[mid] <= item)
+        lo_s = mid;
+      else
+        hi_s = mid;
+    }
+    const uint32_t s = lo_s;
+    const uint32_t part = item - A.item_off[s];
+    const int64_t x0 = A.bb.x0[s], y0 = A.bb.y0[s], z0 = A.bb.z0[s];
+    const int64_t lx = (int64_t)A.bb.x1[s] - x0 + 1, ly = (int64_t)A.bb.y1[s] - y0 + 1;
+    const int64_t rows = ly * ((int64_t)A.bb.z1[s] - z0 + 1);
+    const int64_t rpi = A.rows_per_item[s];
+    const int64_t r0 = (int64_t)part * rpi;
+    const int64_t r1 = r0 + rpi < rows ? r0 + rpi : rows;
+    const int64_t span = (r1 - r0) * lx;
+
+    for (int i = t; i < m * B; i += kAggThreads) hist_l[i] = 0;
+    if (t < m) {
+      kmin_l[t] = 0xFFFFFFFFu;
+      kmax_l[t] = 0u;
+      K[t] = A.vars[(int64_t)t * g.n + A.sites[s]];
+    }
+    float hi[R], lo[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) hi[r] = lo[r] = 0.0f;
+    __syncthreads();
+
+    for (int64_t base = 0; base < span; base += kAggThreads) {
+      const int64_t idx = base + t;
+      bool match = false;
+      int64_t v = 0;
+      if (idx < span) {
+        int64_t r = r0 + idx / lx;
+        int64_t x = x0 + idx % lx;
+        int64_t y = y0 + r % ly;
+        int64_t z = z0 + r / ly;
+        v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+        match = A.cell[v] == s;
+      }
+      uint64_t bal = __ballot(match);
+      if (lane_id() == 0) wcnt[wid] = (uint32_t)__popcll(bal);
+      __syncthreads();
+      uint32_t slot = (uint32_t)__popcll(bal & lanemask_lt());
+      for (int w = 0; w < wid; ++w) slot += wcnt[w];
+      if (t == 0) s_ntile = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+      if (match) {
+        for (int j = 0; j < m; ++j) {
+          float xv = A.vars[(int64_t)j * g.n + v];
+          vals[j * kAggThreads + slot] = xv;
+          uint32_t kk = f2key(xv);
+          atomicMin(&kmin_l[j], kk);
+          atomicMax(&kmax_l[j], kk);
+          if (B > 0) {
+            const float *e = A.edges + (int64_t)j * (B + 1);
+            int bin = 0;
+            for (int q = 1; q < B; ++q) bin += (e[q] <= xv) ? 1 : 0;
+            atomicAdd(&hist_l[j * B + bin], 1u);
+          }
+        }
+      }
+      __syncthreads();
+      const uint32_t ntile = s_ntile;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int u = R == 1 ? t % U : t + r * kAggThreads;
+        const bool worker = R == 1 ? t < G * U : u < U;
+        if (!worker) continue;
+        if (u < m) {
+          const float kj = K[u];
+          for (uint32_t q = grp; q < ntile; q += G) {
+            float d = vals[u * kAggThreads + q] - kj;
+            acc(hi[r], lo[r], d, 0.0f);
+          }
+        } else {
+          const int p = u - m;
+          const int j = A.pairs.j[p], k = A.pairs.k[p];
+          const float kj = K[j], kk = K[k];
+          for (uint32_t q = grp; q < ntile; q += G) {
+            float dj = vals[j * kAggThreads + q] - kj;
+            float dk = vals[k * kAggThreads + q] - kk;
+            float pr = dj * dk;
+            float pe = __builtin_fmaf(dj, dk, -pr);  // exact error of the product
+            acc(hi[r], lo[r], pr, pe);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // combine the lane groups in group order
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int u = R == 1 ? t % U : t + r * kAggThreads;
+      const bool worker = R == 1 ? t < G * U : u < U;
+      if (worker) {
+        ph[grp * U + u] = hi[r];
+        pl[grp * U + u] = lo[r];
+      }
+    }
+    __syncthreads();
+    for (int u = t; u < U; u += kAggThreads) {
+      float H = 0.0f, Lo = 0.0f;
+      for (int gg = 0; gg < G; ++gg) {
+        acc(H, Lo, ph[gg * U + u], 0.0f);
+        Lo += pl[gg * U + u];
+      }
+      A.part_hi[(int64_t)item * U + u] = H;
+      A.part_lo[(int64_t)item * U + u] = Lo;
+    }
+    // flush exact integer/compare statistics
+    if (A.hist) {
+      uint32_t *dst = A.hist + (int64_t)s * m * B;
+      for (int i = t; i < m * B; i += kAggThreads)
+        if (hist_l[i]) atomicAdd(&dst[i], hist_l[i]);
+    }
+    if (t < m) {
+      if (kmin_l[t] != 0xFFFFFFFFu) atomicMin(&A.kmin[(int64_t)s * m + t], kmin_l[t]);
+      if (kmax_l[t] != 0u) atomicMax(&A.kmax[(int64_t)s * m + t], kmax_l[t]);
+    }
+    __syncthreads();
+  }
+}
+
+// 4. per-cell finalize: combine item partials (item order), form the float32
+// statistics and the float64 merge inputs.
+struct FinArgs {
+  uint32_t S;
+  int m, U, P;  // P = number of pair units (all pairs, or the diagonal only)
+  Pairs pairs;
+  const uint32_t *sites;
+  const float *vars;
+  int64_t n;
+  const unsigned long long *cnt;
+  const uint32_t *item_off;
+  const float *part_hi, *part_lo;
+  const uint32_t *kmin, *kmax;
+  // outputs
+  uint64_t *out_n;
+  float *mean32, *m2_32, *vmin, *vmax, *cov32;  // cov32 [S][m(m+1)/2] (only with cov)
+  int with_cov;
+  double *mean64;  // [S][m]
+  double *c64;     // [S][P]
+};
+
+__global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
+  extern __shared__ uint8_t smem[];
+  float *th = reinterpret_cast<float *>(smem);  // [U]
+  float *tl = th + A.U;                         // [U]
+  float *K = tl + A.U;                          // [m]
+  const int t = threadIdx.x;
+  const int m = A.m;
+  for (uint32_t s = blockIdx.x; s < A.S; s += gridDim.x) {
+    const uint64_t n = A.cnt[s];
+    const uint32_t i0 = A.item_off[s], i1 = A.item_off[s + 1];
+    for (int u = t; u < A.U; u += kAggThreads) {
+      float H = 0.0f, Lo = 0.0f;
+      for (uint32_t it = i0; it < i1; ++it) {
+        acc(H, Lo, A.part_hi[(int64_t)it * A.U + u], 0.0f);
+        Lo += A.part_lo[(int64_t)it * A.U + u];
+      }
+      th[u] = H;
+      tl[u] = Lo;
+    }
+    if (t < m) K[t] = n ? A.vars[(int64_t)t * A.n + A.sites[s]] : 0.0f;
+    __syncthreads();
+    if (t == 0) A.out_n[s] = n;
+    const float fn = (float)n;
+    const double dn = (double)n;
+    for (int j = t; j < m; j += kAggThreads) {
+      float mean = 0.0f;
+      double mean64 = 0.0;
+      if (n) {
+        float sj = th[j] + tl[j];
+        mean = K[j] + sj / fn;
+        mean64 = (double)K[j] + ((double)th[j] + (double)tl[j]) / dn;
+      }
+      A.mean32[(int64_t)s * m + j] = mean;
+      A.mean64[(int64_t)s * m + j] = mean64;
+      A.vmin[(int64_t)s * m + j] = n ? key2f(A.kmin[(int64_t)s * m + j]) : __builtin_inff();
+      A.vmax[(int64_t)s * m + j] = n ? key2f(A.kmax[(int64_t)s * m + j]) : -__builtin_inff();
+    }
+    for (int p = t; p < A.P; p += kAggThreads) {
+      const int j = A.pairs.j[p], k = A.pairs.k[p];
+      float c32 = 0.0f;
+      double c64 = 0.0;
+      if (n) {
+        const int uq = m + p;
+        float sj = th[j] + tl[j], sk = th[k] + tl[k];
+        float tt = sj * (sk / fn);
+        c32 = (th[uq] - tt) + tl[uq];
+        if (j == k && c32 < 0.0f) c32 = 0.0f;
+        double dj = (double)th[j] + (double)tl[j], dk = (double)th[k] + (double)tl[k];
+        c64 = ((double)th[uq] + (double)tl[uq]) - dj * dk / dn;
+        if (j == k && c64 < 0.0) c64 = 0.0;
+      }
+      A.c64[(int64_t)s * A.P + p] = c64;
+      if (j == k) A.m2_32[(int64_t)s * m + j] = c32;
+      if (A.with_cov) A.cov32[(int64_t)s * A.P + p] = c32;
+    }
+    __syncthreads();
+  }
+}
+
+// 5a. exact merges of counts, extrema and histograms to the two upper levels
+struct ExactArgs {
+  uint32_t S;
+  int m, B;
+  const uint32_t *site_comp;
+  const uint8_t *comp_band;
+  uint32_t n_comp;
+  const unsigned long long *cnt;
+  const uint32_t *kmin, *kmax;    // cell keys [S][m]
+  const uint32_t *hist;           // cell hist [S][m][B] or null
+  unsigned long long *cnt_c, *cnt_b;
+  uint32_t *kmin_c, *kmax_c, *kmin_b, *kmax_b;
+  uint32_t *hist_c, *hist_b;
+};
+
+__global__ void k_agg_exact(ExactArgs A) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)A.m * (A.B > 0 ? A.B : 1);
+  if (i >= (int64_t)A.S * per) return;
+  const uint32_t s = (uint32_t)(i / per);
+  const int64_t r = i % per;
+  const uint32_t c = A.site_comp[s];
+  if (c >= A.n_comp || A.cnt[s] == 0) return;
+  const uint32_t b = A.comp_band[c];
+  if (r == 0) {
+    atomicAdd(&A.cnt_c[c], A.cnt[s]);
+    atomicAdd(&A.cnt_b[b], A.cnt[s]);
+  }
+  const int B = A.B > 0 ? A.B : 1;
+  const int j = (int)(r / B), bin = (int)(r % B);
+  if (bin == 0) {
+    uint32_t kn = A.kmin[(int64_t)s * A.m + j], kx = A.kmax[(int64_t)s * A.m + j];
+    atomicMin(&A.kmin_c[(int64_t)c * A.m + j], kn);
+    atomicMax(&A.kmax_c[(int64_t)c * A.m + j], kx);
+    atomicMin(&A.kmin_b[(int64_t)b * A.m + j], kn);
+    atomicMax(&A.kmax_b[(int64_t)b * A.m + j], kx);
+  }
+  if (A.hist && A.B > 0) {
+    uint32_t h = A.hist[((int64_t)s * A.m + j) * A.B + bin];
+    if (h) {
+      atomicAdd(&A.hist_c[((int64_t)c * A.m + j) * A.B + bin], h);
+      atomicAdd(&A.hist_b[((int64_t)b * A.m + j) * A.B + bin], h);
+    }
+  }
+}
+
+__global__ void k_decode_minmax(const uint32_t *kmin, const uint32_t *kmax, const unsigned long long *cnt, int64_t units,
+                                int m, float *vmin, float *vmax, uint64_t *out_n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= units * m) return;
+  int64_t u = i / m;
+  bool any = cnt[u] != 0;
+  vmin[i] = any ? key2f(kmin[i]) : __builtin_inff();
+  vmax[i] = any ? key2f(kmax[i]) : -__builtin_inff();
+  if (i % m == 0) out_n[u] = cnt[u];
+}
+
+// 5b. Chan pairwise merge in float64, one thread per (group, pair unit):
+// members of group g are order[off[g] .. off[g+1]) in that order.
+struct MergeArgs {
+  uint32_t n_groups;
+  int m, P;
+  Pairs pairs;
+  const uint32_t *order;
+  const uint32_t *off;
+  const uint32_t *member_id;       // maps a sorted position to the member index (order)
+  const double *in_n;              // member counts as double, or null (then in_cnt)
+  const unsigned long long *in_cnt;
+  const double *in_mean;           // [members][m]
+  const double *in_c;              // [members][P]
+  double *out_mean;                // [groups][m]
+  double *out_m2;                  // [groups][m]
+  double *out_c;                   // [groups][P] (internal, always)
+  double *out_cov;                 // [groups][m(m+1)/2] or null (user output)
+  int with_cov;
+};
+
+__global__ void k_chan_merge(MergeArgs A) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)A.n_groups * A.P) return;
+  const uint32_t gidx = (uint32_t)(i / A.P);
+  const int p = (int)(i % A.P);
+  const int j = A.pairs.j[p], k = A.pairs.k[p];
+  double n = 0.0, mj = 0.0, mk = 0.0, c = 0.0;
+  for (uint32_t q = A.off[gidx]; q < A.off[gidx + 1]; ++q) {
+    const uint32_t mem = A.order[q];
+    const double ni = (double)A.in_cnt[mem];
+    if (ni == 0.0) continue;
+    const double aj = A.in_mean[(int64_t)mem * A.m + j], ak = A.in_mean[(int64_t)mem * A.m + k];
+    const double ci = A.in_c[(int64_t)mem * A.P + p];
+    if (n == 0.0) {
+      n = ni;
+      mj = aj;
+      mk = ak;
+      c = ci;
+      continue;
+    }
+    const double nn = n + ni;
+    const double dj = aj - mj, dk = ak - mk;
+    c = c + ci + dj * dk * (n * ni / nn);
+    mj = mj + dj * (ni / nn);
+    mk = mk + dk * (ni / nn);
+    n = nn;
+  }
+  A.out_c[(int64_t)gidx * A.P + p] = c;
+  if (j == k) {
+    A.out_mean[(int64_t)gidx * A.m + j] = mj;
+    A.out_m2[(int64_t)gidx * A.m + j] = c;
+  }
+  if (A.with_cov) A.out_cov[(int64_t)gidx * A.P + p] = c;
+}
+
+// helpers for sorting sites by component
+__global__ void k_digit(const uint32_t *key, uint32_t n, int shift, uint8_t *digit) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) digit[i] = (uint8_t)(key[i] >> shift);
+}
+__global__ void k_permute(const uint32_t *key, const uint32_t *val, const uint32_t *pos, uint32_t n, uint32_t *key_out,
+                          uint32_t *val_out) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    key_out[pos[i]] = key[i];
+    val_out[pos[i]] = val[i];
+  }
+}
+__global__ void k_init_sort(const uint32_t *site_comp, uint32_t S, uint32_t n_comp, uint32_t *key, uint32_t *val,
+                            uint32_t *count) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < S) {
+    uint32_t c = site_comp[i];
+    if (c > n_comp) c = n_comp;  // out-of-range components collect in a last, unmerged group
+    key[i] = c;
+    val[i] = i;
+    atomicAdd(&count[c], 1u);
+  }
+}
+__global__ void k_iota(uint32_t *p, uint32_t n) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = i;
+}
+
+struct AggWork {
+  unsigned long long *cnt, *cnt_c, *cnt_b;
+  uint32_t *bbox;  // 6 x S
+  uint32_t *items, *rpi, *item_off;
+  float *part_hi, *part_lo;
+  uint32_t *kmin, *kmax, *kmin_c, *kmax_c, *kmin_b, *kmax_b;
+  double *mean64, *c64, *mean64_c, *c64_c, *m2tmp_c, *mean64_b, *c64_b, *m2tmp_b;
+  uint32_t *key_a, *val_a, *key_b, *val_b, *pos, *ccount, *coff, *corder, *bucket;
+  uint8_t *digit;
+  void *scratch;
+  size_t scratch_bytes;
+  int64_t item_cap;
+};
+
+int64_t item_capacity(const Geom &g, uint32_t S) { return (int64_t)S + 4 * (g.n / kItemVoxels) + 1024; }
+
+template <class A>
+void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_bands, int m, int U, int P, AggWork *W) {
+  size_t s1 = S ? S : 1, c1 = n_comp + 2, b1 = (size_t)n_bands + 1;
+  int64_t ic = item_capacity(g, S);
+  auto cnt = a.template take<unsigned long long>(s1);
+  auto cnt_c = a.template take<unsigned long long>(c1);
+  auto cnt_b = a.template take<unsigned long long>(b1);
+  auto bbox = a.template take<uint32_t>(6 * s1);
+  auto items = a.template take<uint32_t>(s1);
+  auto rpi = a.template take<uint32_t>(s1);
+  auto ioff = a.template take<uint32_t>(s1 + 1);
+  auto ph = a.template take<float>(ic * U);
+  auto pl = a.template take<float>(ic * U);
+  auto kmin = a.template take<uint32_t>(s1 * m);
+  auto kmax = a.template take<uint32_t>(s1 * m);
+  auto kminc = a.template take<uint32_t>(c1 * m);
+  auto kmaxc = a.template take<uint32_t>(c1 * m);
+  auto kminb = a.template take<uint32_t>(b1 * m);
+  auto kmaxb = a.template take<uint32_t>(b1 * m);
+  auto mean64 = a.template take<double>(s1 * m);
+  auto c64 = a.template take<double>(s1 * P);
+  auto mean64c = a.template take<double>(c1 * m);
+  auto c64c = a.template take<double>(c1 * P);
+  auto m2c = a.template take<double>(c1 * m);
+  auto mean64b = a.template take<double>(b1 * m);
+  auto c64b = a.template take<double>(b1 * P);
+  auto m2b = a.template take<double>(b1 * m);
+  size_t sortn = s1 > c1 ? s1 : c1;
+  auto ka = a.template take<uint32_t>(sortn);
+  auto va = a.template take<uint32_t>(sortn);
+  auto kb = a.template take<uint32_t>(sortn);
+  auto vb = a.template take<uint32_t>(sortn);
+  auto pos = a.template take<uint32_t>(sortn);
+  auto ccount = a.template take<uint32_t>(c1 + 1);
+  auto coff = a.template take<uint32_t>(c1 + 2);
+  auto corder = a.template take<uint32_t>(c1);
+  auto bucket = a.template take<uint32_t>(257);
+  auto digit = a.template take<uint8_t>(sortn);
+  if (W) {
+    W->cnt = cnt;
+    W->cnt_c = cnt_c;
+    W->cnt_b = cnt_b;
+    W->bbox = bbox;
+    W->items = items;
+    W->rpi = rpi;
+    W->item_off = ioff;
+    W->part_hi = ph;
+    W->part_lo = pl;
+    W->kmin = kmin;
+    W->kmax = kmax;
+    W->kmin_c = kminc;
+    W->kmax_c = kmaxc;
+    W->kmin_b = kminb;
+    W->kmax_b = kmaxb;
+    W->mean64 = mean64;
+    W->c64 = c64;
+    W->mean64_c = mean64c;
+    W->c64_c = c64c;
+    W->m2tmp_c = m2c;
+    W->mean64_b = mean64b;
+    W->c64_b = c64b;
+    W->m2tmp_b = m2b;
+    W->key_a = ka;
+    W->val_a = va;
+    W->key_b = kb;
+    W->val_b = vb;
+    W->pos = pos;
+    W->ccount = ccount;
+    W->coff = coff;
+    W->corder = corder;
+    W->bucket = bucket;
+    W->digit = digit;
+    W->item_cap = ic;
+  }
+}
+
+struct SizerT : Sizer {
+  template <class T>
+  T *take(size_t c) {
+    Sizer::take<T>(c);
+    return nullptr;
+  }
+};
+
+void units_for(int m, bool cov, int &P, int &U, Pairs &pairs) {
+  P = 0;
+  for (int j = 0; j < m; ++j)
+    for (int k = j; k < m; ++k)
+      if (cov || j == k) {
+        pairs.j[P] = (uint8_t)j;
+        pairs.k[P] = (uint8_t)k;
+        ++P;
+      }
+  U = m + P;
+}
+
+size_t scratch_need(uint32_t S, uint32_t n_comp) {
+  size_t a = ScanU32::workspace((int64_t)S + 1);
+  size_t b = StableSort8::workspace((int64_t)(S > n_comp + 2 ? S : n_comp + 2));
+  size_t c = ScanU32::workspace((int64_t)n_comp + 2);
+  size_t r = a > b ? a : b;
+  return (r > c ? r : c) + 256;
+}
+
+}  // namespace
+
+}  // namespace lsrvt
+
+using namespace lsrvt;
+
+extern "C" size_t lsrvt_aggregate_workspace(lsrvt_dims dims, uint32_t n_sites, uint32_t n_comp, int32_t n_bands,
+                                            int32_t n_vars, int32_t n_bins, uint32_t flags) {
+  (void)n_bins;
+  Geom g;
+  if (make_geom(dims, g)) return 0;
+  if (n_vars < 1 || n_vars > kMaxVars || n_bands < 1 || n_bands > 255) return 0;
+  int P, U;
+  Pairs pairs;
+  units_for(n_vars, (flags & LSRVT_STATS_COV) != 0, P, U, pairs);
+  SizerT z;
+  agg_layout(z, g, n_sites, n_comp, n_bands, n_vars, U, P, nullptr);
+  return z.off + scratch_need(n_sites, n_comp);
+}
+
+extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t *d_sites,
+                                   const uint32_t *d_site_comp, uint32_t n_sites, const uint8_t *d_comp_band,
+                                   uint32_t n_comp, int32_t n_bands, const float *d_vars, int32_t n_vars,
+                                   const float *d_edges, int32_t n_bins, uint32_t flags, const lsrvt_cell_stats *cell,
+                                   const lsrvt_group_stats *comp, const lsrvt_group_stats *band, void *d_work,
+                                   size_t work_bytes, void *stream) {
+  Geom g;
+  int32_t rc = make_geom(dims, g);
+  if (rc) return rc;
+  if (n_vars < 1 || n_vars > kMaxVars || n_bands < 1 || n_bands > 255) return LSRVT_EINVAL;
+  if (!d_cell || !d_vars || !cell || !comp || !band) return LSRVT_EINVAL;
+  if (n_sites && (!d_sites || !d_site_comp)) return LSRVT_EINVAL;
+  if (n_comp && !d_comp_band) return LSRVT_EINVAL;
+  const bool want_hist = (flags & LSRVT_STATS_HIST) != 0;
+  const bool want_cov = (flags & LSRVT_STATS_COV) != 0;
+  const int B = want_hist ? n_bins : 0;
+  if (want_hist && (n_bins < 1 || !d_edges || (int64_t)n_vars * n_bins > kMaxHist)) return LSRVT_EINVAL;
+  const lsrvt_cell_stats &cs = *cell;
+  const lsrvt_group_stats *lv[2] = {comp, band};
+  if (!cs.n || !cs.mean || !cs.m2 || !cs.vmin || !cs.vmax || (want_hist && !cs.hist) || (want_cov && !cs.cov))
+    return LSRVT_EINVAL;
+  for (const lsrvt_group_stats *q : lv)
+    if (!q->n || !q->mean || !q->m2 || !q->vmin || !q->vmax || (want_hist && !q->hist) || (want_cov && !q->cov))
+      return LSRVT_EINVAL;
+  const size_t need = lsrvt_aggregate_workspace(dims, n_sites, n_comp, n_bands, n_vars, n_bins, flags);
+  if ((rc = check_work(d_work, work_bytes, need))) return rc;
+  int P, U;
+  Pairs pairs;
+  units_for(n_vars, want_cov, P, U, pairs);
+  const int m = n_vars;
+  Carve cv(d_work, work_bytes);
+  AggWork W;
+  agg_layout(cv, g, n_sites, n_comp, n_bands, m, U, P, &W);
+  if (!cv.ok) return LSRVT_EWORKSPACE;
+  W.scratch = cv.base + cv.off;
+  W.scratch_bytes = cv.size - cv.off;
+  hipStream_t s = as_stream(stream);
+  const uint32_t S = n_sites;
+  const uint32_t C = n_comp;
+  const int64_t Pfull = (int64_t)m * (m + 1) / 2;
+
+  // zero / identity initialisation
+  if ((rc = fill<unsigned long long>(W.cnt, S ? S : 1, 0ull, s))) return rc;
+  if ((rc = fill<unsigned long long>(W.cnt_c, C + 2, 0ull, s))) return rc;
+  if ((rc = fill<unsigned long long>(W.cnt_b, n_bands + 1, 0ull, s))) return rc;
+  for (int q = 0; q < 6; ++q)
+    if ((rc = fill<uint32_t>(W.bbox + (size_t)q * (S ? S : 1), S ? S : 1, (q % 2 == 0) ? 0xFFFFFFFFu : 0u, s)))
+      return rc;
+  if ((rc = fill<uint32_t>(W.kmin, (int64_t)(S ? S : 1) * m, 0xFFFFFFFFu, s))) return rc;
+  if ((rc = fill<uint32_t>(W.kmax, (int64_t)(S ? S : 1) * m, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.kmin_c, (int64_t)(C + 2) * m, 0xFFFFFFFFu, s))) return rc;
+  if ((rc = fill<uint32_t>(W.kmax_c, (int64_t)(C + 2) * m, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.kmin_b, (int64_t)(n_bands + 1) * m, 0xFFFFFFFFu, s))) return rc;
+  if ((rc = fill<uint32_t>(W.kmax_b, (int64_t)(n_bands + 1) * m, 0u, s))) return rc;
+  if (want_hist) {
+    if ((rc = fill<uint32_t>(cs.hist, (int64_t)S * m * B, 0u, s))) return rc;
+    if ((rc = fill<uint32_t>(comp->hist, (int64_t)C * m * B, 0u, s))) return rc;
+    if ((rc = fill<uint32_t>(band->hist, (int64_t)n_bands * m * B, 0u, s))) return rc;
+  }
+  BBox bb{W.bbox, W.bbox + (S ? S : 1), W.bbox + 2 * (size_t)(S ? S : 1), W.bbox + 3 * (size_t)(S ? S : 1),
+          W.bbox + 4 * (size_t)(S ? S : 1), W.bbox + 5 * (size_t)(S ? S : 1)};
+
+  // 1-2. counts, boxes, items
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  uint32_t n_items = 0;
+  if (S) {
+    hipLaunchKernelGGL(k_agg_bbox, dim3((unsigned)(rows < 262144 ? rows : 262144)), dim3(kWave), 0, s, d_cell, g, S,
+                       W.cnt, bb);
+    LSRVT_LAUNCHED();
+    int64_t target = kItemVoxels;
+    while (true) {
+      hipLaunchKernelGGL(k_agg_items, dim3((S + 255) / 256), dim3(256), 0, s, W.cnt, bb, S, target, W.items, W.rpi);
+      LSRVT_LAUNCHED();
+      if ((rc = ScanU32::run(W.items, S, W.item_off, W.scratch, W.scratch_bytes, s))) return rc;
+      LSRVT_HIP(hipMemcpyAsync(&n_items, W.item_off + S, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+      LSRVT_HIP(hipStreamSynchronize(s));
+      if ((int64_t)n_items <= W.item_cap) break;
+      target *= 2;
+    }
+  }
+
+  // 3. per-item sums
+  if (n_items) {
+    CellArgs A;
+    A.cell = d_cell;
+    A.g = g;
+    A.S = S;
+    A.sites = d_sites;
+    A.vars = d_vars;
+    A.edges = d_edges;
+    A.m = m;
+    A.B = B;
+    A.U = U;
+    A.P = P;
+    A.pairs = pairs;
+    A.bb = bb;
+    A.item_off = W.item_off;
+    A.rows_per_item = W.rpi;
+    A.n_items = n_items;
+    A.part_hi = W.part_hi;
+    A.part_lo = W.part_lo;
+    A.hist = want_hist ? cs.hist : nullptr;
+    A.kmin = W.kmin;
+    A.kmax = W.kmax;
+    const int R = (U + kAggThreads - 1) / kAggThreads;
+    A.G = R == 1 ? kAggThreads / U : 1;
+    size_t lds = sizeof(float) * ((size_t)m * kAggThreads + (size_t)m * B + 3 * m + 2 * (size_t)A.G * U);
+    if (lds > 65536 || R > 3) return LSRVT_EINVAL;
+    unsigned grid = n_items < 8192 ? n_items : 8192;
+    if (R == 1)
+      hipLaunchKernelGGL(k_agg_cell<1>, dim3(grid), dim3(kAggThreads), lds, s, A);
+    else if (R == 2)
+      hipLaunchKernelGGL(k_agg_cell<2>, dim3(grid), dim3(kAggThreads), lds, s, A);
+    else
+      hipLaunchKernelGGL(k_agg_cell<3>, dim3(grid), dim3(kAggThreads), lds, s, A);
+    LSRVT_LAUNCHED();
+  }
+
+  // 4. per-cell finalize
+  if (S) {
+    FinArgs F;
+    F.S = S;
+    F.m = m;
+    F.U = U;
+    F.P = P;
+    F.pairs = pairs;
+    F.sites = d_sites;
+    F.vars = d_vars;
+    F.n = g.n;
+    F.cnt = W.cnt;
+    F.item_off = W.item_off;
+    F.part_hi = W.part_hi;
+    F.part_lo = W.part_lo;
+    F.kmin = W.kmin;
+    F.kmax = W.kmax;
+    F.out_n = cs.n;
+    F.mean32 = cs.mean;
+    F.m2_32 = cs.m2;
+    F.vmin = cs.vmin;
+    F.vmax = cs.vmax;
+    F.cov32 = cs.cov;
+    F.with_cov = want_cov;
+    F.mean64 = W.mean64;
+    F.c64 = W.c64;
+    size_t lds = sizeof(float) * (2 * (size_t)U + m);
+    hipLaunchKernelGGL(k_agg_finalize, dim3(S < 16384 ? S : 16384), dim3(kAggThreads), lds, s, F);
+    LSRVT_LAUNCHED();
+  }
+
+  // 5a. exact merges
+  if (S) {
+    ExactArgs E;
+    E.S = S;
+    E.m = m;
+    E.B = B;
+    E.site_comp = d_site_comp;
+    E.comp_band = d_comp_band;
+    E.n_comp = C;
+    E.cnt = W.cnt;
+    E.kmin = W.kmin;
+    E.kmax = W.kmax;
+    E.hist = want_hist ? cs.hist : nullptr;
+    E.cnt_c = W.cnt_c;
+    E.cnt_b = W.cnt_b;
+    E.kmin_c = W.kmin_c;
+    E.kmax_c = W.kmax_c;
+    E.kmin_b = W.kmin_b;
+    E.kmax_b = W.kmax_b;
+    E.hist_c = want_hist ? comp->hist : nullptr;
+    E.hist_b = want_hist ? band->hist : nullptr;
+    int64_t total = (int64_t)S * m * (B > 0 ? B : 1);
+    hipLaunchKernelGGL(k_agg_exact, dim3(grid_for(total, 256, 1 << 30)), dim3(256), 0, s, E);
+    LSRVT_LAUNCHED();
+  }
+  if (C) {
+    hipLaunchKernelGGL(k_decode_minmax, dim3(grid_for((int64_t)C * m, 256, 1 << 30)), dim3(256), 0, s, W.kmin_c,
+                       W.kmax_c, W.cnt_c, (int64_t)C, m, comp->vmin, comp->vmax, comp->n);
+    LSRVT_LAUNCHED();
+  }
+  hipLaunchKernelGGL(k_decode_minmax, dim3(grid_for((int64_t)n_bands * m, 256, 1 << 30)), dim3(256), 0, s, W.kmin_b,
+                     W.kmax_b, W.cnt_b, (int64_t)n_bands, m, band->vmin, band->vmax, band->n);
+  LSRVT_LAUNCHED();
+
+  // 5b. sites sorted by component (stable in site id), then the cell -> component merge
+  if (C) {
+    if ((rc = fill<uint32_t>(W.ccount, C + 2, 0u, s))) return rc;
+    if (S) {
+      hipLaunchKernelGGL(k_init_sort, dim3((S + 255) / 256), dim3(256), 0, s, d_site_comp, S, C, W.key_a, W.val_a,
+                         W.ccount);
+      LSRVT_LAUNCHED();
+      int passes = 1;
+      while (passes < 4 && ((uint64_t)C >> (8 * passes)) != 0) ++passes;
+      uint32_t *ka = W.key_a, *va = W.val_a, *kb = W.key_b, *vb = W.val_b;
+      for (int p = 0; p < passes; ++p) {
+        hipLaunchKernelGGL(k_digit, dim3((S + 255) / 256), dim3(256), 0, s, ka, S, 8 * p, W.digit);
+        LSRVT_LAUNCHED();
+        if ((rc = StableSort8::run(W.digit, S, W.pos, nullptr, W.scratch, W.scratch_bytes, s))) return rc;
+        hipLaunchKernelGGL(k_permute, dim3((S + 255) / 256), dim3(256), 0, s, ka, va, W.pos, S, kb, vb);
+        LSRVT_LAUNCHED();
+        uint32_t *t1 = ka, *t2 = va;
+        ka = kb;
+        va = vb;
+        kb = t1;
+        vb = t2;
+      }
+      if ((rc = ScanU32::run(W.ccount, C + 1, W.coff, W.scratch, W.scratch_bytes, s))) return rc;
+      MergeArgs M;
+      M.n_groups = C;
+      M.m = m;
+      M.P = P;
+      M.pairs = pairs;
+      M.order = va;
+      M.off = W.coff;
+      M.member_id = nullptr;
+      M.in_n = nullptr;
+      M.in_cnt = W.cnt;
+      M.in_mean = W.mean64;
+      M.in_c = W.c64;
+      M.out_mean = comp->mean;
+      M.out_m2 = comp->m2;
+      M.out_c = W.c64_c;
+      M.out_cov = comp->cov;
+      M.with_cov = want_cov;
+      hipLaunchKernelGGL(k_chan_merge, dim3(grid_for((int64_t)C * P, 256, 1 << 30)), dim3(256), 0, s, M);
+      LSRVT_LAUNCHED();
+      // keep float64 component means for the band merge
+      LSRVT_HIP(hipMemcpyAsync(W.mean64_c, comp->mean, sizeof(double) * (size_t)C * m, hipMemcpyDeviceToDevice, s));
+    } else {
+      if ((rc = fill<double>(comp->mean, (int64_t)C * m, 0.0, s))) return rc;
+      if ((rc = fill<double>(comp->m2, (int64_t)C * m, 0.0, s))) return rc;
+      if (want_cov && (rc = fill<double>(comp->cov, (int64_t)C * Pfull, 0.0, s))) return rc;
+      if ((rc = fill<double>(W.mean64_c, (int64_t)C * m, 0.0, s))) return rc;
+      if ((rc = fill<double>(W.c64_c, (int64_t)C * P, 0.0, s))) return rc;
+    }
+  }
+
+  // 5c. component -> band merge, components of a band in id order
+  {
+    if (C) {
+      hipLaunchKernelGGL(k_iota, dim3((C + 255) / 256), dim3(256), 0, s, W.corder, C);
+      LSRVT_LAUNCHED();
+      if ((rc = StableSort8::run(d_comp_band, C, W.pos, W.bucket, W.scratch, W.scratch_bytes, s))) return rc;
+      hipLaunchKernelGGL(k_permute, dim3((C + 255) / 256), dim3(256), 0, s, W.corder, W.corder, W.pos, C, W.key_b,
+                         W.val_b);
+      LSRVT_LAUNCHED();
+    } else {
+      if ((rc = fill<uint32_t>(W.bucket, 257, 0u, s))) return rc;
+    }
+    MergeArgs M;
+    M.n_groups = (uint32_t)n_bands;
+    M.m = m;
+    M.P = P;
+    M.pairs = pairs;
+    M.order = W.val_b;
+    M.off = W.bucket;
+    M.member_id = nullptr;
+    M.in_n = nullptr;
+    M.in_cnt = W.cnt_c;
+    M.in_mean = W.mean64_c;
+    M.in_c = W.c64_c;
+    M.out_mean = band->mean;
+    M.out_m2 = band->m2;
+    M.out_c = W.c64_b;
+    M.out_cov = band->cov;
+    M.with_cov = want_cov;
+    hipLaunchKernelGGL(k_chan_merge, dim3(grid_for((int64_t)n_bands * P, 256, 1 << 30)), dim3(256), 0, s, M);
+    LSRVT_LAUNCHED();
+  }
+  return LSRVT_OK;
+}
