@@ -1,0 +1,211 @@
+"""Benchmark of the level-set restricted Voronoi hot path on one MI355X.
+
+One step = the whole hot path over one synthetic volume, with all inputs
+already resident in HBM: isobands -> components -> Lloyd loop (T updates and
+T + 1 restricted geodesic Voronoi passes) -> statistics of every cell merged to
+components and bands.  The initial sites are an input of the Lloyd loop; they
+are drawn once before timing from the (deterministic) components.
+
+Default workload: the 256^3 turbulence-like Fourier field (8 isovalues at
+quantiles, |grad f| saliency weights as uint16, one site per 4096
+weight-scaled voxels, 20 updates, 8 statistics variables with 32-bin
+histograms and the full 8x8 covariance).
+
+value = voxels * T / step time, in Gvoxels/s per Lloyd iteration, with the
+whole step (isobands, components, final pass and statistics included) in the
+denominator.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+VT_BYTES_PER_VOXEL = 5           # one Voronoi pass must read the band (1 B) and write the cell (4 B)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_vt_round_traffic.json")
+CVT_SOURCE = os.path.join(ROOT, "paper_2208_06970_amd", "csrc", "cvt.hip")
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _source_hash():
+    with open(CVT_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _traffic_per_launch():
+    """HBM bytes per launch of the round kernel from committed rocprofv3 counters,
+    or None when they are missing or the kernel source changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256_16") != _source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, seeds, T_sample=2):
+    """The oracle as it stands, single-threaded, on the same volume with
+    T_sample updates (a bounded sample of the step)."""
+    import oracle
+    import numpy as np
+    t0 = time.perf_counter()
+    band = oracle.bands(wl.field, wl.iso)
+    cc = oracle.components(band, wl.n_bands)
+    r = oracle.cvt(cc.comp, seeds, wl.weights, T_sample)
+    S = len(seeds)
+    oracle.stats(r.cell, S, wl.variables, wl.edges, cov=True)
+    comp_unit = np.where(r.cell == oracle.NONE_ID, oracle.NONE_ID, r.site_comp[np.minimum(r.cell, S - 1)])
+    oracle.stats(comp_unit.astype(np.uint32), cc.n_comp, wl.variables, wl.edges, cov=True)
+    band_unit = np.where(r.cell == oracle.NONE_ID, oracle.NONE_ID, band.astype(np.uint32))
+    oracle.stats(band_unit.astype(np.uint32), wl.n_bands, wl.variables, wl.edges, cov=True)
+    dt = time.perf_counter() - t0
+    n = wl.field.size
+    return {"value": n * T_sample / dt / 1e9, "unit": "Gvoxels/s per Lloyd iteration", "cores": 1,
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"same {wl.field.shape[2]}x{wl.field.shape[1]}x{wl.field.shape[0]} volume, full pipeline "
+                      f"(isobands, components, Lloyd loop, three-level statistics) with {T_sample} updates "
+                      f"instead of {wl.iters}; single-threaded C"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--size", type=int, default=256, help="edge of the cubic Fourier volume")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2208_06970_amd as L
+    import synth
+
+    torch.cuda.set_device(0)
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
+        return
+    _log("generating workload")
+    wl = synth.fourier_workload(shape=(args.size,) * 3)
+    n = wl.field.size
+    f = torch.from_numpy(wl.field).cuda()
+    w = torch.from_numpy(wl.weights.view(np.int16)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(wl.variables)).cuda()
+    e = torch.from_numpy(wl.edges).cuda()
+    band, _ = L.lsrvt_isobands(f, wl.iso)
+    cc = L.lsrvt_components(band, wl.n_bands)
+    seeds = synth.workload_sites(wl, cc.comp.cpu().numpy().view(np.uint32), cc.n_comp)
+    sd = torch.from_numpy(seeds.view(np.int32)).cuda()
+    _log(f"volume {wl.field.shape} comps={cc.n_comp} sites={len(seeds)}")
+
+    ev = {k: torch.cuda.Event(enable_timing=True) for k in ("t0", "t1", "t2", "t3", "t4")}
+    phase_ms = {"isobands": 0.0, "components": 0.0, "lloyd": 0.0, "aggregate": 0.0}
+
+    def step(record):
+        if record:
+            ev["t0"].record()
+        b, _ = L.lsrvt_isobands(f, wl.iso)
+        if record:
+            ev["t1"].record()
+        c = L.lsrvt_components(b, wl.n_bands)
+        if record:
+            ev["t2"].record()
+        r = L.lsrvt_cvt(b, c.comp, sd, w, wl.iters, want_mean_ds=False)
+        if record:
+            ev["t3"].record()
+        L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, c.comp_band, c.n_comp, wl.n_bands, x, e, cov=True)
+        if record:
+            ev["t4"].record()
+            torch.cuda.synchronize()
+            phase_ms["isobands"] += ev["t0"].elapsed_time(ev["t1"])
+            phase_ms["components"] += ev["t1"].elapsed_time(ev["t2"])
+            phase_ms["lloyd"] += ev["t2"].elapsed_time(ev["t3"])
+            phase_ms["aggregate"] += ev["t3"].elapsed_time(ev["t4"])
+        return r
+
+    for i in range(args.warmup):
+        step(False)
+        _log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    L.lsrvt_timing_read()                      # discard anything recorded so far
+    L.lsrvt_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(True)
+        _log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.lsrvt_timing_enable(False)
+    vt_ms, vt_launches, vt_passes, vox_per_pass = L.lsrvt_timing_read()
+
+    ms_per_step = dt * 1e3 / args.steps
+    value = n * wl.iters / (ms_per_step / 1e3) / 1e9
+    phases = {k: round(v / args.steps, 4) for k, v in phase_ms.items()}
+    # roofline of the dominant kernel: the Voronoi round kernel, HBM-bound
+    alg_bytes_per_launch = VT_BYTES_PER_VOXEL * vox_per_pass * vt_passes / max(vt_launches, 1)
+    avg_launch_s = vt_ms / 1e3 / max(vt_launches, 1)
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    traffic = _traffic_per_launch()
+    out = {
+        "metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
+        "value": round(value, 4),
+        "unit": "Gvoxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"fourier {args.size}^3, 512 modes k^-5/3, 8 isovalues, |grad| uint16 weights, "
+                               f"1 site / 4096 weighted voxels, T={wl.iters}, 8 vars, 32-bin hist, 8x8 cov",
+                   "voxels": n, "iters": wl.iters, "sites": int(len(seeds)), "components": int(cc.n_comp),
+                   "parallelism": "single GPU"},
+        "phases_ms": phases,
+        "lloyd_gvox_per_iter_s": round(n * wl.iters / (phases["lloyd"] / 1e3) / 1e9, 4) if phases["lloyd"] else None,
+        "stats_gvox_s": round(n / (phases["aggregate"] / 1e3) / 1e9, 4) if phases["aggregate"] else None,
+        "stats_dtype": "f32 compensated per cell, f64 merges",
+        "roofline": {"bound": "hbm", "kernel": "k_vt_round", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": traffic,
+                     "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": vt_launches, "passes": vt_passes,
+                     "alg_bytes_per_launch": round(alg_bytes_per_launch, 1)},
+    }
+    if not args.no_cpu_baseline:
+        _log("timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(wl, seeds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

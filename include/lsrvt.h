@@ -234,6 +234,19 @@ int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t 
                         const lsrvt_cell_stats *cell, const lsrvt_group_stats *comp,
                         const lsrvt_group_stats *band, void *d_work, size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Benchmark instrumentation of the Voronoi round kernel (the dominant kernel
+ * of the Lloyd loop).  While enabled, every launch of that kernel is
+ * bracketed by a hipEvent pair recorded on the stream it is launched on.
+ * lsrvt_timing_read waits for the recorded events and returns, since the
+ * previous read: the summed kernel milliseconds, the number of launches, the
+ * number of Voronoi passes they belong to and the voxels of one pass; then it
+ * resets the totals.  Adds a small per-launch overhead; process-global state,
+ * meant for benchmarks, not for concurrent production use.
+ */
+int32_t lsrvt_timing_enable(int32_t enable);
+int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,7 +34,7 @@ STATS_COV = 2
 EXPORTS = (
     "lsrvt_status_string", "lsrvt_version", "lsrvt_isobands", "lsrvt_components_workspace",
     "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
-    "lsrvt_aggregate_workspace", "lsrvt_aggregate",
+    "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
 
@@ -92,8 +92,11 @@ def _lib():
         lib.lsrvt_aggregate.argtypes = [P, Dims, P, P, u32, P, u32, i32, P, i32, P, i32, u32,
                                         ctypes.POINTER(CellStatsC), ctypes.POINTER(GroupStatsC),
                                         ctypes.POINTER(GroupStatsC), P, S, P]
+        lib.lsrvt_timing_enable.argtypes = [i32]
+        lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
+                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
-                     "lsrvt_aggregate"):
+                     "lsrvt_aggregate", "lsrvt_timing_enable", "lsrvt_timing_read"):
             getattr(lib, name).restype = i32
         _LIB = lib
     return _LIB
@@ -367,3 +370,16 @@ def lsrvt_aggregate(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int
                                ctypes.byref(c_band), wptr, wbytes, _stream(stream))
     _check(code, "lsrvt_aggregate")
     return out
+
+
+def lsrvt_timing_enable(enable: bool = True) -> None:
+    """Bracket every Voronoi round-kernel launch with a hipEvent pair (benchmarks)."""
+    _check(_lib().lsrvt_timing_enable(1 if enable else 0), "lsrvt_timing_enable")
+
+
+def lsrvt_timing_read():
+    """(kernel ms, launches, passes, voxels per pass) since the previous read."""
+    ms, la, pa, vx = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64()
+    _check(_lib().lsrvt_timing_read(ctypes.byref(ms), ctypes.byref(la), ctypes.byref(pa), ctypes.byref(vx)),
+           "lsrvt_timing_read")
+    return ms.value, la.value, pa.value, vx.value

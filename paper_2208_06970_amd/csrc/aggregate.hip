@@ -56,38 +56,82 @@ __device__ __forceinline__ void acc(float &hi, float &lo, float x, float ex) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. counts and bounding boxes
-__global__ __launch_bounds__(kWave) void k_agg_bbox(const uint32_t *__restrict__ cell, Geom g, uint32_t S,
-                                                    unsigned long long *cnt, BBox bb) {
-  const int64_t rows = (int64_t)g.ny * g.nz;
-  const int lane = lane_id();
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-    const uint32_t y = (uint32_t)(row % g.ny), z = (uint32_t)(row / g.ny);
-    const int64_t base = row * g.nx;
-    for (int x0 = 0; x0 < g.nx; x0 += kWave) {
-      int x = x0 + lane;
-      uint32_t c = x < g.nx ? cell[base + x] : kNone;
-      bool pending = c < S;
-      while (true) {
-        uint64_t act = __ballot(pending);
-        if (!act) break;
-        int leader = __ffsll((long long)act) - 1;
-        uint32_t c0 = __shfl(c, leader, kWave);
-        bool mine = pending && c == c0;
-        uint64_t mm = __ballot(mine);
-        if (lane == leader) {
-          int last = 63 - __clzll((long long)mm);
-          atomicAdd(&cnt[c0], (unsigned long long)__popcll(mm));
-          atomicMin(&bb.x0[c0], (uint32_t)(x0 + leader));
-          atomicMax(&bb.x1[c0], (uint32_t)(x0 + last));
-          atomicMin(&bb.y0[c0], y);
-          atomicMax(&bb.y1[c0], y);
-          atomicMin(&bb.z0[c0], z);
-          atomicMax(&bb.z1[c0], z);
+// 1. counts and bounding boxes: one workgroup per 64x8x8 tile, runs of equal
+// cell id along x, an LDS hash table per tile, one set of global atomics per
+// distinct cell in the tile.
+constexpr int TX = 64, TY = 8, TZ = 8;
+constexpr int kTabCap = 512;
+
+
+__global__ __launch_bounds__(256) void k_agg_bbox(const uint32_t *__restrict__ cell, Geom g, uint32_t S,
+                                                  unsigned long long *cnt, BBox bb) {
+  __shared__ uint32_t tkey[kTabCap], tn[kTabCap], tx0[kTabCap], tx1[kTabCap], ty0[kTabCap], ty1[kTabCap],
+      tz0[kTabCap], tz1[kTabCap];
+  const int t = threadIdx.x;
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
+  const int64_t ntiles = (int64_t)ntx * nty * ntz;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int i = t; i < kTabCap; i += 256) {
+      tkey[i] = kNone;
+      tn[i] = 0;
+      tx0[i] = ty0[i] = tz0[i] = 0xFFFFFFFFu;
+      tx1[i] = ty1[i] = tz1[i] = 0;
+    }
+    __syncthreads();
+    const int ttx = (int)(tile % ntx), tty = (int)((tile / ntx) % nty), ttz = (int)(tile / ((int64_t)ntx * nty));
+    const int qx = (t & 3) * 16, ly = (t >> 2) & 7, lz = t >> 5;
+    const int x0 = ttx * TX + qx;
+    const uint32_t y = (uint32_t)(tty * TY + ly), z = (uint32_t)(ttz * TZ + lz);
+    if ((int)y < g.ny && (int)z < g.nz && x0 < g.nx) {
+      const int64_t base = (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      const int xe = x0 + 16 < g.nx ? x0 + 16 : g.nx;
+      uint32_t rc = kNone, rs = 0;
+      auto flush = [&](uint32_t xend) {
+        if (rc < S) {
+          int sl = lds_slot<kTabCap>(tkey, rc);
+          if (sl >= 0) {
+            atomicAdd(&tn[sl], xend - rs);
+            atomicMin(&tx0[sl], rs);
+            atomicMax(&tx1[sl], xend - 1);
+            atomicMin(&ty0[sl], y);
+            atomicMax(&ty1[sl], y);
+            atomicMin(&tz0[sl], z);
+            atomicMax(&tz1[sl], z);
+          } else {
+            atomicAdd(&cnt[rc], (unsigned long long)(xend - rs));
+            atomicMin(&bb.x0[rc], rs);
+            atomicMax(&bb.x1[rc], xend - 1);
+            atomicMin(&bb.y0[rc], y);
+            atomicMax(&bb.y1[rc], y);
+            atomicMin(&bb.z0[rc], z);
+            atomicMax(&bb.z1[rc], z);
+          }
         }
-        pending = pending && !mine;
+      };
+      for (int x = x0; x < xe; ++x) {
+        uint32_t c = cell[base + x];
+        if (c != rc) {
+          flush((uint32_t)x);
+          rc = c;
+          rs = (uint32_t)x;
+        }
+      }
+      flush((uint32_t)xe);
+    }
+    __syncthreads();
+    for (int i = t; i < kTabCap; i += 256) {
+      uint32_t c = tkey[i];
+      if (c != kNone) {
+        atomicAdd(&cnt[c], (unsigned long long)tn[i]);
+        atomicMin(&bb.x0[c], tx0[i]);
+        atomicMax(&bb.x1[c], tx1[i]);
+        atomicMin(&bb.y0[c], ty0[i]);
+        atomicMax(&bb.y1[c], ty1[i]);
+        atomicMin(&bb.z0[c], tz0[i]);
+        atomicMax(&bb.z1[c], tz1[i]);
       }
     }
+    __syncthreads();
   }
 }
 
@@ -110,6 +154,12 @@ __global__ void k_agg_items(const unsigned long long *__restrict__ cnt, BBox bb,
   rows_per_item[s] = (uint32_t)rpi;
 }
 
+__global__ void k_item_cells(const uint32_t *__restrict__ item_off, uint32_t S, uint32_t *item_cell) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  for (uint32_t i = item_off[s]; i < item_off[s + 1]; ++i) item_cell[i] = s;
+}
+
 // 3. per-item compensated sums
 struct CellArgs {
   const uint32_t *cell;
@@ -122,6 +172,7 @@ struct CellArgs {
   Pairs pairs;
   BBox bb;
   const uint32_t *item_off;  // [S + 1]
+  const uint32_t *item_cell; // [n_items]
   const uint32_t *rows_per_item;
   uint32_t n_items;
   float *part_hi, *part_lo;  // [n_items][U]
@@ -143,24 +194,18 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
   float *K = reinterpret_cast<float *>(kmax_l + m);                         // [m]
   float *ph = K + m;                                                        // [G*U]
   float *pl = ph + G * U;                                                   // [G*U]
+  float *edg = pl + G * U;                                                  // [m][B+1]
   __shared__ uint32_t wcnt[4];
   __shared__ uint32_t s_ntile;
   const int t = threadIdx.x;
   const int wid = t / kWave;
   const int grp = R == 1 ? t / U : 0;
   const Geom g = A.g;
+  if (B > 0)
+    for (int i = t; i < m * (B + 1); i += kAggThreads) edg[i] = A.edges[i];
 
   for (uint32_t item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-    // the cell of this item: last s with item_off[s] <= item
-    uint32_t lo_s = 0, hi_s = A.S;
-    while (hi_s - lo_s > 1) {
-      uint32_t mid = (lo_s + hi_s) >> 1;
-      if (A.item_off[mid] <= item)
-        lo_s = mid;
-      else
-        hi_s = mid;
-    }
-    const uint32_t s = lo_s;
+    const uint32_t s = A.item_cell[item];
     const uint32_t part = item - A.item_off[s];
     const int64_t x0 = A.bb.x0[s], y0 = A.bb.y0[s], z0 = A.bb.z0[s];
     const int64_t lx = (int64_t)A.bb.x1[s] - x0 + 1, ly = (int64_t)A.bb.y1[s] - y0 + 1;
@@ -181,16 +226,31 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
     for (int r = 0; r < R; ++r) hi[r] = lo[r] = 0.0f;
     __syncthreads();
 
-    for (int64_t base = 0; base < span; base += kAggThreads) {
-      const int64_t idx = base + t;
+    // walk the item's box rows in tiles of 256 voxels: short rows pack several
+    // rows per tile (lane -> fixed row offset and column), long rows take
+    // several tiles each; all index arithmetic is per tile, in 32 bits
+    const bool packed = lx <= kAggThreads;
+    const int rpt = packed ? kAggThreads / (int)lx : 1;                      // rows per tile
+    const int cpr = packed ? 1 : (int)((lx + kAggThreads - 1) / kAggThreads);  // tiles per row
+    const int dr = packed ? t / (int)lx : 0, dx = packed ? t % (int)lx : t;
+    const int64_t ntiles_item = packed ? (r1 - r0 + rpt - 1) / rpt : (r1 - r0) * cpr;
+    for (int64_t ti = 0; ti < ntiles_item; ++ti) {
+      int64_t r;
+      int xo;
+      if (packed) {
+        r = r0 + ti * rpt + dr;
+        xo = dx;
+      } else {
+        r = r0 + ti / cpr;
+        xo = (int)(ti % cpr) * kAggThreads + dx;
+      }
       bool match = false;
       int64_t v = 0;
-      if (idx < span) {
-        int64_t r = r0 + idx / lx;
-        int64_t x = x0 + idx % lx;
-        int64_t y = y0 + r % ly;
-        int64_t z = z0 + r / ly;
-        v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      if (dr < rpt && r < r1 && xo < lx) {
+        const uint32_t ru = (uint32_t)r;
+        const int64_t y = y0 + ru % (uint32_t)ly;
+        const int64_t z = z0 + ru / (uint32_t)ly;
+        v = (x0 + xo) + (int64_t)g.nx * (y + (int64_t)g.ny * z);
         match = A.cell[v] == s;
       }
       uint64_t bal = __ballot(match);
@@ -207,10 +267,17 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
           atomicMin(&kmin_l[j], kk);
           atomicMax(&kmax_l[j], kk);
           if (B > 0) {
-            const float *e = A.edges + (int64_t)j * (B + 1);
-            int bin = 0;
-            for (int q = 1; q < B; ++q) bin += (e[q] <= xv) ? 1 : 0;
-            atomicAdd(&hist_l[j * B + bin], 1u);
+            // bin = #{interior edges e_1..e_{B-1} <= x}: upper bound by bisection
+            const float *e = edg + j * (B + 1);
+            int lo = 1, hi = B;
+            while (lo < hi) {
+              int mid = (lo + hi) >> 1;
+              if (e[mid] <= xv)
+                lo = mid + 1;
+              else
+                hi = mid;
+            }
+            atomicAdd(&hist_l[j * B + (lo - 1)], 1u);
           }
         }
       }
@@ -295,6 +362,13 @@ struct FinArgs {
   int with_cov;
   double *mean64;  // [S][m]
   double *c64;     // [S][P]
+  // exact merges into the components
+  int B;
+  const uint32_t *hist;           // cell histograms [S][m][B] or null
+  const uint32_t *site_comp;
+  uint32_t n_comp;
+  unsigned long long *cnt_c;
+  uint32_t *kmin_c, *kmax_c, *hist_c;
 };
 
 __global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
@@ -319,6 +393,19 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
     if (t < m) K[t] = n ? A.vars[(int64_t)t * A.n + A.sites[s]] : 0.0f;
     __syncthreads();
     if (t == 0) A.out_n[s] = n;
+    const uint32_t c = A.site_comp[s];
+    if (n && c < A.n_comp) {
+      if (t == 0) atomicAdd(&A.cnt_c[c], (unsigned long long)n);
+      for (int j = t; j < m; j += kAggThreads) {
+        atomicMin(&A.kmin_c[(int64_t)c * m + j], A.kmin[(int64_t)s * m + j]);
+        atomicMax(&A.kmax_c[(int64_t)c * m + j], A.kmax[(int64_t)s * m + j]);
+      }
+      if (A.hist)
+        for (int i = t; i < m * A.B; i += kAggThreads) {
+          uint32_t h = A.hist[(int64_t)s * m * A.B + i];
+          if (h) atomicAdd(&A.hist_c[(int64_t)c * m * A.B + i], h);
+        }
+    }
     const float fn = (float)n;
     const double dn = (double)n;
     for (int j = t; j < m; j += kAggThreads) {
@@ -356,49 +443,63 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
   }
 }
 
-// 5a. exact merges of counts, extrema and histograms to the two upper levels
-struct ExactArgs {
-  uint32_t S;
-  int m, B;
-  const uint32_t *site_comp;
-  const uint8_t *comp_band;
+// 5a. exact band statistics from the components: one workgroup per run of 256
+// components in band order; each lane owns columns (count, minima, maxima,
+// histogram bins) and flushes one atomic per column whenever the band changes.
+struct BandIntArgs {
   uint32_t n_comp;
-  const unsigned long long *cnt;
-  const uint32_t *kmin, *kmax;    // cell keys [S][m]
-  const uint32_t *hist;           // cell hist [S][m][B] or null
-  unsigned long long *cnt_c, *cnt_b;
-  uint32_t *kmin_c, *kmax_c, *kmin_b, *kmax_b;
-  uint32_t *hist_c, *hist_b;
+  int m, B;
+  const uint32_t *order;  // components sorted by band
+  const uint8_t *comp_band;
+  const unsigned long long *cnt_c;
+  const uint32_t *kmin_c, *kmax_c, *hist_c;
+  unsigned long long *cnt_b;
+  uint32_t *kmin_b, *kmax_b, *hist_b;
 };
 
-__global__ void k_agg_exact(ExactArgs A) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t per = (int64_t)A.m * (A.B > 0 ? A.B : 1);
-  if (i >= (int64_t)A.S * per) return;
-  const uint32_t s = (uint32_t)(i / per);
-  const int64_t r = i % per;
-  const uint32_t c = A.site_comp[s];
-  if (c >= A.n_comp || A.cnt[s] == 0) return;
-  const uint32_t b = A.comp_band[c];
-  if (r == 0) {
-    atomicAdd(&A.cnt_c[c], A.cnt[s]);
-    atomicAdd(&A.cnt_b[b], A.cnt[s]);
-  }
-  const int B = A.B > 0 ? A.B : 1;
-  const int j = (int)(r / B), bin = (int)(r % B);
-  if (bin == 0) {
-    uint32_t kn = A.kmin[(int64_t)s * A.m + j], kx = A.kmax[(int64_t)s * A.m + j];
-    atomicMin(&A.kmin_c[(int64_t)c * A.m + j], kn);
-    atomicMax(&A.kmax_c[(int64_t)c * A.m + j], kx);
-    atomicMin(&A.kmin_b[(int64_t)b * A.m + j], kn);
-    atomicMax(&A.kmax_b[(int64_t)b * A.m + j], kx);
-  }
-  if (A.hist && A.B > 0) {
-    uint32_t h = A.hist[((int64_t)s * A.m + j) * A.B + bin];
-    if (h) {
-      atomicAdd(&A.hist_c[((int64_t)c * A.m + j) * A.B + bin], h);
-      atomicAdd(&A.hist_b[((int64_t)b * A.m + j) * A.B + bin], h);
+__global__ __launch_bounds__(256) void k_band_int(BandIntArgs A) {
+  const int m = A.m, B = A.B;
+  const int64_t cols = 1 + 2 * (int64_t)m + (int64_t)m * B;
+  const uint32_t q0 = blockIdx.x * 256u;
+  const uint32_t q1 = q0 + 256u < A.n_comp ? q0 + 256u : A.n_comp;
+  for (int64_t col = threadIdx.x; col < cols; col += 256) {
+    const int kind = col == 0 ? 0 : col <= m ? 1 : col <= 2 * m ? 2 : 3;
+    const int64_t sub = kind == 1 ? col - 1 : kind == 2 ? col - 1 - m : col - 1 - 2 * m;
+    uint64_t acc = kind == 1 ? 0xFFFFFFFFull : 0ull;
+    int band = -1;
+    auto flush = [&]() {
+      if (band < 0) return;
+      if (kind == 0) {
+        if (acc) atomicAdd(&A.cnt_b[band], (unsigned long long)acc);
+      } else if (kind == 1) {
+        if (acc != 0xFFFFFFFFull) atomicMin(&A.kmin_b[(int64_t)band * m + sub], (uint32_t)acc);
+      } else if (kind == 2) {
+        if (acc) atomicMax(&A.kmax_b[(int64_t)band * m + sub], (uint32_t)acc);
+      } else {
+        if (acc) atomicAdd(&A.hist_b[(int64_t)band * m * B + sub], (uint32_t)acc);
+      }
+    };
+    for (uint32_t q = q0; q < q1; ++q) {
+      const uint32_t c = A.order[q];
+      const int bc = A.comp_band[c];
+      if (bc != band) {
+        flush();
+        band = bc;
+        acc = kind == 1 ? 0xFFFFFFFFull : 0ull;
+      }
+      if (kind == 0) {
+        acc += A.cnt_c[c];
+      } else if (kind == 1) {
+        uint32_t v = A.kmin_c[(int64_t)c * m + sub];
+        if (v < acc) acc = v;
+      } else if (kind == 2) {
+        uint32_t v = A.kmax_c[(int64_t)c * m + sub];
+        if (v > acc) acc = v;
+      } else {
+        acc += A.hist_c[(int64_t)c * m * B + sub];
+      }
     }
+    flush();
   }
 }
 
@@ -413,59 +514,119 @@ __global__ void k_decode_minmax(const uint32_t *kmin, const uint32_t *kmax, cons
   if (i % m == 0) out_n[u] = cnt[u];
 }
 
-// 5b. Chan pairwise merge in float64, one thread per (group, pair unit):
-// members of group g are order[off[g] .. off[g+1]) in that order.
+// 5b. Chan pairwise merge in float64.  Members of group g are
+// order[off[g] .. off[g+1]) in that order.  Groups of at most kSmallGroup
+// members: one thread per (group, pair unit) merges them one after another.
+// Larger groups: one workgroup per (group, pair unit); lane t merges its
+// contiguous share of the members in order, then the 256 lane states merge
+// pairwise in a fixed tree (t with t + 128, ..., t with t + 1).
+constexpr uint32_t kSmallGroup = 32;
+
 struct MergeArgs {
   uint32_t n_groups;
   int m, P;
   Pairs pairs;
   const uint32_t *order;
   const uint32_t *off;
-  const uint32_t *member_id;       // maps a sorted position to the member index (order)
-  const double *in_n;              // member counts as double, or null (then in_cnt)
   const unsigned long long *in_cnt;
   const double *in_mean;           // [members][m]
   const double *in_c;              // [members][P]
   double *out_mean;                // [groups][m]
   double *out_m2;                  // [groups][m]
   double *out_c;                   // [groups][P] (internal, always)
-  double *out_cov;                 // [groups][m(m+1)/2] or null (user output)
+  double *out_cov;                 // [groups][P] user output, or null
   int with_cov;
+  const uint32_t *big;             // groups larger than kSmallGroup
+  const uint32_t *big_cnt;
 };
 
-__global__ void k_chan_merge(MergeArgs A) {
+struct ChanState {
+  double n, mj, mk, c;
+};
+
+__device__ __forceinline__ void chan_add(ChanState &a, double ni, double aj, double ak, double ci) {
+  if (ni == 0.0) return;
+  if (a.n == 0.0) {
+    a = ChanState{ni, aj, ak, ci};
+    return;
+  }
+  const double nn = a.n + ni;
+  const double dj = aj - a.mj, dk = ak - a.mk;
+  a.c = a.c + ci + dj * dk * (a.n * ni / nn);
+  a.mj = a.mj + dj * (ni / nn);
+  a.mk = a.mk + dk * (ni / nn);
+  a.n = nn;
+}
+
+__device__ __forceinline__ void chan_write(const MergeArgs &A, uint32_t gidx, int p, const ChanState &st) {
+  const int j = A.pairs.j[p], k = A.pairs.k[p];
+  A.out_c[(int64_t)gidx * A.P + p] = st.c;
+  if (j == k) {
+    A.out_mean[(int64_t)gidx * A.m + j] = st.mj;
+    A.out_m2[(int64_t)gidx * A.m + j] = st.c;
+  }
+  if (A.with_cov) A.out_cov[(int64_t)gidx * A.P + p] = st.c;
+}
+
+__global__ void k_chan_small(MergeArgs A) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)A.n_groups * A.P) return;
   const uint32_t gidx = (uint32_t)(i / A.P);
   const int p = (int)(i % A.P);
+  const uint32_t q0 = A.off[gidx], q1 = A.off[gidx + 1];
+  if (q1 - q0 > kSmallGroup) return;
   const int j = A.pairs.j[p], k = A.pairs.k[p];
-  double n = 0.0, mj = 0.0, mk = 0.0, c = 0.0;
-  for (uint32_t q = A.off[gidx]; q < A.off[gidx + 1]; ++q) {
+  ChanState st{0.0, 0.0, 0.0, 0.0};
+  for (uint32_t q = q0; q < q1; ++q) {
     const uint32_t mem = A.order[q];
-    const double ni = (double)A.in_cnt[mem];
-    if (ni == 0.0) continue;
-    const double aj = A.in_mean[(int64_t)mem * A.m + j], ak = A.in_mean[(int64_t)mem * A.m + k];
-    const double ci = A.in_c[(int64_t)mem * A.P + p];
-    if (n == 0.0) {
-      n = ni;
-      mj = aj;
-      mk = ak;
-      c = ci;
-      continue;
+    chan_add(st, (double)A.in_cnt[mem], A.in_mean[(int64_t)mem * A.m + j], A.in_mean[(int64_t)mem * A.m + k],
+             A.in_c[(int64_t)mem * A.P + p]);
+  }
+  chan_write(A, gidx, p, st);
+}
+
+__global__ void k_chan_list_big(const uint32_t *off, uint32_t n_groups, uint32_t *big, uint32_t *big_cnt) {
+  uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n_groups && off[g + 1] - off[g] > kSmallGroup) big[atomicAdd(big_cnt, 1u)] = g;
+}
+
+__global__ __launch_bounds__(256) void k_chan_big(MergeArgs A) {
+  __shared__ double sn[256], sj[256], sk[256], sc[256];
+  const int t = threadIdx.x;
+  const int64_t work = (int64_t)(*A.big_cnt) * A.P;
+  for (int64_t w = blockIdx.x; w < work; w += gridDim.x) {
+    const uint32_t gidx = A.big[w / A.P];
+    const int p = (int)(w % A.P);
+    const int j = A.pairs.j[p], k = A.pairs.k[p];
+    const uint32_t q0 = A.off[gidx], q1 = A.off[gidx + 1];
+    const uint32_t len = q1 - q0, share = (len + 255) / 256;
+    const uint32_t a0 = q0 + t * share;
+    const uint32_t a1 = a0 + share < q1 ? a0 + share : q1;
+    ChanState st{0.0, 0.0, 0.0, 0.0};
+    for (uint32_t q = a0; q < a1; ++q) {
+      const uint32_t mem = A.order[q];
+      chan_add(st, (double)A.in_cnt[mem], A.in_mean[(int64_t)mem * A.m + j], A.in_mean[(int64_t)mem * A.m + k],
+               A.in_c[(int64_t)mem * A.P + p]);
     }
-    const double nn = n + ni;
-    const double dj = aj - mj, dk = ak - mk;
-    c = c + ci + dj * dk * (n * ni / nn);
-    mj = mj + dj * (ni / nn);
-    mk = mk + dk * (ni / nn);
-    n = nn;
+    sn[t] = st.n;
+    sj[t] = st.mj;
+    sk[t] = st.mk;
+    sc[t] = st.c;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (t < o) {
+        ChanState a{sn[t], sj[t], sk[t], sc[t]};
+        chan_add(a, sn[t + o], sj[t + o], sk[t + o], sc[t + o]);
+        sn[t] = a.n;
+        sj[t] = a.mj;
+        sk[t] = a.mk;
+        sc[t] = a.c;
+      }
+      __syncthreads();
+    }
+    if (t == 0) chan_write(A, gidx, p, ChanState{sn[0], sj[0], sk[0], sc[0]});
+    __syncthreads();
   }
-  A.out_c[(int64_t)gidx * A.P + p] = c;
-  if (j == k) {
-    A.out_mean[(int64_t)gidx * A.m + j] = mj;
-    A.out_m2[(int64_t)gidx * A.m + j] = c;
-  }
-  if (A.with_cov) A.out_cov[(int64_t)gidx * A.P + p] = c;
 }
 
 // helpers for sorting sites by component
@@ -504,8 +665,9 @@ struct AggWork {
   float *part_hi, *part_lo;
   uint32_t *kmin, *kmax, *kmin_c, *kmax_c, *kmin_b, *kmax_b;
   double *mean64, *c64, *mean64_c, *c64_c, *m2tmp_c, *mean64_b, *c64_b, *m2tmp_b;
-  uint32_t *key_a, *val_a, *key_b, *val_b, *pos, *ccount, *coff, *corder, *bucket;
+  uint32_t *key_a, *val_a, *key_b, *val_b, *key_c, *val_c, *pos, *ccount, *coff, *corder, *bucket;
   uint8_t *digit;
+  uint32_t *item_cell, *big, *big_cnt;
   void *scratch;
   size_t scratch_bytes;
   int64_t item_cap;
@@ -545,12 +707,17 @@ void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_band
   auto va = a.template take<uint32_t>(sortn);
   auto kb = a.template take<uint32_t>(sortn);
   auto vb = a.template take<uint32_t>(sortn);
+  auto kc = a.template take<uint32_t>(sortn);
+  auto vc = a.template take<uint32_t>(sortn);
   auto pos = a.template take<uint32_t>(sortn);
   auto ccount = a.template take<uint32_t>(c1 + 1);
   auto coff = a.template take<uint32_t>(c1 + 2);
   auto corder = a.template take<uint32_t>(c1);
   auto bucket = a.template take<uint32_t>(257);
   auto digit = a.template take<uint8_t>(sortn);
+  auto icell = a.template take<uint32_t>(ic);
+  auto big = a.template take<uint32_t>(c1 > b1 ? c1 : b1);
+  auto bigc = a.template take<uint32_t>(4);
   if (W) {
     W->cnt = cnt;
     W->cnt_c = cnt_c;
@@ -579,12 +746,17 @@ void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_band
     W->val_a = va;
     W->key_b = kb;
     W->val_b = vb;
+    W->key_c = kc;
+    W->val_c = vc;
     W->pos = pos;
     W->ccount = ccount;
     W->coff = coff;
     W->corder = corder;
     W->bucket = bucket;
     W->digit = digit;
+    W->item_cell = icell;
+    W->big = big;
+    W->big_cnt = bigc;
     W->item_cap = ic;
   }
 }
@@ -700,10 +872,10 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
           W.bbox + 4 * (size_t)(S ? S : 1), W.bbox + 5 * (size_t)(S ? S : 1)};
 
   // 1-2. counts, boxes, items
-  const int64_t rows = (int64_t)g.ny * g.nz;
   uint32_t n_items = 0;
   if (S) {
-    hipLaunchKernelGGL(k_agg_bbox, dim3((unsigned)(rows < 262144 ? rows : 262144)), dim3(kWave), 0, s, d_cell, g, S,
+    const int64_t ntiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+    hipLaunchKernelGGL(k_agg_bbox, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(256), 0, s, d_cell, g, S,
                        W.cnt, bb);
     LSRVT_LAUNCHED();
     int64_t target = kItemVoxels;
@@ -720,6 +892,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
 
   // 3. per-item sums
   if (n_items) {
+    hipLaunchKernelGGL(k_item_cells, dim3((S + 255) / 256), dim3(256), 0, s, W.item_off, S, W.item_cell);
     CellArgs A;
     A.cell = d_cell;
     A.g = g;
@@ -734,6 +907,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     A.pairs = pairs;
     A.bb = bb;
     A.item_off = W.item_off;
+    A.item_cell = W.item_cell;
     A.rows_per_item = W.rpi;
     A.n_items = n_items;
     A.part_hi = W.part_hi;
@@ -743,9 +917,10 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     A.kmax = W.kmax;
     const int R = (U + kAggThreads - 1) / kAggThreads;
     A.G = R == 1 ? kAggThreads / U : 1;
-    size_t lds = sizeof(float) * ((size_t)m * kAggThreads + (size_t)m * B + 3 * m + 2 * (size_t)A.G * U);
+    size_t lds = sizeof(float) * ((size_t)m * kAggThreads + (size_t)m * B + 3 * m + 2 * (size_t)A.G * U +
+                                  (size_t)m * (B + 1));
     if (lds > 65536 || R > 3) return LSRVT_EINVAL;
-    unsigned grid = n_items < 8192 ? n_items : 8192;
+    unsigned grid = n_items < 16384 ? n_items : 16384;
     if (R == 1)
       hipLaunchKernelGGL(k_agg_cell<1>, dim3(grid), dim3(kAggThreads), lds, s, A);
     else if (R == 2)
@@ -755,7 +930,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     LSRVT_LAUNCHED();
   }
 
-  // 4. per-cell finalize
+  // 4. per-cell finalize, plus exact merges of counts, extrema and histograms into components
   if (S) {
     FinArgs F;
     F.S = S;
@@ -781,44 +956,65 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     F.with_cov = want_cov;
     F.mean64 = W.mean64;
     F.c64 = W.c64;
+    F.B = B;
+    F.hist = want_hist ? cs.hist : nullptr;
+    F.site_comp = d_site_comp;
+    F.n_comp = C;
+    F.cnt_c = W.cnt_c;
+    F.kmin_c = W.kmin_c;
+    F.kmax_c = W.kmax_c;
+    F.hist_c = want_hist ? comp->hist : nullptr;
     size_t lds = sizeof(float) * (2 * (size_t)U + m);
     hipLaunchKernelGGL(k_agg_finalize, dim3(S < 16384 ? S : 16384), dim3(kAggThreads), lds, s, F);
     LSRVT_LAUNCHED();
   }
 
-  // 5a. exact merges
-  if (S) {
-    ExactArgs E;
-    E.S = S;
-    E.m = m;
-    E.B = B;
-    E.site_comp = d_site_comp;
-    E.comp_band = d_comp_band;
-    E.n_comp = C;
-    E.cnt = W.cnt;
-    E.kmin = W.kmin;
-    E.kmax = W.kmax;
-    E.hist = want_hist ? cs.hist : nullptr;
-    E.cnt_c = W.cnt_c;
-    E.cnt_b = W.cnt_b;
-    E.kmin_c = W.kmin_c;
-    E.kmax_c = W.kmax_c;
-    E.kmin_b = W.kmin_b;
-    E.kmax_b = W.kmax_b;
-    E.hist_c = want_hist ? comp->hist : nullptr;
-    E.hist_b = want_hist ? band->hist : nullptr;
-    int64_t total = (int64_t)S * m * (B > 0 ? B : 1);
-    hipLaunchKernelGGL(k_agg_exact, dim3(grid_for(total, 256, 1 << 30)), dim3(256), 0, s, E);
-    LSRVT_LAUNCHED();
-  }
+  // 5a. components sorted by band (stable in id); exact band statistics
   if (C) {
+    hipLaunchKernelGGL(k_iota, dim3((C + 255) / 256), dim3(256), 0, s, W.corder, C);
+    LSRVT_LAUNCHED();
+    if ((rc = StableSort8::run(d_comp_band, C, W.pos, W.bucket, W.scratch, W.scratch_bytes, s))) return rc;
+    hipLaunchKernelGGL(k_permute, dim3((C + 255) / 256), dim3(256), 0, s, W.corder, W.corder, W.pos, C, W.key_b,
+                       W.val_b);
+    LSRVT_LAUNCHED();
+    BandIntArgs BI;
+    BI.n_comp = C;
+    BI.m = m;
+    BI.B = B;
+    BI.order = W.val_b;
+    BI.comp_band = d_comp_band;
+    BI.cnt_c = W.cnt_c;
+    BI.kmin_c = W.kmin_c;
+    BI.kmax_c = W.kmax_c;
+    BI.hist_c = want_hist ? comp->hist : nullptr;
+    BI.cnt_b = W.cnt_b;
+    BI.kmin_b = W.kmin_b;
+    BI.kmax_b = W.kmax_b;
+    BI.hist_b = want_hist ? band->hist : nullptr;
+    hipLaunchKernelGGL(k_band_int, dim3((C + 255) / 256), dim3(256), 0, s, BI);
+    LSRVT_LAUNCHED();
     hipLaunchKernelGGL(k_decode_minmax, dim3(grid_for((int64_t)C * m, 256, 1 << 30)), dim3(256), 0, s, W.kmin_c,
                        W.kmax_c, W.cnt_c, (int64_t)C, m, comp->vmin, comp->vmax, comp->n);
     LSRVT_LAUNCHED();
+  } else {
+    if ((rc = fill<uint32_t>(W.bucket, 257, 0u, s))) return rc;
   }
   hipLaunchKernelGGL(k_decode_minmax, dim3(grid_for((int64_t)n_bands * m, 256, 1 << 30)), dim3(256), 0, s, W.kmin_b,
                      W.kmax_b, W.cnt_b, (int64_t)n_bands, m, band->vmin, band->vmax, band->n);
   LSRVT_LAUNCHED();
+
+  auto run_merge = [&](MergeArgs &M) -> int32_t {
+    int32_t r;
+    if ((r = fill<uint32_t>(W.big_cnt, 1, 0u, s))) return r;
+    M.big = W.big;
+    M.big_cnt = W.big_cnt;
+    hipLaunchKernelGGL(k_chan_small, dim3(grid_for((int64_t)M.n_groups * M.P, 256, 1 << 30)), dim3(256), 0, s, M);
+    hipLaunchKernelGGL(k_chan_list_big, dim3((M.n_groups + 255) / 256), dim3(256), 0, s, M.off, M.n_groups, W.big,
+                       W.big_cnt);
+    hipLaunchKernelGGL(k_chan_big, dim3(1024), dim3(256), 0, s, M);
+    LSRVT_LAUNCHED();
+    return LSRVT_OK;
+  };
 
   // 5b. sites sorted by component (stable in site id), then the cell -> component merge
   if (C) {
@@ -834,14 +1030,16 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
         hipLaunchKernelGGL(k_digit, dim3((S + 255) / 256), dim3(256), 0, s, ka, S, 8 * p, W.digit);
         LSRVT_LAUNCHED();
         if ((rc = StableSort8::run(W.digit, S, W.pos, nullptr, W.scratch, W.scratch_bytes, s))) return rc;
-        hipLaunchKernelGGL(k_permute, dim3((S + 255) / 256), dim3(256), 0, s, ka, va, W.pos, S, kb, vb);
+        // ping-pong between (key_a, val_a) and (key_c, val_c): key_b/val_b hold the band order
+        uint32_t *ko = (ka == W.key_a) ? W.key_c : W.key_a;
+        uint32_t *vo = (va == W.val_a) ? W.val_c : W.val_a;
+        hipLaunchKernelGGL(k_permute, dim3((S + 255) / 256), dim3(256), 0, s, ka, va, W.pos, S, ko, vo);
         LSRVT_LAUNCHED();
-        uint32_t *t1 = ka, *t2 = va;
-        ka = kb;
-        va = vb;
-        kb = t1;
-        vb = t2;
+        ka = ko;
+        va = vo;
       }
+      (void)kb;
+      (void)vb;
       if ((rc = ScanU32::run(W.ccount, C + 1, W.coff, W.scratch, W.scratch_bytes, s))) return rc;
       MergeArgs M;
       M.n_groups = C;
@@ -850,8 +1048,6 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
       M.pairs = pairs;
       M.order = va;
       M.off = W.coff;
-      M.member_id = nullptr;
-      M.in_n = nullptr;
       M.in_cnt = W.cnt;
       M.in_mean = W.mean64;
       M.in_c = W.c64;
@@ -860,8 +1056,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
       M.out_c = W.c64_c;
       M.out_cov = comp->cov;
       M.with_cov = want_cov;
-      hipLaunchKernelGGL(k_chan_merge, dim3(grid_for((int64_t)C * P, 256, 1 << 30)), dim3(256), 0, s, M);
-      LSRVT_LAUNCHED();
+      if ((rc = run_merge(M))) return rc;
       // keep float64 component means for the band merge
       LSRVT_HIP(hipMemcpyAsync(W.mean64_c, comp->mean, sizeof(double) * (size_t)C * m, hipMemcpyDeviceToDevice, s));
     } else {
@@ -875,16 +1070,6 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
 
   // 5c. component -> band merge, components of a band in id order
   {
-    if (C) {
-      hipLaunchKernelGGL(k_iota, dim3((C + 255) / 256), dim3(256), 0, s, W.corder, C);
-      LSRVT_LAUNCHED();
-      if ((rc = StableSort8::run(d_comp_band, C, W.pos, W.bucket, W.scratch, W.scratch_bytes, s))) return rc;
-      hipLaunchKernelGGL(k_permute, dim3((C + 255) / 256), dim3(256), 0, s, W.corder, W.corder, W.pos, C, W.key_b,
-                         W.val_b);
-      LSRVT_LAUNCHED();
-    } else {
-      if ((rc = fill<uint32_t>(W.bucket, 257, 0u, s))) return rc;
-    }
     MergeArgs M;
     M.n_groups = (uint32_t)n_bands;
     M.m = m;
@@ -892,8 +1077,6 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     M.pairs = pairs;
     M.order = W.val_b;
     M.off = W.bucket;
-    M.member_id = nullptr;
-    M.in_n = nullptr;
     M.in_cnt = W.cnt_c;
     M.in_mean = W.mean64_c;
     M.in_c = W.c64_c;
@@ -902,8 +1085,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     M.out_c = W.c64_b;
     M.out_cov = band->cov;
     M.with_cov = want_cov;
-    hipLaunchKernelGGL(k_chan_merge, dim3(grid_for((int64_t)n_bands * P, 256, 1 << 30)), dim3(256), 0, s, M);
-    LSRVT_LAUNCHED();
+    if ((rc = run_merge(M))) return rc;
   }
   return LSRVT_OK;
 }

@@ -128,6 +128,23 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
+// Slot of key c in an open-addressing LDS table of Cap keys (kNone = empty),
+// inserting it if absent; -1 when the table is full.
+template <int Cap>
+__device__ __forceinline__ int lds_slot(uint32_t *keys, uint32_t c) {
+  uint32_t h = (c * 2654435761u) & (Cap - 1);
+  for (int probe = 0; probe < Cap; ++probe) {
+    uint32_t k = __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (k == c) return (int)h;
+    if (k == kNone) {
+      uint32_t old = atomicCAS(&keys[h], kNone, c);
+      if (old == kNone || old == c) return (int)h;
+    }
+    h = (h + 1) & (Cap - 1);
+  }
+  return -1;
+}
+
 // Fill kernel used instead of hipMemsetAsync (graph-capture safe).
 template <class T>
 __global__ void k_fill(T *p, int64_t n, T v) {

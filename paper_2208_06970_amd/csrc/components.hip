@@ -12,7 +12,8 @@
 //  3. roots (label[v] == v) are compacted in linear order, then stably sorted
 //     by band: the position is the canonical component id;
 //  4. every voxel finds its root and takes the root's id; component sizes
-//     are summed with wave-aggregated atomics.
+//     are summed per tile in an LDS hash table, then one atomic per distinct
+//     component and tile.
 #include "common.h"
 
 namespace lsrvt {
@@ -234,38 +235,72 @@ __global__ void k_cc_tables(const uint32_t *__restrict__ roots, const uint8_t *_
   }
 }
 
-__global__ __launch_bounds__(256) void k_cc_relabel(const uint32_t *__restrict__ label, int64_t n, uint32_t *comp,
+// Relabel: one workgroup per 64x8x8 tile, each thread walks 16 consecutive
+// voxels of a row; the root of a label is cached across a run of equal labels;
+// component sizes accumulate per run in an LDS hash table and are flushed with
+// one atomic per distinct component in the tile.
+constexpr int RX = 64, RY = 8, RZ = 8;
+constexpr int kRelCap = 512;
+
+__global__ __launch_bounds__(256) void k_cc_relabel(const uint32_t *__restrict__ label, Geom g, uint32_t *comp,
                                                     uint64_t *comp_size, int count_sizes) {
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t nround = (n + stride - 1) / stride;
-  for (int64_t k = 0; k < nround; ++k) {
-    int64_t v = k * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool valid = v < n;
-    uint32_t cid = kNone;
-    if (valid) {
-      uint32_t r = label[v];
-      uint32_t q = label[r];
-      while (q != r) {
-        r = q;
-        q = label[r];
-      }
-      cid = comp[r];
-      if (r != (uint32_t)v) comp[v] = cid;
+  __shared__ uint32_t tkey[kRelCap], tcnt[kRelCap];
+  const int t = threadIdx.x;
+  const int ntx = (g.nx + RX - 1) / RX, nty = (g.ny + RY - 1) / RY, ntz = (g.nz + RZ - 1) / RZ;
+  const int64_t ntiles = (int64_t)ntx * nty * ntz;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int i = t; i < kRelCap; i += 256) {
+      tkey[i] = kNone;
+      tcnt[i] = 0;
     }
-    if (count_sizes) {
-      // wave-aggregated size counts: one atomic per distinct id in the wave
-      bool pending = valid;
-      while (true) {
-        uint64_t act = __ballot(pending);
-        if (!act) break;
-        int leader = __ffsll((long long)act) - 1;
-        uint32_t c0 = __shfl(cid, leader, kWave);
-        bool mine = pending && cid == c0;
-        uint64_t mm = __ballot(mine);
-        if (lane_id() == leader) atomicAdd((unsigned long long *)&comp_size[c0], (unsigned long long)__popcll(mm));
-        pending = pending && !mine;
+    __syncthreads();
+    const int ttx = (int)(tile % ntx), tty = (int)((tile / ntx) % nty), ttz = (int)(tile / ((int64_t)ntx * nty));
+    const int x0 = ttx * RX + (t & 3) * 16, y = tty * RY + ((t >> 2) & 7), z = ttz * RZ + (t >> 5);
+    if (y < g.ny && z < g.nz && x0 < g.nx) {
+      const int64_t base = (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      const int xe = x0 + 16 < g.nx ? x0 + 16 : g.nx;
+      uint32_t last_lab = kNone, last_cid = kNone, run_cid = kNone, run_n = 0;
+      auto flush = [&]() {
+        if (run_n && count_sizes) {
+          int sl = lds_slot<kRelCap>(tkey, run_cid);
+          if (sl >= 0)
+            atomicAdd(&tcnt[sl], run_n);
+          else
+            atomicAdd((unsigned long long *)&comp_size[run_cid], (unsigned long long)run_n);
+        }
+      };
+      for (int x = x0; x < xe; ++x) {
+        const int64_t v = base + x;
+        const uint32_t lab = label[v];
+        uint32_t r = lab;
+        uint32_t cid;
+        if (r == last_lab) {
+          cid = last_cid;
+        } else {
+          last_lab = r;
+          uint32_t q = label[r];
+          while (q != r) {
+            r = q;
+            q = label[r];
+          }
+          cid = comp[r];
+          last_cid = cid;
+        }
+        if (lab != (uint32_t)v) comp[v] = cid;
+        if (cid != run_cid) {
+          flush();
+          run_cid = cid;
+          run_n = 0;
+        }
+        ++run_n;
       }
+      flush();
     }
+    __syncthreads();
+    if (count_sizes)
+      for (int i = t; i < kRelCap; i += 256)
+        if (tkey[i] != kNone) atomicAdd((unsigned long long *)&comp_size[tkey[i]], (unsigned long long)tcnt[i]);
+    __syncthreads();
   }
 }
 
@@ -372,8 +407,11 @@ extern "C" int32_t lsrvt_components(const uint8_t *d_band, lsrvt_dims dims, int3
                        write_tables, d_comp, d_comp_band, d_comp_first, d_comp_size);
     LSRVT_LAUNCHED();
   }
-  hipLaunchKernelGGL(k_cc_relabel, dim3(grid_for(g.n, 256, 8192)), dim3(256), 0, s, L.label, g.n, d_comp,
-                     d_comp_size, write_tables);
+  {
+    const int64_t nt = (int64_t)((g.nx + RX - 1) / RX) * ((g.ny + RY - 1) / RY) * ((g.nz + RZ - 1) / RZ);
+    hipLaunchKernelGGL(k_cc_relabel, dim3((unsigned)(nt < 65535 ? nt : 65535)), dim3(256), 0, s, L.label, g, d_comp,
+                       d_comp_size, write_tables);
+  }
   LSRVT_LAUNCHED();
   if (!write_tables) return LSRVT_ECAPACITY;
   LSRVT_HIP(hipMemcpyAsync(d_band_offset, L.bucket, sizeof(uint32_t) * (n_bands + 1), hipMemcpyDeviceToDevice, s));

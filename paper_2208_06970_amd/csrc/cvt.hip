@@ -1,27 +1,30 @@
 // Restricted geodesic Voronoi pass (Eq. 1), snapped centroid update (Sec. 3.1
 // "Centroids"; Sec. 3.2.3) and the fixed-iteration Lloyd loop (Algorithm 1).
 //
-// Voronoi pass.  Every voxel carries a 64-bit key (hop distance << 32 | site
-// id).  The regions of Eq. 1 with ties to the lower id are the unique fixed
-// point of key(v) = min(key(v), key(w) + (1 << 32)) over same-band face
-// neighbours w, started from key = (0, s) at every site and +inf elsewhere:
-// every key is the length of a real path, so it never undercuts the true
-// lexicographic minimum, and at a fixed point the minimum is reached along
-// any shortest path.  Because the fixed point is unique, relaxations may run
-// in any order and the result is bit-deterministic.
+// Voronoi pass.  The regions of Eq. 1 with ties to the lower id are computed
+// by a breadth-first search restricted to same-band face edges, run level
+// by level over the whole volume.  Level 0 holds the sites; at level L every
+// voxel not reached yet that has a same-band neighbour reached at level L - 1
+// takes the smallest site id among those neighbours.  By induction a voxel
+// at hop distance L from its nearest sites receives exactly the smallest of
+// their ids: each such site reaches it through a neighbour at distance L - 1
+// whose own id is no larger, and every neighbour's id names a site within
+// distance L.  Each level is one launch, so the ids of level L - 1 are final
+// when level L reads them and the result does not depend on scheduling.
 //
-// The volume is cut into 16^3 bricks.  A round relaxes a list of bricks, one
-// workgroup each: the brick's bands and keys sit in LDS, its own sites and
-// the keys its six neighbours last published on their facing faces seed it,
-// and alternating forward/backward line sweeps along x, y and z (each a
-// min-plus scan over a same-band run) repeat until nothing changes.  The
-// brick then writes its cells and publishes its six faces; a neighbour is
-// queued for the next round only if a facing face key changed.  The first
-// round of a pass processes every brick without halos.  Rounds repeat until
-// no brick is queued.
+// The volume is cut into 16^3 bricks.  Per brick row (16 voxels along x) the
+// search keeps three 16-bit masks in global memory: the same-band edges in
+// each direction (built once per call, since bands do not change), the
+// voxels reached so far and the frontier of the last two levels.  A level
+// launch visits only the bricks listed for it, one workgroup per brick and
+// one thread per row; a brick that reached anything lists itself and its six
+// neighbours for the next level.  Frontier rows of bricks that were not
+// visited at a level are stale, but only hold voxels whose neighbours were
+// all reached one level after them, so they are masked off by the reached
+// mask.  Each voxel is written once per pass.
 //
 // Update.  Per site, M = sum w and S_a = sum w a are exact uint64 sums
-// (wave-aggregated atomics).  The nearest lattice point to S/M with ties
+// (per-tile LDS aggregation, then one global atomic per distinct cell).  The nearest lattice point to S/M with ties
 // rounded down, q_a = floor((2 S_a + M - 1) / (2 M)), is the answer whenever
 // it lies in the cell (it then minimises the distance over all lattice
 // points, and among tied points the all-lower corner has the smallest linear
@@ -29,6 +32,14 @@
 // around q; voxels outside the cube are at least r + 1/2 from the centroid,
 // so the search stops once 4 D_best < (M (2 r + 1))^2, comparing
 // D = sum_a (M a - S_a)^2 exactly in 128 bits.
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <algorithm>
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "common.h"
 
 namespace lsrvt {
@@ -36,283 +47,161 @@ namespace lsrvt {
 namespace {
 
 constexpr int BX = 16, BY = 16, BZ = 16;
-constexpr int PX = BX + 1;  // padded LDS pitch (u64 elements) for conflict-free x sweeps
-constexpr int kBrickVox = BX * BY * BZ;
+constexpr int kRows = BY * BZ;  // a brick is 256 rows of 16 voxels along x
 constexpr int kVTThreads = 256;
-constexpr int kFaceLen = 256;  // every face of a 16^3 brick has 256 voxels
-constexpr int kFaces = 6;
-constexpr uint64_t kD1 = 1ull << 32;
-constexpr uint8_t kOutside = 255;
-constexpr int kMaxSweepCycles = 1 << 14;
+constexpr int kHistLen = 8192;  // per-level record of active brick counts
 
 struct VTGrid {
   int32_t nbx, nby, nbz;
   int64_t nbricks;
 };
 
-struct VTArgs {
-  const uint8_t *band;
+// Global level-synchronous BFS state.  Brick b, row r (y = r & 15,
+// z = r >> 4) holds 16 voxels along x as the low 16 bits of a word.
+struct BFSArgs {
   Geom g;
   VTGrid bg;
-  const uint32_t *sites;
-  const uint32_t *blist;  // site ids bucketed by brick
-  const uint32_t *boff;   // [nbricks + 1]
-  const uint8_t *site_band;
-  uint64_t *faces;        // [nbricks][6][256]
-  uint32_t *cell;
-  uint32_t *queued;       // [nbricks] last epoch tag
-  uint32_t *list_in;
-  uint32_t *list_out;
-  uint32_t *cnt;          // [3] rotating list counters
+  const uint32_t *eq;  // [nbricks][256][3]: (x- | x+ << 16), (y- | y+ << 16), (z- | z+ << 16) same-band bits
+  uint32_t *fr;        // [2][nbricks][256] voxels reached at the previous / current level
+  uint32_t *vis;       // [nbricks][256] voxels reached so far
+  uint32_t *cell;      // [N] site id of every reached voxel (NONE elsewhere)
+  uint32_t *queued;    // [nbricks] tag of the last level a brick was queued for
+  uint32_t *list_in, *list_out;
+  uint32_t *cnt;       // [3] rotating list counters
+  uint32_t *hist;      // [kHistLen] active bricks per level
   uint32_t *err;
 };
 
-__device__ __forceinline__ int kidx(int lx, int ly, int lz) { return (lz * BY + ly) * PX + lx; }
-__device__ __forceinline__ int bidx(int lx, int ly, int lz) { return (lz * BY + ly) * BX + lx; }
+__device__ __forceinline__ int64_t brick_row_base(const Geom &g, int x0, int y, int z) {
+  return x0 + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+}
 
-// Face f of a brick: 0:-x 1:+x (index [lz][ly]), 2:-y 3:+y ([lz][lx]), 4:-z 5:+z ([ly][lx]).
-__device__ __forceinline__ void face_voxel(int f, int p, int &lx, int &ly, int &lz) {
-  int a = p & 15, c = p >> 4;
-  switch (f) {
-    case 0: lx = 0; ly = a; lz = c; break;
-    case 1: lx = BX - 1; ly = a; lz = c; break;
-    case 2: lx = a; ly = 0; lz = c; break;
-    case 3: lx = a; ly = BY - 1; lz = c; break;
-    case 4: lx = a; ly = c; lz = 0; break;
-    default: lx = a; ly = c; lz = BZ - 1; break;
+// Queue brick (bx, by, bz) and its six face neighbours for the level tagged `tag`.
+__device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *out_cnt) {
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
+    int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
+    int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
+    if (nx < 0 || ny < 0 || nz < 0 || nx >= A.bg.nbx || ny >= A.bg.nby || nz >= A.bg.nbz) continue;
+    uint32_t nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
+    if (atomicMax(&A.queued[nb], tag) < tag) A.list_out[atomicAdd(out_cnt, 1u)] = nb;
   }
 }
 
-__global__ __launch_bounds__(kVTThreads) void k_vt_round(VTArgs A, uint32_t epoch, int all) {
-  __shared__ uint64_t key[BZ * BY * PX];
-  __shared__ uint8_t bnd[kBrickVox];
-  __shared__ int s_changed;
+// Same-band masks of every row toward its six neighbours (across brick faces
+// too); voxels outside the volume have no edges.  Bands do not change during
+// a Lloyd loop, so this runs once per call.
+__global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict__ band, Geom g, VTGrid bg,
+                                                      uint32_t *__restrict__ eq) {
+  const int t = threadIdx.x, ly = t & 15, lz = t >> 4;
+  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
+    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+    const int x0 = bx * BX, y = by * BY + ly, z = bz * BZ + lz;
+    uint32_t m[6] = {0, 0, 0, 0, 0, 0};
+    if (y < g.ny && z < g.nz) {
+      const int64_t base = brick_row_base(g, x0, y, z);
+      const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+      for (int x = 0; x < BX && x0 + x < g.nx; ++x) {
+        const uint8_t bv = band[base + x];
+        if (x0 + x > 0 && band[base + x - 1] == bv) m[0] |= 1u << x;
+        if (x0 + x + 1 < g.nx && band[base + x + 1] == bv) m[1] |= 1u << x;
+        if (y > 0 && band[base + x - sy] == bv) m[2] |= 1u << x;
+        if (y + 1 < g.ny && band[base + x + sy] == bv) m[3] |= 1u << x;
+        if (z > 0 && band[base + x - sz] == bv) m[4] |= 1u << x;
+        if (z + 1 < g.nz && band[base + x + sz] == bv) m[5] |= 1u << x;
+      }
+    }
+    uint32_t *dst = eq + (b * kRows + t) * 3;
+    dst[0] = m[0] | (m[1] << 16);
+    dst[1] = m[2] | (m[3] << 16);
+    dst[2] = m[4] | (m[5] << 16);
+  }
+}
+
+// Level 0: every site reaches its own voxel; co-located sites keep the lowest id.
+__global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A, uint32_t tag) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  uint32_t v = sites[s];
+  if ((int64_t)v >= A.g.n) {
+    atomicOr(A.err, 1u);
+    return;
+  }
+  uint32_t x = v % (uint32_t)A.g.nx, r = v / (uint32_t)A.g.nx;
+  uint32_t y = r % (uint32_t)A.g.ny, z = r / (uint32_t)A.g.ny;
+  int bx = x / BX, by = y / BY, bz = z / BZ;
+  uint32_t b = bx + A.bg.nbx * (by + A.bg.nby * bz);
+  uint32_t row = (y % BY) + BY * (z % BZ), bit = 1u << (x % BX);
+  atomicMin(&A.cell[v], s);
+  atomicOr(&A.vis[(int64_t)b * kRows + row], bit);
+  atomicOr(&A.fr[(int64_t)b * kRows + row], bit);  // parity 0 = level 0
+  queue_around(A, bx, by, bz, tag, &A.cnt[1]);
+}
+
+// Level L: a voxel not reached yet is reached now when a same-band face
+// neighbour was reached at level L - 1; it takes the smallest id among those
+// neighbours (Eq. 1 with ties to the lower id).  Processes only the bricks
+// queued for this level; queues a brick and its neighbours for L + 1 when
+// anything was reached.
+__global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L, uint32_t tag) {
   __shared__ uint32_t s_count;
   const int t = threadIdx.x;
   if (t == 0) {
-    s_count = all ? (uint32_t)A.bg.nbricks : A.cnt[epoch % 3];
-    if (blockIdx.x == 0) A.cnt[(epoch + 2) % 3] = 0;  // the list the round after next appends to
+    s_count = A.cnt[L % 3];
+    if (blockIdx.x == 0) {
+      A.cnt[(L + 2) % 3] = 0;  // the list of level L + 2 starts empty
+      A.hist[L % kHistLen] = s_count;
+    }
   }
   __syncthreads();
   const uint32_t count = s_count;
-  uint32_t *out_cnt = &A.cnt[(epoch + 1) % 3];
-
+  uint32_t *out_cnt = &A.cnt[(L + 1) % 3];
+  const uint32_t *fin = A.fr + (size_t)((L - 1) & 1) * A.bg.nbricks * kRows;
+  uint32_t *fout = A.fr + (size_t)(L & 1) * A.bg.nbricks * kRows;
+  const int ly = t & 15, lz = t >> 4;
+  const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-    const uint32_t b = all ? item : A.list_in[item];
+    const uint32_t b = A.list_in[item];
     const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby), bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
-    // bands and +inf keys
-    for (int li = t; li < kBrickVox; li += kVTThreads) {
-      int lx = li & 15, ly = (li >> 4) & 15, lz = li >> 8;
-      int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-      bool valid = gx < A.g.nx && gy < A.g.ny && gz < A.g.nz;
-      bnd[li] = valid ? A.band[gx + (int64_t)A.g.nx * (gy + (int64_t)A.g.ny * gz)] : kOutside;
-      key[kidx(lx, ly, lz)] = kInfKey;
+    const int64_t rb = (int64_t)b * kRows;
+    const uint32_t F = fin[rb + t];
+    const uint32_t vrow = A.vis[rb + t];
+    const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
+    const uint32_t fym = ly > 0 ? fin[rb + t - 1] : (by > 0 ? fin[(b - bsy) * kRows + t + 15] : 0u);
+    const uint32_t fyp = ly < BY - 1 ? fin[rb + t + 1] : (by < A.bg.nby - 1 ? fin[(b + bsy) * kRows + t - 15] : 0u);
+    const uint32_t fzm = lz > 0 ? fin[rb + t - 16] : (bz > 0 ? fin[(b - bsz) * kRows + t + 240] : 0u);
+    const uint32_t fzp = lz < BZ - 1 ? fin[rb + t + 16] : (bz < A.bg.nbz - 1 ? fin[(b + bsz) * kRows + t - 240] : 0u);
+    const uint32_t xin_m = bx > 0 ? (fin[(b - 1) * kRows + t] >> 15) & 1u : 0u;
+    const uint32_t xin_p = bx < A.bg.nbx - 1 ? fin[(b + 1) * kRows + t] & 1u : 0u;
+    const uint32_t sxm = (F << 1) | xin_m, sxp = (F >> 1) | (xin_p << 15);
+    uint32_t nw = (sxm | sxp | fym | fyp | fzm | fzp) & ~vrow & 0xFFFFu;
+    if (nw) {
+      const uint32_t e0 = A.eq[(rb + t) * 3], e1 = A.eq[(rb + t) * 3 + 1], e2 = A.eq[(rb + t) * 3 + 2];
+      const uint32_t fxm = sxm & e0 & 0xFFFFu, fxp = sxp & (e0 >> 16);
+      const uint32_t gym = fym & e1, gyp = fyp & (e1 >> 16);
+      const uint32_t gzm = fzm & e2, gzp = fzp & (e2 >> 16);
+      nw &= fxm | fxp | gym | gyp | gzm | gzp;
+      const int64_t base = brick_row_base(A.g, bx * BX, by * BY + ly, bz * BZ + lz);
+      uint32_t bits = nw;
+      while (bits) {
+        const int x = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int64_t v = base + x;
+        uint32_t id = kNone;
+        if ((fxm >> x) & 1u) id = min(id, A.cell[v - 1]);
+        if ((fxp >> x) & 1u) id = min(id, A.cell[v + 1]);
+        if ((gym >> x) & 1u) id = min(id, A.cell[v - sy]);
+        if ((gyp >> x) & 1u) id = min(id, A.cell[v + sy]);
+        if ((gzm >> x) & 1u) id = min(id, A.cell[v - sz]);
+        if ((gzp >> x) & 1u) id = min(id, A.cell[v + sz]);
+        A.cell[v] = id;
+      }
+      if (nw) A.vis[rb + t] = vrow | nw;
     }
-    __syncthreads();
-    // own sites at distance 0 (co-located sites: the lower id wins the min)
-    for (uint32_t i = A.boff[b] + t; i < A.boff[b + 1]; i += kVTThreads) {
-      uint32_t s = A.blist[i];
-      uint32_t v = A.sites[s];
-      int gx = (int)(v % (uint32_t)A.g.nx);
-      uint32_t r = v / (uint32_t)A.g.nx;
-      int gy = (int)(r % (uint32_t)A.g.ny), gz = (int)(r / (uint32_t)A.g.ny);
-      atomicMin((unsigned long long *)&key[kidx(gx - x0, gy - y0, gz - z0)], (unsigned long long)s);
-    }
-    // halo: the keys the neighbours published on the faces facing this brick
-    if (!all) {
-      for (int f = 0; f < kFaces; ++f) {
-        int nbx = bx + (f == 0 ? -1 : f == 1 ? 1 : 0);
-        int nby = by + (f == 2 ? -1 : f == 3 ? 1 : 0);
-        int nbz = bz + (f == 4 ? -1 : f == 5 ? 1 : 0);
-        if (nbx < 0 || nby < 0 || nbz < 0 || nbx >= A.bg.nbx || nby >= A.bg.nby || nbz >= A.bg.nbz) continue;
-        int64_t nb = nbx + (int64_t)A.bg.nbx * (nby + (int64_t)A.bg.nby * nbz);
-        const uint64_t *src = A.faces + (nb * kFaces + (f ^ 1)) * kFaceLen;
-        uint64_t kv = src[t];
-        if (kv != kInfKey) {
-          int lx, ly, lz;
-          face_voxel(f, t, lx, ly, lz);
-          uint8_t mb = bnd[bidx(lx, ly, lz)];
-          if (mb != kOutside && A.site_band[(uint32_t)kv] == mb)
-            atomicMin((unsigned long long *)&key[kidx(lx, ly, lz)], (unsigned long long)(kv + kD1));
-        }
-      }
-    }
-    __syncthreads();
-
-    // relax: x, y, z line sweeps until a full cycle changes nothing
-    int cycles = 0;
-    while (true) {
-      bool ch = false;
-      {  // x lines
-        const int ly = t & 15, lz = t >> 4;
-        uint64_t *row = &key[kidx(0, ly, lz)];
-        const uint8_t *br = &bnd[bidx(0, ly, lz)];
-        uint64_t k[BX];
-        uint8_t bb[BX];
-#pragma unroll
-        for (int x = 0; x < BX; ++x) {
-          k[x] = row[x];
-          bb[x] = br[x];
-        }
-        bool c = false;
-#pragma unroll
-        for (int x = 1; x < BX; ++x)
-          if (bb[x] == bb[x - 1] && k[x - 1] + kD1 < k[x] && k[x - 1] != kInfKey) {
-            k[x] = k[x - 1] + kD1;
-            c = true;
-          }
-#pragma unroll
-        for (int x = BX - 2; x >= 0; --x)
-          if (bb[x] == bb[x + 1] && k[x + 1] + kD1 < k[x] && k[x + 1] != kInfKey) {
-            k[x] = k[x + 1] + kD1;
-            c = true;
-          }
-        if (c) {
-#pragma unroll
-          for (int x = 0; x < BX; ++x) row[x] = k[x];
-        }
-        ch |= c;
-      }
-      __syncthreads();
-      {  // y lines
-        const int lx = t & 15, lz = t >> 4;
-        uint64_t k[BY];
-        uint8_t bb[BY];
-#pragma unroll
-        for (int y = 0; y < BY; ++y) {
-          k[y] = key[kidx(lx, y, lz)];
-          bb[y] = bnd[bidx(lx, y, lz)];
-        }
-        bool c = false;
-#pragma unroll
-        for (int y = 1; y < BY; ++y)
-          if (bb[y] == bb[y - 1] && k[y - 1] + kD1 < k[y] && k[y - 1] != kInfKey) {
-            k[y] = k[y - 1] + kD1;
-            c = true;
-          }
-#pragma unroll
-        for (int y = BY - 2; y >= 0; --y)
-          if (bb[y] == bb[y + 1] && k[y + 1] + kD1 < k[y] && k[y + 1] != kInfKey) {
-            k[y] = k[y + 1] + kD1;
-            c = true;
-          }
-        if (c) {
-#pragma unroll
-          for (int y = 0; y < BY; ++y) key[kidx(lx, y, lz)] = k[y];
-        }
-        ch |= c;
-      }
-      __syncthreads();
-      {  // z lines
-        const int lx = t & 15, ly = t >> 4;
-        uint64_t k[BZ];
-        uint8_t bb[BZ];
-#pragma unroll
-        for (int z = 0; z < BZ; ++z) {
-          k[z] = key[kidx(lx, ly, z)];
-          bb[z] = bnd[bidx(lx, ly, z)];
-        }
-        bool c = false;
-#pragma unroll
-        for (int z = 1; z < BZ; ++z)
-          if (bb[z] == bb[z - 1] && k[z - 1] + kD1 < k[z] && k[z - 1] != kInfKey) {
-            k[z] = k[z - 1] + kD1;
-            c = true;
-          }
-#pragma unroll
-        for (int z = BZ - 2; z >= 0; --z)
-          if (bb[z] == bb[z + 1] && k[z + 1] + kD1 < k[z] && k[z + 1] != kInfKey) {
-            k[z] = k[z + 1] + kD1;
-            c = true;
-          }
-        if (c) {
-#pragma unroll
-          for (int z = 0; z < BZ; ++z) key[kidx(lx, ly, z)] = k[z];
-        }
-        ch |= c;
-      }
-      int any = __syncthreads_or(ch ? 1 : 0);
-      if (!any) break;
-      if (++cycles >= kMaxSweepCycles) {
-        if (t == 0) atomicOr(A.err, 2u);
-        break;
-      }
-    }
-
-    // cells
-    for (int li = t; li < kBrickVox; li += kVTThreads) {
-      int lx = li & 15, ly = (li >> 4) & 15, lz = li >> 8;
-      int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-      if (gx < A.g.nx && gy < A.g.ny && gz < A.g.nz) {
-        uint64_t kv = key[kidx(lx, ly, lz)];
-        A.cell[gx + (int64_t)A.g.nx * (gy + (int64_t)A.g.ny * gz)] = kv == kInfKey ? kNone : (uint32_t)kv;
-      }
-    }
-    // publish faces; queue a neighbour when a facing key changed
-    for (int f = 0; f < kFaces; ++f) {
-      int nbx = bx + (f == 0 ? -1 : f == 1 ? 1 : 0);
-      int nby = by + (f == 2 ? -1 : f == 3 ? 1 : 0);
-      int nbz = bz + (f == 4 ? -1 : f == 5 ? 1 : 0);
-      bool exists = !(nbx < 0 || nby < 0 || nbz < 0 || nbx >= A.bg.nbx || nby >= A.bg.nby || nbz >= A.bg.nbz);
-      if (!exists) continue;  // uniform across the workgroup
-      int lx, ly, lz;
-      face_voxel(f, t, lx, ly, lz);
-      uint64_t kv = key[kidx(lx, ly, lz)];
-      uint64_t *dst = A.faces + ((int64_t)b * kFaces + f) * kFaceLen;
-      bool diff;
-      if (all) {
-        diff = kv != kInfKey;
-        dst[t] = kv;
-      } else {
-        uint64_t old = dst[t];
-        diff = kv != old;
-        if (diff) dst[t] = kv;
-      }
-      int any = __syncthreads_or(diff ? 1 : 0);
-      if (any && t == 0) {
-        uint32_t nb = (uint32_t)(nbx + A.bg.nbx * (nby + A.bg.nby * nbz));
-        uint32_t old = atomicMax(&A.queued[nb], epoch + 1);
-        if (old < epoch + 1) {
-          uint32_t pos = atomicAdd(out_cnt, 1u);
-          A.list_out[pos] = nb;
-        }
-      }
-    }
-    __syncthreads();
+    fout[rb + t] = nw;
+    if (__syncthreads_or(nw != 0) && t == 0) queue_around(A, bx, by, bz, tag, out_cnt);
   }
-}
-
-// Sites: count per brick and note each site's band; out-of-range sites are
-// reported through err and left out.
-__global__ void k_site_count(const uint32_t *__restrict__ sites, uint32_t S, const uint8_t *__restrict__ band, Geom g,
-                             VTGrid bg, uint32_t *bcount, uint8_t *site_band, uint32_t *err) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  uint32_t v = sites[s];
-  if ((int64_t)v >= g.n) {
-    atomicOr(err, 1u);
-    site_band[s] = kOutside;
-    return;
-  }
-  uint32_t x = v % (uint32_t)g.nx, r = v / (uint32_t)g.nx;
-  uint32_t y = r % (uint32_t)g.ny, z = r / (uint32_t)g.ny;
-  uint32_t b = x / BX + bg.nbx * (y / BY + bg.nby * (z / BZ));
-  atomicAdd(&bcount[b], 1u);
-  site_band[s] = band[v];
-}
-
-__global__ void k_site_fill(const uint32_t *__restrict__ sites, uint32_t S, Geom g, VTGrid bg,
-                            const uint32_t *__restrict__ boff, uint32_t *bfill, uint32_t *blist) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  uint32_t v = sites[s];
-  if ((int64_t)v >= g.n) return;
-  uint32_t x = v % (uint32_t)g.nx, r = v / (uint32_t)g.nx;
-  uint32_t y = r % (uint32_t)g.ny, z = r / (uint32_t)g.ny;
-  uint32_t b = x / BX + bg.nbx * (y / BY + bg.nby * (z / BZ));
-  uint32_t pos = boff[b] + atomicAdd(&bfill[b], 1u);
-  blist[pos] = s;
 }
 
 // ----------------------------------------------------------------------------
@@ -322,40 +211,78 @@ struct Sums {
   unsigned long long *M, *Sx, *Sy, *Sz;
 };
 
-// One wave per row (y, z) at a time; along the row the wave takes 64 voxels per
-// step, and equal cell ids inside the step are reduced before the atomics.
-// Along a row y and z are fixed, so S_y = M y and S_z = M z.
-__global__ __launch_bounds__(kWave) void k_centroid(const uint32_t *__restrict__ cell, const uint16_t *__restrict__ w,
-                                                    Geom g, uint32_t S, Sums sums) {
-  const int64_t rows = (int64_t)g.ny * g.nz;
-  const int lane = lane_id();
-  for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-    const uint64_t y = (uint64_t)(row % g.ny), z = (uint64_t)(row / g.ny);
-    const int64_t base = row * g.nx;
-    for (int x0 = 0; x0 < g.nx; x0 += kWave) {
-      int x = x0 + lane;
-      bool valid = x < g.nx;
-      uint32_t c = valid ? cell[base + x] : kNone;
-      uint64_t wv = 0;
-      if (valid && c != kNone && c < S) wv = w ? (uint64_t)w[base + x] : 1ull;
-      bool pending = valid && c != kNone && c < S;
-      while (true) {
-        uint64_t act = __ballot(pending);
-        if (!act) break;
-        int leader = __ffsll((long long)act) - 1;
-        uint32_t c0 = __shfl(c, leader, kWave);
-        bool mine = pending && c == c0;
-        uint64_t m = wave_sum_u64(mine ? wv : 0ull);
-        uint64_t sx = wave_sum_u64(mine ? wv * (uint64_t)x : 0ull);
-        if (lane == leader && m) {
-          atomicAdd(&sums.M[c0], (unsigned long long)m);
-          atomicAdd(&sums.Sx[c0], (unsigned long long)sx);
-          atomicAdd(&sums.Sy[c0], (unsigned long long)(m * y));
-          atomicAdd(&sums.Sz[c0], (unsigned long long)(m * z));
+// One workgroup per 64x8x8 tile: each thread folds 16 consecutive voxels of a
+// row into runs of equal cell id, the runs accumulate in an LDS hash table
+// keyed by cell id (LDS atomics), and the table is flushed with one set of
+// global atomics per distinct cell in the tile.  Along a row y and z are
+// fixed, so S_y = M y and S_z = M z per run.
+constexpr int TX = 64, TY = 8, TZ = 8;
+constexpr int kTabCap = 512;
+
+
+__global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ cell, const uint16_t *__restrict__ w,
+                                                  Geom g, uint32_t S, Sums sums) {
+  __shared__ uint32_t tkey[kTabCap];
+  __shared__ unsigned long long tM[kTabCap], tX[kTabCap], tY[kTabCap], tZ[kTabCap];
+  const int t = threadIdx.x;
+  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
+  const int64_t ntiles = (int64_t)ntx * nty * ntz;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int i = t; i < kTabCap; i += 256) {
+      tkey[i] = kNone;
+      tM[i] = tX[i] = tY[i] = tZ[i] = 0ull;
+    }
+    __syncthreads();
+    const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
+    // thread -> (quarter row, y, z) inside the tile
+    const int qx = (t & 3) * 16, ly = (t >> 2) & 7, lz = t >> 5;
+    const int x0 = tx * TX + qx, y = ty * TY + ly, z = tz * TZ + lz;
+    if (y < g.ny && z < g.nz && x0 < g.nx) {
+      const int64_t base = (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      const int xe = x0 + 16 < g.nx ? x0 + 16 : g.nx;
+      uint32_t rc = kNone;
+      uint64_t rm = 0, rx = 0;
+      auto flush = [&]() {
+        if (rc != kNone && rc < S && rm) {
+          int sl = lds_slot<kTabCap>(tkey, rc);
+          if (sl >= 0) {
+            atomicAdd(&tM[sl], (unsigned long long)rm);
+            atomicAdd(&tX[sl], (unsigned long long)rx);
+            atomicAdd(&tY[sl], (unsigned long long)(rm * (uint64_t)y));
+            atomicAdd(&tZ[sl], (unsigned long long)(rm * (uint64_t)z));
+          } else {
+            atomicAdd(&sums.M[rc], (unsigned long long)rm);
+            atomicAdd(&sums.Sx[rc], (unsigned long long)rx);
+            atomicAdd(&sums.Sy[rc], (unsigned long long)(rm * (uint64_t)y));
+            atomicAdd(&sums.Sz[rc], (unsigned long long)(rm * (uint64_t)z));
+          }
         }
-        pending = pending && !mine;
+      };
+      for (int x = x0; x < xe; ++x) {
+        uint32_t c = cell[base + x];
+        uint64_t wv = w ? (uint64_t)w[base + x] : 1ull;
+        if (c != rc) {
+          flush();
+          rc = c;
+          rm = 0;
+          rx = 0;
+        }
+        rm += wv;
+        rx += wv * (uint64_t)x;
+      }
+      flush();
+    }
+    __syncthreads();
+    for (int i = t; i < kTabCap; i += 256) {
+      uint32_t c = tkey[i];
+      if (c != kNone && tM[i]) {
+        atomicAdd(&sums.M[c], tM[i]);
+        atomicAdd(&sums.Sx[c], tX[i]);
+        atomicAdd(&sums.Sy[c], tY[i]);
+        atomicAdd(&sums.Sz[c], tZ[i]);
       }
     }
+    __syncthreads();
   }
 }
 
@@ -482,18 +409,34 @@ __global__ __launch_bounds__(256) void k_snap_fallback(const uint32_t *__restric
   }
 }
 
-// Mean of ds[0..S) in a fixed order (one workgroup).
-__global__ __launch_bounds__(256) void k_mean_ds(const double *ds, uint32_t S, double *out) {
-  __shared__ double part[256];
+// Mean of ds[0..S) in a fixed order: 256 contiguous chunks summed by 256
+// workgroups, then the chunk sums in order by one workgroup.
+constexpr int kMeanParts = 256;
+__global__ __launch_bounds__(256) void k_mean_ds_part(const double *ds, uint32_t S, double *part) {
+  __shared__ double red[256];
+  const uint32_t chunk = (S + kMeanParts - 1) / kMeanParts;
+  const uint32_t b0 = blockIdx.x * chunk;
+  const uint32_t b1 = b0 + chunk < S ? b0 + chunk : S;
   double acc = 0.0;
-  for (uint32_t i = threadIdx.x; i < S; i += 256) acc += ds[i];
-  part[threadIdx.x] = acc;
+  for (uint32_t i = b0 + threadIdx.x; i < b1; i += 256) acc += ds[i];
+  red[threadIdx.x] = acc;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = S ? part[0] / (double)S : 0.0;
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_mean_ds(const double *part, uint32_t S, double *out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = S ? red[0] / (double)S : 0.0;
 }
 
 __global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, const uint32_t *__restrict__ comp, Geom g,
@@ -513,13 +456,12 @@ __global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, con
 // host side
 
 struct CvtWork {
-  uint64_t *faces;
-  uint32_t *queued, *list_a, *list_b, *cnt, *bcount, *boff, *bfill, *blist, *fb_list, *fb_cnt, *err;
-  uint8_t *site_band;
+  uint32_t *eq, *fr, *vis;
+  uint32_t *queued, *list_a, *list_b, *cnt;  // cnt[0..2] level counters, cnt[3] error bits
+  uint32_t *fb_list, *fb_cnt, *err;
+  uint32_t *hist;
   unsigned long long *sums;  // 4 x S
-  double *ds, *mean;
-  void *scan_work;
-  size_t scan_bytes;
+  double *ds, *mean, *mean_part;
 };
 
 VTGrid vt_grid(const Geom &g) {
@@ -536,39 +478,36 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   VTGrid bg = vt_grid(g);
   int64_t nb = bg.nbricks;
   size_t s1 = S ? S : 1;
-  auto faces = a.template take<uint64_t>(nb * kFaces * kFaceLen);
+  auto eq = a.template take<uint32_t>(nb * kRows * 3);
+  auto fr = a.template take<uint32_t>(2 * nb * kRows);
+  auto vis = a.template take<uint32_t>(nb * kRows);
   auto queued = a.template take<uint32_t>(nb);
   auto la = a.template take<uint32_t>(nb);
   auto lb = a.template take<uint32_t>(nb);
   auto cnt = a.template take<uint32_t>(4);
-  auto bcount = a.template take<uint32_t>(nb);
-  auto boff = a.template take<uint32_t>(nb + 1);
-  auto bfill = a.template take<uint32_t>(nb);
-  auto blist = a.template take<uint32_t>(s1);
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
-  auto err = a.template take<uint32_t>(4);
-  auto sb = a.template take<uint8_t>(s1);
   auto sums = a.template take<unsigned long long>(4 * s1);
   auto ds = a.template take<double>(s1);
   auto mean = a.template take<double>(iters > 0 ? iters : 1);
+  auto mpart = a.template take<double>(kMeanParts);
+  auto hist = a.template take<uint32_t>(kHistLen);
   if (W) {
-    W->faces = faces;
+    W->eq = eq;
+    W->fr = fr;
+    W->vis = vis;
     W->queued = queued;
     W->list_a = la;
     W->list_b = lb;
     W->cnt = cnt;
-    W->bcount = bcount;
-    W->boff = boff;
-    W->bfill = bfill;
-    W->blist = blist;
+    W->err = cnt + 3;
     W->fb_list = fbl;
     W->fb_cnt = fbc;
-    W->err = err;
-    W->site_band = sb;
     W->sums = sums;
     W->ds = ds;
     W->mean = mean;
+    W->mean_part = mpart;
+    W->hist = hist;
   }
 }
 
@@ -583,88 +522,179 @@ struct SizerT : Sizer {
 size_t cvt_workspace(const Geom &g, uint32_t S, int32_t iters) {
   SizerT z;
   cvt_layout(z, g, S, iters, nullptr);
-  return z.off + ScanU32::workspace(vt_grid(g).nbricks + 1) + 256;
+  return z.off + 256;
 }
 
 int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t iters, CvtWork &W) {
   Carve cv(d_work, bytes);
   cvt_layout(cv, g, S, iters, &W);
-  if (!cv.ok) return LSRVT_EWORKSPACE;
-  W.scan_work = cv.base + cv.off;
-  W.scan_bytes = cv.size - cv.off;
-  return LSRVT_OK;
+  return cv.ok ? LSRVT_OK : LSRVT_EWORKSPACE;
 }
 
-// Driver state of one Lloyd run (epochs and a round-count hint).
+// Driver state of one Lloyd run: the queue tag of the next level and the
+// active-brick counts per level of the previous pass (sites move little
+// between passes, so they size the next pass's launches).
 struct VTState {
-  uint32_t epoch = 1;
-  int rounds_hint = 4;
+  uint32_t tag = 1;
+  std::vector<uint32_t> prev;
 };
 
-int32_t read_u32(const uint32_t *d, uint32_t &h, hipStream_t s) {
-  LSRVT_HIP(hipMemcpyAsync(&h, d, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+// Benchmark timing of the level kernel: an event pair on the launch stream
+// around every launch while enabled; read back by lsrvt_timing_read.
+struct KernelTimer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, pool;
+  double ms = 0.0;
+  uint64_t launches = 0;
+  uint64_t passes = 0;
+  int64_t voxels_per_pass = 0;
+};
+KernelTimer &timer() {
+  static KernelTimer t;
+  return t;
+}
+
+int32_t timed_begin(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
+  KernelTimer &T = timer();
+  std::lock_guard<std::mutex> lk(T.mu);
+  if (T.pool.empty()) {
+    hipEvent_t a, b;
+    LSRVT_HIP(hipEventCreate(&a));
+    LSRVT_HIP(hipEventCreate(&b));
+    T.pool.push_back({a, b});
+  }
+  ev = T.pool.back();
+  T.pool.pop_back();
+  LSRVT_HIP(hipEventRecord(ev.first, s));
   return LSRVT_OK;
 }
 
-int32_t run_vt(const uint8_t *band, const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W,
-               VTState &st, hipStream_t s) {
+int32_t timed_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> &ev) {
+  KernelTimer &T = timer();
+  LSRVT_HIP(hipEventRecord(ev.second, s));
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.pending.push_back(ev);
+  ++T.launches;
+  return LSRVT_OK;
+}
+
+// Voxels never reached (components without a site) get LSRVT_NONE.
+__global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint32_t *__restrict__ vis, Geom g, VTGrid bg,
+                                                             uint32_t *__restrict__ cell) {
+  const int t = threadIdx.x, ly = t & 15, lz = t >> 4;
+  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
+    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+    const int x0 = bx * BX, y = by * BY + ly, z = bz * BZ + lz;
+    if (y >= g.ny || z >= g.nz) continue;
+    const int w = g.nx - x0 < BX ? g.nx - x0 : BX;
+    uint32_t miss = ~vis[b * kRows + t] & ((1u << w) - 1u);
+    const int64_t base = brick_row_base(g, x0, y, z);
+    while (miss) {
+      const int x = __ffs(miss) - 1;
+      miss &= miss - 1;
+      cell[base + x] = kNone;
+    }
+  }
+}
+
+__global__ void k_sites_clear(const uint32_t *__restrict__ sites, uint32_t S, int64_t n, uint32_t *cell) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < S && (int64_t)sites[s] < n) cell[sites[s]] = kNone;
+}
+
+unsigned vt_grid_cap(const VTGrid &bg) { return (unsigned)(bg.nbricks < 65535 ? bg.nbricks : 65535); }
+
+int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s) {
+  VTGrid bg = vt_grid(g);
+  hipLaunchKernelGGL(k_vt_eq, dim3(vt_grid_cap(bg)), dim3(kVTThreads), 0, s, band, g, bg, W.eq);
+  LSRVT_LAUNCHED();
+  return LSRVT_OK;
+}
+
+// One restricted Voronoi pass: level 0 at the sites, then one launch per BFS
+// level over the bricks the front passes through, until a level reaches
+// nothing.
+int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
+               hipStream_t s) {
   VTGrid bg = vt_grid(g);
   int32_t rc;
-  // bucket the sites by brick
-  if ((rc = fill<uint32_t>(W.bcount, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.bfill, bg.nbricks, 0u, s))) return rc;
-  if (S) {
-    hipLaunchKernelGGL(k_site_count, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, band, g, bg, W.bcount,
-                       W.site_band, W.err);
-    LSRVT_LAUNCHED();
-  }
-  if ((rc = ScanU32::run(W.bcount, bg.nbricks, W.boff, W.scan_work, W.scan_bytes, s))) return rc;
-  if (S) {
-    hipLaunchKernelGGL(k_site_fill, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g, bg, W.boff, W.bfill, W.blist);
-    LSRVT_LAUNCHED();
-  }
-  VTArgs A;
-  A.band = band;
+  if ((rc = fill<uint32_t>(W.fr, 2 * bg.nbricks * kRows, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.vis, bg.nbricks * kRows, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.cnt, 3, 0u, s))) return rc;
+  BFSArgs A;
   A.g = g;
   A.bg = bg;
-  A.sites = sites;
-  A.blist = W.blist;
-  A.boff = W.boff;
-  A.site_band = W.site_band;
-  A.faces = W.faces;
+  A.eq = W.eq;
+  A.fr = W.fr;
+  A.vis = W.vis;
   A.cell = cell;
   A.queued = W.queued;
   A.cnt = W.cnt;
+  A.hist = W.hist;
   A.err = W.err;
-  const unsigned grid_all = (unsigned)(bg.nbricks < 65535 ? bg.nbricks : 65535);
-  const unsigned grid_list = (unsigned)(bg.nbricks < 2048 ? bg.nbricks : 2048);
-  const int64_t max_rounds = 2 * bg.nbricks + 16;
-  int64_t done_rounds = 0;
-  bool first = true;
-  int batch = st.rounds_hint;
-  while (true) {
-    for (int i = 0; i < batch; ++i) {
-      bool all = first;
-      A.list_in = (st.epoch & 1) ? W.list_a : W.list_b;
-      A.list_out = (st.epoch & 1) ? W.list_b : W.list_a;
-      hipLaunchKernelGGL(k_vt_round, dim3(all ? grid_all : grid_list), dim3(kVTThreads), 0, s, A, st.epoch,
-                         all ? 1 : 0);
-      LSRVT_LAUNCHED();
-      ++st.epoch;
-      ++done_rounds;
-      first = false;
-    }
-    uint32_t pending = 0, err = 0;
-    if ((rc = read_u32(&W.cnt[st.epoch % 3], pending, s))) return rc;
-    if ((rc = read_u32(W.err, err, s))) return rc;
-    if (err & 1u) return LSRVT_EINVAL;
-    if (err) return LSRVT_EDEVICE;
-    if (pending == 0) break;
-    if (done_rounds > max_rounds) return LSRVT_EDEVICE;
-    batch = 2;
+  A.list_in = W.list_a;
+  A.list_out = W.list_b;  // level 1 reads list_b
+  if (S) {
+    hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g.n, cell);
+    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A, st.tag);
+    LSRVT_LAUNCHED();
   }
-  st.rounds_hint = (int)(done_rounds < 2 ? 2 : done_rounds);
+  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
+  const unsigned cap = vt_grid_cap(bg);
+  const int64_t max_levels = g.n + 2;
+  std::vector<uint32_t> counts;
+  uint32_t L = 0;
+  bool more = S != 0;
+  int batch = st.prev.empty() ? 8 : (int)st.prev.size();
+  while (more) {
+    for (int i = 0; i < batch; ++i) {
+      ++L;
+      A.list_in = (L & 1) ? W.list_b : W.list_a;
+      A.list_out = (L & 1) ? W.list_a : W.list_b;
+      unsigned grid = cap;
+      if (L - 1 < st.prev.size()) {
+        const uint32_t p = st.prev[L - 1];
+        grid = (unsigned)std::min<uint64_t>(cap, (uint64_t)p + p / 4 + 64);
+      }
+      const bool timed = timer().on;
+      std::pair<hipEvent_t, hipEvent_t> ev;
+      if (timed && (rc = timed_begin(s, ev))) return rc;
+      hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kVTThreads), 0, s, A, L, st.tag + L);
+      LSRVT_LAUNCHED();
+      if (timed && (rc = timed_end(s, ev))) return rc;
+    }
+    uint32_t c[4];
+    LSRVT_HIP(hipMemcpyAsync(c, W.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    if (c[3] & 1u) return LSRVT_EINVAL;
+    if (c[3]) return LSRVT_EDEVICE;
+    more = c[(L + 1) % 3] != 0;
+    if ((int64_t)L > max_levels) return LSRVT_EDEVICE;
+    batch = 4;
+  }
+  st.tag += L + 2;
+  // per-level brick counts of this pass size the next one
+  const uint32_t nl = L < (uint32_t)kHistLen ? L : (uint32_t)kHistLen - 1;
+  std::vector<uint32_t> h(nl + 1, 0);
+  if (nl) {
+    LSRVT_HIP(hipMemcpyAsync(h.data(), W.hist, sizeof(uint32_t) * (nl + 1), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+  }
+  st.prev.clear();
+  for (uint32_t l = 1; l <= nl && h[l]; ++l) st.prev.push_back(h[l]);
+  hipLaunchKernelGGL(k_vt_unreached, dim3(cap), dim3(kVTThreads), 0, s, W.vis, g, bg, cell);
+  LSRVT_LAUNCHED();
+  if (timer().on) {
+    std::lock_guard<std::mutex> lk(timer().mu);
+    timer().passes += 1;
+    timer().voxels_per_pass = g.n;
+  }
+  if (debug_levels) {
+    fprintf(stderr, "[lsrvt] vt levels=%u active bricks:", L);
+    for (uint32_t l = 1; l <= nl; ++l) fprintf(stderr, " %u", h[l]);
+    fprintf(stderr, "\n");
+  }
   return LSRVT_OK;
 }
 
@@ -675,8 +705,8 @@ int32_t run_update(const uint32_t *cell, const Geom &g, const uint16_t *w, uint3
   if ((rc = fill<unsigned long long>(W.sums, 4 * (int64_t)S, 0ull, s))) return rc;
   if ((rc = fill<uint32_t>(W.fb_cnt, 1, 0u, s))) return rc;
   Sums sm{W.sums, W.sums + S, W.sums + 2 * (size_t)S, W.sums + 3 * (size_t)S};
-  int64_t rows = (int64_t)g.ny * g.nz;
-  hipLaunchKernelGGL(k_centroid, dim3((unsigned)(rows < 262144 ? rows : 262144)), dim3(kWave), 0, s, cell, w, g, S, sm);
+  const int64_t ntiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+  hipLaunchKernelGGL(k_centroid, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(256), 0, s, cell, w, g, S, sm);
   hipLaunchKernelGGL(k_snap, dim3((S + 255) / 256), dim3(256), 0, s, cell, g, S, sm, sites, ds, W.fb_list, W.fb_cnt);
   hipLaunchKernelGGL(k_snap_fallback, dim3(S < 1024 ? S : 1024), dim3(256), 0, s, cell, g, sm, sites, ds, W.fb_list,
                      W.fb_cnt);
@@ -689,7 +719,6 @@ int32_t begin(CvtWork &W, const Geom &g, hipStream_t s) {
   VTGrid bg = vt_grid(g);
   if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.cnt, 4, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.err, 1, 0u, s))) return rc;
   return LSRVT_OK;
 }
 
@@ -716,8 +745,9 @@ extern "C" int32_t lsrvt_vt(const uint8_t *d_band, lsrvt_dims dims, const uint32
   if ((rc = carve_cvt(d_work, work_bytes, g, n_sites, 0, W))) return rc;
   hipStream_t s = as_stream(stream);
   if ((rc = begin(W, g, s))) return rc;
+  if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
-  return run_vt(d_band, g, d_sites, n_sites, d_cell, W, st, s);
+  return run_vt(g, d_sites, n_sites, d_cell, W, st, s);
 }
 
 extern "C" int32_t lsrvt_update(const uint32_t *d_cell, lsrvt_dims dims, const uint16_t *d_weights, uint32_t *d_sites,
@@ -751,17 +781,47 @@ extern "C" int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrv
                        d_site_comp, W.err);
     LSRVT_LAUNCHED();
   }
+  if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
   for (int32_t t = 0; t <= iters; ++t) {
-    if ((rc = run_vt(d_band, g, d_sites, n_sites, d_cell, W, st, s))) return rc;
+    if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
     if (t == iters) break;
     if ((rc = run_update(d_cell, g, d_weights, d_sites, n_sites, W.ds, W, s))) return rc;
-    hipLaunchKernelGGL(k_mean_ds, dim3(1), dim3(256), 0, s, W.ds, n_sites, W.mean + t);
+    hipLaunchKernelGGL(k_mean_ds_part, dim3(kMeanParts), dim3(256), 0, s, W.ds, n_sites, W.mean_part);
+    hipLaunchKernelGGL(k_mean_ds, dim3(1), dim3(256), 0, s, W.mean_part, n_sites, W.mean + t);
     LSRVT_LAUNCHED();
   }
   if (h_mean_ds && iters > 0) {
     LSRVT_HIP(hipMemcpyAsync(h_mean_ds, W.mean, sizeof(double) * iters, hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
   }
+  return LSRVT_OK;
+}
+
+extern "C" int32_t lsrvt_timing_enable(int32_t enable) {
+  KernelTimer &T = timer();
+  std::lock_guard<std::mutex> lk(T.mu);
+  T.on = enable != 0;
+  return LSRVT_OK;
+}
+
+extern "C" int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass) {
+  KernelTimer &T = timer();
+  std::lock_guard<std::mutex> lk(T.mu);
+  for (auto &ev : T.pending) {
+    LSRVT_HIP(hipEventSynchronize(ev.second));
+    float dt = 0.0f;
+    LSRVT_HIP(hipEventElapsedTime(&dt, ev.first, ev.second));
+    T.ms += dt;
+    T.pool.push_back(ev);
+  }
+  T.pending.clear();
+  if (ms) *ms = T.ms;
+  if (launches) *launches = T.launches;
+  if (passes) *passes = T.passes;
+  if (voxels_per_pass) *voxels_per_pass = T.voxels_per_pass;
+  T.ms = 0.0;
+  T.launches = 0;
+  T.passes = 0;
   return LSRVT_OK;
 }
