@@ -201,9 +201,10 @@ int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrvt_dims dims
  *   d_vars        float32[m][N]    the variables, one volume after another
  *   d_edges       float32[m][B+1]  increasing edges (needed with HIST)
  *   flags         LSRVT_STATS_HIST | LSRVT_STATS_COV
- * Does not synchronise.  Errors: EINVAL (m < 1 or > 32, B < 1 with HIST,
- * NULL output arrays that the flags require).
- * Workspace: lsrvt_aggregate_workspace(...).
+ * Synchronises the stream twice (to size its work lists).  Errors: EINVAL
+ * (m < 1 or > 32, B < 1 with HIST, m * B > 8192, NULL output arrays that the
+ * flags require).  Workspace: lsrvt_aggregate_workspace(...); it includes a
+ * structured layout of the cells (see lsrvt_layout).
  */
 typedef struct {
   uint64_t *n;
@@ -235,7 +236,46 @@ int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t 
                         const lsrvt_group_stats *band, void *d_work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
- * Benchmark instrumentation of the Voronoi round kernel (the dominant kernel
+ * Structured hierarchical layout (Sec. 3.2.4, "Data Reduction and Structured
+ * Data Layout"; Fig. 5): the voxels that lie in a cell, ordered by band, then
+ * component, then cell, then linear index, so that every band, component
+ * and cell is one contiguous range addressed by offsets.  Cells of a
+ * component are ordered by site id; components must be numbered band-major
+ * (as lsrvt_components numbers them).  Voxels labelled LSRVT_NONE (or with a
+ * label >= n_sites) are left out.  The linear indices in d_perm are the
+ * voxel coordinates of the layout.
+ *   d_cell        uint32[N]         cells (lsrvt_cvt)
+ *   d_site_comp   uint32[n_sites]   component of each site; values >= n_comp
+ *                                   are placed after all components
+ *   d_comp_band   uint8[n_comp]     band of each component, nondecreasing
+ *   d_perm        uint32[N]         output: the first *h_n_placed entries are
+ *                                   the placed voxels in layout order
+ *   d_site_order  uint32[n_sites]   output: the site of the k-th cell
+ *   d_cell_off    uint32[n_sites+1] output: cell k is perm[cell_off[k] ..
+ *                                   cell_off[k+1])
+ *   d_comp_off    uint32[n_comp+1]  output: component c is perm[comp_off[c]
+ *                                   .. comp_off[c+1])
+ *   d_band_off    uint32[n_bands+1] output: band b is perm[band_off[b] ..
+ *                                   band_off[b+1])
+ *   h_n_placed    output (may be NULL): number of placed voxels
+ * Deterministic.  Synchronises the stream twice.
+ * Workspace: lsrvt_layout_workspace(dims, n_sites, n_comp).
+ */
+size_t lsrvt_layout_workspace(lsrvt_dims dims, uint32_t n_sites, uint32_t n_comp);
+int32_t lsrvt_layout(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t *d_site_comp,
+                     uint32_t n_sites, const uint8_t *d_comp_band, uint32_t n_comp, int32_t n_bands,
+                     uint32_t *d_perm, uint32_t *d_site_order, uint32_t *d_cell_off,
+                     uint32_t *d_comp_off, uint32_t *d_band_off, uint32_t *h_n_placed, void *d_work,
+                     size_t work_bytes, void *stream);
+
+/* Raw-data extraction in layout order: d_out[j][k] = d_vars[j][d_perm[k]]
+ * for k < n_placed and j < n_vars (float32, variable-major).  d_perm entries
+ * >= N give NaN.  Needs no workspace; does not synchronise. */
+int32_t lsrvt_extract(const float *d_vars, int32_t n_vars, lsrvt_dims dims, const uint32_t *d_perm,
+                      uint32_t n_placed, float *d_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Benchmark instrumentation of the Voronoi level kernel (the dominant kernel
  * of the Lloyd loop).  While enabled, every launch of that kernel is
  * bracketed by a hipEvent pair recorded on the stream it is launched on.
  * lsrvt_timing_read waits for the recorded events and returns, since the

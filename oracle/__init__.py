@@ -22,6 +22,10 @@ ctypes.  Each function cites the passage of the paper it follows:
   histograms and covariance, computed directly per unit in double precision
 * :func:`chan_merge`  -- pairwise merge of (n, mean, M2, C) summaries, used by
   the tests to check that merged cell statistics equal the direct ones
+* :func:`layout`      -- Sec. 3.2.4 "Data Reduction and Structured Data
+  Layout" / Fig. 5: the voxels of the cells ordered by band, component and
+  cell, with offsets per cell, component and band (numpy, stable sorts)
+* :func:`extract`     -- the raw variables in that order
 """
 from __future__ import annotations
 
@@ -244,3 +248,44 @@ def chan_merge(n_a, mean_a, m2_a, cov_a, n_b, mean_b, m2_b, cov_b):
         dd = np.concatenate([delta[j] * delta[j:] for j in range(m)])
         cv = cov_a + cov_b + dd * f
     return n, mean, m2, cv
+
+
+@dataclass
+class Layout:
+    perm: np.ndarray        # uint32[n_placed] voxel linear indices in layout order
+    site_order: np.ndarray  # uint32[S] site of the k-th cell
+    cell_off: np.ndarray    # uint32[S + 1]
+    comp_off: np.ndarray    # uint32[n_comp + 1]
+    band_off: np.ndarray    # uint32[n_bands + 1]
+
+
+def layout(cell: np.ndarray, site_comp, comp_band, n_comp: int, n_bands: int) -> Layout:
+    """Structured hierarchical layout (Sec. 3.2.4, Fig. 5).
+
+    Cells are ordered by (component, site id) -- components being numbered
+    band-major, this is also band-major -- and the voxels of a cell by linear
+    index.  Voxels whose label is not a site id are left out.  A site whose
+    component is >= n_comp sorts after every component."""
+    c = np.asarray(cell, dtype=np.uint32).ravel()
+    sc = np.minimum(np.asarray(site_comp, dtype=np.uint64), n_comp).astype(np.int64)
+    S = len(sc)
+    order = np.argsort(sc, kind="stable").astype(np.uint32)      # sites by (component, id)
+    rank = np.empty(S, dtype=np.int64)
+    rank[order] = np.arange(S)
+    placed = np.flatnonzero(c < S)
+    key = rank[c[placed]]
+    perm = placed[np.argsort(key, kind="stable")].astype(np.uint32)  # by cell rank, then index
+    per_cell = np.bincount(key, minlength=S)
+    cell_off = np.concatenate([[0], np.cumsum(per_cell)]).astype(np.uint32)
+    first_rank = np.concatenate([[0], np.cumsum(np.bincount(sc, minlength=n_comp + 1))])[: n_comp + 1]
+    comp_off = cell_off[first_rank].astype(np.uint32)
+    cb = np.asarray(comp_band, dtype=np.int64)
+    first_comp = np.searchsorted(cb, np.arange(n_bands + 1), side="left")
+    band_off = comp_off[first_comp].astype(np.uint32)
+    return Layout(perm, order, cell_off, comp_off, band_off)
+
+
+def extract(variables: np.ndarray, perm) -> np.ndarray:
+    """out[j][k] = variables[j].flat[perm[k]]."""
+    x = np.asarray(variables)
+    return x.reshape(x.shape[0], -1)[:, np.asarray(perm, dtype=np.int64)]

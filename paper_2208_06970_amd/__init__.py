@@ -34,7 +34,8 @@ STATS_COV = 2
 EXPORTS = (
     "lsrvt_status_string", "lsrvt_version", "lsrvt_isobands", "lsrvt_components_workspace",
     "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
-    "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_timing_enable", "lsrvt_timing_read",
+    "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract",
+    "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
 
@@ -92,11 +93,16 @@ def _lib():
         lib.lsrvt_aggregate.argtypes = [P, Dims, P, P, u32, P, u32, i32, P, i32, P, i32, u32,
                                         ctypes.POINTER(CellStatsC), ctypes.POINTER(GroupStatsC),
                                         ctypes.POINTER(GroupStatsC), P, S, P]
+        lib.lsrvt_layout_workspace.argtypes = [Dims, u32, u32]
+        lib.lsrvt_layout_workspace.restype = S
+        lib.lsrvt_layout.argtypes = [P, Dims, P, u32, P, u32, i32, P, P, P, P, P, ctypes.POINTER(u32), P, S, P]
+        lib.lsrvt_extract.argtypes = [P, i32, Dims, P, u32, P, P]
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
-                     "lsrvt_aggregate", "lsrvt_timing_enable", "lsrvt_timing_read"):
+                     "lsrvt_aggregate", "lsrvt_layout", "lsrvt_extract", "lsrvt_timing_enable",
+                     "lsrvt_timing_read"):
             getattr(lib, name).restype = i32
         _LIB = lib
     return _LIB
@@ -372,8 +378,58 @@ def lsrvt_aggregate(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int
     return out
 
 
+@dataclass
+class Layout:
+    perm: "object"        # int32[n_placed] voxel linear indices in layout order
+    site_order: "object"  # int32[S] site of the k-th cell
+    cell_off: "object"    # int32[S + 1]
+    comp_off: "object"    # int32[n_comp + 1]
+    band_off: "object"    # int32[n_bands + 1]
+    n_placed: int
+
+
+def lsrvt_layout(cell, site_comp, comp_band, n_comp: int, n_bands: int, ws: Workspace | None = None,
+                 stream=None) -> Layout:
+    """Structured hierarchical layout: placed voxels sorted by (band, component, cell, index)."""
+    torch = _torch()
+    _need(cell, torch.int32, "lsrvt_layout")
+    _need(site_comp, torch.int32, "lsrvt_layout")
+    _need(comp_band, torch.uint8, "lsrvt_layout")
+    lib = _lib()
+    dims = _dims(cell.shape)
+    dev = cell.device
+    S = site_comp.numel()
+    perm = torch.empty(cell.numel(), dtype=torch.int32, device=dev)
+    order = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    cell_off = torch.empty(S + 1, dtype=torch.int32, device=dev)
+    comp_off = torch.empty(n_comp + 1, dtype=torch.int32, device=dev)
+    band_off = torch.empty(n_bands + 1, dtype=torch.int32, device=dev)
+    placed = ctypes.c_uint32()
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_layout_workspace(dims, S, n_comp))
+    code = lib.lsrvt_layout(_ptr(cell), dims, _ptr(site_comp), S, _ptr(comp_band), n_comp, n_bands, _ptr(perm),
+                            _ptr(order), _ptr(cell_off), _ptr(comp_off), _ptr(band_off), ctypes.byref(placed), wptr,
+                            wbytes, _stream(stream))
+    _check(code, "lsrvt_layout")
+    return Layout(perm[:placed.value], order[:S], cell_off, comp_off, band_off, int(placed.value))
+
+
+def lsrvt_extract(variables, perm, out=None, stream=None):
+    """Raw variables in layout order: out[j][k] = variables[j].flat[perm[k]]."""
+    torch = _torch()
+    _need(variables, torch.float32, "lsrvt_extract")
+    _need(perm, torch.int32, "lsrvt_extract")
+    m = int(variables.shape[0])
+    dims = _dims(variables.shape[1:])
+    k = perm.numel()
+    if out is None:
+        out = torch.empty((m, k), dtype=torch.float32, device=variables.device)
+    _check(_lib().lsrvt_extract(_ptr(variables), m, dims, _ptr(perm), k, _ptr(out), _stream(stream)), "lsrvt_extract")
+    return out
+
+
 def lsrvt_timing_enable(enable: bool = True) -> None:
-    """Bracket every Voronoi round-kernel launch with a hipEvent pair (benchmarks)."""
+    """Bracket every Voronoi level-kernel launch with a hipEvent pair (benchmarks)."""
     _check(_lib().lsrvt_timing_enable(1 if enable else 0), "lsrvt_timing_enable")
 
 

@@ -2,25 +2,24 @@
 // "Aggregation"; the hierarchy of Sec. 3.2.4 / Fig. 5).
 //
 // Pipeline:
-//  1. one pass over the cells: voxel count and bounding box of every cell
-//     (wave-aggregated atomics along rows);
-//  2. every cell's bounding box is cut into work items of whole box rows
-//     (about kItemVoxels voxels each; giant cells get many items);
-//  3. one workgroup per item walks its rows, compacts the voxels that belong
-//     to the cell into LDS, and accumulates, per "unit", float32 sums with an
-//     error-free two-sum compensation (hi + lo) of the values shifted by the
-//     value at the cell's site: units are sum d_j and sum d_j d_k (the product
-//     error of d_j d_k is folded into lo with an FMA).  Lanes own units, so
-//     the order of every sum is fixed.  Histograms and extrema are integer /
-//     compare operations and go through LDS and then global atomics;
+//  1. the structured layout (layout.hip) lists the voxels of every cell as
+//     one contiguous range, cells in (component, site id) order and voxels
+//     in index order;
+//  2. every cell's range is cut into work items of at most kItemVoxels;
+//  3. one workgroup per item gathers the item's values into LDS, shifted by
+//     the value at the cell's site, and accumulates per "unit" float32 sums
+//     with an error-free two-sum compensation (hi + lo): units are sum d_j
+//     and sum d_j d_k (the product error of d_j d_k is folded into lo with
+//     an FMA).  Lanes own units, so the order of every sum is fixed.
+//     Histograms and extrema are integer / compare operations and go through
+//     LDS and then global atomics;
 //  4. per cell, the item partials are combined in item order; mean, M2 and
 //     co-moments are formed in float32 (cell outputs) and expanded to
 //     float64 for the merges;
 //  5. Chan et al.'s pairwise merge in float64: cells of a component in site
-//     id order (sites sorted by component with a stable LSD radix sort), then
-//     components of a band in component id order.  Counts, extrema and
-//     histograms merge exactly with atomics.
-#include "common.h"
+//     id order, then components of a band in component id order.  Counts,
+//     extrema and histograms merge exactly with atomics.
+#include "layout.h"
 
 namespace lsrvt {
 
@@ -29,7 +28,7 @@ namespace {
 constexpr int kAggThreads = 256;
 constexpr int kMaxVars = 32;
 constexpr int kMaxPairs = kMaxVars * (kMaxVars + 1) / 2;
-constexpr int64_t kItemVoxels = 8192;
+constexpr int64_t kItemVoxels = 4096;
 constexpr int kMaxHist = 8192;  // n_vars * n_bins
 
 struct Pairs {
@@ -56,129 +55,51 @@ __device__ __forceinline__ void acc(float &hi, float &lo, float x, float ex) {
 }
 
 // ---------------------------------------------------------------------------
-// 1. counts and bounding boxes: one workgroup per 64x8x8 tile, runs of equal
-// cell id along x, an LDS hash table per tile, one set of global atomics per
-// distinct cell in the tile.
-constexpr int TX = 64, TY = 8, TZ = 8;
-constexpr int kTabCap = 512;
-
-
-__global__ __launch_bounds__(256) void k_agg_bbox(const uint32_t *__restrict__ cell, Geom g, uint32_t S,
-                                                  unsigned long long *cnt, BBox bb) {
-  __shared__ uint32_t tkey[kTabCap], tn[kTabCap], tx0[kTabCap], tx1[kTabCap], ty0[kTabCap], ty1[kTabCap],
-      tz0[kTabCap], tz1[kTabCap];
-  const int t = threadIdx.x;
-  const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
-  const int64_t ntiles = (int64_t)ntx * nty * ntz;
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    for (int i = t; i < kTabCap; i += 256) {
-      tkey[i] = kNone;
-      tn[i] = 0;
-      tx0[i] = ty0[i] = tz0[i] = 0xFFFFFFFFu;
-      tx1[i] = ty1[i] = tz1[i] = 0;
-    }
-    __syncthreads();
-    const int ttx = (int)(tile % ntx), tty = (int)((tile / ntx) % nty), ttz = (int)(tile / ((int64_t)ntx * nty));
-    const int qx = (t & 3) * 16, ly = (t >> 2) & 7, lz = t >> 5;
-    const int x0 = ttx * TX + qx;
-    const uint32_t y = (uint32_t)(tty * TY + ly), z = (uint32_t)(ttz * TZ + lz);
-    if ((int)y < g.ny && (int)z < g.nz && x0 < g.nx) {
-      const int64_t base = (int64_t)g.nx * (y + (int64_t)g.ny * z);
-      const int xe = x0 + 16 < g.nx ? x0 + 16 : g.nx;
-      uint32_t rc = kNone, rs = 0;
-      auto flush = [&](uint32_t xend) {
-        if (rc < S) {
-          int sl = lds_slot<kTabCap>(tkey, rc);
-          if (sl >= 0) {
-            atomicAdd(&tn[sl], xend - rs);
-            atomicMin(&tx0[sl], rs);
-            atomicMax(&tx1[sl], xend - 1);
-            atomicMin(&ty0[sl], y);
-            atomicMax(&ty1[sl], y);
-            atomicMin(&tz0[sl], z);
-            atomicMax(&tz1[sl], z);
-          } else {
-            atomicAdd(&cnt[rc], (unsigned long long)(xend - rs));
-            atomicMin(&bb.x0[rc], rs);
-            atomicMax(&bb.x1[rc], xend - 1);
-            atomicMin(&bb.y0[rc], y);
-            atomicMax(&bb.y1[rc], y);
-            atomicMin(&bb.z0[rc], z);
-            atomicMax(&bb.z1[rc], z);
-          }
-        }
-      };
-      for (int x = x0; x < xe; ++x) {
-        uint32_t c = cell[base + x];
-        if (c != rc) {
-          flush((uint32_t)x);
-          rc = c;
-          rs = (uint32_t)x;
-        }
-      }
-      flush((uint32_t)xe);
-    }
-    __syncthreads();
-    for (int i = t; i < kTabCap; i += 256) {
-      uint32_t c = tkey[i];
-      if (c != kNone) {
-        atomicAdd(&cnt[c], (unsigned long long)tn[i]);
-        atomicMin(&bb.x0[c], tx0[i]);
-        atomicMax(&bb.x1[c], tx1[i]);
-        atomicMin(&bb.y0[c], ty0[i]);
-        atomicMax(&bb.y1[c], ty1[i]);
-        atomicMin(&bb.z0[c], tz0[i]);
-        atomicMax(&bb.z1[c], tz1[i]);
-      }
-    }
-    __syncthreads();
-  }
+// 1-2. the voxels of every cell are a contiguous range of the structured
+// layout (layout.hip); each cell's range is cut into items of at most
+// kItemVoxels voxels, numbered in cell rank order.
+__global__ void k_agg_items(const uint32_t *__restrict__ cnt_rank, uint32_t S, uint32_t *items) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < S) items[r] = (uint32_t)((cnt_rank[r] + kItemVoxels - 1) / kItemVoxels);
 }
 
-// 2. items per cell: whole bounding-box rows, about `target` voxels per item
-__global__ void k_agg_items(const unsigned long long *__restrict__ cnt, BBox bb, uint32_t S, int64_t target,
-                            uint32_t *items, uint32_t *rows_per_item) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  if (cnt[s] == 0) {
-    items[s] = 0;
-    rows_per_item[s] = 1;
-    return;
-  }
-  int64_t lx = (int64_t)bb.x1[s] - bb.x0[s] + 1;
-  int64_t rows = ((int64_t)bb.y1[s] - bb.y0[s] + 1) * ((int64_t)bb.z1[s] - bb.z0[s] + 1);
-  int64_t rpi = target / lx;
-  if (rpi < 1) rpi = 1;
-  if (rpi > rows) rpi = rows;
-  items[s] = (uint32_t)((rows + rpi - 1) / rpi);
-  rows_per_item[s] = (uint32_t)rpi;
-}
-
-__global__ void k_item_cells(const uint32_t *__restrict__ item_off, uint32_t S, uint32_t *item_cell) {
-  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  for (uint32_t i = item_off[s]; i < item_off[s + 1]; ++i) item_cell[i] = s;
+__global__ void k_item_cells(const uint32_t *__restrict__ item_off, uint32_t S, uint32_t *item_rank) {
+  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S) return;
+  for (uint32_t i = item_off[r]; i < item_off[r + 1]; ++i) item_rank[i] = r;
 }
 
 // 3. per-item compensated sums
 struct CellArgs {
-  const uint32_t *cell;
-  Geom g;
-  uint32_t S;
+  const uint32_t *perm;       // layout order of the voxels
+  const uint32_t *cell_off;   // [S + 1] by rank
+  const uint32_t *order;      // rank -> site
   const uint32_t *sites;
   const float *vars;  // [m][N]
   const float *edges; // [m][B+1] or null
-  int m, B, U, G, P;
+  int64_t n;
+  int m, B, U, G, P, tile;  // tile: voxels staged in LDS per round (multiple of 256, at most 1024)
   Pairs pairs;
-  BBox bb;
-  const uint32_t *item_off;  // [S + 1]
-  const uint32_t *item_cell; // [n_items]
-  const uint32_t *rows_per_item;
+  const uint32_t *item_off;   // [S + 1] by rank
+  const uint32_t *item_rank;  // [n_items]
   uint32_t n_items;
   float *part_hi, *part_lo;  // [n_items][U]
   uint32_t *hist;            // cell histograms [S][m][B] (zeroed) or null
   uint32_t *kmin, *kmax;     // ordered keys [S][m]
 };
+
+constexpr int kMaxVPT = 4;  // voxels per thread and round
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, kWave));
+  return v;
+}
 
 // R = unit slots per lane: with R == 1 the U units are replicated over
 // G = 256 / U lane groups that split the voxels; with R > 1 (more units than
@@ -186,124 +107,119 @@ struct CellArgs {
 template <int R>
 __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
   extern __shared__ uint8_t smem[];
-  const int m = A.m, B = A.B, U = A.U, G = A.G;
-  float *vals = reinterpret_cast<float *>(smem);                           // [m][256]
-  uint32_t *hist_l = reinterpret_cast<uint32_t *>(vals + m * kAggThreads);  // [m*B]
-  uint32_t *kmin_l = hist_l + m * B;                                        // [m]
-  uint32_t *kmax_l = kmin_l + m;                                            // [m]
-  float *K = reinterpret_cast<float *>(kmax_l + m);                         // [m]
-  float *ph = K + m;                                                        // [G*U]
-  float *pl = ph + G * U;                                                   // [G*U]
-  float *edg = pl + G * U;                                                  // [m][B+1]
-  __shared__ uint32_t wcnt[4];
-  __shared__ uint32_t s_ntile;
+  const int m = A.m, B = A.B, U = A.U, G = A.G, TL = A.tile, ld = A.tile + 1;
+  float *dv = reinterpret_cast<float *>(smem);                       // [m][TL + 1] values minus the site value
+  uint32_t *hist_l = reinterpret_cast<uint32_t *>(dv + m * ld);      // [m*B]
+  uint32_t *kmin_l = hist_l + m * B;                                 // [m]
+  uint32_t *kmax_l = kmin_l + m;                                     // [m]
+  float *K = reinterpret_cast<float *>(kmax_l + m);                  // [m]
+  float *ph = K + m;                                                 // [G*U]
+  float *pl = ph + G * U;                                            // [G*U]
+  float *edg = pl + G * U;                                           // [m][B+1]
   const int t = threadIdx.x;
-  const int wid = t / kWave;
+  const int lane = lane_id();
   const int grp = R == 1 ? t / U : 0;
-  const Geom g = A.g;
   if (B > 0)
     for (int i = t; i < m * (B + 1); i += kAggThreads) edg[i] = A.edges[i];
 
   for (uint32_t item = blockIdx.x; item < A.n_items; item += gridDim.x) {
-    const uint32_t s = A.item_cell[item];
-    const uint32_t part = item - A.item_off[s];
-    const int64_t x0 = A.bb.x0[s], y0 = A.bb.y0[s], z0 = A.bb.z0[s];
-    const int64_t lx = (int64_t)A.bb.x1[s] - x0 + 1, ly = (int64_t)A.bb.y1[s] - y0 + 1;
-    const int64_t rows = ly * ((int64_t)A.bb.z1[s] - z0 + 1);
-    const int64_t rpi = A.rows_per_item[s];
-    const int64_t r0 = (int64_t)part * rpi;
-    const int64_t r1 = r0 + rpi < rows ? r0 + rpi : rows;
-    const int64_t span = (r1 - r0) * lx;
+    const uint32_t r = A.item_rank[item];
+    const uint32_t s = A.order[r];
+    const uint32_t part = item - A.item_off[r];
+    const uint32_t start = A.cell_off[r] + part * (uint32_t)kItemVoxels;
+    const uint32_t stop = min(A.cell_off[r + 1], start + (uint32_t)kItemVoxels);
 
     for (int i = t; i < m * B; i += kAggThreads) hist_l[i] = 0;
     if (t < m) {
       kmin_l[t] = 0xFFFFFFFFu;
       kmax_l[t] = 0u;
-      K[t] = A.vars[(int64_t)t * g.n + A.sites[s]];
+      K[t] = A.vars[(int64_t)t * A.n + A.sites[s]];
     }
     float hi[R], lo[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) hi[r] = lo[r] = 0.0f;
+    for (int q = 0; q < R; ++q) hi[q] = lo[q] = 0.0f;
     __syncthreads();
 
-    // walk the item's box rows in tiles of 256 voxels: short rows pack several
-    // rows per tile (lane -> fixed row offset and column), long rows take
-    // several tiles each; all index arithmetic is per tile, in 32 bits
-    const bool packed = lx <= kAggThreads;
-    const int rpt = packed ? kAggThreads / (int)lx : 1;                      // rows per tile
-    const int cpr = packed ? 1 : (int)((lx + kAggThreads - 1) / kAggThreads);  // tiles per row
-    const int dr = packed ? t / (int)lx : 0, dx = packed ? t % (int)lx : t;
-    const int64_t ntiles_item = packed ? (r1 - r0 + rpt - 1) / rpt : (r1 - r0) * cpr;
-    for (int64_t ti = 0; ti < ntiles_item; ++ti) {
-      int64_t r;
-      int xo;
-      if (packed) {
-        r = r0 + ti * rpt + dr;
-        xo = dx;
-      } else {
-        r = r0 + ti / cpr;
-        xo = (int)(ti % cpr) * kAggThreads + dx;
+    for (uint32_t base = start; base < stop; base += (uint32_t)TL) {
+      const int nt = (int)min((uint32_t)TL, stop - base);
+      // stage: thread t owns voxels t, t + 256, ... of the round
+      uint32_t vv[kMaxVPT];
+      bool ok[kMaxVPT];
+#pragma unroll
+      for (int i = 0; i < kMaxVPT; ++i) {
+        const int q = t + i * kAggThreads;
+        ok[i] = q < nt;
+        vv[i] = ok[i] ? A.perm[base + q] : 0u;
       }
-      bool match = false;
-      int64_t v = 0;
-      if (dr < rpt && r < r1 && xo < lx) {
-        const uint32_t ru = (uint32_t)r;
-        const int64_t y = y0 + ru % (uint32_t)ly;
-        const int64_t z = z0 + ru / (uint32_t)ly;
-        v = (x0 + xo) + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-        match = A.cell[v] == s;
-      }
-      uint64_t bal = __ballot(match);
-      if (lane_id() == 0) wcnt[wid] = (uint32_t)__popcll(bal);
-      __syncthreads();
-      uint32_t slot = (uint32_t)__popcll(bal & lanemask_lt());
-      for (int w = 0; w < wid; ++w) slot += wcnt[w];
-      if (t == 0) s_ntile = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-      if (match) {
-        for (int j = 0; j < m; ++j) {
-          float xv = A.vars[(int64_t)j * g.n + v];
-          vals[j * kAggThreads + slot] = xv;
-          uint32_t kk = f2key(xv);
-          atomicMin(&kmin_l[j], kk);
-          atomicMax(&kmax_l[j], kk);
-          if (B > 0) {
+#pragma unroll 2
+      for (int j = 0; j < m; ++j) {
+        const float kj = K[j];
+        const float *col = A.vars + (int64_t)j * A.n;
+        float x[kMaxVPT];
+#pragma unroll
+        for (int i = 0; i < kMaxVPT; ++i) x[i] = ok[i] ? col[vv[i]] : 0.0f;
+        uint32_t kmn = 0xFFFFFFFFu, kmx = 0u;
+#pragma unroll
+        for (int i = 0; i < kMaxVPT; ++i) {
+          if (!ok[i]) continue;
+          dv[j * ld + t + i * kAggThreads] = x[i] - kj;
+          const uint32_t kk = f2key(x[i]);
+          kmn = min(kmn, kk);
+          kmx = max(kmx, kk);
+        }
+        kmn = wave_min_u32(kmn);
+        kmx = wave_max_u32(kmx);
+        if (lane == 0) {
+          if (kmn != 0xFFFFFFFFu) atomicMin(&kmin_l[j], kmn);
+          if (kmx != 0u) atomicMax(&kmax_l[j], kmx);
+        }
+        if (B > 0) {
+          const float *e = edg + j * (B + 1);
+#pragma unroll
+          for (int i = 0; i < kMaxVPT; ++i) {
+            if (i * kAggThreads >= TL) break;
             // bin = #{interior edges e_1..e_{B-1} <= x}: upper bound by bisection
-            const float *e = edg + j * (B + 1);
-            int lo = 1, hi = B;
-            while (lo < hi) {
-              int mid = (lo + hi) >> 1;
-              if (e[mid] <= xv)
-                lo = mid + 1;
-              else
-                hi = mid;
+            int bin = -1;
+            if (ok[i]) {
+              int a = 1, b = B;
+              while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (e[mid] <= x[i])
+                  a = mid + 1;
+                else
+                  b = mid;
+              }
+              bin = a - 1;
             }
-            atomicAdd(&hist_l[j * B + (lo - 1)], 1u);
+            // one LDS atomic per distinct bin of the wave
+            uint64_t rem = __ballot(bin >= 0);
+            while (rem) {
+              const int leader = __ffsll((unsigned long long)rem) - 1;
+              const int b0 = __builtin_amdgcn_readlane(bin, leader);
+              const uint64_t same = __ballot(bin == b0);
+              rem &= ~same;
+              if (lane == leader) atomicAdd(&hist_l[j * B + b0], (uint32_t)__popcll(same));
+            }
           }
         }
       }
       __syncthreads();
-      const uint32_t ntile = s_ntile;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int u = R == 1 ? t % U : t + r * kAggThreads;
+      for (int q = 0; q < R; ++q) {
+        const int u = R == 1 ? t % U : t + q * kAggThreads;
         const bool worker = R == 1 ? t < G * U : u < U;
         if (!worker) continue;
         if (u < m) {
-          const float kj = K[u];
-          for (uint32_t q = grp; q < ntile; q += G) {
-            float d = vals[u * kAggThreads + q] - kj;
-            acc(hi[r], lo[r], d, 0.0f);
-          }
+          const float *du = dv + u * ld;
+          for (int v = grp; v < nt; v += G) acc(hi[q], lo[q], du[v], 0.0f);
         } else {
           const int p = u - m;
-          const int j = A.pairs.j[p], k = A.pairs.k[p];
-          const float kj = K[j], kk = K[k];
-          for (uint32_t q = grp; q < ntile; q += G) {
-            float dj = vals[j * kAggThreads + q] - kj;
-            float dk = vals[k * kAggThreads + q] - kk;
-            float pr = dj * dk;
-            float pe = __builtin_fmaf(dj, dk, -pr);  // exact error of the product
-            acc(hi[r], lo[r], pr, pe);
+          const float *dj = dv + A.pairs.j[p] * ld, *dk = dv + A.pairs.k[p] * ld;
+          for (int v = grp; v < nt; v += G) {
+            const float a = dj[v], b = dk[v];
+            const float pr = a * b;
+            const float pe = __builtin_fmaf(a, b, -pr);  // exact error of the product
+            acc(hi[q], lo[q], pr, pe);
           }
         }
       }
@@ -311,12 +227,12 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
     }
     // combine the lane groups in group order
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int u = R == 1 ? t % U : t + r * kAggThreads;
+    for (int q = 0; q < R; ++q) {
+      const int u = R == 1 ? t % U : t + q * kAggThreads;
       const bool worker = R == 1 ? t < G * U : u < U;
       if (worker) {
-        ph[grp * U + u] = hi[r];
-        pl[grp * U + u] = lo[r];
+        ph[grp * U + u] = hi[q];
+        pl[grp * U + u] = lo[q];
       }
     }
     __syncthreads();
@@ -353,7 +269,8 @@ struct FinArgs {
   const float *vars;
   int64_t n;
   const unsigned long long *cnt;
-  const uint32_t *item_off;
+  const uint32_t *rank;      // site -> cell rank
+  const uint32_t *item_off;  // by rank
   const float *part_hi, *part_lo;
   const uint32_t *kmin, *kmax;
   // outputs
@@ -380,7 +297,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
   const int m = A.m;
   for (uint32_t s = blockIdx.x; s < A.S; s += gridDim.x) {
     const uint64_t n = A.cnt[s];
-    const uint32_t i0 = A.item_off[s], i1 = A.item_off[s + 1];
+    const uint32_t i0 = A.item_off[A.rank[s]], i1 = A.item_off[A.rank[s] + 1];
     for (int u = t; u < A.U; u += kAggThreads) {
       float H = 0.0f, Lo = 0.0f;
       for (uint32_t it = i0; it < i1; ++it) {
@@ -629,11 +546,7 @@ __global__ __launch_bounds__(256) void k_chan_big(MergeArgs A) {
   }
 }
 
-// helpers for sorting sites by component
-__global__ void k_digit(const uint32_t *key, uint32_t n, int shift, uint8_t *digit) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) digit[i] = (uint8_t)(key[i] >> shift);
-}
+// helpers for ordering components by band
 __global__ void k_permute(const uint32_t *key, const uint32_t *val, const uint32_t *pos, uint32_t n, uint32_t *key_out,
                           uint32_t *val_out) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -642,49 +555,38 @@ __global__ void k_permute(const uint32_t *key, const uint32_t *val, const uint32
     val_out[pos[i]] = val[i];
   }
 }
-__global__ void k_init_sort(const uint32_t *site_comp, uint32_t S, uint32_t n_comp, uint32_t *key, uint32_t *val,
-                            uint32_t *count) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < S) {
-    uint32_t c = site_comp[i];
-    if (c > n_comp) c = n_comp;  // out-of-range components collect in a last, unmerged group
-    key[i] = c;
-    val[i] = i;
-    atomicAdd(&count[c], 1u);
-  }
-}
 __global__ void k_iota(uint32_t *p, uint32_t n) {
   uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = i;
 }
 
 struct AggWork {
-  unsigned long long *cnt, *cnt_c, *cnt_b;
-  uint32_t *bbox;  // 6 x S
-  uint32_t *items, *rpi, *item_off;
+  LayoutWork lay;
+  uint32_t *perm;  // [N]
+  unsigned long long *cnt_c, *cnt_b;
+  uint32_t *items, *item_off;
   float *part_hi, *part_lo;
   uint32_t *kmin, *kmax, *kmin_c, *kmax_c, *kmin_b, *kmax_b;
   double *mean64, *c64, *mean64_c, *c64_c, *m2tmp_c, *mean64_b, *c64_b, *m2tmp_b;
-  uint32_t *key_a, *val_a, *key_b, *val_b, *key_c, *val_c, *pos, *ccount, *coff, *corder, *bucket;
-  uint8_t *digit;
-  uint32_t *item_cell, *big, *big_cnt;
+  uint32_t *key_b, *val_b, *pos, *corder, *bucket;
+  uint32_t *item_rank, *big, *big_cnt;
   void *scratch;
   size_t scratch_bytes;
   int64_t item_cap;
 };
 
-int64_t item_capacity(const Geom &g, uint32_t S) { return (int64_t)S + 4 * (g.n / kItemVoxels) + 1024; }
+// Items: one per started kItemVoxels of every cell.
+int64_t item_capacity(const Geom &g, uint32_t S) { return (int64_t)S + g.n / kItemVoxels + 1; }
 
 template <class A>
 void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_bands, int m, int U, int P, AggWork *W) {
   size_t s1 = S ? S : 1, c1 = n_comp + 2, b1 = (size_t)n_bands + 1;
   int64_t ic = item_capacity(g, S);
-  auto cnt = a.template take<unsigned long long>(s1);
+  layout_take(a, g, S, n_comp, W ? &W->lay : nullptr);
+  auto perm = a.template take<uint32_t>(g.n);
   auto cnt_c = a.template take<unsigned long long>(c1);
   auto cnt_b = a.template take<unsigned long long>(b1);
-  auto bbox = a.template take<uint32_t>(6 * s1);
   auto items = a.template take<uint32_t>(s1);
-  auto rpi = a.template take<uint32_t>(s1);
   auto ioff = a.template take<uint32_t>(s1 + 1);
   auto ph = a.template take<float>(ic * U);
   auto pl = a.template take<float>(ic * U);
@@ -702,29 +604,19 @@ void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_band
   auto mean64b = a.template take<double>(b1 * m);
   auto c64b = a.template take<double>(b1 * P);
   auto m2b = a.template take<double>(b1 * m);
-  size_t sortn = s1 > c1 ? s1 : c1;
-  auto ka = a.template take<uint32_t>(sortn);
-  auto va = a.template take<uint32_t>(sortn);
-  auto kb = a.template take<uint32_t>(sortn);
-  auto vb = a.template take<uint32_t>(sortn);
-  auto kc = a.template take<uint32_t>(sortn);
-  auto vc = a.template take<uint32_t>(sortn);
-  auto pos = a.template take<uint32_t>(sortn);
-  auto ccount = a.template take<uint32_t>(c1 + 1);
-  auto coff = a.template take<uint32_t>(c1 + 2);
+  auto kb = a.template take<uint32_t>(c1);
+  auto vb = a.template take<uint32_t>(c1);
+  auto pos = a.template take<uint32_t>(c1);
   auto corder = a.template take<uint32_t>(c1);
   auto bucket = a.template take<uint32_t>(257);
-  auto digit = a.template take<uint8_t>(sortn);
-  auto icell = a.template take<uint32_t>(ic);
+  auto irank = a.template take<uint32_t>(ic);
   auto big = a.template take<uint32_t>(c1 > b1 ? c1 : b1);
   auto bigc = a.template take<uint32_t>(4);
   if (W) {
-    W->cnt = cnt;
+    W->perm = perm;
     W->cnt_c = cnt_c;
     W->cnt_b = cnt_b;
-    W->bbox = bbox;
     W->items = items;
-    W->rpi = rpi;
     W->item_off = ioff;
     W->part_hi = ph;
     W->part_lo = pl;
@@ -742,19 +634,12 @@ void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_band
     W->mean64_b = mean64b;
     W->c64_b = c64b;
     W->m2tmp_b = m2b;
-    W->key_a = ka;
-    W->val_a = va;
     W->key_b = kb;
     W->val_b = vb;
-    W->key_c = kc;
-    W->val_c = vc;
     W->pos = pos;
-    W->ccount = ccount;
-    W->coff = coff;
     W->corder = corder;
     W->bucket = bucket;
-    W->digit = digit;
-    W->item_cell = icell;
+    W->item_rank = irank;
     W->big = big;
     W->big_cnt = bigc;
     W->item_cap = ic;
@@ -781,12 +666,14 @@ void units_for(int m, bool cov, int &P, int &U, Pairs &pairs) {
   U = m + P;
 }
 
-size_t scratch_need(uint32_t S, uint32_t n_comp) {
+size_t scratch_need(const Geom &g, uint32_t S, uint32_t n_comp) {
   size_t a = ScanU32::workspace((int64_t)S + 1);
-  size_t b = StableSort8::workspace((int64_t)(S > n_comp + 2 ? S : n_comp + 2));
+  size_t b = StableSort8::workspace((int64_t)n_comp + 2);
   size_t c = ScanU32::workspace((int64_t)n_comp + 2);
+  size_t d = layout_scratch(g, S, n_comp);
   size_t r = a > b ? a : b;
-  return (r > c ? r : c) + 256;
+  r = r > c ? r : c;
+  return (r > d ? r : d) + 256;
 }
 
 }  // namespace
@@ -806,7 +693,7 @@ extern "C" size_t lsrvt_aggregate_workspace(lsrvt_dims dims, uint32_t n_sites, u
   units_for(n_vars, (flags & LSRVT_STATS_COV) != 0, P, U, pairs);
   SizerT z;
   agg_layout(z, g, n_sites, n_comp, n_bands, n_vars, U, P, nullptr);
-  return z.off + scratch_need(n_sites, n_comp);
+  return z.off + scratch_need(g, n_sites, n_comp);
 }
 
 extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t *d_sites,
@@ -851,12 +738,8 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
   const int64_t Pfull = (int64_t)m * (m + 1) / 2;
 
   // zero / identity initialisation
-  if ((rc = fill<unsigned long long>(W.cnt, S ? S : 1, 0ull, s))) return rc;
   if ((rc = fill<unsigned long long>(W.cnt_c, C + 2, 0ull, s))) return rc;
   if ((rc = fill<unsigned long long>(W.cnt_b, n_bands + 1, 0ull, s))) return rc;
-  for (int q = 0; q < 6; ++q)
-    if ((rc = fill<uint32_t>(W.bbox + (size_t)q * (S ? S : 1), S ? S : 1, (q % 2 == 0) ? 0xFFFFFFFFu : 0u, s)))
-      return rc;
   if ((rc = fill<uint32_t>(W.kmin, (int64_t)(S ? S : 1) * m, 0xFFFFFFFFu, s))) return rc;
   if ((rc = fill<uint32_t>(W.kmax, (int64_t)(S ? S : 1) * m, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.kmin_c, (int64_t)(C + 2) * m, 0xFFFFFFFFu, s))) return rc;
@@ -868,47 +751,42 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     if ((rc = fill<uint32_t>(comp->hist, (int64_t)C * m * B, 0u, s))) return rc;
     if ((rc = fill<uint32_t>(band->hist, (int64_t)n_bands * m * B, 0u, s))) return rc;
   }
-  BBox bb{W.bbox, W.bbox + (S ? S : 1), W.bbox + 2 * (size_t)(S ? S : 1), W.bbox + 3 * (size_t)(S ? S : 1),
-          W.bbox + 4 * (size_t)(S ? S : 1), W.bbox + 5 * (size_t)(S ? S : 1)};
 
-  // 1-2. counts, boxes, items
+  // 1. sites in (component, id) order and the voxels of every cell as one range
+  W.lay.scratch = W.scratch;
+  W.lay.scratch_bytes = W.scratch_bytes;
+  if ((rc = layout_sites(d_site_comp, S, C, W.lay, s))) return rc;
+  if ((rc = layout_voxels(d_cell, g, S, W.lay, W.perm, s))) return rc;
+
+  // 2. items
   uint32_t n_items = 0;
   if (S) {
-    const int64_t ntiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
-    hipLaunchKernelGGL(k_agg_bbox, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(256), 0, s, d_cell, g, S,
-                       W.cnt, bb);
+    hipLaunchKernelGGL(k_agg_items, dim3((S + 255) / 256), dim3(256), 0, s, W.lay.cnt_rank, S, W.items);
     LSRVT_LAUNCHED();
-    int64_t target = kItemVoxels;
-    while (true) {
-      hipLaunchKernelGGL(k_agg_items, dim3((S + 255) / 256), dim3(256), 0, s, W.cnt, bb, S, target, W.items, W.rpi);
-      LSRVT_LAUNCHED();
-      if ((rc = ScanU32::run(W.items, S, W.item_off, W.scratch, W.scratch_bytes, s))) return rc;
-      LSRVT_HIP(hipMemcpyAsync(&n_items, W.item_off + S, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-      LSRVT_HIP(hipStreamSynchronize(s));
-      if ((int64_t)n_items <= W.item_cap) break;
-      target *= 2;
-    }
+    if ((rc = ScanU32::run(W.items, S, W.item_off, W.scratch, W.scratch_bytes, s))) return rc;
+    LSRVT_HIP(hipMemcpyAsync(&n_items, W.item_off + S, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    if ((int64_t)n_items > W.item_cap) return LSRVT_EDEVICE;  // cannot happen: the capacity is an upper bound
   }
 
   // 3. per-item sums
   if (n_items) {
-    hipLaunchKernelGGL(k_item_cells, dim3((S + 255) / 256), dim3(256), 0, s, W.item_off, S, W.item_cell);
+    hipLaunchKernelGGL(k_item_cells, dim3((S + 255) / 256), dim3(256), 0, s, W.item_off, S, W.item_rank);
     CellArgs A;
-    A.cell = d_cell;
-    A.g = g;
-    A.S = S;
+    A.perm = W.perm;
+    A.cell_off = W.lay.cell_off;
+    A.order = W.lay.order;
     A.sites = d_sites;
     A.vars = d_vars;
     A.edges = d_edges;
+    A.n = g.n;
     A.m = m;
     A.B = B;
     A.U = U;
     A.P = P;
     A.pairs = pairs;
-    A.bb = bb;
     A.item_off = W.item_off;
-    A.item_cell = W.item_cell;
-    A.rows_per_item = W.rpi;
+    A.item_rank = W.item_rank;
     A.n_items = n_items;
     A.part_hi = W.part_hi;
     A.part_lo = W.part_lo;
@@ -917,10 +795,16 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     A.kmax = W.kmax;
     const int R = (U + kAggThreads - 1) / kAggThreads;
     A.G = R == 1 ? kAggThreads / U : 1;
-    size_t lds = sizeof(float) * ((size_t)m * kAggThreads + (size_t)m * B + 3 * m + 2 * (size_t)A.G * U +
-                                  (size_t)m * (B + 1));
+    // the largest staging round that keeps the workgroup within 48 KiB of LDS
+    const size_t fixed = sizeof(float) * ((size_t)m * B + 3 * m + 2 * (size_t)A.G * U + (size_t)m * (B + 1));
+    size_t lds = 0;
+    for (int tl = kMaxVPT * kAggThreads; tl >= kAggThreads; tl /= 2) {
+      A.tile = tl;
+      lds = fixed + sizeof(float) * (size_t)m * (tl + 1);
+      if (lds <= 49152) break;
+    }
     if (lds > 65536 || R > 3) return LSRVT_EINVAL;
-    unsigned grid = n_items < 16384 ? n_items : 16384;
+    unsigned grid = n_items < 65535 ? n_items : 65535;
     if (R == 1)
       hipLaunchKernelGGL(k_agg_cell<1>, dim3(grid), dim3(kAggThreads), lds, s, A);
     else if (R == 2)
@@ -941,7 +825,8 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     F.sites = d_sites;
     F.vars = d_vars;
     F.n = g.n;
-    F.cnt = W.cnt;
+    F.cnt = W.lay.cnt;
+    F.rank = W.lay.rank;
     F.item_off = W.item_off;
     F.part_hi = W.part_hi;
     F.part_lo = W.part_lo;
@@ -1016,39 +901,17 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     return LSRVT_OK;
   };
 
-  // 5b. sites sorted by component (stable in site id), then the cell -> component merge
+  // 5b. the cell -> component merge, cells of a component in site id order
   if (C) {
-    if ((rc = fill<uint32_t>(W.ccount, C + 2, 0u, s))) return rc;
     if (S) {
-      hipLaunchKernelGGL(k_init_sort, dim3((S + 255) / 256), dim3(256), 0, s, d_site_comp, S, C, W.key_a, W.val_a,
-                         W.ccount);
-      LSRVT_LAUNCHED();
-      int passes = 1;
-      while (passes < 4 && ((uint64_t)C >> (8 * passes)) != 0) ++passes;
-      uint32_t *ka = W.key_a, *va = W.val_a, *kb = W.key_b, *vb = W.val_b;
-      for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL(k_digit, dim3((S + 255) / 256), dim3(256), 0, s, ka, S, 8 * p, W.digit);
-        LSRVT_LAUNCHED();
-        if ((rc = StableSort8::run(W.digit, S, W.pos, nullptr, W.scratch, W.scratch_bytes, s))) return rc;
-        // ping-pong between (key_a, val_a) and (key_c, val_c): key_b/val_b hold the band order
-        uint32_t *ko = (ka == W.key_a) ? W.key_c : W.key_a;
-        uint32_t *vo = (va == W.val_a) ? W.val_c : W.val_a;
-        hipLaunchKernelGGL(k_permute, dim3((S + 255) / 256), dim3(256), 0, s, ka, va, W.pos, S, ko, vo);
-        LSRVT_LAUNCHED();
-        ka = ko;
-        va = vo;
-      }
-      (void)kb;
-      (void)vb;
-      if ((rc = ScanU32::run(W.ccount, C + 1, W.coff, W.scratch, W.scratch_bytes, s))) return rc;
       MergeArgs M;
       M.n_groups = C;
       M.m = m;
       M.P = P;
       M.pairs = pairs;
-      M.order = va;
-      M.off = W.coff;
-      M.in_cnt = W.cnt;
+      M.order = W.lay.order;
+      M.off = W.lay.coff;
+      M.in_cnt = W.lay.cnt;
       M.in_mean = W.mean64;
       M.in_c = W.c64;
       M.out_mean = comp->mean;

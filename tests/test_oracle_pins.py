@@ -395,3 +395,66 @@ def test_mean_ds_decays_like_fig9():
     r = oracle.cvt(cc.comp, seeds, w, 10)
     assert r.mean_ds[0] > 0.5
     assert r.mean_ds[9] < 0.35 * r.mean_ds[0]
+
+
+# ---------------------------------------------------------------------------
+# Structured layout (Sec. 3.2.4, Fig. 5)
+
+def test_layout_hand_example():
+    """Worked by hand: sites 0 and 2 in component 0 (band 0), site 1 in
+    component 1 (band 1); voxel 3 carries a label that is no site and voxel 6
+    is unlabelled, so both are left out."""
+    cell = np.array([1, 0, 0, 5, 1, 2, NONE, 2], dtype=np.uint32)
+    L = oracle.layout(cell, [0, 1, 0], [0, 1], 2, 2)
+    assert L.site_order.tolist() == [0, 2, 1]
+    assert L.perm.tolist() == [1, 2, 5, 7, 0, 4]
+    assert L.cell_off.tolist() == [0, 2, 4, 6]
+    assert L.comp_off.tolist() == [0, 4, 6]
+    assert L.band_off.tolist() == [0, 4, 6]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_layout_against_tuple_sort(seed):
+    """Brute force: sort the placed voxels by the tuple (band, component,
+    site, index) with Python's sort and count the ranges in plain loops."""
+    rng = np.random.default_rng(seed)
+    n, S, C, NB = 300, 17, 5, 4
+    cell = rng.integers(0, S + 3, size=n).astype(np.uint32)
+    cell[rng.random(n) < 0.1] = NONE
+    site_comp = rng.integers(0, C + 1, size=S).astype(np.uint32)  # C = beyond the components
+    comp_band = np.sort(rng.integers(0, NB, size=C)).astype(np.uint8)
+    L = oracle.layout(cell, site_comp, comp_band, C, NB)
+
+    def key(v):
+        s = int(cell[v])
+        c = min(int(site_comp[s]), C)
+        b = int(comp_band[c]) if c < C else NB
+        return (b, c, s, v)
+
+    placed = [v for v in range(n) if cell[v] < S]
+    assert L.perm.tolist() == sorted(placed, key=key)
+    assert sorted(L.site_order.tolist(), key=lambda s: (min(int(site_comp[s]), C), s)) == L.site_order.tolist()
+    assert sorted(L.site_order.tolist()) == list(range(S))
+    for k in range(S):
+        s = int(L.site_order[k])
+        members = [v for v in L.perm[L.cell_off[k]:L.cell_off[k + 1]]]
+        assert members == sorted(v for v in placed if cell[v] == s)
+    for c in range(C):
+        seg = L.perm[L.comp_off[c]:L.comp_off[c + 1]].tolist()
+        assert seg == sorted((v for v in placed if site_comp[cell[v]] == c), key=key)
+    for b in range(NB):
+        seg = L.perm[L.band_off[b]:L.band_off[b + 1]].tolist()
+        assert seg == sorted((v for v in placed if site_comp[cell[v]] < C and comp_band[site_comp[cell[v]]] == b),
+                             key=key)
+
+
+def test_extract_is_gather():
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(3, 2, 3, 4)).astype(np.float32)
+    perm = np.array([5, 0, 23, 7], dtype=np.uint32)
+    out = oracle.extract(x, perm)
+    for j in range(3):
+        for k, v in enumerate(perm):
+            z, r = divmod(int(v), 12)
+            y, xx = divmod(r, 4)
+            assert out[j, k] == x[j, z, y, xx]
