@@ -19,6 +19,8 @@
 //  5. Chan et al.'s pairwise merge in float64: cells of a component in site
 //     id order, then components of a band in component id order.  Counts,
 //     extrema and histograms merge exactly with atomics.
+#include <algorithm>
+
 #include "layout.h"
 
 namespace lsrvt {
@@ -29,6 +31,7 @@ constexpr int kAggThreads = 256;
 constexpr int kMaxVars = 32;
 constexpr int kMaxPairs = kMaxVars * (kMaxVars + 1) / 2;
 constexpr int64_t kItemVoxels = 4096;
+constexpr int kSmallCell = 256;  // cells up to this size are summed by a single wave
 constexpr int kMaxHist = 8192;  // n_vars * n_bins
 
 struct Pairs {
@@ -63,10 +66,40 @@ __global__ void k_agg_items(const uint32_t *__restrict__ cnt_rank, uint32_t S, u
   if (r < S) items[r] = (uint32_t)((cnt_rank[r] + kItemVoxels - 1) / kItemVoxels);
 }
 
-__global__ void k_item_cells(const uint32_t *__restrict__ item_off, uint32_t S, uint32_t *item_rank) {
-  uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= S) return;
-  for (uint32_t i = item_off[r]; i < item_off[r + 1]; ++i) item_rank[i] = r;
+// item -> cell rank, and the split into cells small enough for one wave
+// (their single item) and the items of larger cells
+__global__ void k_item_cells(const uint32_t *__restrict__ item_off, const uint32_t *__restrict__ cnt_rank, uint32_t S,
+                             int small_ok, uint32_t *item_rank, uint32_t *small_list, uint32_t *big_list,
+                             uint32_t *counts) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = r < S;
+  const uint32_t i0 = in ? item_off[r] : 0u, i1 = in ? item_off[r + 1] : 0u;
+  const bool small = in && small_ok && cnt_rank[r] <= (uint32_t)kSmallCell;
+  const uint32_t n = i1 - i0;
+  // one counter atomic per wave and list: wave prefix sums of the item counts
+  const int lane = lane_id();
+  uint32_t ns = small ? n : 0u, nb = small ? 0u : n;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t a = __shfl_up(ns, o, kWave), b = __shfl_up(nb, o, kWave);
+    if (lane >= o) {
+      ns += a;
+      nb += b;
+    }
+  }
+  const uint32_t ts = __shfl(ns, kWave - 1, kWave), tb = __shfl(nb, kWave - 1, kWave);
+  uint32_t bs = 0, bb = 0;
+  if (lane == 0) {
+    if (ts) bs = atomicAdd(&counts[0], ts);
+    if (tb) bb = atomicAdd(&counts[1], tb);
+  }
+  bs = __shfl(bs, 0, kWave);
+  bb = __shfl(bb, 0, kWave);
+  const uint32_t p = small ? bs + ns - n : bb + nb - n;
+  for (uint32_t i = i0; i < i1; ++i) {
+    item_rank[i] = r;
+    (small ? small_list : big_list)[p + (i - i0)] = i;
+  }
 }
 
 // 3. per-item compensated sums
@@ -82,7 +115,8 @@ struct CellArgs {
   Pairs pairs;
   const uint32_t *item_off;   // [S + 1] by rank
   const uint32_t *item_rank;  // [n_items]
-  uint32_t n_items;
+  const uint32_t *list;       // items of this launch
+  const uint32_t *list_cnt;   // their number (device)
   float *part_hi, *part_lo;  // [n_items][U]
   uint32_t *hist;            // cell histograms [S][m][B] (zeroed) or null
   uint32_t *kmin, *kmax;     // ordered keys [S][m]
@@ -122,7 +156,9 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
   if (B > 0)
     for (int i = t; i < m * (B + 1); i += kAggThreads) edg[i] = A.edges[i];
 
-  for (uint32_t item = blockIdx.x; item < A.n_items; item += gridDim.x) {
+  const uint32_t n_list = *A.list_cnt;
+  for (uint32_t k = blockIdx.x; k < n_list; k += gridDim.x) {
+    const uint32_t item = A.list[k];
     const uint32_t r = A.item_rank[item];
     const uint32_t s = A.order[r];
     const uint32_t part = item - A.item_off[r];
@@ -256,6 +292,160 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
       if (kmax_l[t] != 0u) atomicMax(&A.kmax[(int64_t)s * m + t], kmax_l[t]);
     }
     __syncthreads();
+  }
+}
+
+// The same sums for cells of at most kSmallCell voxels, one wave per cell:
+// each wave has its own LDS region and synchronises only with itself.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+__host__ __device__ inline size_t wave_region_words(int m, int B, int U, int G) {
+  return (size_t)m * (kSmallCell + 1) + (size_t)m * B + 3 * (size_t)m + 2 * (size_t)G * U;
+}
+
+template <int R>
+__global__ __launch_bounds__(kAggThreads) void k_agg_cell_wave(CellArgs A) {
+  extern __shared__ uint8_t smem[];
+  constexpr int kWaves = kAggThreads / kWave;
+  constexpr int VPT = kSmallCell / kWave;
+  const int m = A.m, B = A.B, U = A.U, G = A.G, ld = kSmallCell + 1;
+  const int wid = threadIdx.x / kWave, lane = lane_id();
+  float *edg = reinterpret_cast<float *>(smem);  // [m][B+1], shared by the waves
+  float *dv = edg + m * (B + 1) + (size_t)wid * wave_region_words(m, B, U, G);
+  uint32_t *hist_l = reinterpret_cast<uint32_t *>(dv + m * ld);  // [m*B]
+  uint32_t *kmin_l = hist_l + m * B;
+  uint32_t *kmax_l = kmin_l + m;
+  float *K = reinterpret_cast<float *>(kmax_l + m);
+  float *ph = K + m;
+  float *pl = ph + G * U;
+  const int grp = R == 1 ? lane / U : 0;
+  if (B > 0)
+    for (int i = threadIdx.x; i < m * (B + 1); i += kAggThreads) edg[i] = A.edges[i];
+  __syncthreads();
+  const uint32_t n_list = *A.list_cnt;
+  for (uint32_t k = blockIdx.x * kWaves + wid; k < n_list; k += gridDim.x * kWaves) {
+    const uint32_t item = A.list[k];
+    const uint32_t r = A.item_rank[item];
+    const uint32_t s = A.order[r];
+    const uint32_t start = A.cell_off[r];
+    const int nt = (int)(A.cell_off[r + 1] - start);
+    for (int i = lane; i < m * B; i += kWave) hist_l[i] = 0;
+    for (int j = lane; j < m; j += kWave) K[j] = A.vars[(int64_t)j * A.n + A.sites[s]];
+    wave_sync();
+    uint32_t vv[VPT];
+    bool ok[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+      const int q = lane + i * kWave;
+      ok[i] = q < nt;
+      vv[i] = ok[i] ? A.perm[start + q] : 0u;
+    }
+#pragma unroll 2
+    for (int j = 0; j < m; ++j) {
+      const float kj = K[j];
+      const float *col = A.vars + (int64_t)j * A.n;
+      float x[VPT];
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) x[i] = ok[i] ? col[vv[i]] : 0.0f;
+      uint32_t kmn = 0xFFFFFFFFu, kmx = 0u;
+#pragma unroll
+      for (int i = 0; i < VPT; ++i) {
+        if (!ok[i]) continue;
+        dv[j * ld + lane + i * kWave] = x[i] - kj;
+        const uint32_t kk = f2key(x[i]);
+        kmn = min(kmn, kk);
+        kmx = max(kmx, kk);
+      }
+      kmn = wave_min_u32(kmn);
+      kmx = wave_max_u32(kmx);
+      if (lane == 0) {
+        kmin_l[j] = kmn;
+        kmax_l[j] = kmx;
+      }
+      if (B > 0) {
+        const float *e = edg + j * (B + 1);
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+          if (i * kWave >= nt) break;
+          int bin = -1;
+          if (ok[i]) {
+            int a = 1, b = B;
+            while (a < b) {
+              const int mid = (a + b) >> 1;
+              if (e[mid] <= x[i])
+                a = mid + 1;
+              else
+                b = mid;
+            }
+            bin = a - 1;
+          }
+          uint64_t rem = __ballot(bin >= 0);
+          while (rem) {
+            const int leader = __ffsll((unsigned long long)rem) - 1;
+            const int b0 = __builtin_amdgcn_readlane(bin, leader);
+            const uint64_t same = __ballot(bin == b0);
+            rem &= ~same;
+            if (lane == leader) hist_l[j * B + b0] += (uint32_t)__popcll(same);
+            wave_sync();
+          }
+        }
+      }
+    }
+    wave_sync();
+    float hi[R], lo[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      hi[q] = lo[q] = 0.0f;
+      const int u = R == 1 ? lane % U : lane + q * kWave;
+      const bool worker = R == 1 ? lane < G * U : u < U;
+      if (!worker) continue;
+      if (u < m) {
+        const float *du = dv + u * ld;
+        for (int v = grp; v < nt; v += G) acc(hi[q], lo[q], du[v], 0.0f);
+      } else {
+        const int p = u - m;
+        const float *dj = dv + A.pairs.j[p] * ld, *dk = dv + A.pairs.k[p] * ld;
+        for (int v = grp; v < nt; v += G) {
+          const float a = dj[v], b = dk[v];
+          const float pr = a * b;
+          const float pe = __builtin_fmaf(a, b, -pr);
+          acc(hi[q], lo[q], pr, pe);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int u = R == 1 ? lane % U : lane + q * kWave;
+      const bool worker = R == 1 ? lane < G * U : u < U;
+      if (worker) {
+        ph[grp * U + u] = hi[q];
+        pl[grp * U + u] = lo[q];
+      }
+    }
+    wave_sync();
+    for (int u = lane; u < U; u += kWave) {
+      float H = 0.0f, Lo = 0.0f;
+      for (int gg = 0; gg < G; ++gg) {
+        acc(H, Lo, ph[gg * U + u], 0.0f);
+        Lo += pl[gg * U + u];
+      }
+      A.part_hi[(int64_t)item * U + u] = H;
+      A.part_lo[(int64_t)item * U + u] = Lo;
+    }
+    if (A.hist) {
+      uint32_t *dst = A.hist + (int64_t)s * m * B;
+      for (int i = lane; i < m * B; i += kWave)
+        if (hist_l[i]) atomicAdd(&dst[i], hist_l[i]);
+    }
+    for (int j = lane; j < m; j += kWave) {
+      if (kmin_l[j] != 0xFFFFFFFFu) atomicMin(&A.kmin[(int64_t)s * m + j], kmin_l[j]);
+      if (kmax_l[j] != 0u) atomicMax(&A.kmax[(int64_t)s * m + j], kmax_l[j]);
+    }
+    wave_sync();
   }
 }
 
@@ -569,7 +759,7 @@ struct AggWork {
   uint32_t *kmin, *kmax, *kmin_c, *kmax_c, *kmin_b, *kmax_b;
   double *mean64, *c64, *mean64_c, *c64_c, *m2tmp_c, *mean64_b, *c64_b, *m2tmp_b;
   uint32_t *key_b, *val_b, *pos, *corder, *bucket;
-  uint32_t *item_rank, *big, *big_cnt;
+  uint32_t *item_rank, *small_list, *big_list, *big, *big_cnt;
   void *scratch;
   size_t scratch_bytes;
   int64_t item_cap;
@@ -610,6 +800,8 @@ void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_band
   auto corder = a.template take<uint32_t>(c1);
   auto bucket = a.template take<uint32_t>(257);
   auto irank = a.template take<uint32_t>(ic);
+  auto slist = a.template take<uint32_t>(ic);
+  auto blist = a.template take<uint32_t>(ic);
   auto big = a.template take<uint32_t>(c1 > b1 ? c1 : b1);
   auto bigc = a.template take<uint32_t>(4);
   if (W) {
@@ -640,6 +832,8 @@ void agg_layout(A &a, const Geom &g, uint32_t S, uint32_t n_comp, int32_t n_band
     W->corder = corder;
     W->bucket = bucket;
     W->item_rank = irank;
+    W->small_list = slist;
+    W->big_list = blist;
     W->big = big;
     W->big_cnt = bigc;
     W->item_cap = ic;
@@ -769,9 +963,8 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     if ((int64_t)n_items > W.item_cap) return LSRVT_EDEVICE;  // cannot happen: the capacity is an upper bound
   }
 
-  // 3. per-item sums
+  // 3. per-item sums: cells of at most kSmallCell voxels one wave each, larger cells one workgroup per item
   if (n_items) {
-    hipLaunchKernelGGL(k_item_cells, dim3((S + 255) / 256), dim3(256), 0, s, W.item_off, S, W.item_rank);
     CellArgs A;
     A.perm = W.perm;
     A.cell_off = W.lay.cell_off;
@@ -787,12 +980,38 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     A.pairs = pairs;
     A.item_off = W.item_off;
     A.item_rank = W.item_rank;
-    A.n_items = n_items;
     A.part_hi = W.part_hi;
     A.part_lo = W.part_lo;
     A.hist = want_hist ? cs.hist : nullptr;
     A.kmin = W.kmin;
     A.kmax = W.kmax;
+    // wave path: U units over 64 lanes, LDS for four waves
+    const int Rw = (U + kWave - 1) / kWave;
+    const int Gw = Rw == 1 ? kWave / U : 1;
+    const size_t lds_w =
+        sizeof(float) * ((size_t)m * (B + 1) + (kAggThreads / kWave) * wave_region_words(m, B, U, Gw));
+    const bool small_ok = Rw <= 3 && lds_w <= 65536;
+    if ((rc = fill<uint32_t>(W.big_cnt + 1, 2, 0u, s))) return rc;
+    uint32_t *counts = W.big_cnt + 1;
+    hipLaunchKernelGGL(k_item_cells, dim3((S + 255) / 256), dim3(256), 0, s, W.item_off, W.lay.cnt_rank, S,
+                       small_ok ? 1 : 0, W.item_rank, W.small_list, W.big_list, counts);
+    LSRVT_LAUNCHED();
+    if (small_ok) {
+      A.list = W.small_list;
+      A.list_cnt = counts;
+      A.G = Gw;
+      A.tile = kSmallCell;
+      const unsigned grid = (unsigned)std::min<uint64_t>(65535, (n_items + 3) / 4);
+      if (Rw == 1)
+        hipLaunchKernelGGL(k_agg_cell_wave<1>, dim3(grid), dim3(kAggThreads), lds_w, s, A);
+      else if (Rw == 2)
+        hipLaunchKernelGGL(k_agg_cell_wave<2>, dim3(grid), dim3(kAggThreads), lds_w, s, A);
+      else
+        hipLaunchKernelGGL(k_agg_cell_wave<3>, dim3(grid), dim3(kAggThreads), lds_w, s, A);
+      LSRVT_LAUNCHED();
+    }
+    A.list = W.big_list;
+    A.list_cnt = counts + 1;
     const int R = (U + kAggThreads - 1) / kAggThreads;
     A.G = R == 1 ? kAggThreads / U : 1;
     // the largest staging round that keeps the workgroup within 48 KiB of LDS
@@ -804,7 +1023,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
       if (lds <= 49152) break;
     }
     if (lds > 65536 || R > 3) return LSRVT_EINVAL;
-    unsigned grid = n_items < 65535 ? n_items : 65535;
+    unsigned grid = n_items < 16384 ? n_items : 16384;
     if (R == 1)
       hipLaunchKernelGGL(k_agg_cell<1>, dim3(grid), dim3(kAggThreads), lds, s, A);
     else if (R == 2)

@@ -66,8 +66,8 @@ struct BFSArgs {
   uint32_t *vis;       // [nbricks][256] voxels reached so far
   uint32_t *cell;      // [N] site id of every reached voxel (NONE elsewhere)
   uint32_t *queued;    // [nbricks] tag of the last level a brick was queued for
-  uint32_t *list_in, *list_out;
-  uint32_t *cnt;       // [3] rotating list counters
+  uint32_t *list0, *list1;  // bricks of even / odd levels
+  uint32_t *cnt;       // [3] rotating list counters: cnt[L % 3] bricks of level L
   uint32_t *hist;      // [kHistLen] active bricks per level
   uint32_t *err;
 };
@@ -76,46 +76,83 @@ __device__ __forceinline__ int64_t brick_row_base(const Geom &g, int x0, int y, 
   return x0 + (int64_t)g.nx * (y + (int64_t)g.ny * z);
 }
 
-// Queue brick (bx, by, bz) and its six face neighbours for the level tagged `tag`.
-__device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *out_cnt) {
+// Queue brick (bx, by, bz) and its six face neighbours for the level tagged
+// `tag`: lanes 0..6 of the calling wave take one brick each, so the tag
+// atomics of the seven bricks overlap.  Called by a whole wave.
+__device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *out,
+                             uint32_t *out_cnt) {
+  const int k = lane_id();
+  bool want = false;
+  uint32_t nb = 0;
+  if (k < 7) {
+    const int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
+    const int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
+    const int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
+    if (nx >= 0 && ny >= 0 && nz >= 0 && nx < A.bg.nbx && ny < A.bg.nby && nz < A.bg.nbz) {
+      nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
+      want = A.queued[nb] < tag && atomicMax(&A.queued[nb], tag) < tag;
+    }
+  }
+  const uint64_t m = __ballot(want);
+  if (!m) return;
+  uint32_t base = 0;
+  if (k == 0) base = atomicAdd(out_cnt, (uint32_t)__popcll(m));
+  base = __shfl(base, 0, kWave);
+  if (want) out[base + (uint32_t)__popcll(m & lanemask_lt())] = nb;
+}
+
+// Per-thread variant for the sites of level 0.
+__device__ void queue_around_one(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *out_cnt) {
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
-    int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
-    int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
-    int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
+    const int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
+    const int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
+    const int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
     if (nx < 0 || ny < 0 || nz < 0 || nx >= A.bg.nbx || ny >= A.bg.nby || nz >= A.bg.nbz) continue;
-    uint32_t nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
-    if (atomicMax(&A.queued[nb], tag) < tag) A.list_out[atomicAdd(out_cnt, 1u)] = nb;
+    const uint32_t nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
+    if (A.queued[nb] < tag && atomicMax(&A.queued[nb], tag) < tag) A.list1[atomicAdd(out_cnt, 1u)] = nb;
   }
 }
 
 // Same-band masks of every row toward its six neighbours (across brick faces
-// too); voxels outside the volume have no edges.  Bands do not change during
-// a Lloyd loop, so this runs once per call.
+// too); voxels outside the volume have no edges.  One voxel per lane, so a
+// wave covers four rows of a brick and the band reads are coalesced.  Bands
+// do not change during a Lloyd loop, so this runs once per call.
 __global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict__ band, Geom g, VTGrid bg,
                                                       uint32_t *__restrict__ eq) {
-  const int t = threadIdx.x, ly = t & 15, lz = t >> 4;
-  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
-    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-    const int x0 = bx * BX, y = by * BY + ly, z = bz * BZ + lz;
-    uint32_t m[6] = {0, 0, 0, 0, 0, 0};
-    if (y < g.ny && z < g.nz) {
-      const int64_t base = brick_row_base(g, x0, y, z);
-      const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
-      for (int x = 0; x < BX && x0 + x < g.nx; ++x) {
-        const uint8_t bv = band[base + x];
-        if (x0 + x > 0 && band[base + x - 1] == bv) m[0] |= 1u << x;
-        if (x0 + x + 1 < g.nx && band[base + x + 1] == bv) m[1] |= 1u << x;
-        if (y > 0 && band[base + x - sy] == bv) m[2] |= 1u << x;
-        if (y + 1 < g.ny && band[base + x + sy] == bv) m[3] |= 1u << x;
-        if (z > 0 && band[base + x - sz] == bv) m[4] |= 1u << x;
-        if (z + 1 < g.nz && band[base + x + sz] == bv) m[5] |= 1u << x;
+  const int64_t slots = bg.nbricks * kRows * BX;
+  const int lane = lane_id();
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool p[6] = {false, false, false, false, false, false};
+    const int64_t row = i >> 4;  // brick * 256 + (ly + 16 lz)
+    if (i < slots) {
+      const int64_t b = row / kRows;
+      const int t = (int)(row % kRows);
+      const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+      const int x = bx * BX + (int)(i & 15), y = by * BY + (t & 15), z = bz * BZ + (t >> 4);
+      if (x < g.nx && y < g.ny && z < g.nz) {
+        const int64_t v = x + sy * y + sz * z;
+        const uint8_t bv = band[v];
+        p[0] = x > 0 && band[v - 1] == bv;
+        p[1] = x + 1 < g.nx && band[v + 1] == bv;
+        p[2] = y > 0 && band[v - sy] == bv;
+        p[3] = y + 1 < g.ny && band[v + sy] == bv;
+        p[4] = z > 0 && band[v - sz] == bv;
+        p[5] = z + 1 < g.nz && band[v + sz] == bv;
       }
     }
-    uint32_t *dst = eq + (b * kRows + t) * 3;
-    dst[0] = m[0] | (m[1] << 16);
-    dst[1] = m[2] | (m[3] << 16);
-    dst[2] = m[4] | (m[5] << 16);
+    uint64_t m[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) m[k] = __ballot(p[k]);
+    if (i < slots && (lane & 15) == 0) {
+      const int sh = lane;  // this lane's row occupies ballot bits sh .. sh + 15
+      uint32_t *dst = eq + row * 3;
+      dst[0] = (uint32_t)((m[0] >> sh) & 0xFFFFu) | ((uint32_t)((m[1] >> sh) & 0xFFFFu) << 16);
+      dst[1] = (uint32_t)((m[2] >> sh) & 0xFFFFu) | ((uint32_t)((m[3] >> sh) & 0xFFFFu) << 16);
+      dst[2] = (uint32_t)((m[4] >> sh) & 0xFFFFu) | ((uint32_t)((m[5] >> sh) & 0xFFFFu) << 16);
+    }
   }
 }
 
@@ -136,33 +173,26 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
   atomicMin(&A.cell[v], s);
   atomicOr(&A.vis[(int64_t)b * kRows + row], bit);
   atomicOr(&A.fr[(int64_t)b * kRows + row], bit);  // parity 0 = level 0
-  queue_around(A, bx, by, bz, tag, &A.cnt[1]);
+  queue_around_one(A, bx, by, bz, tag, &A.cnt[1]);
 }
 
 // Level L: a voxel not reached yet is reached now when a same-band face
 // neighbour was reached at level L - 1; it takes the smallest id among those
-// neighbours (Eq. 1 with ties to the lower id).  Processes only the bricks
-// queued for this level; queues a brick and its neighbours for L + 1 when
-// anything was reached.
-__global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L, uint32_t tag) {
-  __shared__ uint32_t s_count;
+// neighbours (Eq. 1 with ties to the lower id).  Processes the bricks listed
+// for this level (items first, first + stride, ...); a brick that reached
+// anything lists itself and its neighbours for L + 1.
+__device__ void bfs_level(const BFSArgs &A, uint32_t L, uint32_t count, uint32_t tag, uint32_t first,
+                          uint32_t stride) {
   const int t = threadIdx.x;
-  if (t == 0) {
-    s_count = A.cnt[L % 3];
-    if (blockIdx.x == 0) {
-      A.cnt[(L + 2) % 3] = 0;  // the list of level L + 2 starts empty
-      A.hist[L % kHistLen] = s_count;
-    }
-  }
-  __syncthreads();
-  const uint32_t count = s_count;
+  const uint32_t *list_in = (L & 1) ? A.list1 : A.list0;
+  uint32_t *list_out = (L & 1) ? A.list0 : A.list1;
   uint32_t *out_cnt = &A.cnt[(L + 1) % 3];
   const uint32_t *fin = A.fr + (size_t)((L - 1) & 1) * A.bg.nbricks * kRows;
   uint32_t *fout = A.fr + (size_t)(L & 1) * A.bg.nbricks * kRows;
   const int ly = t & 15, lz = t >> 4;
   const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
-  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-    const uint32_t b = A.list_in[item];
+  for (uint32_t item = first; item < count; item += stride) {
+    const uint32_t b = list_in[item];
     const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby), bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
     const int64_t rb = (int64_t)b * kRows;
     const uint32_t F = fin[rb + t];
@@ -200,8 +230,27 @@ __global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L,
       if (nw) A.vis[rb + t] = vrow | nw;
     }
     fout[rb + t] = nw;
-    if (__syncthreads_or(nw != 0) && t == 0) queue_around(A, bx, by, bz, tag, out_cnt);
+    if (__syncthreads_or(nw != 0) && t < kWave) queue_around(A, bx, by, bz, tag, list_out, out_cnt);
   }
+}
+
+// One BFS level per launch.  Workgroup 0 clears the list counter of level
+// L + 2 (level L + 1 appends to it), so launches may be enqueued past the
+// last level: they find an empty list and return.
+__global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L) {
+  __shared__ uint32_t s_count;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    s_count = A.cnt[L % 3];
+    if (blockIdx.x == 0) {
+      A.cnt[(L + 2) % 3] = 0;
+      A.hist[L % kHistLen] = s_count;
+    }
+  }
+  __syncthreads();
+  const uint32_t count = s_count;
+  if (count == 0) return;
+  bfs_level(A, L, count, L + 1, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -258,17 +307,24 @@ __global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ c
           }
         }
       };
-      for (int x = x0; x < xe; ++x) {
-        uint32_t c = cell[base + x];
-        uint64_t wv = w ? (uint64_t)w[base + x] : 1ull;
-        if (c != rc) {
+      // all 16 loads in flight before the runs are folded
+      uint32_t cc[16], ww[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const bool in = x0 + i < xe;
+        cc[i] = in ? cell[base + x0 + i] : kNone;
+        ww[i] = in ? (w ? (uint32_t)w[base + x0 + i] : 1u) : 0u;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        if (cc[i] != rc) {
           flush();
-          rc = c;
+          rc = cc[i];
           rm = 0;
           rx = 0;
         }
-        rm += wv;
-        rx += wv * (uint64_t)x;
+        rm += ww[i];
+        rx += (uint64_t)ww[i] * (uint64_t)(x0 + i);
       }
       flush();
     }
@@ -484,7 +540,7 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto queued = a.template take<uint32_t>(nb);
   auto la = a.template take<uint32_t>(nb);
   auto lb = a.template take<uint32_t>(nb);
-  auto cnt = a.template take<uint32_t>(4);
+  auto cnt = a.template take<uint32_t>(4);  // 3 list counters, errors
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
   auto sums = a.template take<unsigned long long>(4 * s1);
@@ -531,11 +587,9 @@ int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t
   return cv.ok ? LSRVT_OK : LSRVT_EWORKSPACE;
 }
 
-// Driver state of one Lloyd run: the queue tag of the next level and the
-// active-brick counts per level of the previous pass (sites move little
-// between passes, so they size the next pass's launches).
+// Driver state of one Lloyd run: the active-brick counts per level of the
+// previous pass, which size the launches of the next one.
 struct VTState {
-  uint32_t tag = 1;
   std::vector<uint32_t> prev;
 };
 
@@ -607,7 +661,9 @@ unsigned vt_grid_cap(const VTGrid &bg) { return (unsigned)(bg.nbricks < 65535 ? 
 
 int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s) {
   VTGrid bg = vt_grid(g);
-  hipLaunchKernelGGL(k_vt_eq, dim3(vt_grid_cap(bg)), dim3(kVTThreads), 0, s, band, g, bg, W.eq);
+  const int64_t slots = bg.nbricks * kRows * BX;
+  const unsigned grid = (unsigned)std::min<int64_t>((slots + kVTThreads - 1) / kVTThreads, 65535);
+  hipLaunchKernelGGL(k_vt_eq, dim3(grid), dim3(kVTThreads), 0, s, band, g, bg, W.eq);
   LSRVT_LAUNCHED();
   return LSRVT_OK;
 }
@@ -615,12 +671,16 @@ int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s
 // One restricted Voronoi pass: level 0 at the sites, then one launch per BFS
 // level over the bricks the front passes through, until a level reaches
 // nothing.
+// One restricted Voronoi pass: level 0 at the sites, then launches of the
+// level kernel, enqueued in batches sized by the previous pass (sites move
+// little between passes) until the device reports an empty level.
 int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
                hipStream_t s) {
   VTGrid bg = vt_grid(g);
   int32_t rc;
   if ((rc = fill<uint32_t>(W.fr, 2 * bg.nbricks * kRows, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.vis, bg.nbricks * kRows, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.cnt, 3, 0u, s))) return rc;
   BFSArgs A;
   A.g = g;
@@ -633,56 +693,55 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   A.cnt = W.cnt;
   A.hist = W.hist;
   A.err = W.err;
-  A.list_in = W.list_a;
-  A.list_out = W.list_b;  // level 1 reads list_b
+  A.list0 = W.list_a;
+  A.list1 = W.list_b;  // level 1 reads list1
   if (S) {
     hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g.n, cell);
-    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A, st.tag);
+    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A, 1u);
     LSRVT_LAUNCHED();
   }
-  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
+  const int64_t max_level = g.n + 2;
   const unsigned cap = vt_grid_cap(bg);
-  const int64_t max_levels = g.n + 2;
-  std::vector<uint32_t> counts;
-  uint32_t L = 0;
+  uint32_t L = 0;  // levels enqueued
+  int batch = st.prev.empty() ? 16 : (int)st.prev.size() + 4;
   bool more = S != 0;
-  int batch = st.prev.empty() ? 8 : (int)st.prev.size();
+  uint32_t c[4] = {0, 0, 0, 0};
   while (more) {
     for (int i = 0; i < batch; ++i) {
       ++L;
-      A.list_in = (L & 1) ? W.list_b : W.list_a;
-      A.list_out = (L & 1) ? W.list_a : W.list_b;
       unsigned grid = cap;
       if (L - 1 < st.prev.size()) {
         const uint32_t p = st.prev[L - 1];
         grid = (unsigned)std::min<uint64_t>(cap, (uint64_t)p + p / 4 + 64);
+      } else if (!st.prev.empty()) {
+        grid = 64;  // most likely past the last level
       }
       const bool timed = timer().on;
       std::pair<hipEvent_t, hipEvent_t> ev;
       if (timed && (rc = timed_begin(s, ev))) return rc;
-      hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kVTThreads), 0, s, A, L, st.tag + L);
+      hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kVTThreads), 0, s, A, L);
       LSRVT_LAUNCHED();
       if (timed && (rc = timed_end(s, ev))) return rc;
     }
-    uint32_t c[4];
     LSRVT_HIP(hipMemcpyAsync(c, W.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
     if (c[3] & 1u) return LSRVT_EINVAL;
     if (c[3]) return LSRVT_EDEVICE;
-    more = c[(L + 1) % 3] != 0;
-    if ((int64_t)L > max_levels) return LSRVT_EDEVICE;
-    batch = 4;
+    more = c[(L + 1) % 3] != 0;  // bricks listed for the next level
+    if ((int64_t)L > max_level) return LSRVT_EDEVICE;
+    batch = 8;
   }
-  st.tag += L + 2;
-  // per-level brick counts of this pass size the next one
-  const uint32_t nl = L < (uint32_t)kHistLen ? L : (uint32_t)kHistLen - 1;
-  std::vector<uint32_t> h(nl + 1, 0);
-  if (nl) {
-    LSRVT_HIP(hipMemcpyAsync(h.data(), W.hist, sizeof(uint32_t) * (nl + 1), hipMemcpyDeviceToHost, s));
+  const uint32_t launched = L;
+  // the brick counts of levels 1 .. L size the next pass (trailing empty levels dropped)
+  const uint32_t nl = std::min<uint32_t>(L + 1, kHistLen);
+  std::vector<uint32_t> h(nl, 0);
+  if (nl > 1) {
+    LSRVT_HIP(hipMemcpyAsync(h.data(), W.hist, sizeof(uint32_t) * nl, hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
   }
-  st.prev.clear();
-  for (uint32_t l = 1; l <= nl && h[l]; ++l) st.prev.push_back(h[l]);
+  uint32_t levels = 0;
+  while (levels + 1 < nl && h[levels + 1]) ++levels;
+  st.prev.assign(h.begin() + 1, h.begin() + 1 + levels);
   hipLaunchKernelGGL(k_vt_unreached, dim3(cap), dim3(kVTThreads), 0, s, W.vis, g, bg, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
@@ -690,11 +749,22 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     timer().passes += 1;
     timer().voxels_per_pass = g.n;
   }
+  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
   if (debug_levels) {
-    fprintf(stderr, "[lsrvt] vt levels=%u active bricks:", L);
-    for (uint32_t l = 1; l <= nl; ++l) fprintf(stderr, " %u", h[l]);
+    fprintf(stderr, "[lsrvt] vt levels=%u launches=%u active bricks:", levels, launched);
+    for (uint32_t l = 1; l <= levels; ++l) fprintf(stderr, " %u", h[l]);
     fprintf(stderr, "\n");
   }
+  return LSRVT_OK;
+}
+
+// Errors a run reported on the device (synchronises).
+int32_t vt_errors(CvtWork &W, hipStream_t s) {
+  uint32_t e = 0;
+  LSRVT_HIP(hipMemcpyAsync(&e, W.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LSRVT_HIP(hipStreamSynchronize(s));
+  if (e & 1u) return LSRVT_EINVAL;
+  if (e) return LSRVT_EDEVICE;
   return LSRVT_OK;
 }
 
@@ -747,7 +817,8 @@ extern "C" int32_t lsrvt_vt(const uint8_t *d_band, lsrvt_dims dims, const uint32
   if ((rc = begin(W, g, s))) return rc;
   if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
-  return run_vt(g, d_sites, n_sites, d_cell, W, st, s);
+  if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
+  return vt_errors(W, s);
 }
 
 extern "C" int32_t lsrvt_update(const uint32_t *d_cell, lsrvt_dims dims, const uint16_t *d_weights, uint32_t *d_sites,
@@ -793,9 +864,8 @@ extern "C" int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrv
   }
   if (h_mean_ds && iters > 0) {
     LSRVT_HIP(hipMemcpyAsync(h_mean_ds, W.mean, sizeof(double) * iters, hipMemcpyDeviceToHost, s));
-    LSRVT_HIP(hipStreamSynchronize(s));
   }
-  return LSRVT_OK;
+  return vt_errors(W, s);
 }
 
 extern "C" int32_t lsrvt_timing_enable(int32_t enable) {
