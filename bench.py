@@ -195,7 +195,7 @@ def main():
         "lloyd_gvox_per_iter_s": round(n * wl.iters / (phases["lloyd"] / 1e3) / 1e9, 4) if phases["lloyd"] else None,
         "stats_gvox_s": round(n / (phases["aggregate"] / 1e3) / 1e9, 4) if phases["aggregate"] else None,
         "stats_dtype": "f32 compensated per cell, f64 merges",
-        "roofline": {"bound": "hbm", "kernel": "k_bfs_pass", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "k_bfs_level", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                      "traffic": traffic,
                      "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": vt_launches, "passes": vt_passes,

@@ -276,13 +276,14 @@ int32_t lsrvt_extract(const float *d_vars, int32_t n_vars, lsrvt_dims dims, cons
 
 /* ------------------------------------------------------------------------
  * Benchmark instrumentation of the Voronoi level kernel (the dominant kernel
- * of the Lloyd loop).  While enabled, every launch of that kernel is
- * bracketed by a hipEvent pair recorded on the stream it is launched on.
- * lsrvt_timing_read waits for the recorded events and returns, since the
- * previous read: the summed kernel milliseconds, the number of launches, the
- * number of Voronoi passes they belong to and the voxels of one pass; then it
- * resets the totals.  Adds a small per-launch overhead; process-global state,
- * meant for benchmarks, not for concurrent production use.
+ * of the Lloyd loop; one launch per breadth-first level).  While enabled,
+ * every batch of back-to-back level launches is bracketed by one hipEvent
+ * pair recorded on the stream it is launched on.  lsrvt_timing_read waits
+ * for the recorded events and returns, since the previous read: the summed
+ * milliseconds of those batches, the number of level launches in them, the
+ * number of Voronoi passes they belong to and the voxels of one pass; then
+ * it resets the totals.  Process-global state, meant for benchmarks, not for
+ * concurrent production use.
  */
 int32_t lsrvt_timing_enable(int32_t enable);
 int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass);

@@ -429,7 +429,7 @@ def lsrvt_extract(variables, perm, out=None, stream=None):
 
 
 def lsrvt_timing_enable(enable: bool = True) -> None:
-    """Bracket every Voronoi level-kernel launch with a hipEvent pair (benchmarks)."""
+    """Bracket every batch of Voronoi level-kernel launches with a hipEvent pair (benchmarks)."""
     _check(_lib().lsrvt_timing_enable(1 if enable else 0), "lsrvt_timing_enable")
 
 

@@ -213,19 +213,35 @@ __device__ void bfs_level(const BFSArgs &A, uint32_t L, uint32_t count, uint32_t
       const uint32_t gzm = fzm & e2, gzp = fzp & (e2 >> 16);
       nw &= fxm | fxp | gym | gyp | gzm | gzp;
       const int64_t base = brick_row_base(A.g, bx * BX, by * BY + ly, bz * BZ + lz);
+      // ids of the new voxels, four at a time: all loads of a group are in
+      // flight before its stores, so a row does not wait once per voxel
       uint32_t bits = nw;
       while (bits) {
-        const int x = __ffs(bits) - 1;
-        bits &= bits - 1;
-        const int64_t v = base + x;
-        uint32_t id = kNone;
-        if ((fxm >> x) & 1u) id = min(id, A.cell[v - 1]);
-        if ((fxp >> x) & 1u) id = min(id, A.cell[v + 1]);
-        if ((gym >> x) & 1u) id = min(id, A.cell[v - sy]);
-        if ((gyp >> x) & 1u) id = min(id, A.cell[v + sy]);
-        if ((gzm >> x) & 1u) id = min(id, A.cell[v - sz]);
-        if ((gzp >> x) & 1u) id = min(id, A.cell[v + sz]);
-        A.cell[v] = id;
+        int xs[4];
+        uint32_t idv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          xs[j] = bits ? __ffs(bits) - 1 : -1;
+          bits &= bits - 1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          uint32_t id = kNone;
+          const int x = xs[j];
+          if (x >= 0) {
+            const int64_t v = base + x;
+            if ((fxm >> x) & 1u) id = min(id, A.cell[v - 1]);
+            if ((fxp >> x) & 1u) id = min(id, A.cell[v + 1]);
+            if ((gym >> x) & 1u) id = min(id, A.cell[v - sy]);
+            if ((gyp >> x) & 1u) id = min(id, A.cell[v + sy]);
+            if ((gzm >> x) & 1u) id = min(id, A.cell[v - sz]);
+            if ((gzp >> x) & 1u) id = min(id, A.cell[v + sz]);
+          }
+          idv[j] = id;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (xs[j] >= 0) A.cell[base + xs[j]] = idv[j];
       }
       if (nw) A.vis[rb + t] = vrow | nw;
     }
@@ -251,308 +267,6 @@ __global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L)
   const uint32_t count = s_count;
   if (count == 0) return;
   bfs_level(A, L, count, L + 1, blockIdx.x, gridDim.x);
-}
-
-// ----------------------------------------------------------------------------
-// Brick rounds: every brick relaxes its own keys to a fixed point in LDS
-// (line sweeps), seeded by its sites and by the keys its neighbours last
-// published on the facing faces; a brick is processed again only when a
-// facing face changed.
-
-constexpr int PX = BX + 1;  // padded LDS pitch (u64 elements): x lines of neighbouring rows use different banks
-constexpr int kFaceLen = 256;
-constexpr int kFaces = 6;
-constexpr uint64_t kD1 = 1ull << 32;
-constexpr uint8_t kOutside = 255;
-constexpr int kMaxSweepCycles = 1 << 14;
-
-struct RoundArgs {
-  const uint8_t *band;
-  Geom g;
-  VTGrid bg;
-  const uint32_t *sites;
-  const uint32_t *blist;  // site ids bucketed by brick
-  const uint32_t *boff;   // [nbricks + 1]
-  const uint8_t *site_band;
-  uint64_t *faces;        // [nbricks][6][256] keys on each face, as last published
-  uint32_t *cell;
-  uint32_t *queued;       // [nbricks] tag of the last round a brick was queued for
-  uint32_t *list_in, *list_out;
-  uint32_t *cnt;          // [3] rotating list counters
-  uint32_t *err;
-  uint32_t *stats;        // [2] bricks processed, sweep cycles (or null)
-};
-
-__device__ __forceinline__ int kidx(int lx, int ly, int lz) { return (lz * BY + ly) * PX + lx; }
-__device__ __forceinline__ int bidx(int lx, int ly, int lz) { return (lz * BY + ly) * BX + lx; }
-
-// Face f of a brick: 0:-x 1:+x (index ly + 16 lz), 2:-y 3:+y (lx + 16 lz), 4:-z 5:+z (lx + 16 ly).
-__device__ __forceinline__ void face_voxel(int f, int p, int &lx, int &ly, int &lz) {
-  const int a = p & 15, c = p >> 4;
-  switch (f) {
-    case 0: lx = 0; ly = a; lz = c; break;
-    case 1: lx = BX - 1; ly = a; lz = c; break;
-    case 2: lx = a; ly = 0; lz = c; break;
-    case 3: lx = a; ly = BY - 1; lz = c; break;
-    case 4: lx = a; ly = c; lz = 0; break;
-    default: lx = a; ly = c; lz = BZ - 1; break;
-  }
-}
-
-// Min-plus scan of one line of 16 keys in both directions over same-band
-// neighbours (bit i of m: voxels i - 1 and i share a band); returns whether
-// a key dropped.
-__device__ __forceinline__ bool sweep_line(uint64_t (&k)[16], uint32_t m) {
-  bool c = false;
-#pragma unroll
-  for (int i = 1; i < 16; ++i) {
-    const uint64_t cand = k[i - 1] + kD1;
-    if (((m >> i) & 1u) && k[i - 1] != kInfKey && cand < k[i]) {
-      k[i] = cand;
-      c = true;
-    }
-  }
-#pragma unroll
-  for (int i = 14; i >= 0; --i) {
-    const uint64_t cand = k[i + 1] + kD1;
-    if (((m >> (i + 1)) & 1u) && k[i + 1] != kInfKey && cand < k[i]) {
-      k[i] = cand;
-      c = true;
-    }
-  }
-  return c;
-}
-
-__global__ __launch_bounds__(kVTThreads, 4) void k_vt_round(RoundArgs A, uint32_t epoch, int all) {
-  // keys; before they are initialised the first 4 KiB hold the brick's bands
-  __shared__ uint64_t key[BZ * BY * PX];
-  __shared__ uint16_t lmask[3][kRows];  // same-band bits of the x, y and z lines
-  __shared__ uint32_t s_count;
-  __shared__ int s_face[kFaces];
-  uint8_t *bnd = reinterpret_cast<uint8_t *>(key);
-  const int t = threadIdx.x;
-  if (t == 0) {
-    s_count = all ? (uint32_t)A.bg.nbricks : A.cnt[epoch % 3];
-    if (blockIdx.x == 0) A.cnt[(epoch + 2) % 3] = 0;  // the round after next lists into it
-  }
-  __syncthreads();
-  const uint32_t count = s_count;
-  uint32_t *out_cnt = &A.cnt[(epoch + 1) % 3];
-  const int ly = t & 15, lz = t >> 4;
-  const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
-  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-    const uint32_t b = all ? item : A.list_in[item];
-    const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby),
-              bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * BZ;
-    // bands, 16 consecutive lanes per x line (coalesced)
-#pragma unroll 4
-    for (int it = 0; it < 16; ++it) {
-      const int li = it * kVTThreads + t;
-      const int gx = x0 + (li & 15), gy = y0 + ((li >> 4) & 15), gz = z0 + (li >> 8);
-      const bool in = gx < A.g.nx && gy < A.g.ny && gz < A.g.nz;
-      bnd[li] = in ? A.band[gx + sy * gy + sz * gz] : kOutside;
-    }
-    __syncthreads();
-    // line masks; halo seeds that match the band of their face voxel
-    {
-      uint32_t mx = 0, my = 0, mzz = 0;
-      const int lx = t & 15, lyz = t >> 4;
-      uint8_t px = bnd[bidx(0, ly, lz)], py = bnd[bidx(lx, 0, lyz)], pz = bnd[bidx(lx, lyz, 0)];
-#pragma unroll
-      for (int i = 1; i < 16; ++i) {
-        const uint8_t cx = bnd[bidx(i, ly, lz)], cy = bnd[bidx(lx, i, lyz)], cz = bnd[bidx(lx, lyz, i)];
-        if (cx == px && cx != kOutside) mx |= 1u << i;
-        if (cy == py && cy != kOutside) my |= 1u << i;
-        if (cz == pz && cz != kOutside) mzz |= 1u << i;
-        px = cx;
-        py = cy;
-        pz = cz;
-      }
-      lmask[0][t] = (uint16_t)mx;   // x line (ly, lz) = t
-      lmask[1][t] = (uint16_t)my;   // y line (lx, lz) = t
-      lmask[2][t] = (uint16_t)mzz;  // z line (lx, ly) = t
-    }
-    // band of this thread's voxel on each face (for the halo seeds below)
-    uint32_t fb_lo = 0, fb_hi = 0;
-#pragma unroll
-    for (int f = 0; f < kFaces; ++f) {
-      int lx, fy, fz;
-      face_voxel(f, t, lx, fy, fz);
-      const uint32_t mb = bnd[bidx(lx, fy, fz)];
-      if (f < 4)
-        fb_lo |= mb << (8 * f);
-      else
-        fb_hi |= mb << (8 * (f - 4));
-    }
-    __syncthreads();  // bands are dead from here on
-#pragma unroll
-    for (int x = 0; x < 16; ++x) key[kidx(x, ly, lz)] = kInfKey;
-    __syncthreads();
-    // own sites at distance 0 (co-located sites: the lower id wins)
-    for (uint32_t i = A.boff[b] + t; i < A.boff[b + 1]; i += kVTThreads) {
-      const uint32_t s = A.blist[i];
-      const uint32_t v = A.sites[s];
-      const int gx = (int)(v % (uint32_t)A.g.nx);
-      const uint32_t r = v / (uint32_t)A.g.nx;
-      const int gy = (int)(r % (uint32_t)A.g.ny), gz = (int)(r / (uint32_t)A.g.ny);
-      atomicMin((unsigned long long *)&key[kidx(gx - x0, gy - y0, gz - z0)], (unsigned long long)s);
-    }
-    // halo: a published neighbour key one hop away, when the bands match
-    if (!all) {
-#pragma unroll
-      for (int f = 0; f < kFaces; ++f) {
-        const int nbx = bx + (f == 0 ? -1 : f == 1 ? 1 : 0);
-        const int nby = by + (f == 2 ? -1 : f == 3 ? 1 : 0);
-        const int nbz = bz + (f == 4 ? -1 : f == 5 ? 1 : 0);
-        if (nbx < 0 || nby < 0 || nbz < 0 || nbx >= A.bg.nbx || nby >= A.bg.nby || nbz >= A.bg.nbz) continue;
-        const int64_t nb = nbx + (int64_t)A.bg.nbx * (nby + (int64_t)A.bg.nby * nbz);
-        const uint64_t kv = A.faces[(nb * kFaces + (f ^ 1)) * kFaceLen + t];
-        if (kv == kInfKey) continue;
-        const uint32_t mb = f < 4 ? (fb_lo >> (8 * f)) & 0xFFu : (fb_hi >> (8 * (f - 4))) & 0xFFu;
-        if (mb == kOutside || A.site_band[(uint32_t)kv] != mb) continue;
-        int lx, fy, fz;
-        face_voxel(f, t, lx, fy, fz);
-        atomicMin((unsigned long long *)&key[kidx(lx, fy, fz)], (unsigned long long)(kv + kD1));
-      }
-    }
-    __syncthreads();
-
-    // relax: x, y, z line sweeps until a full cycle changes nothing
-    const uint32_t mlx = lmask[0][t], mly = lmask[1][t], mlz = lmask[2][t];
-    int cycles = 0;
-    while (true) {
-      bool ch = false;
-      {  // x line (ly, lz)
-        uint64_t k[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) k[i] = key[kidx(i, ly, lz)];
-        if (sweep_line(k, mlx)) {
-          ch = true;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) key[kidx(i, ly, lz)] = k[i];
-        }
-      }
-      __syncthreads();
-      {  // y line (lx, lz) = (t & 15, t >> 4)
-        const int lx = t & 15;
-        uint64_t k[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) k[i] = key[kidx(lx, i, lz)];
-        if (sweep_line(k, mly)) {
-          ch = true;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) key[kidx(lx, i, lz)] = k[i];
-        }
-      }
-      __syncthreads();
-      {  // z line (lx, ly) = (t & 15, t >> 4)
-        const int lx = t & 15, yy = t >> 4;
-        uint64_t k[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) k[i] = key[kidx(lx, yy, i)];
-        if (sweep_line(k, mlz)) {
-          ch = true;
-#pragma unroll
-          for (int i = 0; i < 16; ++i) key[kidx(lx, yy, i)] = k[i];
-        }
-      }
-      ++cycles;
-      if (!__syncthreads_or(ch ? 1 : 0)) break;
-      if (cycles >= kMaxSweepCycles) {
-        if (t == 0) atomicOr(A.err, 2u);
-        break;
-      }
-    }
-    if (A.stats && t == 0) {
-      atomicAdd(&A.stats[0], 1u);
-      atomicAdd(&A.stats[1], (uint32_t)cycles);
-    }
-
-    // cells, 16 consecutive lanes per x line (coalesced)
-#pragma unroll 4
-    for (int it = 0; it < 16; ++it) {
-      const int li = it * kVTThreads + t;
-      const int lx = li & 15, yy = (li >> 4) & 15, zz = li >> 8;
-      const int gx = x0 + lx, gy = y0 + yy, gz = z0 + zz;
-      if (gx < A.g.nx && gy < A.g.ny && gz < A.g.nz) {
-        const uint64_t kv = key[kidx(lx, yy, zz)];
-        A.cell[gx + sy * gy + sz * gz] = kv == kInfKey ? kNone : (uint32_t)kv;
-      }
-    }
-    // publish the six faces; queue a neighbour whose facing face changed
-    if (t < kFaces) s_face[t] = 0;
-    __syncthreads();
-    uint64_t *dst = A.faces + (int64_t)b * kFaces * kFaceLen;
-    uint64_t kvf[kFaces], old[kFaces];
-#pragma unroll
-    for (int f = 0; f < kFaces; ++f) {
-      int lx, fy, fz;
-      face_voxel(f, t, lx, fy, fz);
-      kvf[f] = key[kidx(lx, fy, fz)];
-      old[f] = all ? kInfKey : dst[f * kFaceLen + t];
-    }
-#pragma unroll
-    for (int f = 0; f < kFaces; ++f) {
-      if (all || kvf[f] != old[f]) dst[f * kFaceLen + t] = kvf[f];
-      if (kvf[f] != old[f]) s_face[f] = 1;
-    }
-    __syncthreads();
-    if (t < kWave) {
-      // lanes 0..5 queue the neighbour behind each changed face, in parallel
-      const int f = t;
-      bool want = false;
-      uint32_t nb = 0;
-      if (f < kFaces && s_face[f]) {
-        const int nbx = bx + (f == 0 ? -1 : f == 1 ? 1 : 0);
-        const int nby = by + (f == 2 ? -1 : f == 3 ? 1 : 0);
-        const int nbz = bz + (f == 4 ? -1 : f == 5 ? 1 : 0);
-        if (nbx >= 0 && nby >= 0 && nbz >= 0 && nbx < A.bg.nbx && nby < A.bg.nby && nbz < A.bg.nbz) {
-          nb = (uint32_t)(nbx + A.bg.nbx * (nby + A.bg.nby * nbz));
-          want = A.queued[nb] < epoch + 1 && atomicMax(&A.queued[nb], epoch + 1) < epoch + 1;
-        }
-      }
-      const uint64_t m = __ballot(want);
-      if (m) {
-        uint32_t base = 0;
-        if (t == 0) base = atomicAdd(out_cnt, (uint32_t)__popcll(m));
-        base = __shfl(base, 0, kWave);
-        if (want) A.list_out[base + (uint32_t)__popcll(m & lanemask_lt())] = nb;
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// Sites: count per brick and note each site's band; out-of-range sites are
-// reported through err and left out.
-__global__ void k_site_count(const uint32_t *__restrict__ sites, uint32_t S, const uint8_t *__restrict__ band, Geom g,
-                             VTGrid bg, uint32_t *bcount, uint8_t *site_band, uint32_t *err) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint32_t v = sites[s];
-  if ((int64_t)v >= g.n) {
-    atomicOr(err, 1u);
-    site_band[s] = kOutside;
-    return;
-  }
-  const uint32_t x = v % (uint32_t)g.nx, r = v / (uint32_t)g.nx;
-  const uint32_t y = r % (uint32_t)g.ny, z = r / (uint32_t)g.ny;
-  const uint32_t b = x / BX + bg.nbx * (y / BY + bg.nby * (z / BZ));
-  atomicAdd(&bcount[b], 1u);
-  site_band[s] = band[v];
-}
-
-__global__ void k_site_fill(const uint32_t *__restrict__ sites, uint32_t S, Geom g, VTGrid bg,
-                            const uint32_t *__restrict__ boff, uint32_t *bfill, uint32_t *blist) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint32_t v = sites[s];
-  if ((int64_t)v >= g.n) return;
-  const uint32_t x = v % (uint32_t)g.nx, r = v / (uint32_t)g.nx;
-  const uint32_t y = r % (uint32_t)g.ny, z = r / (uint32_t)g.ny;
-  const uint32_t b = x / BX + bg.nbx * (y / BY + bg.nby * (z / BZ));
-  blist[boff[b] + atomicAdd(&bfill[b], 1u)] = s;
 }
 
 // ----------------------------------------------------------------------------
@@ -814,11 +528,6 @@ __global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, con
 // host side
 
 struct CvtWork {
-  uint64_t *faces;
-  uint32_t *bcount, *boff, *bfill, *blist, *rstats;
-  uint8_t *site_band;
-  void *scan_work;
-  size_t scan_bytes;
   uint32_t *eq, *fr, *vis;
   uint32_t *queued, *list_a, *list_b, *cnt;  // cnt[0..2] level counters, cnt[3] error bits
   uint32_t *fb_list, *fb_cnt, *err;
@@ -855,13 +564,6 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto mean = a.template take<double>(iters > 0 ? iters : 1);
   auto mpart = a.template take<double>(kMeanParts);
   auto hist = a.template take<uint32_t>(kHistLen);
-  auto faces = a.template take<uint64_t>(nb * kFaces * kFaceLen);
-  auto bcount = a.template take<uint32_t>(nb);
-  auto boff = a.template take<uint32_t>(nb + 1);
-  auto bfill = a.template take<uint32_t>(nb);
-  auto blist = a.template take<uint32_t>(s1);
-  auto sband = a.template take<uint8_t>(s1);
-  auto rstats = a.template take<uint32_t>(4);
   if (W) {
     W->eq = eq;
     W->fr = fr;
@@ -878,13 +580,6 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
     W->mean = mean;
     W->mean_part = mpart;
     W->hist = hist;
-    W->faces = faces;
-    W->bcount = bcount;
-    W->boff = boff;
-    W->bfill = bfill;
-    W->blist = blist;
-    W->site_band = sband;
-    W->rstats = rstats;
   }
 }
 
@@ -899,16 +594,13 @@ struct SizerT : Sizer {
 size_t cvt_workspace(const Geom &g, uint32_t S, int32_t iters) {
   SizerT z;
   cvt_layout(z, g, S, iters, nullptr);
-  return z.off + ScanU32::workspace(vt_grid(g).nbricks + 1) + 256;
+  return z.off + 256;
 }
 
 int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t iters, CvtWork &W) {
   Carve cv(d_work, bytes);
   cvt_layout(cv, g, S, iters, &W);
-  if (!cv.ok) return LSRVT_EWORKSPACE;
-  W.scan_work = cv.base + cv.off;
-  W.scan_bytes = cv.size - cv.off;
-  return LSRVT_OK;
+  return cv.ok ? LSRVT_OK : LSRVT_EWORKSPACE;
 }
 
 // Driver state of one Lloyd run: the active-brick counts per level of the
@@ -917,8 +609,9 @@ struct VTState {
   std::vector<uint32_t> prev;
 };
 
-// Benchmark timing of the level kernel: an event pair on the launch stream
-// around every launch while enabled; read back by lsrvt_timing_read.
+// Benchmark timing of the level kernel: while enabled, an event pair on the
+// launch stream around every batch of level launches; read back by
+// lsrvt_timing_read.
 struct KernelTimer {
   std::mutex mu;
   bool on = false;
@@ -948,12 +641,12 @@ int32_t timed_begin(hipStream_t s, std::pair<hipEvent_t, hipEvent_t> &ev) {
   return LSRVT_OK;
 }
 
-int32_t timed_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> &ev) {
+int32_t timed_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> &ev, uint64_t launches) {
   KernelTimer &T = timer();
   LSRVT_HIP(hipEventRecord(ev.second, s));
   std::lock_guard<std::mutex> lk(T.mu);
   T.pending.push_back(ev);
-  ++T.launches;
+  T.launches += launches;
   return LSRVT_OK;
 }
 
@@ -1031,6 +724,11 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   bool more = S != 0;
   uint32_t c[4] = {0, 0, 0, 0};
   while (more) {
+    // one event pair around a batch of back-to-back level launches (while
+    // timing is on): the launches of a batch run without gaps
+    const bool timed = timer().on;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (timed && (rc = timed_begin(s, ev))) return rc;
     for (int i = 0; i < batch; ++i) {
       ++L;
       unsigned grid = cap;
@@ -1040,13 +738,10 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
       } else if (!st.prev.empty()) {
         grid = 64;  // most likely past the last level
       }
-      const bool timed = timer().on;
-      std::pair<hipEvent_t, hipEvent_t> ev;
-      if (timed && (rc = timed_begin(s, ev))) return rc;
       hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kVTThreads), 0, s, A, L);
       LSRVT_LAUNCHED();
-      if (timed && (rc = timed_end(s, ev))) return rc;
     }
+    if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
     LSRVT_HIP(hipMemcpyAsync(c, W.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
     if (c[3] & 1u) return LSRVT_EINVAL;
@@ -1080,96 +775,6 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     fprintf(stderr, "\n");
   }
   return LSRVT_OK;
-}
-
-// The same pass by brick rounds (see k_vt_round).  The first round relaxes
-// every brick from its own sites; later rounds the bricks whose neighbours
-// published changed faces, until no brick is queued.
-int32_t run_vt_rounds(const uint8_t *band, const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
-                      CvtWork &W, VTState &st, hipStream_t s) {
-  VTGrid bg = vt_grid(g);
-  int32_t rc;
-  if ((rc = fill<uint32_t>(W.bcount, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.bfill, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.cnt, 3, 0u, s))) return rc;
-  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
-  if (debug_levels && (rc = fill<uint32_t>(W.rstats, 2, 0u, s))) return rc;
-  if (S) {
-    hipLaunchKernelGGL(k_site_count, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, band, g, bg, W.bcount,
-                       W.site_band, W.err);
-    LSRVT_LAUNCHED();
-  }
-  if ((rc = ScanU32::run(W.bcount, bg.nbricks, W.boff, W.scan_work, W.scan_bytes, s))) return rc;
-  if (S) {
-    hipLaunchKernelGGL(k_site_fill, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g, bg, W.boff, W.bfill, W.blist);
-    LSRVT_LAUNCHED();
-  }
-  RoundArgs A;
-  A.band = band;
-  A.g = g;
-  A.bg = bg;
-  A.sites = sites;
-  A.blist = W.blist;
-  A.boff = W.boff;
-  A.site_band = W.site_band;
-  A.faces = W.faces;
-  A.cell = cell;
-  A.queued = W.queued;
-  A.cnt = W.cnt;
-  A.err = W.err;
-  A.stats = debug_levels ? W.rstats : nullptr;
-  const unsigned grid_all = (unsigned)(bg.nbricks < 65535 ? bg.nbricks : 65535);
-  const unsigned grid_list = (unsigned)(bg.nbricks < 4096 ? bg.nbricks : 4096);
-  const int64_t max_rounds = 2 * bg.nbricks + 16;
-  uint32_t epoch = 1;
-  int64_t done = 0;
-  int batch = st.prev.empty() ? 4 : (int)st.prev[0];
-  uint32_t c[4] = {0, 0, 0, 0};
-  while (true) {
-    for (int i = 0; i < batch; ++i) {
-      const bool all = done == 0;
-      A.list_in = (epoch & 1) ? W.list_a : W.list_b;
-      A.list_out = (epoch & 1) ? W.list_b : W.list_a;
-      const bool timed = timer().on;
-      std::pair<hipEvent_t, hipEvent_t> ev;
-      if (timed && (rc = timed_begin(s, ev))) return rc;
-      hipLaunchKernelGGL(k_vt_round, dim3(all ? grid_all : grid_list), dim3(kVTThreads), 0, s, A, epoch, all ? 1 : 0);
-      LSRVT_LAUNCHED();
-      if (timed && (rc = timed_end(s, ev))) return rc;
-      ++epoch;
-      ++done;
-    }
-    LSRVT_HIP(hipMemcpyAsync(c, W.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
-    LSRVT_HIP(hipStreamSynchronize(s));
-    if (c[3] & 1u) return LSRVT_EINVAL;
-    if (c[3]) return LSRVT_EDEVICE;
-    if (c[epoch % 3] == 0) break;
-    if (done > max_rounds) return LSRVT_EDEVICE;
-    batch = 2;
-  }
-  st.prev.assign(1, (uint32_t)done);
-  if (timer().on) {
-    std::lock_guard<std::mutex> lk(timer().mu);
-    timer().passes += 1;
-    timer().voxels_per_pass = g.n;
-  }
-  if (debug_levels) {
-    uint32_t h[2];
-    LSRVT_HIP(hipMemcpyAsync(h, W.rstats, sizeof(h), hipMemcpyDeviceToHost, s));
-    LSRVT_HIP(hipStreamSynchronize(s));
-    fprintf(stderr, "[lsrvt] vt rounds=%lld bricks=%u sweep cycles/brick=%.2f\n", (long long)done, h[0],
-            h[0] ? (double)h[1] / h[0] : 0.0);
-  }
-  return LSRVT_OK;
-}
-
-bool use_rounds() {
-  static const bool r = [] {
-    const char *e = getenv("LSRVT_VT");
-    return e && e[0] == 'r';
-  }();
-  return r;
 }
 
 // Errors a run reported on the device (synchronises).
@@ -1231,11 +836,7 @@ extern "C" int32_t lsrvt_vt(const uint8_t *d_band, lsrvt_dims dims, const uint32
   if ((rc = begin(W, g, s))) return rc;
   if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
-  if (use_rounds()) {
-    if ((rc = run_vt_rounds(d_band, g, d_sites, n_sites, d_cell, W, st, s))) return rc;
-  } else if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) {
-    return rc;
-  }
+  if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
   return vt_errors(W, s);
 }
 
@@ -1273,9 +874,7 @@ extern "C" int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrv
   if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
   for (int32_t t = 0; t <= iters; ++t) {
-    rc = use_rounds() ? run_vt_rounds(d_band, g, d_sites, n_sites, d_cell, W, st, s)
-                      : run_vt(g, d_sites, n_sites, d_cell, W, st, s);
-    if (rc) return rc;
+    if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
     if (t == iters) break;
     if ((rc = run_update(d_cell, g, d_weights, d_sites, n_sites, W.ds, W, s))) return rc;
     hipLaunchKernelGGL(k_mean_ds_part, dim3(kMeanParts), dim3(256), 0, s, W.ds, n_sites, W.mean_part);
