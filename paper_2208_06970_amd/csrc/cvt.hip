@@ -50,6 +50,7 @@ constexpr int BX = 16, BY = 16, BZ = 16;
 constexpr int kRows = BY * BZ;  // a brick is 256 rows of 16 voxels along x
 constexpr int kVTThreads = 256;
 constexpr int kHistLen = 8192;  // per-level record of active brick counts
+constexpr int kSub = 64;        // sub-lists per level, so that list appends rarely share a counter
 
 struct VTGrid {
   int32_t nbx, nby, nbz;
@@ -67,7 +68,7 @@ struct BFSArgs {
   uint32_t *cell;      // [N] site id of every reached voxel (NONE elsewhere)
   uint32_t *queued;    // [nbricks] tag of the last level a brick was queued for
   uint32_t *list0, *list1;  // bricks of even / odd levels
-  uint32_t *cnt;       // [3] rotating list counters: cnt[L % 3] bricks of level L
+  uint32_t *cnt;       // [3][kSub] rotating list counters: cnt[L % 3][j] bricks in sub-list j of level L
   uint32_t *hist;      // [kHistLen] active bricks per level
   uint32_t *err;
 };
@@ -76,15 +77,16 @@ __device__ __forceinline__ int64_t brick_row_base(const Geom &g, int x0, int y, 
   return x0 + (int64_t)g.nx * (y + (int64_t)g.ny * z);
 }
 
-// Queue brick (bx, by, bz) and its six face neighbours for the level tagged
-// `tag`: lanes 0..6 of the calling wave take one brick each, so the tag
-// atomics of the seven bricks overlap.  Called by a whole wave.
-__device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *out,
-                             uint32_t *out_cnt) {
+// Queue brick (bx, by, bz) (bit 0 of `which`) and its neighbours at x-, x+,
+// y-, y+, z-, z+ (bits 1..6) for the level tagged `tag` into sub-list `j`
+// (list + j * nbricks, counter cnt[j]): lanes 0..6 of the calling wave take
+// one brick each, so the tag atomics overlap.  Called by a whole wave.
+__device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *list, uint32_t *cnt,
+                             uint32_t j, uint32_t which) {
   const int k = lane_id();
   bool want = false;
   uint32_t nb = 0;
-  if (k < 7) {
+  if (k < 7 && ((which >> k) & 1u)) {
     const int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
     const int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
     const int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
@@ -96,13 +98,14 @@ __device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t 
   const uint64_t m = __ballot(want);
   if (!m) return;
   uint32_t base = 0;
-  if (k == 0) base = atomicAdd(out_cnt, (uint32_t)__popcll(m));
+  if (k == 0) base = atomicAdd(&cnt[j], (uint32_t)__popcll(m));
   base = __shfl(base, 0, kWave);
-  if (want) out[base + (uint32_t)__popcll(m & lanemask_lt())] = nb;
+  if (want) list[(size_t)j * A.bg.nbricks + base + (uint32_t)__popcll(m & lanemask_lt())] = nb;
 }
 
 // Per-thread variant for the sites of level 0.
-__device__ void queue_around_one(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *out_cnt) {
+__device__ void queue_around_one(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *list,
+                                 uint32_t *cnt, uint32_t j) {
 #pragma unroll
   for (int k = 0; k < 7; ++k) {
     const int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
@@ -110,7 +113,8 @@ __device__ void queue_around_one(const BFSArgs &A, int bx, int by, int bz, uint3
     const int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
     if (nx < 0 || ny < 0 || nz < 0 || nx >= A.bg.nbx || ny >= A.bg.nby || nz >= A.bg.nbz) continue;
     const uint32_t nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
-    if (A.queued[nb] < tag && atomicMax(&A.queued[nb], tag) < tag) A.list1[atomicAdd(out_cnt, 1u)] = nb;
+    if (A.queued[nb] < tag && atomicMax(&A.queued[nb], tag) < tag)
+      list[(size_t)j * A.bg.nbricks + atomicAdd(&cnt[j], 1u)] = nb;
   }
 }
 
@@ -173,7 +177,7 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
   atomicMin(&A.cell[v], s);
   atomicOr(&A.vis[(int64_t)b * kRows + row], bit);
   atomicOr(&A.fr[(int64_t)b * kRows + row], bit);  // parity 0 = level 0
-  queue_around_one(A, bx, by, bz, tag, &A.cnt[1]);
+  queue_around_one(A, bx, by, bz, tag, A.list1, A.cnt + kSub, blockIdx.x % kSub);
 }
 
 // Level L: a voxel not reached yet is reached now when a same-band face
@@ -181,23 +185,33 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
 // neighbours (Eq. 1 with ties to the lower id).  Processes the bricks listed
 // for this level (items first, first + stride, ...); a brick that reached
 // anything lists itself and its neighbours for L + 1.
-__device__ void bfs_level(const BFSArgs &A, uint32_t L, uint32_t count, uint32_t tag, uint32_t first,
+__device__ void bfs_level(const BFSArgs &A, uint32_t L, const uint32_t *off, uint32_t tag, uint32_t first,
                           uint32_t stride) {
   const int t = threadIdx.x;
+  const uint32_t count = off[kSub];
   const uint32_t *list_in = (L & 1) ? A.list1 : A.list0;
   uint32_t *list_out = (L & 1) ? A.list0 : A.list1;
-  uint32_t *out_cnt = &A.cnt[(L + 1) % 3];
+  uint32_t *out_cnt = A.cnt + ((L + 1) % 3) * kSub;
   const uint32_t *fin = A.fr + (size_t)((L - 1) & 1) * A.bg.nbricks * kRows;
   uint32_t *fout = A.fr + (size_t)(L & 1) * A.bg.nbricks * kRows;
   const int ly = t & 15, lz = t >> 4;
   const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
   for (uint32_t item = first; item < count; item += stride) {
-    const uint32_t b = list_in[item];
+    // item -> (sub-list, position) by bisection over the sub-list offsets
+    uint32_t lo = 0, hi = kSub;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (off[mid] <= item)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t b = list_in[(size_t)lo * A.bg.nbricks + (item - off[lo])];
     const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby), bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
     const int64_t rb = (int64_t)b * kRows;
+    const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
     const uint32_t F = fin[rb + t];
     const uint32_t vrow = A.vis[rb + t];
-    const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
     const uint32_t fym = ly > 0 ? fin[rb + t - 1] : (by > 0 ? fin[(b - bsy) * kRows + t + 15] : 0u);
     const uint32_t fyp = ly < BY - 1 ? fin[rb + t + 1] : (by < A.bg.nby - 1 ? fin[(b + bsy) * kRows + t - 15] : 0u);
     const uint32_t fzm = lz > 0 ? fin[rb + t - 16] : (bz > 0 ? fin[(b - bsz) * kRows + t + 240] : 0u);
@@ -246,7 +260,7 @@ __device__ void bfs_level(const BFSArgs &A, uint32_t L, uint32_t count, uint32_t
       if (nw) A.vis[rb + t] = vrow | nw;
     }
     fout[rb + t] = nw;
-    if (__syncthreads_or(nw != 0) && t < kWave) queue_around(A, bx, by, bz, tag, list_out, out_cnt);
+    if (__syncthreads_or(nw != 0) && t < kWave) queue_around(A, bx, by, bz, tag, list_out, out_cnt, b % kSub, 0x7Fu);
   }
 }
 
@@ -254,19 +268,25 @@ __device__ void bfs_level(const BFSArgs &A, uint32_t L, uint32_t count, uint32_t
 // L + 2 (level L + 1 appends to it), so launches may be enqueued past the
 // last level: they find an empty list and return.
 __global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L) {
-  __shared__ uint32_t s_count;
+  __shared__ uint32_t off[kSub + 1];
   const int t = threadIdx.x;
-  if (t == 0) {
-    s_count = A.cnt[L % 3];
-    if (blockIdx.x == 0) {
-      A.cnt[(L + 2) % 3] = 0;
-      A.hist[L % kHistLen] = s_count;
+  if (t < kWave) {
+    // exclusive prefix of the sub-list counts of level L
+    const uint32_t c = t < kSub ? A.cnt[(L % 3) * kSub + t] : 0u;
+    uint32_t inc = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t v = __shfl_up(inc, o, kWave);
+      if (t >= o) inc += v;
     }
+    if (t < kSub) off[t] = inc - c;
+    if (t == kSub - 1) off[kSub] = inc;
+    if (blockIdx.x == 0 && t < kSub) A.cnt[((L + 2) % 3) * kSub + t] = 0;  // level L + 1 lists into them
   }
   __syncthreads();
-  const uint32_t count = s_count;
-  if (count == 0) return;
-  bfs_level(A, L, count, L + 1, blockIdx.x, gridDim.x);
+  if (blockIdx.x == 0 && t == 0) A.hist[L % kHistLen] = off[kSub];
+  if (off[kSub] == 0) return;
+  bfs_level(A, L, off, L + 1, blockIdx.x, gridDim.x);
 }
 
 // ----------------------------------------------------------------------------
@@ -276,20 +296,20 @@ struct Sums {
   unsigned long long *M, *Sx, *Sy, *Sz;
 };
 
-// One workgroup per 64x8x8 tile: each thread folds 16 consecutive voxels of a
-// row into runs of equal cell id, the runs accumulate in an LDS hash table
-// keyed by cell id (LDS atomics), and the table is flushed with one set of
-// global atomics per distinct cell in the tile.  Along a row y and z are
-// fixed, so S_y = M y and S_z = M z per run.
+// One workgroup per 64x8x8 tile; each wave takes rows of the tile with one
+// lane per voxel (coalesced loads).  A segmented scan over the lanes sums
+// (w, w x) over each run of equal cell id; the last lane of a run adds the
+// run into an LDS hash table keyed by cell id, and the table is flushed with
+// one set of global atomics per distinct cell in the tile.  Along a row y
+// and z are fixed, so S_y = M y and S_z = M z per run.
 constexpr int TX = 64, TY = 8, TZ = 8;
 constexpr int kTabCap = 512;
-
 
 __global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ cell, const uint16_t *__restrict__ w,
                                                   Geom g, uint32_t S, Sums sums) {
   __shared__ uint32_t tkey[kTabCap];
   __shared__ unsigned long long tM[kTabCap], tX[kTabCap], tY[kTabCap], tZ[kTabCap];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
   const int ntx = (g.nx + TX - 1) / TX, nty = (g.ny + TY - 1) / TY, ntz = (g.nz + TZ - 1) / TZ;
   const int64_t ntiles = (int64_t)ntx * nty * ntz;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -299,54 +319,50 @@ __global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ c
     }
     __syncthreads();
     const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
-    // thread -> (quarter row, y, z) inside the tile
-    const int qx = (t & 3) * 16, ly = (t >> 2) & 7, lz = t >> 5;
-    const int x0 = tx * TX + qx, y = ty * TY + ly, z = tz * TZ + lz;
-    if (y < g.ny && z < g.nz && x0 < g.nx) {
-      const int64_t base = (int64_t)g.nx * (y + (int64_t)g.ny * z);
-      const int xe = x0 + 16 < g.nx ? x0 + 16 : g.nx;
-      uint32_t rc = kNone;
-      uint64_t rm = 0, rx = 0;
-      auto flush = [&]() {
-        if (rc != kNone && rc < S && rm) {
-          int sl = lds_slot<kTabCap>(tkey, rc);
-          if (sl >= 0) {
-            atomicAdd(&tM[sl], (unsigned long long)rm);
-            atomicAdd(&tX[sl], (unsigned long long)rx);
-            atomicAdd(&tY[sl], (unsigned long long)(rm * (uint64_t)y));
-            atomicAdd(&tZ[sl], (unsigned long long)(rm * (uint64_t)z));
-          } else {
-            atomicAdd(&sums.M[rc], (unsigned long long)rm);
-            atomicAdd(&sums.Sx[rc], (unsigned long long)rx);
-            atomicAdd(&sums.Sy[rc], (unsigned long long)(rm * (uint64_t)y));
-            atomicAdd(&sums.Sz[rc], (unsigned long long)(rm * (uint64_t)z));
-          }
-        }
-      };
-      // all 16 loads in flight before the runs are folded
-      uint32_t cc[16], ww[16];
+    const int x = tx * TX + lane;
+    for (int r = wid; r < TY * TZ; r += 256 / kWave) {
+      const int y = ty * TY + (r & 7), z = tz * TZ + (r >> 3);
+      if (y >= g.ny || z >= g.nz) continue;  // uniform across the wave
+      const bool in = x < g.nx;
+      const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      const uint32_t c = in ? cell[v] : kNone;
+      const uint32_t wv = in ? (w ? (uint32_t)w[v] : 1u) : 0u;
+      // segmented inclusive scan over runs of equal c
+      const uint32_t cl = __shfl_up(c, 1, kWave), cr = __shfl_down(c, 1, kWave);
+      const bool head = lane == 0 || cl != c;
+      const bool tail = lane == kWave - 1 || cr != c;
+      uint32_t m = wv;
+      uint64_t sx = (uint64_t)wv * (uint64_t)x;
+      bool seg = head;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const bool in = x0 + i < xe;
-        cc[i] = in ? cell[base + x0 + i] : kNone;
-        ww[i] = in ? (w ? (uint32_t)w[base + x0 + i] : 1u) : 0u;
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (cc[i] != rc) {
-          flush();
-          rc = cc[i];
-          rm = 0;
-          rx = 0;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t mo = __shfl_up(m, d, kWave);
+        const uint64_t so = __shfl_up(sx, d, kWave);
+        const bool fo = __shfl_up(seg ? 1 : 0, d, kWave) != 0;
+        if (lane >= d && !seg) {
+          m += mo;
+          sx += so;
+          seg = fo;
         }
-        rm += ww[i];
-        rx += (uint64_t)ww[i] * (uint64_t)(x0 + i);
       }
-      flush();
+      if (tail && c < S && m) {
+        const int sl = lds_slot<kTabCap>(tkey, c);
+        if (sl >= 0) {
+          atomicAdd(&tM[sl], (unsigned long long)m);
+          atomicAdd(&tX[sl], (unsigned long long)sx);
+          atomicAdd(&tY[sl], (unsigned long long)m * (uint64_t)y);
+          atomicAdd(&tZ[sl], (unsigned long long)m * (uint64_t)z);
+        } else {
+          atomicAdd(&sums.M[c], (unsigned long long)m);
+          atomicAdd(&sums.Sx[c], (unsigned long long)sx);
+          atomicAdd(&sums.Sy[c], (unsigned long long)m * (uint64_t)y);
+          atomicAdd(&sums.Sz[c], (unsigned long long)m * (uint64_t)z);
+        }
+      }
     }
     __syncthreads();
     for (int i = t; i < kTabCap; i += 256) {
-      uint32_t c = tkey[i];
+      const uint32_t c = tkey[i];
       if (c != kNone && tM[i]) {
         atomicAdd(&sums.M[c], tM[i]);
         atomicAdd(&sums.Sx[c], tX[i]);
@@ -529,7 +545,7 @@ __global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, con
 
 struct CvtWork {
   uint32_t *eq, *fr, *vis;
-  uint32_t *queued, *list_a, *list_b, *cnt;  // cnt[0..2] level counters, cnt[3] error bits
+  uint32_t *queued, *list_a, *list_b, *cnt;  // cnt[3][kSub] list counters, then error bits
   uint32_t *fb_list, *fb_cnt, *err;
   uint32_t *hist;
   unsigned long long *sums;  // 4 x S
@@ -554,9 +570,9 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto fr = a.template take<uint32_t>(2 * nb * kRows);
   auto vis = a.template take<uint32_t>(nb * kRows);
   auto queued = a.template take<uint32_t>(nb);
-  auto la = a.template take<uint32_t>(nb);
-  auto lb = a.template take<uint32_t>(nb);
-  auto cnt = a.template take<uint32_t>(4);  // 3 list counters, errors
+  auto la = a.template take<uint32_t>((size_t)kSub * nb);
+  auto lb = a.template take<uint32_t>((size_t)kSub * nb);
+  auto cnt = a.template take<uint32_t>(3 * kSub + 1);  // list counters, then error bits
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
   auto sums = a.template take<unsigned long long>(4 * s1);
@@ -572,7 +588,7 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
     W->list_a = la;
     W->list_b = lb;
     W->cnt = cnt;
-    W->err = cnt + 3;
+    W->err = cnt + 3 * kSub;
     W->fb_list = fbl;
     W->fb_cnt = fbc;
     W->sums = sums;
@@ -698,7 +714,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   if ((rc = fill<uint32_t>(W.fr, 2 * bg.nbricks * kRows, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.vis, bg.nbricks * kRows, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.cnt, 3, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.cnt, 3 * kSub, 0u, s))) return rc;
   BFSArgs A;
   A.g = g;
   A.bg = bg;
@@ -722,7 +738,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   uint32_t L = 0;  // levels enqueued
   int batch = st.prev.empty() ? 16 : (int)st.prev.size() + 4;
   bool more = S != 0;
-  uint32_t c[4] = {0, 0, 0, 0};
+  std::vector<uint32_t> c(3 * kSub + 1, 0);
   while (more) {
     // one event pair around a batch of back-to-back level launches (while
     // timing is on): the launches of a batch run without gaps
@@ -742,11 +758,13 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
       LSRVT_LAUNCHED();
     }
     if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
-    LSRVT_HIP(hipMemcpyAsync(c, W.cnt, sizeof(c), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipMemcpyAsync(c.data(), W.cnt, sizeof(uint32_t) * c.size(), hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
-    if (c[3] & 1u) return LSRVT_EINVAL;
-    if (c[3]) return LSRVT_EDEVICE;
-    more = c[(L + 1) % 3] != 0;  // bricks listed for the next level
+    const uint32_t e = c[3 * kSub];
+    if (e & 1u) return LSRVT_EINVAL;
+    if (e) return LSRVT_EDEVICE;
+    more = false;  // bricks listed for the next level?
+    for (int j = 0; j < kSub; ++j) more = more || c[((L + 1) % 3) * kSub + j] != 0;
     if ((int64_t)L > max_level) return LSRVT_EDEVICE;
     batch = 8;
   }
@@ -807,7 +825,7 @@ int32_t begin(CvtWork &W, const Geom &g, hipStream_t s) {
   int32_t rc;
   VTGrid bg = vt_grid(g);
   if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.cnt, 4, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.cnt, 3 * kSub + 1, 0u, s))) return rc;
   return LSRVT_OK;
 }
 
