@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 VT_BYTES_PER_VOXEL = 5           # one Voronoi pass must read the band (1 B) and write the cell (4 B)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_vt_round_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bfs_level_traffic.json")
 CVT_SOURCE = os.path.join(ROOT, "paper_2208_06970_amd", "csrc", "cvt.hip")
 
 
@@ -46,7 +46,7 @@ def _source_hash():
 
 
 def _traffic_per_launch():
-    """HBM bytes per launch of the round kernel from committed rocprofv3 counters,
+    """HBM bytes per launch of the Voronoi level kernel from committed rocprofv3 counters,
     or None when they are missing or the kernel source changed since."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -169,7 +169,7 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     value = n * wl.iters / (ms_per_step / 1e3) / 1e9
     phases = {k: round(v / args.steps, 4) for k, v in phase_ms.items()}
-    # roofline of the dominant kernel: the Voronoi round kernel, HBM-bound
+    # roofline of the dominant kernel: the Voronoi level kernel, HBM-bound
     alg_bytes_per_launch = VT_BYTES_PER_VOXEL * vox_per_pass * vt_passes / max(vt_launches, 1)
     avg_launch_s = vt_ms / 1e3 / max(vt_launches, 1)
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
