@@ -16,6 +16,15 @@ whole step (isobands, components, final pass and statistics included) in the
 denominator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Two more modes print their own JSON line instead of the main one:
+  --batch   64 independent Fourier volumes (edges 32..192, cubes and 2:1:1
+            boxes, 3..10 isovalues, 15 updates) through lsrvt_batch_run on
+            several streams, against the same jobs run one at a time;
+  --serve   a Poisson stream of jobs (edges 64..192 per axis, 3..12
+            isovalues, 10..30 updates, 4..8 variables) through the serving
+            loop with HBM-footprint admission, against one slot; reports
+            p50/p99 latency and throughput per arrival rate.
 """
 from __future__ import annotations
 
@@ -82,6 +91,123 @@ def cpu_baseline(wl, seeds, T_sample=2):
                       f"instead of {wl.iters}; single-threaded C"}
 
 
+def _fourier_job_inputs(shape, seed, n_iso, n_vars, n_bins, rho, n_modes=128):
+    """Host arrays of one Fourier job (field, isovalues, weights, variables, edges)."""
+    import numpy as np
+    import synth
+    f = synth.fourier_field(shape, seed, n_modes=n_modes)
+    iso = synth.quantile_isovalues(f, [(i + 1) / (n_iso + 1) for i in range(n_iso)])
+    w = synth.gradient_weight(f)
+    x = np.stack([synth.fourier_field(shape, 1000 * seed + 1 + j, n_modes=n_modes) for j in range(n_vars)])
+    return f, iso, w, np.ascontiguousarray(x), synth.histogram_edges(x, n_bins)
+
+
+def _device_job(shape, seed, n_iso, n_vars, n_bins, rho, iters):
+    """A job with inputs on the device; sites drawn from its components (computed once, outside timing)."""
+    import numpy as np
+    import torch
+    import paper_2208_06970_amd as L
+    import synth
+    f, iso, w, x, e = _fourier_job_inputs(shape, seed, n_iso, n_vars, n_bins, rho)
+    fd = torch.from_numpy(f).cuda()
+    band, _ = L.lsrvt_isobands(fd, iso)
+    cc = L.lsrvt_components(band, n_iso + 1)
+    comp = cc.comp.cpu().numpy().view(np.uint32)
+    seeds = synth.seed_sites(comp, cc.n_comp, w, rho, 7919 * seed + 1)
+    return dict(field=fd, iso=iso, seeds=torch.from_numpy(seeds.view(np.int32)).cuda(),
+                weights=torch.from_numpy(w.view(np.int16)).cuda(), iters=iters,
+                variables=torch.from_numpy(x).cuda(), edges=torch.from_numpy(e).cuda(), cov=True,
+                cap_comp=int(cc.n_comp) + 16, voxels=f.size)
+
+
+def bench_batch(args):
+    """64 uneven volumes: lsrvt_batch_run on several streams vs one job at a time."""
+    import numpy as np
+    import torch
+    import paper_2208_06970_amd as L
+    rng = np.random.default_rng(3)
+    specs = []
+    for j in range(args.batch_jobs):
+        e = int(rng.choice(np.arange(32, 193, 16)))
+        if rng.random() < 0.5:
+            shape = (e, e, e)
+        else:
+            shape = [e // 2, e // 2, e // 2]
+            shape[int(rng.integers(0, 3))] = e
+            shape = tuple(shape)
+        specs.append((shape, 3000 + j, int(rng.integers(3, 11))))
+    _log(f"batch: generating {len(specs)} volumes")
+    jobs = [_device_job(sh, sd, k, 8, 32, 4096.0, 15) for sh, sd, k in specs]
+    vox_iters = sum(j["voxels"] * j["iters"] for j in jobs)
+
+    def make():
+        return [L.BatchJob(field=j["field"], iso=j["iso"], seeds=j["seeds"], weights=j["weights"], iters=j["iters"],
+                           variables=j["variables"], edges=j["edges"], cov=True, cap_comp=j["cap_comp"])
+                for j in jobs]
+
+    def serial():
+        ws = L.Workspace()
+        for j in jobs:
+            band, _ = L.lsrvt_isobands(j["field"], j["iso"])
+            cc = L.lsrvt_components(band, len(j["iso"]) + 1, cap_comp=j["cap_comp"], ws=ws)
+            r = L.lsrvt_cvt(band, cc.comp, j["seeds"], j["weights"], j["iters"], ws=ws, want_mean_ds=False)
+            L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, cc.comp_band, cc.n_comp, len(j["iso"]) + 1,
+                              j["variables"], j["edges"], cov=True, ws=ws)
+        torch.cuda.synchronize()
+
+    res = {}
+    ws = L.Workspace()
+    for name, fn in (("serial", serial), ("batched", lambda: L.lsrvt_batch_run(make(), n_streams=args.streams, ws=ws))):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res[name] = float(np.median(ts))
+        _log(f"batch {name}: {res[name] * 1e3:.1f} ms")
+    print(json.dumps({"metric": "Gvoxels/s per Lloyd iteration, 64-volume batch (whole path per job)",
+                      "unit": "Gvoxels/s", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
+                      "value": round(vox_iters / res["batched"] / 1e9, 4),
+                      "serial_value": round(vox_iters / res["serial"] / 1e9, 4),
+                      "ms_batched": round(res["batched"] * 1e3, 3), "ms_serial": round(res["serial"] * 1e3, 3),
+                      "speedup": round(res["serial"] / res["batched"], 3), "streams": args.streams,
+                      "config": {"workload": "64 Fourier volumes, edges 32..192 (cubes and 2:1:1), 3..10 isovalues, "
+                                             "T=15, 8 vars, 32-bin hist, 8x8 cov", "voxels": int(sum(j["voxels"] for j in jobs))},
+                      "dtype": "u32", "data": "synthetic"}), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals through the serving loop, several slots vs one slot."""
+    import numpy as np
+    import paper_2208_06970_amd.serve as srv
+    rng = np.random.default_rng(5)
+    specs = []
+    for j in range(args.serve_jobs):
+        shape = tuple(int(v) for v in rng.integers(64, 193, size=3))
+        specs.append((shape, 5000 + j, int(rng.integers(3, 13)), int(rng.integers(4, 9)), int(rng.integers(10, 31))))
+    _log(f"serve: generating {len(specs)} jobs")
+    made = [_device_job(sh, sd, k, m, 32, 4096.0, t) for sh, sd, k, m, t in specs]
+    jobs = [srv.Job(field=d["field"], iso=d["iso"], seeds=d["seeds"], weights=d["weights"], iters=d["iters"],
+                    variables=d["variables"], edges=d["edges"], cov=True, cap_comp=d["cap_comp"]) for d in made]
+    budget = int(args.budget_gib * 2**30)
+    srv.serve(jobs[:2], [0.0, 0.0], slots=2, budget_bytes=budget)  # warm-up
+    out = {"metric": "p50/p99 request latency and throughput, Poisson job stream", "unit": "ms / Gvoxels/s",
+           "n_gpus": 1, "data": "synthetic", "dtype": "u32",
+           "config": {"workload": f"{len(jobs)} jobs, edges 64..192 per axis, 3..12 isovalues, T=10..30, 4..8 vars, "
+                                  f"32-bin hist, cov", "budget_gib": args.budget_gib, "slots": args.slots},
+           "rates": {}}
+    for rate in args.rates:
+        arr = srv.poisson_arrivals(len(jobs), rate, 5)
+        a = srv.serve(jobs, arr, slots=args.slots, budget_bytes=budget).summary()
+        b = srv.serve(jobs, arr, slots=1, budget_bytes=budget).summary()
+        out["rates"][str(rate)] = {"served": a, "one_slot": b}
+        _log(f"serve rate {rate}: {a['p50_ms']} / {a['p99_ms']} ms (one slot {b['p50_ms']} / {b['p99_ms']})")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +215,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--size", type=int, default=256, help="edge of the cubic Fourier volume")
+    ap.add_argument("--batch", action="store_true", help="64-volume batch vs serial (own JSON line)")
+    ap.add_argument("--batch-jobs", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--serve", action="store_true", help="Poisson serving loop (own JSON line)")
+    ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--rates", type=float, nargs="*", default=[5.0, 20.0, 50.0])
+    ap.add_argument("--budget-gib", type=float, default=96.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -104,6 +238,12 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.batch:
+        bench_batch(args)
+        return
+    if args.serve:
+        bench_serve(args)
+        return
     if args.copy_mib:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

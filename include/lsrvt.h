@@ -236,6 +236,63 @@ int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t 
                         const lsrvt_group_stats *band, void *d_work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Many independent jobs through the whole path in one call (one job = one
+ * volume: Sec. 3.1 isobands and components, Algorithm 1, Sec. 3.3 statistics,
+ * as the four calls above compute them).  Jobs run on up to n_streams
+ * library-created HIP streams (default priority) driven by as many host
+ * threads, so small jobs overlap on the device and one job's host waits do
+ * not stall the others; every job's outputs are bit-identical to running its
+ * four calls alone.  The call waits for work already enqueued on `stream`
+ * before starting and returns when every job is done (it synchronises).
+ * Per job: inputs as for the single calls (seeds refer to voxels of the
+ * job's volume, cap_comp bounds the component count and sizes the component
+ * tables and component statistics); outputs are written to the job's
+ * buffers, n_comp and status are set (status LSRVT_ECAPACITY when the
+ * volume has more components than cap_comp, with d_comp and n_comp valid).
+ * Returns LSRVT_OK when every job succeeded, else the first failing job's
+ * status.  Workspace: lsrvt_batch_workspace(jobs, n_jobs, n_streams), one
+ * slice per stream sized for the largest job.
+ */
+typedef struct {
+  /* inputs */
+  lsrvt_dims dims;
+  const float *d_field;      /* float32[N] */
+  const float *h_iso;        /* host, n_iso increasing finite isovalues (n_iso + 1 bands) */
+  int32_t n_iso;
+  const uint32_t *d_seeds;   /* uint32[n_sites] */
+  uint32_t n_sites;
+  const uint16_t *d_weights; /* uint16[N] or NULL */
+  int32_t iters;
+  const float *d_vars;       /* float32[n_vars][N] */
+  int32_t n_vars;
+  const float *d_edges;      /* float32[n_vars][n_bins + 1] or NULL */
+  int32_t n_bins;
+  uint32_t flags;            /* LSRVT_STATS_HIST | LSRVT_STATS_COV */
+  uint32_t cap_comp;
+  /* outputs (device, caller-allocated) */
+  uint8_t *d_band;           /* [N] */
+  uint32_t *d_status;        /* [1] NaN flag of the isoband pass */
+  uint32_t *d_comp;          /* [N] */
+  uint8_t *d_comp_band;      /* [cap_comp] */
+  uint64_t *d_comp_size;     /* [cap_comp] */
+  uint32_t *d_comp_first;    /* [cap_comp] */
+  uint32_t *d_band_offset;   /* [n_iso + 2] */
+  uint32_t *d_cell;          /* [N] */
+  uint32_t *d_sites;         /* [n_sites] */
+  uint32_t *d_site_comp;     /* [n_sites] */
+  lsrvt_cell_stats cell;     /* n_sites units */
+  lsrvt_group_stats comp;    /* cap_comp units (the first n_comp are written) */
+  lsrvt_group_stats band;    /* n_iso + 1 units */
+  /* filled by the call */
+  uint32_t n_comp;
+  int32_t status;
+} lsrvt_job;
+
+size_t lsrvt_batch_workspace(const lsrvt_job *jobs, int32_t n_jobs, int32_t n_streams);
+int32_t lsrvt_batch_run(lsrvt_job *jobs, int32_t n_jobs, int32_t n_streams, void *d_work,
+                        size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Structured hierarchical layout (Sec. 3.2.4, "Data Reduction and Structured
  * Data Layout"; Fig. 5): the voxels that lie in a cell, ordered by band, then
  * component, then cell, then linear index, so that every band, component

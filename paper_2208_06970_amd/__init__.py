@@ -34,7 +34,8 @@ STATS_COV = 2
 EXPORTS = (
     "lsrvt_status_string", "lsrvt_version", "lsrvt_isobands", "lsrvt_components_workspace",
     "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
-    "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract",
+    "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
+    "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract",
     "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
@@ -65,6 +66,20 @@ class GroupStatsC(ctypes.Structure):
     _fields_ = [(k, ctypes.c_void_p) for k in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov")]
 
 
+class JobC(ctypes.Structure):
+    """Mirror of lsrvt_job."""
+    _fields_ = ([("dims", Dims), ("d_field", ctypes.c_void_p), ("h_iso", ctypes.c_void_p), ("n_iso", ctypes.c_int32),
+                 ("d_seeds", ctypes.c_void_p), ("n_sites", ctypes.c_uint32), ("d_weights", ctypes.c_void_p),
+                 ("iters", ctypes.c_int32), ("d_vars", ctypes.c_void_p), ("n_vars", ctypes.c_int32),
+                 ("d_edges", ctypes.c_void_p), ("n_bins", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                 ("cap_comp", ctypes.c_uint32)]
+                + [(k, ctypes.c_void_p) for k in ("d_band", "d_status", "d_comp", "d_comp_band", "d_comp_size",
+                                                  "d_comp_first", "d_band_offset", "d_cell", "d_sites",
+                                                  "d_site_comp")]
+                + [("cell", CellStatsC), ("comp", GroupStatsC), ("band", GroupStatsC), ("n_comp", ctypes.c_uint32),
+                   ("status", ctypes.c_int32)])
+
+
 _LIB = None
 
 
@@ -93,6 +108,9 @@ def _lib():
         lib.lsrvt_aggregate.argtypes = [P, Dims, P, P, u32, P, u32, i32, P, i32, P, i32, u32,
                                         ctypes.POINTER(CellStatsC), ctypes.POINTER(GroupStatsC),
                                         ctypes.POINTER(GroupStatsC), P, S, P]
+        lib.lsrvt_batch_workspace.argtypes = [ctypes.POINTER(JobC), i32, i32]
+        lib.lsrvt_batch_workspace.restype = S
+        lib.lsrvt_batch_run.argtypes = [ctypes.POINTER(JobC), i32, i32, P, S, P]
         lib.lsrvt_layout_workspace.argtypes = [Dims, u32, u32]
         lib.lsrvt_layout_workspace.restype = S
         lib.lsrvt_layout.argtypes = [P, Dims, P, u32, P, u32, i32, P, P, P, P, P, ctypes.POINTER(u32), P, S, P]
@@ -101,7 +119,7 @@ def _lib():
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
-                     "lsrvt_aggregate", "lsrvt_layout", "lsrvt_extract", "lsrvt_timing_enable",
+                     "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_timing_enable",
                      "lsrvt_timing_read"):
             getattr(lib, name).restype = i32
         _LIB = lib
@@ -376,6 +394,125 @@ def lsrvt_aggregate(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int
                                ctypes.byref(c_band), wptr, wbytes, _stream(stream))
     _check(code, "lsrvt_aggregate")
     return out
+
+
+def lsrvt_cvt_workspace_bytes(shape, n_sites: int, iters: int) -> int:
+    """Workspace bytes of lsrvt_cvt for a volume of `shape` (nz, ny, nx)."""
+    return int(_lib().lsrvt_cvt_workspace(_dims(shape), int(n_sites), max(int(iters), 0)))
+
+
+def lsrvt_aggregate_workspace_bytes(shape, n_sites: int, n_comp: int, n_bands: int, n_vars: int, n_bins: int,
+                                    cov: bool) -> int:
+    """Workspace bytes of lsrvt_aggregate."""
+    flags = (STATS_HIST if n_bins else 0) | (STATS_COV if cov else 0)
+    return int(_lib().lsrvt_aggregate_workspace(_dims(shape), int(n_sites), int(n_comp), int(n_bands), int(n_vars),
+                                                int(n_bins), flags))
+
+
+@dataclass
+class BatchJob:
+    """One job of lsrvt_batch_run: its inputs (device tensors, host isovalues) and, after the call, its
+    outputs (labels, tables, statistics) as tensors."""
+    field: "object"
+    iso: "object"
+    seeds: "object"
+    weights: "object"
+    iters: int
+    variables: "object"
+    edges: "object" = None
+    cov: bool = False
+    cap_comp: int = 0
+    band: "object" = None
+    comp: "object" = None
+    comp_band: "object" = None
+    comp_size: "object" = None
+    comp_first: "object" = None
+    band_offset: "object" = None
+    cell: "object" = None
+    sites: "object" = None
+    site_comp: "object" = None
+    stats: "object" = None  # (cell, comp, band) LevelStats
+    n_comp: int = 0
+    status: int = -1
+
+
+def _job_struct(j: BatchJob, keep: list) -> JobC:
+    torch = _torch()
+    _need(j.field, torch.float32, "lsrvt_batch_run")
+    _need(j.seeds, torch.int32, "lsrvt_batch_run")
+    _need(j.variables, torch.float32, "lsrvt_batch_run")
+    dev = j.field.device
+    shape = tuple(j.field.shape)
+    n = j.field.numel()
+    iso = np.ascontiguousarray(np.asarray(j.iso, dtype=np.float32))
+    keep.append(iso)
+    K = len(iso)
+    nb = K + 1
+    S = j.seeds.numel()
+    m = int(j.variables.shape[0])
+    B = 0 if j.edges is None else int(j.edges.shape[1]) - 1
+    cap = int(j.cap_comp) if j.cap_comp else max(1024, n // 16)
+    j.cap_comp = cap
+    j.band = torch.empty(shape, dtype=torch.uint8, device=dev)
+    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    j.comp = torch.empty(shape, dtype=torch.int32, device=dev)
+    j.comp_band = torch.empty(cap, dtype=torch.uint8, device=dev)
+    j.comp_size = torch.empty(cap, dtype=torch.int64, device=dev)
+    j.comp_first = torch.empty(cap, dtype=torch.int32, device=dev)
+    j.band_offset = torch.empty(nb + 1, dtype=torch.int32, device=dev)
+    j.cell = torch.empty(shape, dtype=torch.int32, device=dev)
+    j.sites = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    j.site_comp = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    hist = j.edges is not None
+    j.stats = (_alloc_level(S, m, B, hist, j.cov, torch.float32, dev),
+               _alloc_level(cap, m, B, hist, j.cov, torch.float64, dev),
+               _alloc_level(nb, m, B, hist, j.cov, torch.float64, dev))
+    keep.append(status)
+    c = JobC()
+    c.dims = _dims(shape)
+    c.d_field = j.field.data_ptr()
+    c.h_iso = iso.ctypes.data
+    c.n_iso = K
+    c.d_seeds = j.seeds.data_ptr() if S else None
+    c.n_sites = S
+    c.d_weights = None if j.weights is None else j.weights.data_ptr()
+    c.iters = int(j.iters)
+    c.d_vars = j.variables.data_ptr()
+    c.n_vars = m
+    c.d_edges = None if j.edges is None else j.edges.data_ptr()
+    c.n_bins = B
+    c.flags = (STATS_HIST if hist else 0) | (STATS_COV if j.cov else 0)
+    c.cap_comp = cap
+    for k, t in (("d_band", j.band), ("d_status", status), ("d_comp", j.comp), ("d_comp_band", j.comp_band),
+                 ("d_comp_size", j.comp_size), ("d_comp_first", j.comp_first), ("d_band_offset", j.band_offset),
+                 ("d_cell", j.cell), ("d_sites", j.sites), ("d_site_comp", j.site_comp)):
+        setattr(c, k, t.data_ptr())
+    c.cell = _cstruct(CellStatsC, j.stats[0])
+    c.comp = _cstruct(GroupStatsC, j.stats[1])
+    c.band = _cstruct(GroupStatsC, j.stats[2])
+    return c
+
+
+def lsrvt_batch_run(jobs, n_streams: int = 4, ws: Workspace | None = None, stream=None):
+    """Run every job's whole path (isobands, components, Lloyd loop, statistics) on up to n_streams streams.
+
+    Fills each job's outputs; raises if a job fails.  Synchronises."""
+    lib = _lib()
+    keep = []
+    arr = (JobC * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        arr[i] = _job_struct(j, keep)
+    nbytes = lib.lsrvt_batch_workspace(arr, len(jobs), int(n_streams))
+    if len(jobs) and nbytes == 0:
+        raise LsrvtError(EINVAL, "lsrvt_batch_workspace", "a job has invalid sizes")
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(nbytes)
+    code = lib.lsrvt_batch_run(arr, len(jobs), int(n_streams), wptr, wbytes, _stream(stream))
+    for i, j in enumerate(jobs):
+        j.status = int(arr[i].status)
+        j.n_comp = int(arr[i].n_comp)
+    _check(code, "lsrvt_batch_run")
+    return jobs
 
 
 @dataclass

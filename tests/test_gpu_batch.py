@@ -1,0 +1,99 @@
+"""Many jobs in one call (lsrvt_batch_run): every job's outputs must be
+bit-identical to running its four calls alone, whatever else shares the
+GPU, and its labels must match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2208_06970_amd as L
+import synth
+from tests.gpu_util import banner, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def _job(shape, seed, n_iso, iters, m, bins, cov, rho):
+    f = synth.fourier_field(shape, seed, n_modes=48)
+    iso = synth.quantile_isovalues(f, [(i + 1) / (n_iso + 1) for i in range(n_iso)])
+    w = synth.gradient_weight(f)
+    x = np.stack([synth.fourier_field(shape, 100 * seed + j, n_modes=48) for j in range(m)])
+    edges = None
+    if bins:
+        edges = np.stack([np.linspace(x[j].min(), x[j].max(), bins + 1) for j in range(m)]).astype(np.float32)
+    band = oracle.bands(f, iso)
+    cc = oracle.components(band, n_iso + 1)
+    seeds = synth.seed_sites(cc.comp, cc.n_comp, w, rho, seed + 7)
+    return dict(f=f, iso=iso, w=w, x=x, edges=edges, seeds=seeds, iters=iters, cov=cov, cc=cc, band=band)
+
+
+def _alone(d):
+    f, w, x = dev(d["f"]), dev(d["w"]), dev(np.ascontiguousarray(d["x"]))
+    e = None if d["edges"] is None else dev(d["edges"])
+    band, _ = L.lsrvt_isobands(f, d["iso"])
+    cc = L.lsrvt_components(band, len(d["iso"]) + 1)
+    r = L.lsrvt_cvt(band, cc.comp, dev(d["seeds"]), w, d["iters"], want_mean_ds=False)
+    st = L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, cc.comp_band, cc.n_comp, len(d["iso"]) + 1, x, e, cov=d["cov"])
+    return band, cc, r, st
+
+
+SPECS = [((24, 40, 32), 1, 3, 3, 2, 16, False, 64.0),
+         ((48, 16, 40), 2, 5, 2, 4, 8, True, 96.0),
+         ((32, 32, 32), 3, 8, 4, 3, 0, True, 48.0),
+         ((17, 50, 29), 4, 2, 1, 1, 12, False, 128.0),
+         ((40, 40, 8), 5, 6, 0, 2, 16, True, 80.0),
+         ((64, 20, 20), 6, 4, 5, 5, 4, False, 200.0)]
+
+
+def test_batch_matches_alone_and_oracle():
+    data = [_job(*sp) for sp in SPECS]
+    alone = []
+    for i, d in enumerate(data):
+        banner(f"batch: job {i} alone {d['f'].shape}")
+        alone.append(_alone(d))
+    jobs = [L.BatchJob(field=dev(d["f"]), iso=d["iso"], seeds=dev(d["seeds"]), weights=dev(d["w"]), iters=d["iters"],
+                       variables=dev(np.ascontiguousarray(d["x"])),
+                       edges=None if d["edges"] is None else dev(d["edges"]), cov=d["cov"],
+                       cap_comp=int(d["cc"].n_comp) + 5)
+            for d in data]
+    banner(f"batch: {len(jobs)} jobs on 3 streams")
+    L.lsrvt_batch_run(jobs, n_streams=3)
+    for i, (d, j, (band, cc, r, st)) in enumerate(zip(data, jobs, alone)):
+        assert j.status == 0 and j.n_comp == cc.n_comp, i
+        np.testing.assert_array_equal(host(j.band), host(band))
+        np.testing.assert_array_equal(host(j.comp), host(cc.comp))
+        np.testing.assert_array_equal(host(j.comp_band)[:j.n_comp], host(cc.comp_band))
+        np.testing.assert_array_equal(host(j.comp_size)[:j.n_comp], host(cc.comp_size))
+        np.testing.assert_array_equal(host(j.cell), host(r.cell))
+        S = len(d["seeds"])
+        np.testing.assert_array_equal(host(j.sites)[:S], host(r.sites))
+        np.testing.assert_array_equal(host(j.site_comp)[:S], host(r.site_comp))
+        for lvl, (a, b) in enumerate(zip(j.stats, st)):
+            units = j.n_comp if lvl == 1 else None
+            for k in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov"):
+                ga, gb = getattr(a, k), getattr(b, k)
+                if ga is None:
+                    assert gb is None
+                    continue
+                ga = host(ga)[:units] if units is not None else host(ga)
+                assert np.array_equal(ga, host(gb)), (i, lvl, k)
+        # labels against the oracle
+        np.testing.assert_array_equal(host(j.band), d["band"])
+        np.testing.assert_array_equal(host(j.comp, np.uint32), d["cc"].comp)
+        want = oracle.cvt(d["cc"].comp, d["seeds"], d["w"], d["iters"])
+        np.testing.assert_array_equal(host(j.cell, np.uint32), want.cell)
+        np.testing.assert_array_equal(host(j.sites, np.uint32)[:S], want.sites)
+
+
+def test_batch_capacity_and_validation():
+    d = _job((20, 20, 20), 9, 4, 1, 1, 0, False, 64.0)
+    banner("batch: capacity")
+    small = L.BatchJob(field=dev(d["f"]), iso=d["iso"], seeds=dev(d["seeds"]), weights=None, iters=1,
+                       variables=dev(np.ascontiguousarray(d["x"])), cap_comp=1)
+    ok = L.BatchJob(field=dev(d["f"]), iso=d["iso"], seeds=dev(d["seeds"]), weights=None, iters=1,
+                    variables=dev(np.ascontiguousarray(d["x"])), cap_comp=int(d["cc"].n_comp))
+    if d["cc"].n_comp > 1:
+        with pytest.raises(L.LsrvtError):
+            L.lsrvt_batch_run([small, ok], n_streams=2)
+        assert small.status == L.ECAPACITY and small.n_comp == d["cc"].n_comp
+        assert ok.status == 0
+    L.lsrvt_batch_run([], n_streams=2)
