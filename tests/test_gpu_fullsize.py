@@ -1,0 +1,96 @@
+"""The benchmark workload at full size (the 256^3 Fourier field, 8 isovalues,
+|grad| weights, ~1.15e5 sites, 8 variables with histograms and covariance),
+in the launch configuration bench.py times.
+
+Labels are compared with the oracle element by element for the isobands,
+the components and a 1-update Lloyd loop (the oracle finishes those in
+seconds); the per-cell statistics of that loop's cells within the stated
+tolerances (the merges to components and bands are checked against the
+oracle on smaller volumes).  The 20-update loop bench.py times is checked through
+properties that hold at any size: every labelled voxel's cell is a site of
+its own component, exactly the components without a site stay unlabelled,
+every site lies in its own cell (or a co-located lower id owns its voxel),
+and repeated runs give identical bits.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2208_06970_amd as L
+import synth
+from tests.gpu_util import banner, dev, host
+from tests.test_gpu_stats import _check_level
+
+pytestmark = pytest.mark.gpu
+NONE = oracle.NONE_ID
+
+
+@pytest.fixture(scope="module")
+def workload():
+    banner("fullsize: generating the 256^3 Fourier workload")
+    wl = synth.fourier_workload()
+    band = oracle.bands(wl.field, wl.iso)
+    cc = oracle.components(band, wl.n_bands)
+    seeds = synth.workload_sites(wl, cc.comp, cc.n_comp)
+    return wl, band, cc, seeds
+
+
+def test_fullsize_labels_and_one_update(workload):
+    wl, band, cc, seeds = workload
+    banner("fullsize: isobands + components")
+    f = dev(wl.field)
+    b, st = L.lsrvt_isobands(f, wl.iso)
+    np.testing.assert_array_equal(host(b), band)
+    assert int(host(st)[0]) == 0
+    g = L.lsrvt_components(b, wl.n_bands)
+    assert g.n_comp == cc.n_comp
+    np.testing.assert_array_equal(host(g.comp, np.uint32), cc.comp)
+    np.testing.assert_array_equal(host(g.comp_band), cc.comp_band)
+    banner("fullsize: Lloyd loop, 1 update")
+    r = L.lsrvt_cvt(b, g.comp, dev(seeds), dev(wl.weights), 1)
+    want = oracle.cvt(cc.comp, seeds, wl.weights, 1)
+    np.testing.assert_array_equal(host(r.sites, np.uint32), want.sites)
+    np.testing.assert_array_equal(host(r.cell, np.uint32), want.cell)
+    np.testing.assert_allclose(r.mean_ds, want.mean_ds, rtol=1e-12, atol=0)
+    banner("fullsize: statistics of the 1-update cells")
+    S = len(seeds)
+    x = np.ascontiguousarray(wl.variables)
+    cs, gs, bs = L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, g.comp_band, g.n_comp, wl.n_bands, dev(x),
+                                   dev(wl.edges), cov=True)
+    w_cell = oracle.stats(want.cell, S, x, wl.edges, cov=True)
+    _check_level("cell", cs, w_cell, x.shape[0])
+    # merged levels: exact voxel counts per component and band
+    n_b = np.bincount(band.ravel()[want.cell.ravel() != NONE], minlength=wl.n_bands)
+    np.testing.assert_array_equal(host(bs.n).astype(np.int64), n_b)
+    n_c = np.bincount(want.site_comp[want.cell.ravel()[want.cell.ravel() != NONE]], minlength=cc.n_comp)
+    np.testing.assert_array_equal(host(gs.n).astype(np.int64), n_c)
+
+
+def test_fullsize_bench_loop_properties(workload):
+    wl, band, cc, seeds = workload
+    banner(f"fullsize: Lloyd loop, {wl.iters} updates (bench configuration), twice")
+    b = dev(band)
+    comp = dev(cc.comp)
+    runs = [L.lsrvt_cvt(b, comp, dev(seeds), dev(wl.weights), wl.iters) for _ in range(2)]
+    cell = host(runs[0].cell, np.uint32)
+    sites = host(runs[0].sites, np.uint32)
+    site_comp = host(runs[0].site_comp, np.uint32)
+    for k in ("cell", "sites", "site_comp"):
+        assert np.array_equal(host(getattr(runs[0], k)), host(getattr(runs[1], k))), k
+    assert np.array_equal(runs[0].mean_ds, runs[1].mean_ds)
+    comp_flat = cc.comp.ravel()
+    cflat = cell.ravel()
+    # every labelled voxel belongs to a site of its own component
+    lab = cflat != NONE
+    assert np.all(cflat[lab] < len(seeds))
+    np.testing.assert_array_equal(site_comp[cflat[lab]], comp_flat[lab])
+    # unlabelled voxels are exactly those of components without a site
+    seeded = np.zeros(cc.n_comp, dtype=bool)
+    seeded[site_comp] = True
+    np.testing.assert_array_equal(lab, seeded[comp_flat])
+    # every site lies in its own component and, unless a co-located lower id owns the voxel, in its own cell
+    np.testing.assert_array_equal(comp_flat[sites], site_comp)
+    owner = cflat[sites]
+    ok = (owner == np.arange(len(sites))) | (sites[owner] == sites)
+    assert np.all(ok)
+    assert runs[0].mean_ds[-1] < runs[0].mean_ds[0]
