@@ -13,15 +13,18 @@
 // when level L reads them and the result does not depend on scheduling.
 //
 // The volume is cut into 16^3 bricks.  Per brick row (16 voxels along x) the
-// search keeps three 16-bit masks in global memory: the same-band edges in
-// each direction (built once per call, since bands do not change), the
-// voxels reached so far and the frontier of the last two levels.  A level
-// launch visits only the bricks listed for it, one workgroup per brick and
-// one thread per row; a brick that reached anything lists itself and its six
-// neighbours for the next level.  Frontier rows of bricks that were not
-// visited at a level are stale, but only hold voxels whose neighbours were
-// all reached one level after them, so they are masked off by the reached
-// mask.  Each voxel is written once per pass.
+// search keeps 16-bit masks in global memory: the same-band edges in each
+// direction (built once per call, since bands do not change), the voxels
+// reached so far and the frontier of the last two levels, plus the
+// frontier's brick faces packed into a few words for the neighbours to read.
+// A level launch has one wave per brick; a brick works only if it was marked
+// for the level (a brick that reached anything marks itself and its six
+// neighbours for the next one, with plain stores of the level number).
+// Frontier words of bricks that reached nothing at a level are stale, but
+// only hold voxels whose neighbours were all reached one level after them,
+// so they are masked off by the reached mask, and a voxel that is new at
+// some level has no such stale neighbour.  Each voxel is written once per
+// pass.
 //
 // Update.  Per site, M = sum w and S_a = sum w a are exact uint64 sums
 // (per-tile LDS aggregation, then one global atomic per distinct cell).  The nearest lattice point to S/M with ties
@@ -49,8 +52,7 @@ namespace {
 constexpr int BX = 16, BY = 16, BZ = 16;
 constexpr int kRows = BY * BZ;  // a brick is 256 rows of 16 voxels along x
 constexpr int kVTThreads = 256;
-constexpr int kHistLen = 8192;  // per-level record of active brick counts
-constexpr int kSub = 64;        // sub-lists per level, so that list appends rarely share a counter
+constexpr int kHistLen = 8192;  // per-level record of which levels reached anything
 
 struct VTGrid {
   int32_t nbx, nby, nbz;
@@ -63,13 +65,15 @@ struct BFSArgs {
   Geom g;
   VTGrid bg;
   const uint32_t *eq;  // [nbricks][256][3]: (x- | x+ << 16), (y- | y+ << 16), (z- | z+ << 16) same-band bits
-  uint32_t *fr;        // [2][nbricks][256] voxels reached at the previous / current level
-  uint32_t *vis;       // [nbricks][256] voxels reached so far
+  uint16_t *fr;        // [2][nbricks][256] voxels reached at the level of that parity
+  uint16_t *vis;       // [nbricks][256] voxels reached so far
+  unsigned long long *xf;  // [2][nbricks][8] x = 0 face (words 0..3), x = 15 face (4..7) of the frontier;
+                           // bit t of word k is row (t & 15) + 16 (4 (t >> 4) + k)
+  uint16_t *yf;        // [2][nbricks][32] y = 0 face rows (0..15), y = 15 face rows (16..31) of the frontier, by z
   uint32_t *cell;      // [N] site id of every reached voxel (NONE elsewhere)
-  uint32_t *queued;    // [nbricks] tag of the last level a brick was queued for
-  uint32_t *list0, *list1;  // bricks of even / odd levels
-  uint32_t *cnt;       // [3][kSub] rotating list counters: cnt[L % 3][j] bricks in sub-list j of level L
-  uint32_t *hist;      // [kHistLen] active bricks per level
+  uint32_t *act;       // [2][nbricks]: act[L & 1][b] == L when brick b takes part in level L
+  uint32_t *alive;     // [3]: alive[L % 3] != 0 when some brick takes part in level L
+  uint32_t *hist;      // [kHistLen] alive flag of every level
   uint32_t *err;
 };
 
@@ -77,45 +81,14 @@ __device__ __forceinline__ int64_t brick_row_base(const Geom &g, int x0, int y, 
   return x0 + (int64_t)g.nx * (y + (int64_t)g.ny * z);
 }
 
-// Queue brick (bx, by, bz) (bit 0 of `which`) and its neighbours at x-, x+,
-// y-, y+, z-, z+ (bits 1..6) for the level tagged `tag` into sub-list `j`
-// (list + j * nbricks, counter cnt[j]): lanes 0..6 of the calling wave take
-// one brick each, so the tag atomics overlap.  Called by a whole wave.
-__device__ void queue_around(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *list, uint32_t *cnt,
-                             uint32_t j, uint32_t which) {
-  const int k = lane_id();
-  bool want = false;
-  uint32_t nb = 0;
-  if (k < 7 && ((which >> k) & 1u)) {
-    const int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
-    const int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
-    const int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
-    if (nx >= 0 && ny >= 0 && nz >= 0 && nx < A.bg.nbx && ny < A.bg.nby && nz < A.bg.nbz) {
-      nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
-      want = A.queued[nb] < tag && atomicMax(&A.queued[nb], tag) < tag;
-    }
-  }
-  const uint64_t m = __ballot(want);
-  if (!m) return;
-  uint32_t base = 0;
-  if (k == 0) base = atomicAdd(&cnt[j], (uint32_t)__popcll(m));
-  base = __shfl(base, 0, kWave);
-  if (want) list[(size_t)j * A.bg.nbricks + base + (uint32_t)__popcll(m & lanemask_lt())] = nb;
-}
-
-// Per-thread variant for the sites of level 0.
-__device__ void queue_around_one(const BFSArgs &A, int bx, int by, int bz, uint32_t tag, uint32_t *list,
-                                 uint32_t *cnt, uint32_t j) {
-#pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const int nx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
-    const int ny = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
-    const int nz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
-    if (nx < 0 || ny < 0 || nz < 0 || nx >= A.bg.nbx || ny >= A.bg.nby || nz >= A.bg.nbz) continue;
-    const uint32_t nb = (uint32_t)(nx + A.bg.nbx * (ny + A.bg.nby * nz));
-    if (A.queued[nb] < tag && atomicMax(&A.queued[nb], tag) < tag)
-      list[(size_t)j * A.bg.nbricks + atomicAdd(&cnt[j], 1u)] = nb;
-  }
+// Marks brick (bx, by, bz) and its six face neighbours for level L (plain
+// stores: every writer stores the same tag).
+__device__ __forceinline__ void mark_brick(const BFSArgs &A, int bx, int by, int bz, int k, uint32_t L) {
+  const int qx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
+  const int qy = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
+  const int qz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
+  if (qx >= 0 && qy >= 0 && qz >= 0 && qx < A.bg.nbx && qy < A.bg.nby && qz < A.bg.nbz)
+    A.act[(size_t)(L & 1) * A.bg.nbricks + (size_t)(qx + A.bg.nbx * (qy + A.bg.nby * qz))] = L;
 }
 
 // Same-band masks of every row toward its six neighbours (across brick faces
@@ -161,7 +134,7 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict_
 }
 
 // Level 0: every site reaches its own voxel; co-located sites keep the lowest id.
-__global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A, uint32_t tag) {
+__global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   uint32_t v = sites[s];
@@ -173,120 +146,219 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
   uint32_t y = r % (uint32_t)A.g.ny, z = r / (uint32_t)A.g.ny;
   int bx = x / BX, by = y / BY, bz = z / BZ;
   uint32_t b = bx + A.bg.nbx * (by + A.bg.nby * bz);
-  uint32_t row = (y % BY) + BY * (z % BZ), bit = 1u << (x % BX);
+  const uint32_t ly = y % BY, lz = z % BZ, lx = x % BX;
+  const uint32_t row = ly + BY * lz;
   atomicMin(&A.cell[v], s);
-  atomicOr(&A.vis[(int64_t)b * kRows + row], bit);
-  atomicOr(&A.fr[(int64_t)b * kRows + row], bit);  // parity 0 = level 0
-  queue_around_one(A, bx, by, bz, tag, A.list1, A.cnt + kSub, blockIdx.x % kSub);
+  // 16-bit rows are updated through the 32-bit word that holds them (parity 0 = level 0)
+  const size_t w = ((size_t)b * kRows + row) >> 1;
+  const uint32_t bit = (1u << lx) << ((row & 1u) * 16u);
+  atomicOr(reinterpret_cast<uint32_t *>(A.vis) + w, bit);
+  atomicOr(reinterpret_cast<uint32_t *>(A.fr) + w, bit);
+  if (lx == 0 || lx == BX - 1) {
+    const uint32_t lane = ly + 16u * (lz >> 2), k = lz & 3u;
+    atomicOr(&A.xf[(size_t)b * 8 + (lx ? 4 : 0) + k], 1ull << lane);
+  }
+  if (ly == 0 || ly == BY - 1) {
+    const size_t yi = (size_t)b * 32 + (ly ? 16 : 0) + lz;
+    atomicOr(reinterpret_cast<uint32_t *>(A.yf) + (yi >> 1), (1u << lx) << ((yi & 1u) * 16u));
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) mark_brick(A, bx, by, bz, k, 1u);
+  A.alive[1] = 1u;
 }
+
+constexpr int kLvlThreads = 64;  // one wave per brick
+constexpr int kNewCap = 1024;    // new voxels per brick and level shared out through LDS
 
 // Level L: a voxel not reached yet is reached now when a same-band face
 // neighbour was reached at level L - 1; it takes the smallest id among those
-// neighbours (Eq. 1 with ties to the lower id).  Processes the bricks listed
-// for this level (items first, first + stride, ...); a brick that reached
-// anything lists itself and its neighbours for L + 1.
-__device__ void bfs_level(const BFSArgs &A, uint32_t L, const uint32_t *off, uint32_t tag, uint32_t first,
-                          uint32_t stride) {
+// neighbours (Eq. 1 with ties to the lower id).  One wave per brick: lane t
+// owns the four rows ly = t & 15, lz = 4 (t >> 4) + k (k = 0..3), so the y-
+// and z-neighbour rows inside the brick come from other lanes' registers,
+// and the rows beyond the brick's faces from the neighbours' packed face
+// words; every load of the brick's masks is issued at once.  The new voxels
+// are then listed in LDS and shared out one per lane, whatever row they are
+// in.  A brick that reached anything marks itself and its six neighbours
+// for level L + 1.
+__device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *lst, uint32_t *dmp) {
   const int t = threadIdx.x;
-  const uint32_t count = off[kSub];
-  const uint32_t *list_in = (L & 1) ? A.list1 : A.list0;
-  uint32_t *list_out = (L & 1) ? A.list0 : A.list1;
-  uint32_t *out_cnt = A.cnt + ((L + 1) % 3) * kSub;
-  const uint32_t *fin = A.fr + (size_t)((L - 1) & 1) * A.bg.nbricks * kRows;
-  uint32_t *fout = A.fr + (size_t)(L & 1) * A.bg.nbricks * kRows;
-  const int ly = t & 15, lz = t >> 4;
+  const int ly = t & 15, g4 = (t >> 4) * 4;
+  const size_t pin = (size_t)((L - 1) & 1), pout = (size_t)(L & 1);
+  const size_t nbk = (size_t)A.bg.nbricks;
+  const uint16_t *fin = A.fr + pin * nbk * kRows;
+  uint16_t *fout = A.fr + pout * nbk * kRows;
+  const unsigned long long *xin = A.xf + pin * nbk * 8;
+  unsigned long long *xout = A.xf + pout * nbk * 8;
+  const uint16_t *yin = A.yf + pin * nbk * 32;
+  uint16_t *yout = A.yf + pout * nbk * 32;
   const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
-  for (uint32_t item = first; item < count; item += stride) {
-    // item -> (sub-list, position) by bisection over the sub-list offsets
-    uint32_t lo = 0, hi = kSub;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (off[mid] <= item)
-        lo = mid;
-      else
-        hi = mid;
-    }
-    const uint32_t b = list_in[(size_t)lo * A.bg.nbricks + (item - off[lo])];
-    const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby), bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
-    const int64_t rb = (int64_t)b * kRows;
-    const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
-    const uint32_t F = fin[rb + t];
-    const uint32_t vrow = A.vis[rb + t];
-    const uint32_t fym = ly > 0 ? fin[rb + t - 1] : (by > 0 ? fin[(b - bsy) * kRows + t + 15] : 0u);
-    const uint32_t fyp = ly < BY - 1 ? fin[rb + t + 1] : (by < A.bg.nby - 1 ? fin[(b + bsy) * kRows + t - 15] : 0u);
-    const uint32_t fzm = lz > 0 ? fin[rb + t - 16] : (bz > 0 ? fin[(b - bsz) * kRows + t + 240] : 0u);
-    const uint32_t fzp = lz < BZ - 1 ? fin[rb + t + 16] : (bz < A.bg.nbz - 1 ? fin[(b + bsz) * kRows + t - 240] : 0u);
-    const uint32_t xin_m = bx > 0 ? (fin[(b - 1) * kRows + t] >> 15) & 1u : 0u;
-    const uint32_t xin_p = bx < A.bg.nbx - 1 ? fin[(b + 1) * kRows + t] & 1u : 0u;
-    const uint32_t sxm = (F << 1) | xin_m, sxp = (F >> 1) | (xin_p << 15);
-    uint32_t nw = (sxm | sxp | fym | fyp | fzm | fzp) & ~vrow & 0xFFFFu;
-    if (nw) {
-      const uint32_t e0 = A.eq[(rb + t) * 3], e1 = A.eq[(rb + t) * 3 + 1], e2 = A.eq[(rb + t) * 3 + 2];
-      const uint32_t fxm = sxm & e0 & 0xFFFFu, fxp = sxp & (e0 >> 16);
-      const uint32_t gym = fym & e1, gyp = fyp & (e1 >> 16);
-      const uint32_t gzm = fzm & e2, gzp = fzp & (e2 >> 16);
-      nw &= fxm | fxp | gym | gyp | gzm | gzp;
-      const int64_t base = brick_row_base(A.g, bx * BX, by * BY + ly, bz * BZ + lz);
-      // ids of the new voxels, four at a time: all loads of a group are in
-      // flight before its stores, so a row does not wait once per voxel
-      uint32_t bits = nw;
-      while (bits) {
-        int xs[4];
-        uint32_t idv[4];
+  const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
+  const int lm1 = (t + kWave - 1) & (kWave - 1), lp1 = (t + 1) & (kWave - 1);
+  const int lm16 = (t + kWave - 16) & (kWave - 1), lp16 = (t + 16) & (kWave - 1);
+  const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby), bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
+  const int64_t rb = (int64_t)b * kRows;
+  const bool hym = ly == 0 && by > 0, hyp = ly == BY - 1 && by < A.bg.nby - 1;
+  uint32_t F[4], V[4], XM[4], XP[4], YM[4], YP[4], E[4][3];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          xs[j] = bits ? __ffs(bits) - 1 : -1;
-          bits &= bits - 1;
-        }
+  for (int k = 0; k < 4; ++k) {
+    const int r = ly + 16 * (g4 + k);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          uint32_t id = kNone;
-          const int x = xs[j];
-          if (x >= 0) {
-            const int64_t v = base + x;
-            if ((fxm >> x) & 1u) id = min(id, A.cell[v - 1]);
-            if ((fxp >> x) & 1u) id = min(id, A.cell[v + 1]);
-            if ((gym >> x) & 1u) id = min(id, A.cell[v - sy]);
-            if ((gyp >> x) & 1u) id = min(id, A.cell[v + sy]);
-            if ((gzm >> x) & 1u) id = min(id, A.cell[v - sz]);
-            if ((gzp >> x) & 1u) id = min(id, A.cell[v + sz]);
-          }
-          idv[j] = id;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          if (xs[j] >= 0) A.cell[base + xs[j]] = idv[j];
-      }
-      if (nw) A.vis[rb + t] = vrow | nw;
-    }
-    fout[rb + t] = nw;
-    if (__syncthreads_or(nw != 0) && t < kWave) queue_around(A, bx, by, bz, tag, list_out, out_cnt, b % kSub, 0x7Fu);
+    for (int j = 0; j < 3; ++j) E[k][j] = A.eq[(rb + r) * 3 + j];
+    F[k] = fin[rb + r];
+    V[k] = A.vis[rb + r];
+    const unsigned long long xm = bx > 0 ? xin[(size_t)(b - 1) * 8 + 4 + k] : 0ull;
+    const unsigned long long xp = bx < A.bg.nbx - 1 ? xin[(size_t)(b + 1) * 8 + k] : 0ull;
+    XM[k] = (uint32_t)(xm >> t) & 1u;
+    XP[k] = (uint32_t)(xp >> t) & 1u;
+    YM[k] = hym ? yin[(size_t)(b - bsy) * 32 + 16 + g4 + k] : 0u;
+    YP[k] = hyp ? yin[(size_t)(b + bsy) * 32 + g4 + k] : 0u;
   }
+  const uint32_t ZM = (g4 == 0 && bz > 0) ? fin[(b - bsz) * kRows + 240 + ly] : 0u;
+  const uint32_t ZP = (g4 == 12 && bz < A.bg.nbz - 1) ? fin[(b + bsz) * kRows + ly] : 0u;
+  const uint32_t zlo = __shfl(F[3], lm16, kWave), zhi = __shfl(F[0], lp16, kWave);
+  uint32_t nw[4], c = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = ly + 16 * (g4 + k);
+    const uint32_t up = __shfl(F[k], lm1, kWave), dn = __shfl(F[k], lp1, kWave);
+    const uint32_t fym = ly > 0 ? up : YM[k];
+    const uint32_t fyp = ly < BY - 1 ? dn : YP[k];
+    const uint32_t fzm = k > 0 ? F[k - 1] : (g4 > 0 ? zlo : ZM);
+    const uint32_t fzp = k < 3 ? F[k + 1] : (g4 < 12 ? zhi : ZP);
+    const uint32_t sxm = (F[k] << 1) | XM[k];
+    const uint32_t sxp = (F[k] >> 1) | (XP[k] << 15);
+    // reached from each direction: frontier neighbour with a same-band edge
+    const uint32_t d0 = sxm & E[k][0] & 0xFFFFu, d1 = sxp & (E[k][0] >> 16);
+    const uint32_t d2 = fym & E[k][1] & 0xFFFFu, d3 = fyp & (E[k][1] >> 16);
+    const uint32_t d4 = fzm & E[k][2] & 0xFFFFu, d5 = fzp & (E[k][2] >> 16);
+    nw[k] = (d0 | d1 | d2 | d3 | d4 | d5) & ~V[k] & 0xFFFFu;
+    if (nw[k]) {
+      dmp[r] = d0 | (d1 << 16);
+      dmp[kRows + r] = d2 | (d3 << 16);
+      dmp[2 * kRows + r] = d4 | (d5 << 16);
+    }
+    c += (uint32_t)__popc(nw[k]);
+  }
+  uint32_t inc = c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t v = __shfl_up(inc, o, kWave);
+    if (t >= o) inc += v;
+  }
+  const uint32_t total = __shfl(inc, kWave - 1, kWave);
+  // nothing new: the frontier words of this parity stay stale, which is
+  // harmless (see above)
+  if (total == 0) return;
+  if (t < 7) mark_brick(A, bx, by, bz, t, L + 1);
+  if (t == 0) A.alive[(L + 1) % 3] = 1u;
+  const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
+  if (total <= (uint32_t)kNewCap) {
+    uint32_t p = inc - c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t bits = nw[k];
+      const uint32_t r = (uint32_t)(ly + 16 * (g4 + k));
+      while (bits) {
+        const uint32_t x = (uint32_t)(__ffs(bits) - 1);
+        bits &= bits - 1;
+        lst[p++] = (uint16_t)(x | (r << 4));
+      }
+    }
+    __syncthreads();
+    // ids of the listed voxels, two per lane at a time; all six neighbour
+    // loads are issued (a neighbour that is not a source reads the voxel
+    // itself) so that they are in flight together
+    for (uint32_t e = t; e < total; e += 2 * kWave) {
+      int64_t v[2];
+      uint32_t g[2][6], m[2][3];
+      bool have[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint32_t ee = e + (uint32_t)u * kWave;
+        have[u] = ee < total;
+        const uint32_t idx = lst[have[u] ? ee : 0u];
+        const uint32_t r = idx >> 4, x = idx & 15u;
+        v[u] = vb + x + sy * (int64_t)(r & 15u) + sz * (int64_t)(r >> 4);
+        m[u][0] = dmp[r] >> x;
+        m[u][1] = dmp[kRows + r] >> x;
+        m[u][2] = dmp[2 * kRows + r] >> x;
+        g[u][0] = A.cell[(m[u][0] & 1u) ? v[u] - 1 : v[u]];
+        g[u][1] = A.cell[((m[u][0] >> 16) & 1u) ? v[u] + 1 : v[u]];
+        g[u][2] = A.cell[(m[u][1] & 1u) ? v[u] - sy : v[u]];
+        g[u][3] = A.cell[((m[u][1] >> 16) & 1u) ? v[u] + sy : v[u]];
+        g[u][4] = A.cell[(m[u][2] & 1u) ? v[u] - sz : v[u]];
+        g[u][5] = A.cell[((m[u][2] >> 16) & 1u) ? v[u] + sz : v[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        uint32_t id = (m[u][0] & 1u) ? g[u][0] : kNone;
+        id = min(id, ((m[u][0] >> 16) & 1u) ? g[u][1] : kNone);
+        id = min(id, (m[u][1] & 1u) ? g[u][2] : kNone);
+        id = min(id, ((m[u][1] >> 16) & 1u) ? g[u][3] : kNone);
+        id = min(id, (m[u][2] & 1u) ? g[u][4] : kNone);
+        id = min(id, ((m[u][2] >> 16) & 1u) ? g[u][5] : kNone);
+        if (have[u]) A.cell[v[u]] = id;
+      }
+    }
+  } else {
+    // more new voxels than the list holds: each lane takes its own rows
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t bits = nw[k];
+      const int r = ly + 16 * (g4 + k);
+      const int64_t base = vb + sy * (int64_t)(r & 15) + sz * (int64_t)(r >> 4);
+      const uint32_t m0 = dmp[r], m1 = dmp[kRows + r], m2 = dmp[2 * kRows + r];
+      while (bits) {
+        const int x = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int64_t v = base + x;
+        const uint32_t a0 = (m0 >> x) & 1u, a1 = (m0 >> (16 + x)) & 1u, a2 = (m1 >> x) & 1u;
+        const uint32_t a3 = (m1 >> (16 + x)) & 1u, a4 = (m2 >> x) & 1u, a5 = (m2 >> (16 + x)) & 1u;
+        const uint32_t g0 = A.cell[a0 ? v - 1 : v], g1 = A.cell[a1 ? v + 1 : v], g2 = A.cell[a2 ? v - sy : v];
+        const uint32_t g3 = A.cell[a3 ? v + sy : v], g4v = A.cell[a4 ? v - sz : v], g5 = A.cell[a5 ? v + sz : v];
+        uint32_t id = a0 ? g0 : kNone;
+        id = min(id, a1 ? g1 : kNone);
+        id = min(id, a2 ? g2 : kNone);
+        id = min(id, a3 ? g3 : kNone);
+        id = min(id, a4 ? g4v : kNone);
+        id = min(id, a5 ? g5 : kNone);
+        A.cell[v] = id;
+      }
+    }
+  }
+  // this level's frontier: rows, and the packed faces the neighbours read
+  unsigned long long xw = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = ly + 16 * (g4 + k);
+    if (nw[k]) A.vis[rb + r] = (uint16_t)(V[k] | nw[k]);
+    fout[rb + r] = (uint16_t)nw[k];
+    const unsigned long long lo_k = __ballot(nw[k] & 1u), hi_k = __ballot((nw[k] >> 15) & 1u);
+    if (t == k) xw = lo_k;
+    if (t == 4 + k) xw = hi_k;
+    if (ly == 0) yout[(size_t)b * 32 + g4 + k] = (uint16_t)nw[k];
+    if (ly == BY - 1) yout[(size_t)b * 32 + 16 + g4 + k] = (uint16_t)nw[k];
+  }
+  if (t < 8) xout[(size_t)b * 8 + t] = xw;
+  __syncthreads();  // the LDS list and masks are reused by the next brick
 }
 
-// One BFS level per launch.  Workgroup 0 clears the list counter of level
-// L + 2 (level L + 1 appends to it), so launches may be enqueued past the
-// last level: they find an empty list and return.
-__global__ __launch_bounds__(kVTThreads) void k_bfs_level(BFSArgs A, uint32_t L) {
-  __shared__ uint32_t off[kSub + 1];
-  const int t = threadIdx.x;
-  if (t < kWave) {
-    // exclusive prefix of the sub-list counts of level L
-    const uint32_t c = t < kSub ? A.cnt[(L % 3) * kSub + t] : 0u;
-    uint32_t inc = c;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const uint32_t v = __shfl_up(inc, o, kWave);
-      if (t >= o) inc += v;
-    }
-    if (t < kSub) off[t] = inc - c;
-    if (t == kSub - 1) off[kSub] = inc;
-    if (blockIdx.x == 0 && t < kSub) A.cnt[((L + 2) % 3) * kSub + t] = 0;  // level L + 1 lists into them
+// One BFS level per launch over the bricks marked for it.  Workgroup 0
+// records whether level L is alive and clears the flag of level L + 2 (level
+// L + 1 sets it), so launches may be enqueued past the last level: they find
+// no marked brick and return.
+__global__ __launch_bounds__(kLvlThreads) void k_bfs_level(BFSArgs A, uint32_t L) {
+  __shared__ uint16_t lst[kNewCap];
+  __shared__ uint32_t dmp[3 * kRows];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    A.hist[L % kHistLen] = A.alive[L % 3];
+    A.alive[(L + 2) % 3] = 0u;
   }
-  __syncthreads();
-  if (blockIdx.x == 0 && t == 0) A.hist[L % kHistLen] = off[kSub];
-  if (off[kSub] == 0) return;
-  bfs_level(A, L, off, L + 1, blockIdx.x, gridDim.x);
+  const uint32_t *act = A.act + (size_t)(L & 1) * A.bg.nbricks;
+  for (int64_t b = blockIdx.x; b < A.bg.nbricks; b += gridDim.x) {
+    if (__builtin_amdgcn_readfirstlane(act[b]) != L) continue;
+    bfs_brick(A, L, (uint32_t)b, lst, dmp);
+  }
 }
 
 // ----------------------------------------------------------------------------
@@ -544,8 +616,10 @@ __global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, con
 // host side
 
 struct CvtWork {
-  uint32_t *eq, *fr, *vis;
-  uint32_t *queued, *list_a, *list_b, *cnt;  // cnt[3][kSub] list counters, then error bits
+  uint32_t *eq;
+  uint16_t *fr, *vis, *yf;
+  unsigned long long *xf;
+  uint32_t *act, *ctl;  // brick marks; ctl[0..2] level alive flags, ctl[3] error bits
   uint32_t *fb_list, *fb_cnt, *err;
   uint32_t *hist;
   unsigned long long *sums;  // 4 x S
@@ -567,12 +641,12 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   int64_t nb = bg.nbricks;
   size_t s1 = S ? S : 1;
   auto eq = a.template take<uint32_t>(nb * kRows * 3);
-  auto fr = a.template take<uint32_t>(2 * nb * kRows);
-  auto vis = a.template take<uint32_t>(nb * kRows);
-  auto queued = a.template take<uint32_t>(nb);
-  auto la = a.template take<uint32_t>((size_t)kSub * nb);
-  auto lb = a.template take<uint32_t>((size_t)kSub * nb);
-  auto cnt = a.template take<uint32_t>(3 * kSub + 1);  // list counters, then error bits
+  auto fr = a.template take<uint16_t>(2 * nb * kRows);
+  auto vis = a.template take<uint16_t>(nb * kRows);
+  auto xf = a.template take<unsigned long long>(2 * nb * 8);
+  auto yf = a.template take<uint16_t>(2 * nb * 32);
+  auto act = a.template take<uint32_t>(2 * nb);
+  auto ctl = a.template take<uint32_t>(4);
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
   auto sums = a.template take<unsigned long long>(4 * s1);
@@ -584,11 +658,11 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
     W->eq = eq;
     W->fr = fr;
     W->vis = vis;
-    W->queued = queued;
-    W->list_a = la;
-    W->list_b = lb;
-    W->cnt = cnt;
-    W->err = cnt + 3 * kSub;
+    W->xf = xf;
+    W->yf = yf;
+    W->act = act;
+    W->ctl = ctl;
+    W->err = ctl + 3;
     W->fb_list = fbl;
     W->fb_cnt = fbc;
     W->sums = sums;
@@ -619,10 +693,10 @@ int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t
   return cv.ok ? LSRVT_OK : LSRVT_EWORKSPACE;
 }
 
-// Driver state of one Lloyd run: the active-brick counts per level of the
-// previous pass, which size the launches of the next one.
+// Driver state of one Lloyd run: the number of levels of the previous pass,
+// which sizes the first batch of level launches of the next one.
 struct VTState {
-  std::vector<uint32_t> prev;
+  uint32_t levels = 0;
 };
 
 // Benchmark timing of the level kernel: while enabled, an event pair on the
@@ -667,7 +741,7 @@ int32_t timed_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> &ev, ui
 }
 
 // Voxels never reached (components without a site) get LSRVT_NONE.
-__global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint32_t *__restrict__ vis, Geom g, VTGrid bg,
+__global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint16_t *__restrict__ vis, Geom g, VTGrid bg,
                                                              uint32_t *__restrict__ cell) {
   const int t = threadIdx.x, ly = t & 15, lz = t >> 4;
   for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
@@ -701,9 +775,6 @@ int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s
   return LSRVT_OK;
 }
 
-// One restricted Voronoi pass: level 0 at the sites, then one launch per BFS
-// level over the bricks the front passes through, until a level reaches
-// nothing.
 // One restricted Voronoi pass: level 0 at the sites, then launches of the
 // level kernel, enqueued in batches sized by the previous pass (sites move
 // little between passes) until the device reports an empty level.
@@ -711,34 +782,37 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
                hipStream_t s) {
   VTGrid bg = vt_grid(g);
   int32_t rc;
-  if ((rc = fill<uint32_t>(W.fr, 2 * bg.nbricks * kRows, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.vis, bg.nbricks * kRows, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.cnt, 3 * kSub, 0u, s))) return rc;
+  // 16-bit and 64-bit arrays are cleared as 32-bit words (even lengths)
+  if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(W.fr), bg.nbricks * kRows, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(W.vis), bg.nbricks * kRows / 2, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(W.xf), 2 * bg.nbricks * 16, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(W.yf), bg.nbricks * 32, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl, 3, 0u, s))) return rc;
   BFSArgs A;
   A.g = g;
   A.bg = bg;
   A.eq = W.eq;
   A.fr = W.fr;
   A.vis = W.vis;
+  A.xf = W.xf;
+  A.yf = W.yf;
   A.cell = cell;
-  A.queued = W.queued;
-  A.cnt = W.cnt;
+  A.act = W.act;
+  A.alive = W.ctl;
   A.hist = W.hist;
   A.err = W.err;
-  A.list0 = W.list_a;
-  A.list1 = W.list_b;  // level 1 reads list1
   if (S) {
     hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g.n, cell);
-    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A, 1u);
+    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
     LSRVT_LAUNCHED();
   }
   const int64_t max_level = g.n + 2;
   const unsigned cap = vt_grid_cap(bg);
   uint32_t L = 0;  // levels enqueued
-  int batch = st.prev.empty() ? 16 : (int)st.prev.size() + 4;
+  int batch = st.levels ? (int)st.levels + 4 : 16;
   bool more = S != 0;
-  std::vector<uint32_t> c(3 * kSub + 1, 0);
+  uint32_t c[4] = {0, 0, 0, 0};
   while (more) {
     // one event pair around a batch of back-to-back level launches (while
     // timing is on): the launches of a batch run without gaps
@@ -747,29 +821,21 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     if (timed && (rc = timed_begin(s, ev))) return rc;
     for (int i = 0; i < batch; ++i) {
       ++L;
-      unsigned grid = cap;
-      if (L - 1 < st.prev.size()) {
-        const uint32_t p = st.prev[L - 1];
-        grid = (unsigned)std::min<uint64_t>(cap, (uint64_t)p + p / 4 + 64);
-      } else if (!st.prev.empty()) {
-        grid = 64;  // most likely past the last level
-      }
-      hipLaunchKernelGGL(k_bfs_level, dim3(grid), dim3(kVTThreads), 0, s, A, L);
+      hipLaunchKernelGGL(k_bfs_level, dim3(cap), dim3(kLvlThreads), 0, s, A, L);
       LSRVT_LAUNCHED();
     }
     if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
-    LSRVT_HIP(hipMemcpyAsync(c.data(), W.cnt, sizeof(uint32_t) * c.size(), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipMemcpyAsync(c, W.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
-    const uint32_t e = c[3 * kSub];
+    const uint32_t e = c[3];
     if (e & 1u) return LSRVT_EINVAL;
     if (e) return LSRVT_EDEVICE;
-    more = false;  // bricks listed for the next level?
-    for (int j = 0; j < kSub; ++j) more = more || c[((L + 1) % 3) * kSub + j] != 0;
+    more = c[(L + 1) % 3] != 0;  // bricks marked for the next level?
     if ((int64_t)L > max_level) return LSRVT_EDEVICE;
     batch = 8;
   }
   const uint32_t launched = L;
-  // the brick counts of levels 1 .. L size the next pass (trailing empty levels dropped)
+  // the number of levels sizes the first batch of the next pass
   const uint32_t nl = std::min<uint32_t>(L + 1, kHistLen);
   std::vector<uint32_t> h(nl, 0);
   if (nl > 1) {
@@ -778,7 +844,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   }
   uint32_t levels = 0;
   while (levels + 1 < nl && h[levels + 1]) ++levels;
-  st.prev.assign(h.begin() + 1, h.begin() + 1 + levels);
+  st.levels = levels;
   hipLaunchKernelGGL(k_vt_unreached, dim3(cap), dim3(kVTThreads), 0, s, W.vis, g, bg, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
@@ -788,9 +854,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   }
   static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
   if (debug_levels) {
-    fprintf(stderr, "[lsrvt] vt levels=%u launches=%u active bricks:", levels, launched);
-    for (uint32_t l = 1; l <= levels; ++l) fprintf(stderr, " %u", h[l]);
-    fprintf(stderr, "\n");
+    fprintf(stderr, "[lsrvt] vt levels=%u launches=%u\n", levels, launched);
   }
   return LSRVT_OK;
 }
@@ -824,8 +888,8 @@ int32_t run_update(const uint32_t *cell, const Geom &g, const uint16_t *w, uint3
 int32_t begin(CvtWork &W, const Geom &g, hipStream_t s) {
   int32_t rc;
   VTGrid bg = vt_grid(g);
-  if ((rc = fill<uint32_t>(W.queued, bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.cnt, 3 * kSub + 1, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl, 4, 0u, s))) return rc;
   return LSRVT_OK;
 }
 
