@@ -180,6 +180,29 @@ constexpr int kNewCap = 1024;    // new voxels per brick and level shared out th
 // are then listed in LDS and shared out one per lane, whatever row they are
 // in.  A brick that reached anything marks itself and its six neighbours
 // for level L + 1.
+// Ids of the six face neighbours of new voxel v, the sources among them
+// flagged by a0..a5 (x-, x+, y-, y+, z-, z+; at least one is set).  All six
+// loads are issued unconditionally so that they are in flight together; a
+// direction that is not a source reads the first source again, which hits
+// the line that load brings in.
+__device__ __forceinline__ void gather6(const uint32_t *cell, int64_t v, int64_t sy, int64_t sz, uint32_t a0,
+                                        uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4, uint32_t a5,
+                                        uint32_t g[6]) {
+  const int64_t n0 = v - 1, n1 = v + 1, n2 = v - sy, n3 = v + sy, n4 = v - sz, n5 = v + sz;
+  int64_t f = a5 ? n5 : v;
+  f = a4 ? n4 : f;
+  f = a3 ? n3 : f;
+  f = a2 ? n2 : f;
+  f = a1 ? n1 : f;
+  f = a0 ? n0 : f;
+  g[0] = cell[a0 ? n0 : f];
+  g[1] = cell[a1 ? n1 : f];
+  g[2] = cell[a2 ? n2 : f];
+  g[3] = cell[a3 ? n3 : f];
+  g[4] = cell[a4 ? n4 : f];
+  g[5] = cell[a5 ? n5 : f];
+}
+
 __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *lst, uint32_t *dmp) {
   const int t = threadIdx.x;
   const int ly = t & 15, g4 = (t >> 4) * 4;
@@ -265,9 +288,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
       }
     }
     __syncthreads();
-    // ids of the listed voxels, two per lane at a time; all six neighbour
-    // loads are issued (a neighbour that is not a source reads the voxel
-    // itself) so that they are in flight together
+    // ids of the listed voxels, two per lane at a time
     for (uint32_t e = t; e < total; e += 2 * kWave) {
       int64_t v[2];
       uint32_t g[2][6], m[2][3];
@@ -282,12 +303,8 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
         m[u][0] = dmp[r] >> x;
         m[u][1] = dmp[kRows + r] >> x;
         m[u][2] = dmp[2 * kRows + r] >> x;
-        g[u][0] = A.cell[(m[u][0] & 1u) ? v[u] - 1 : v[u]];
-        g[u][1] = A.cell[((m[u][0] >> 16) & 1u) ? v[u] + 1 : v[u]];
-        g[u][2] = A.cell[(m[u][1] & 1u) ? v[u] - sy : v[u]];
-        g[u][3] = A.cell[((m[u][1] >> 16) & 1u) ? v[u] + sy : v[u]];
-        g[u][4] = A.cell[(m[u][2] & 1u) ? v[u] - sz : v[u]];
-        g[u][5] = A.cell[((m[u][2] >> 16) & 1u) ? v[u] + sz : v[u]];
+        gather6(A.cell, v[u], sy, sz, m[u][0] & 1u, (m[u][0] >> 16) & 1u, m[u][1] & 1u, (m[u][1] >> 16) & 1u,
+                m[u][2] & 1u, (m[u][2] >> 16) & 1u, g[u]);
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
@@ -314,14 +331,14 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
         const int64_t v = base + x;
         const uint32_t a0 = (m0 >> x) & 1u, a1 = (m0 >> (16 + x)) & 1u, a2 = (m1 >> x) & 1u;
         const uint32_t a3 = (m1 >> (16 + x)) & 1u, a4 = (m2 >> x) & 1u, a5 = (m2 >> (16 + x)) & 1u;
-        const uint32_t g0 = A.cell[a0 ? v - 1 : v], g1 = A.cell[a1 ? v + 1 : v], g2 = A.cell[a2 ? v - sy : v];
-        const uint32_t g3 = A.cell[a3 ? v + sy : v], g4v = A.cell[a4 ? v - sz : v], g5 = A.cell[a5 ? v + sz : v];
-        uint32_t id = a0 ? g0 : kNone;
-        id = min(id, a1 ? g1 : kNone);
-        id = min(id, a2 ? g2 : kNone);
-        id = min(id, a3 ? g3 : kNone);
-        id = min(id, a4 ? g4v : kNone);
-        id = min(id, a5 ? g5 : kNone);
+        uint32_t gg[6];
+        gather6(A.cell, v, sy, sz, a0, a1, a2, a3, a4, a5, gg);
+        uint32_t id = a0 ? gg[0] : kNone;
+        id = min(id, a1 ? gg[1] : kNone);
+        id = min(id, a2 ? gg[2] : kNone);
+        id = min(id, a3 ? gg[3] : kNone);
+        id = min(id, a4 ? gg[4] : kNone);
+        id = min(id, a5 ? gg[5] : kNone);
         A.cell[v] = id;
       }
     }
@@ -355,7 +372,12 @@ __global__ __launch_bounds__(kLvlThreads) void k_bfs_level(BFSArgs A, uint32_t L
     A.alive[(L + 2) % 3] = 0u;
   }
   const uint32_t *act = A.act + (size_t)(L & 1) * A.bg.nbricks;
-  for (int64_t b = blockIdx.x; b < A.bg.nbricks; b += gridDim.x) {
+  // workgroups are dealt to the eight XCDs in turn (the grid is a multiple of
+  // 8): XCD i % 8 takes the i-th eighth of the bricks, neighbours included
+  const int64_t per = (A.bg.nbricks + 7) / 8;
+  for (int64_t i = blockIdx.x; i < 8 * per; i += gridDim.x) {
+    const int64_t b = (i & 7) * per + (i >> 3);
+    if (b >= A.bg.nbricks) continue;
     if (__builtin_amdgcn_readfirstlane(act[b]) != L) continue;
     bfs_brick(A, L, (uint32_t)b, lst, dmp);
   }
@@ -809,6 +831,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   }
   const int64_t max_level = g.n + 2;
   const unsigned cap = vt_grid_cap(bg);
+  const unsigned lgrid = (unsigned)std::min<int64_t>(8 * ((bg.nbricks + 7) / 8), 65528);
   uint32_t L = 0;  // levels enqueued
   int batch = st.levels ? (int)st.levels + 4 : 16;
   bool more = S != 0;
@@ -821,7 +844,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     if (timed && (rc = timed_begin(s, ev))) return rc;
     for (int i = 0; i < batch; ++i) {
       ++L;
-      hipLaunchKernelGGL(k_bfs_level, dim3(cap), dim3(kLvlThreads), 0, s, A, L);
+      hipLaunchKernelGGL(k_bfs_level, dim3(lgrid), dim3(kLvlThreads), 0, s, A, L);
       LSRVT_LAUNCHED();
     }
     if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
