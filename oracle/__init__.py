@@ -26,6 +26,9 @@ ctypes.  Each function cites the passage of the paper it follows:
   Layout" / Fig. 5: the voxels of the cells ordered by band, component and
   cell, with offsets per cell, component and band (numpy, stable sorts)
 * :func:`extract`     -- the raw variables in that order
+* :func:`seed_stratified` -- Sec. 3.2.1, Eq. 3 and Eq. 4: stratified initial
+  sites (numpy and exact Python integers, in ``seeding.py``, with the
+  Philox4x32-10 generator it draws from)
 """
 from __future__ import annotations
 
@@ -289,3 +292,6 @@ def extract(variables: np.ndarray, perm) -> np.ndarray:
     """out[j][k] = variables[j].flat[perm[k]]."""
     x = np.asarray(variables)
     return x.reshape(x.shape[0], -1)[:, np.asarray(perm, dtype=np.int64)]
+
+
+from .seeding import philox4x32, seed_stratified  # noqa: E402,F401

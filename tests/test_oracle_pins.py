@@ -458,3 +458,169 @@ def test_extract_is_gather():
             z, r = divmod(int(v), 12)
             y, xx = divmod(r, 4)
             assert out[j, k] == x[j, z, y, xx]
+
+
+# --------------------------------------------------------------------------
+# stratified initial sites (Sec. 3.2.1, Eq. 3, Eq. 4)
+from fractions import Fraction  # noqa: E402
+import math  # noqa: E402
+
+from oracle import seeding  # noqa: E402
+
+
+def test_philox_known_answers():
+    # known-answer vectors of Philox4x32-10 published with the generator
+    # (Salmon et al., SC 2011, Random123 known-answer tests)
+    cases = [((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+             ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+             ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+              (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1))]
+    for ctr, key, want in cases:
+        assert oracle.philox4x32(ctr, key) == want
+
+
+def _pieces(seed, shape=(20, 18, 22), n_bands=3):
+    rng = np.random.default_rng(seed)
+    band = brute.random_bands(shape, n_bands, rng, True)
+    cc = oracle.components(band, n_bands)
+    return rng, cc
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_seed_counts_closed_form_uniform(seed):
+    # uniform mass: n_c = max(ceil(|C| / rho), 1) (Eq. 3 with m = 1)
+    rng, cc = _pieces(seed)
+    rho = int(rng.integers(20, 200))
+    s = oracle.seed_stratified(cc.comp, cc.n_comp, None, None, rho=rho, block=8, seed=seed)
+    got = np.bincount(cc.comp.ravel()[s], minlength=cc.n_comp)
+    want = [max(math.ceil(int(n) / rho), 1) for n in cc.comp_size]
+    np.testing.assert_array_equal(got, want)
+
+
+def test_seed_counts_weighted_fraction():
+    rng, cc = _pieces(5)
+    w = rng.integers(0, 1000, size=cc.comp.shape).astype(np.uint16)
+    rho = 37
+    s = oracle.seed_stratified(cc.comp, cc.n_comp, w, None, rho=rho, block=8, seed=3)
+    got = np.bincount(cc.comp.ravel()[s], minlength=cc.n_comp)
+    m = w.ravel().astype(np.int64)
+    total = int(m.sum())
+    n = m.size
+    for c in range(cc.n_comp):
+        mc = int(m[cc.comp.ravel() == c].sum())
+        want = max(math.ceil(Fraction(mc * n, rho * total)), 1)
+        assert got[c] == want, c
+
+
+def test_apportion_is_largest_remainder():
+    # Hamilton's method: every share is floor or ceil of the quota, the total is
+    # n_c, and no block that was rounded down has a larger remainder (or an
+    # equal remainder and a lower block index) than one that was rounded up
+    rng = np.random.default_rng(11)
+    for _ in range(300):
+        k = int(rng.integers(1, 12))
+        masses = [int(v) for v in rng.integers(0, 50, size=k)]
+        if sum(masses) == 0:
+            masses[0] = 1
+        blocks = sorted(int(b) for b in rng.choice(1000, size=k, replace=False))
+        n_c = int(rng.integers(1, 40))
+        got = seeding.apportion(n_c, masses, blocks)
+        total = sum(masses)
+        q = [Fraction(n_c * m, total) for m in masses]
+        assert sum(got) == n_c
+        up = [i for i in range(k) if got[i] == math.floor(q[i]) + 1]
+        down = [i for i in range(k) if got[i] == math.floor(q[i])]
+        assert len(up) + len(down) == k
+        for i in up:
+            for j in down:
+                fi, fj = q[i] - math.floor(q[i]), q[j] - math.floor(q[j])
+                assert fi > fj or (fi == fj and blocks[i] < blocks[j])
+
+
+def test_seed_placement_bruteforce_tiny():
+    # site j of a pair holds point p_j = floor((o + j m(b)) / n_b) in its
+    # cumulative-mass interval, walking the pair's voxels in linear order
+    rng, cc = _pieces(7, shape=(9, 10, 11), n_bands=2)
+    w = rng.integers(0, 9, size=cc.comp.shape).astype(np.uint16)
+    block, rho, key = 4, 6, 0x1234_5678_9ABC
+    s = oracle.seed_stratified(cc.comp, cc.n_comp, w, None, rho=rho, block=block, seed=key)
+    nz, ny, nx = cc.comp.shape
+    comp = cc.comp.ravel()
+    m = w.ravel().astype(np.int64)
+    blk = seeding.block_index(cc.comp.shape, block)
+    k = 0
+    for c in range(cc.n_comp):
+        mine = s[comp[s] == c]
+        if m[comp == c].sum() == 0:
+            assert list(mine) == [int(np.flatnonzero(comp == c)[0])]
+            k += 1
+            continue
+        for b in sorted(set(blk[mine].tolist())):
+            vox = [v for v in range(comp.size) if comp[v] == c and blk[v] == b]
+            mb = int(sum(m[v] for v in vox))
+            got = [int(v) for v in mine if blk[v] == b]
+            nb = len(got)
+            o = seeding.pair_offset(key, b, c, mb)
+            for j in range(nb):
+                p = (o + j * mb) // nb
+                acc = 0
+                for v in vox:
+                    if acc <= p < acc + m[v]:
+                        assert got[j] == v
+                        break
+                    acc += m[v]
+                else:
+                    raise AssertionError("point beyond the pair's mass")
+            k += nb
+    assert k == len(s)
+
+
+def test_seed_uniform_pair_spacing_order_and_determinism():
+    rng, cc = _pieces(9, shape=(24, 24, 24), n_bands=2)
+    s = oracle.seed_stratified(cc.comp, cc.n_comp, None, None, rho=50, block=8, seed=99)
+    comp = cc.comp.ravel()
+    blk = seeding.block_index(cc.comp.shape, 8)
+    key = comp[s].astype(np.int64) * (blk.max() + 1) + blk[s]
+    assert np.all(np.diff(key) >= 0)  # numbered by (component, block)
+    # uniform mass: the picks of a pair are distinct and evenly spaced in the pair's order
+    for c, b in set(zip(comp[s].tolist(), blk[s].tolist())):
+        vox = np.flatnonzero((comp == c) & (blk == b))
+        picks = np.searchsorted(vox, s[(comp[s] == c) & (blk[s] == b)])
+        nb, kb = len(picks), len(vox)
+        d = np.diff(picks)
+        assert len(set(picks.tolist())) == nb
+        assert np.all((d == kb // nb) | (d == -(-kb // nb)))
+    np.testing.assert_array_equal(s, oracle.seed_stratified(cc.comp, cc.n_comp, None, None, rho=50, block=8,
+                                                            seed=99))
+    assert not np.array_equal(s, oracle.seed_stratified(cc.comp, cc.n_comp, None, None, rho=50, block=8, seed=98))
+
+
+def test_seed_lut_and_zero_mass():
+    rng, cc = _pieces(12)
+    w = rng.integers(0, 300, size=cc.comp.shape).astype(np.uint16)
+    ones = np.ones(65536, dtype=np.uint32)
+    np.testing.assert_array_equal(oracle.seed_stratified(cc.comp, cc.n_comp, w, ones, rho=40, block=8, seed=1),
+                                  oracle.seed_stratified(cc.comp, cc.n_comp, None, None, rho=40, block=8, seed=1))
+    # a table that zeroes every weight below 150: no site on a zero-mass voxel
+    lut = np.arange(65536, dtype=np.uint32)
+    lut[:150] = 0
+    s = oracle.seed_stratified(cc.comp, cc.n_comp, w, lut, rho=40, block=8, seed=1)
+    comp = cc.comp.ravel()
+    m = lut[w.ravel()]
+    for v in s:
+        c = comp[v]
+        if m[comp == c].sum() > 0:
+            assert m[v] > 0
+        else:
+            assert v == np.flatnonzero(comp == c)[0]
+
+
+def test_seed_block_index_from_linear_index():
+    # block of voxel v from its linear index v = x + nx (y + ny z)
+    shape, B = (13, 7, 10), 4
+    nz, ny, nx = shape
+    got = seeding.block_index(shape, B)
+    nbx, nby = -(-nx // B), -(-ny // B)
+    for v in range(nx * ny * nz):
+        x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
+        assert got[v] == x // B + nbx * (y // B + nby * (z // B))
