@@ -332,6 +332,46 @@ int32_t lsrvt_extract(const float *d_vars, int32_t n_vars, lsrvt_dims dims, cons
                       uint32_t n_placed, float *d_out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Stratified initial sites (Sec. 3.2.1, Eq. 3 and Eq. 4).  Voxel mass
+ * m(v) = d_mass_lut[w(v)] (the attraction gamma enters through the table,
+ * e.g. round(s * w^gamma)); m = w without a table, m = 1 without weights.
+ * Component C gets n_c = max(ceil(m(C) * N / (rho * M)), 1) sites (M the
+ * total mass: one site per rho voxels of average mass).  The volume is cut
+ * into cubes of edge `block`; the (component, block) pairs of C share its
+ * sites by floor(n_c * m(b) / m(C)) plus one each for the largest
+ * remainders n_c * m(b) mod m(C), ties to the lower block index.  Inside a
+ * pair the n_b sites are placed by systematic sampling proportional to mass
+ * over the pair's voxels in linear-index order: site j is the voxel whose
+ * cumulative-mass interval holds floor((o + j * m(b)) / n_b), with
+ * o = (w0 | w1 << 32) mod m(b) and (w0, w1) the first two words of
+ * Philox4x32-10 with key (seed low, seed high) and counter (block index,
+ * component, 0, 0).  A voxel heavier than m(b) / n_b may be picked twice
+ * (co-located sites are allowed by lsrvt_cvt).  A component of zero mass
+ * gets one site, its first voxel.  Sites are numbered by (component, block
+ * index, j).  All decisions are exact integer arithmetic: deterministic.
+ *   d_comp        uint32[N]        component of every voxel (< n_comp)
+ *   d_comp_first  uint32[n_comp]   smallest linear index of each component
+ *                                  (as lsrvt_components outputs it)
+ *   d_weights     uint16[N] or NULL
+ *   d_mass_lut    uint32[65536] or NULL (requires d_weights)
+ *   rho           voxels per site, >= 1
+ *   block         cube edge, 1..16
+ *   cap_pairs     capacity for (component, block) pairs (sizes the
+ *                 workspace); *h_n_pairs receives the count
+ *   d_sites       uint32[cap_sites] output; *h_n_sites receives the count
+ * LSRVT_ECAPACITY when the pairs or the sites exceed their capacity (the
+ * counts are reported; sites are not written), LSRVT_EINVAL for bad
+ * arguments or a component id >= n_comp, LSRVT_ELIMIT when a site count
+ * does not fit 32 bits.  Synchronises the stream twice.
+ * Workspace: lsrvt_seed_workspace(dims, n_comp, block, cap_pairs).
+ */
+size_t lsrvt_seed_workspace(lsrvt_dims dims, uint32_t n_comp, int32_t block, uint32_t cap_pairs);
+int32_t lsrvt_seed(const uint32_t *d_comp, const uint32_t *d_comp_first, lsrvt_dims dims, uint32_t n_comp,
+                   const uint16_t *d_weights, const uint32_t *d_mass_lut, uint32_t rho, int32_t block,
+                   uint64_t seed, uint32_t cap_pairs, uint32_t *d_sites, uint32_t cap_sites, uint32_t *h_n_sites,
+                   uint32_t *h_n_pairs, void *d_work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Benchmark instrumentation of the Voronoi level kernel (the dominant kernel
  * of the Lloyd loop; one launch per breadth-first level).  While enabled,
  * every batch of back-to-back level launches is bracketed by one hipEvent

@@ -35,7 +35,7 @@ EXPORTS = (
     "lsrvt_status_string", "lsrvt_version", "lsrvt_isobands", "lsrvt_components_workspace",
     "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
     "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
-    "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract",
+    "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed_workspace", "lsrvt_seed",
     "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
@@ -115,12 +115,16 @@ def _lib():
         lib.lsrvt_layout_workspace.restype = S
         lib.lsrvt_layout.argtypes = [P, Dims, P, u32, P, u32, i32, P, P, P, P, P, ctypes.POINTER(u32), P, S, P]
         lib.lsrvt_extract.argtypes = [P, i32, Dims, P, u32, P, P]
+        lib.lsrvt_seed_workspace.argtypes = [Dims, u32, i32, u32]
+        lib.lsrvt_seed_workspace.restype = S
+        lib.lsrvt_seed.argtypes = [P, P, Dims, u32, P, P, u32, i32, ctypes.c_uint64, u32, P, u32,
+                                   ctypes.POINTER(u32), ctypes.POINTER(u32), P, S, P]
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
-                     "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_timing_enable",
-                     "lsrvt_timing_read"):
+                     "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed",
+                     "lsrvt_timing_enable", "lsrvt_timing_read"):
             getattr(lib, name).restype = i32
         _LIB = lib
     return _LIB
@@ -576,3 +580,42 @@ def lsrvt_timing_read():
     _check(_lib().lsrvt_timing_read(ctypes.byref(ms), ctypes.byref(la), ctypes.byref(pa), ctypes.byref(vx)),
            "lsrvt_timing_read")
     return ms.value, la.value, pa.value, vx.value
+
+
+def lsrvt_seed(comp, comp_first, n_comp: int, weights=None, mass_lut=None, rho: int = 4096, block: int = 16,
+               seed: int = 0, cap_pairs: int | None = None, cap_sites: int | None = None, ws: Workspace | None = None,
+               stream=None):
+    """Stratified initial sites (Sec. 3.2.1, Eq. 3 and Eq. 4): int32 tensor of linear indices (uint32 bits)."""
+    torch = _torch()
+    _need(comp, torch.int32, "lsrvt_seed")
+    _need(comp_first, torch.int32, "lsrvt_seed")
+    if weights is not None:
+        _need(weights, torch.int16, "lsrvt_seed")
+    if mass_lut is not None:
+        _need(mass_lut, torch.int32, "lsrvt_seed")
+        if mass_lut.numel() != 65536:
+            raise LsrvtError(EINVAL, "lsrvt_seed", "the mass table has one entry per weight value (65536)")
+    lib = _lib()
+    dims = _dims(comp.shape)
+    dev = comp.device
+    n = comp.numel()
+    nb = -(-comp.shape[2] // block) * -(-comp.shape[1] // block) * -(-comp.shape[0] // block)
+    cap_p = int(cap_pairs) if cap_pairs is not None else min(n, 4 * nb + 2 * int(n_comp))
+    cap_s = int(cap_sites) if cap_sites is not None else max(1024, n // max(int(rho), 1) + 2 * int(n_comp))
+    ws = _ws(ws)
+    n_sites = ctypes.c_uint32(0)
+    n_pairs = ctypes.c_uint32(0)
+    while True:
+        wptr, wbytes = ws.get(lib.lsrvt_seed_workspace(dims, int(n_comp), int(block), cap_p))
+        sites = torch.empty(cap_s, dtype=torch.int32, device=dev)
+        code = lib.lsrvt_seed(_ptr(comp), _ptr(comp_first), dims, int(n_comp), _ptr(weights), _ptr(mass_lut),
+                              int(rho), int(block), int(seed) & 0xFFFFFFFFFFFFFFFF, cap_p, _ptr(sites), cap_s,
+                              ctypes.byref(n_sites), ctypes.byref(n_pairs), wptr, wbytes, _stream(stream))
+        if code == ECAPACITY:
+            cap_p = max(cap_p, int(n_pairs.value))
+            cap_s = max(cap_s, int(n_sites.value))
+            continue
+        _check(code, "lsrvt_seed")
+        break
+    return sites[:int(n_sites.value)]
+

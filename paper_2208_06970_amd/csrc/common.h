@@ -70,10 +70,11 @@ struct Carve {
 struct Sizer {
   size_t off = 0;
   template <class T>
-  void take(size_t count) {
+  T *take(size_t count) {
     size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
     off += bytes;
+    return nullptr;
   }
 };
 

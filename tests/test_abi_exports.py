@@ -62,3 +62,23 @@ def test_host_validation_without_gpu(lib):
                                 fake, 16, nul) == L.EWORKSPACE
     assert lib.lsrvt_cvt(fake, fake, d, fake, 10, nul, -1, fake, fake, fake, nul, fake, 1 << 30, nul) == L.EINVAL
     assert lib.lsrvt_vt(fake, d, fake, 10, fake, fake, 16, nul) == L.EWORKSPACE
+
+
+def test_seed_host_validation_without_gpu(lib):
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(4096)
+    d = L.Dims(64, 64, 64)
+    ns, npairs = ctypes.c_uint32(7), ctypes.c_uint32(7)
+    assert lib.lsrvt_seed_workspace(d, 100, 16, 1000) > 0
+    assert lib.lsrvt_seed_workspace(d, 100, 17, 1000) == 0   # block edge above 16
+    assert lib.lsrvt_seed_workspace(d, 100, 16, 0) == 0
+    args = lambda **k: [k.get("comp", fake), k.get("first", fake), d, k.get("n_comp", 100), k.get("w", nul),
+                        k.get("lut", nul), k.get("rho", 64), k.get("block", 8), 1, k.get("cap", 1000), fake, 10,
+                        ctypes.byref(ns), ctypes.byref(npairs), fake, k.get("wb", 16), nul]
+    assert lib.lsrvt_seed(*args(rho=0)) == L.EINVAL
+    assert lib.lsrvt_seed(*args(first=nul)) == L.EINVAL
+    assert lib.lsrvt_seed(*args(lut=fake)) == L.EINVAL          # a mass table needs weights
+    assert lib.lsrvt_seed(*args(block=0)) == L.EINVAL
+    assert lib.lsrvt_seed(*args(n_comp=0)) == L.EINVAL
+    assert lib.lsrvt_seed(*args()) == L.EWORKSPACE              # 16 bytes of workspace
+    assert ns.value == 0 and npairs.value == 0
