@@ -341,10 +341,28 @@ def main():
                      "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": vt_launches, "passes": vt_passes,
                      "alg_bytes_per_launch": round(alg_bytes_per_launch, 1)},
     }
+    out["seeding"] = bench_seeding(L, cc, w, n)
     if not args.no_cpu_baseline:
         _log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, seeds)
     print(json.dumps(out), flush=True)
+
+
+def bench_seeding(L, cc, w, n, reps: int = 5):
+    """On-device stratified initial sites (lsrvt_seed) on the same volume,
+    timed on their own (the step above takes its sites as an input)."""
+    import torch
+    ws = L.Workspace(w.device)
+    kw = dict(rho=4096, block=16, seed=0x5EED)
+    s = L.lsrvt_seed(cc.comp, cc.comp_first, cc.n_comp, w, None, ws=ws, **kw)  # sizes the workspace
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s = L.lsrvt_seed(cc.comp, cc.comp_first, cc.n_comp, w, None, ws=ws, **kw)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    return {"ms": round(ms, 4), "gvox_s": round(n / (ms / 1e3) / 1e9, 4), "sites": int(s.numel()),
+            "rho": kw["rho"], "block": kw["block"], "includes": "two host synchronisations per call"}
 
 
 if __name__ == "__main__":

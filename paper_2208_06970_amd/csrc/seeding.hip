@@ -333,7 +333,10 @@ __global__ void k_seed_unsort(const uint32_t *idx, int64_t P, const uint32_t *sn
 }
 
 // Per block, each pair with sites: prefix sums of the pair's mass over the
-// block's voxels in linear order, then the systematic points.
+// block's voxels in linear order, then the systematic points.  The block's
+// components and masses are read once into registers (thread t holds voxels
+// 16 t .. 16 t + 15); per pair the prefix sums are a wave scan of the
+// per-thread sums plus the four wave totals.
 __global__ __launch_bounds__(kSeedThreads) void k_seed_place(const uint32_t *__restrict__ comp, SeedGeom G,
                                                              MassIn mi, const uint32_t *poff,
                                                              const uint32_t *pair_comp,
@@ -342,12 +345,24 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_place(const uint32_t *__r
                                                              const uint32_t *soff_pair, uint32_t key_lo,
                                                              uint32_t key_hi, uint32_t *sites, uint32_t cap) {
   __shared__ unsigned long long cum[kBlockCap];
-  __shared__ unsigned long long part[kSeedThreads];
-  const int t = threadIdx.x;
+  __shared__ unsigned long long wtot[kSeedThreads / kWave];
+  const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
   const int nv = G.B * G.B * G.B;
   constexpr int kPer = kBlockCap / kSeedThreads;
   for (int64_t b = blockIdx.x; b < G.nblocks; b += gridDim.x) {
-    for (uint32_t k = poff[b]; k < poff[b + 1]; ++k) {
+    const uint32_t k0 = poff[b], k1 = poff[b + 1];
+    uint32_t any = 0;
+    for (uint32_t k = k0; k < k1; ++k) any |= nb_pair[k];
+    if (!any) continue;  // uniform: no site in this block
+    uint32_t vc[kPer], vm[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int kv = t * kPer + j;
+      const int64_t v = kv < nv ? block_voxel(G, b, kv) : -1;
+      vc[j] = v >= 0 ? comp[v] : kNone;
+      vm[j] = v >= 0 ? voxel_mass(mi, v) : 0u;
+    }
+    for (uint32_t k = k0; k < k1; ++k) {
       const uint32_t nb = nb_pair[k];
       if (nb == 0) continue;  // uniform across the workgroup
       const uint32_t c = pair_comp[k];
@@ -357,24 +372,22 @@ __global__ __launch_bounds__(kSeedThreads) void k_seed_place(const uint32_t *__r
         if (t == 0 && so < cap) sites[so] = comp_first[c];
         continue;
       }
-      // this thread's voxels t * kPer .. + kPer - 1
       unsigned long long run = 0, loc[kPer];
 #pragma unroll
       for (int j = 0; j < kPer; ++j) {
-        const int kv = t * kPer + j;
-        const int64_t v = kv < nv ? block_voxel(G, b, kv) : -1;
-        run += (v >= 0 && comp[v] == c) ? voxel_mass(mi, v) : 0u;
+        run += vc[j] == c ? vm[j] : 0u;
         loc[j] = run;
       }
-      part[t] = run;
-      __syncthreads();
-      for (int o = 1; o < kSeedThreads; o <<= 1) {
-        const unsigned long long x = t >= o ? part[t - o] : 0ull;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
+      unsigned long long inc = run;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const unsigned long long x = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += x;
       }
-      const unsigned long long before = t > 0 ? part[t - 1] : 0ull;
+      if (lane == kWave - 1) wtot[wid] = inc;
+      __syncthreads();
+      unsigned long long before = inc - run;
+      for (int q = 0; q < wid; ++q) before += wtot[q];
 #pragma unroll
       for (int j = 0; j < kPer; ++j) cum[t * kPer + j] = before + loc[j];
       __syncthreads();
