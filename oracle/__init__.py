@@ -26,6 +26,8 @@ ctypes.  Each function cites the passage of the paper it follows:
   Layout" / Fig. 5: the voxels of the cells ordered by band, component and
   cell, with offsets per cell, component and band (numpy, stable sorts)
 * :func:`extract`     -- the raw variables in that order
+* :func:`comoments`   -- Sec. 4.4: centred joint moments of orders 2-4 of
+  every unit, direct two-pass float64 numpy (in ``moments.py``)
 * :func:`seed_stratified` -- Sec. 3.2.1, Eq. 3 and Eq. 4: stratified initial
   sites (numpy and exact Python integers, in ``seeding.py``, with the
   Philox4x32-10 generator it draws from)
@@ -295,3 +297,4 @@ def extract(variables: np.ndarray, perm) -> np.ndarray:
 
 
 from .seeding import philox4x32, seed_stratified  # noqa: E402,F401
+from .moments import Moments, comoments, tuples  # noqa: E402,F401

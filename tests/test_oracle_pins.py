@@ -624,3 +624,64 @@ def test_seed_block_index_from_linear_index():
     for v in range(nx * ny * nz):
         x, y, z = v % nx, (v // nx) % ny, v // (nx * ny)
         assert got[v] == x // B + nbx * (y // B + nby * (z // B))
+
+
+# --------------------------------------------------------------------------
+# joint moments up to fourth order (Sec. 4.4: covariance, coskewness, cokurtosis)
+from scipy import stats as sstats  # noqa: E402
+
+
+def test_comoments_diagonal_match_scipy_moment():
+    rng = np.random.default_rng(21)
+    unit = rng.integers(0, 5, size=(6, 7, 8)).astype(np.uint32)
+    unit.ravel()[::11] = oracle.NONE_ID
+    x = rng.gamma(2.0, size=(3, 6, 7, 8)).astype(np.float32)
+    mo = oracle.comoments(unit, 6, x)
+    t2, t3, t4 = (oracle.tuples(3, r) for r in (2, 3, 4))
+    for u in range(5):
+        sel = unit.ravel() == u
+        n = int(sel.sum())
+        assert mo.n[u] == n
+        for j in range(3):
+            v = x[j].ravel()[sel].astype(np.float64)
+            np.testing.assert_allclose(mo.m2[u, t2.index((j, j))], n * sstats.moment(v, 2), rtol=1e-12)
+            np.testing.assert_allclose(mo.m3[u, t3.index((j, j, j))], n * sstats.moment(v, 3), rtol=1e-9,
+                                       atol=1e-9 * n * v.std() ** 3)
+            np.testing.assert_allclose(mo.m4[u, t4.index((j, j, j, j))], n * sstats.moment(v, 4), rtol=1e-12)
+    assert mo.n[5] == 0 and np.all(mo.m4[5] == 0) and np.all(mo.mean[5] == 0)
+
+
+def test_comoments_exact_cross_terms_fraction():
+    # small integers: every cross moment checked in exact rational arithmetic
+    rng = np.random.default_rng(22)
+    unit = rng.integers(0, 3, size=(3, 4, 5)).astype(np.uint32)
+    x = rng.integers(-4, 5, size=(3, 3, 4, 5)).astype(np.float32)
+    mo = oracle.comoments(unit, 3, x)
+    for u in range(3):
+        sel = unit.ravel() == u
+        rows = [[Fraction(int(v)) for v in x[j].ravel()[sel]] for j in range(3)]
+        n = len(rows[0])
+        mu = [sum(r) / n for r in rows]
+        d = [[v - mu[j] for v in rows[j]] for j in range(3)]
+        for r, got in ((2, mo.m2[u]), (3, mo.m3[u]), (4, mo.m4[u])):
+            for k, tup in enumerate(oracle.tuples(3, r)):
+                want = sum(math.prod(d[i][p] for i in tup) for p in range(n))
+                assert got[k] == pytest.approx(float(want), rel=1e-12, abs=1e-9)
+
+
+def test_comoments_symmetric_and_shift_invariant():
+    # mirrored data (x and 2c - x in equal numbers) has zero odd central moments;
+    # central moments do not change when a constant is added
+    rng = np.random.default_rng(23)
+    half = (np.round(rng.normal(size=(2, 500)) * 1024) / 1024).astype(np.float32)  # multiples of 2^-10
+    x = np.concatenate([half, 2 * 3.0 - half], axis=1).astype(np.float32)
+    unit = np.zeros(x.shape[1], dtype=np.uint32)
+    mo = oracle.comoments(unit, 1, x)
+    scale = mo.m2[0, 0] ** 1.5
+    assert np.all(np.abs(mo.m3[0]) <= 1e-9 * scale)
+    # shift by 8 (exact in float32 for multiples of 2^-10 this small): central moments are unchanged
+    sh = (x + np.float32(8.0)).astype(np.float32)
+    mo2 = oracle.comoments(unit, 1, sh)
+    np.testing.assert_allclose(mo2.mean, mo.mean + 8.0, rtol=1e-12)
+    np.testing.assert_allclose(mo2.m4, mo.m4, rtol=1e-12)
+    np.testing.assert_allclose(mo2.m3, mo.m3, rtol=0, atol=1e-9 * scale)
