@@ -236,6 +236,47 @@ int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t 
                         const lsrvt_group_stats *band, void *d_work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Joint moments up to fourth order of every cell, merged up the hierarchy
+ * cell -> component -> band: the covariance, coskewness and cokurtosis sums
+ * that the joint plots compare between raw data and fitted distribution
+ * models (Sec. 4.4), over the hierarchy of Sec. 3.2.4 / Fig. 5.
+ * For every unit with n voxels and variables x_1..x_m (d = x - mean):
+ *   M2[i,j] = sum d_i d_j (i <= j), M3[i,j,k] = sum d_i d_j d_k (i <= j <= k),
+ *   M4[i,j,k,l] = sum d_i d_j d_k d_l (i <= j <= k <= l),
+ * each packed in lexicographic order of its index tuple (m(m+1)/2,
+ * m(m+1)(m+2)/6 and m(m+1)(m+2)(m+3)/24 entries).  Coskewness and
+ * cokurtosis are these sums over n times the standard deviations involved.
+ * All arithmetic is float64: cells sum products of offsets from the value
+ * at the cell's site and convert them to centred sums; components merge
+ * their cells (by site id) and bands their components (by id) with
+ * pairwise update formulas (Pebay 2008) in a fixed order.  Units with n = 0
+ * report zeros.  Voxels labelled LSRVT_NONE are skipped.
+ *   output arrays (device, caller-allocated, U units): n [U] uint64,
+ *   mean [U][m], m2 [U][P2], m3 [U][P3], m4 [U][P4] float64; cells are
+ *   indexed by site id.
+ *   d_cell, d_sites, d_site_comp, d_comp_band: as for lsrvt_aggregate
+ *   d_vars        float32[m][N], 1 <= m <= 8
+ * Synchronises the stream (layout sizes, merge work lists).  Errors:
+ * EINVAL (m outside 1..8, bands outside 1..255, NULL arrays).
+ * Workspace: lsrvt_comoments_workspace(dims, n_sites, n_comp, n_bands, m).
+ */
+typedef struct {
+  uint64_t *n;
+  double *mean;
+  double *m2;
+  double *m3;
+  double *m4;
+} lsrvt_moments;
+
+size_t lsrvt_comoments_workspace(lsrvt_dims dims, uint32_t n_sites, uint32_t n_comp, int32_t n_bands,
+                                 int32_t n_vars);
+int32_t lsrvt_comoments(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t *d_sites,
+                        const uint32_t *d_site_comp, uint32_t n_sites, const uint8_t *d_comp_band,
+                        uint32_t n_comp, int32_t n_bands, const float *d_vars, int32_t n_vars,
+                        const lsrvt_moments *cell, const lsrvt_moments *comp, const lsrvt_moments *band,
+                        void *d_work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Many independent jobs through the whole path in one call (one job = one
  * volume: Sec. 3.1 isobands and components, Algorithm 1, Sec. 3.3 statistics,
  * as the four calls above compute them).  Jobs run on up to n_streams

@@ -36,6 +36,7 @@ EXPORTS = (
     "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
     "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
     "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed_workspace", "lsrvt_seed",
+    "lsrvt_comoments_workspace", "lsrvt_comoments",
     "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
@@ -56,6 +57,11 @@ class LsrvtError(RuntimeError):
 
 class Dims(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32)]
+
+
+class MomentsC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_void_p), ("mean", ctypes.c_void_p), ("m2", ctypes.c_void_p), ("m3", ctypes.c_void_p),
+                ("m4", ctypes.c_void_p)]
 
 
 class CellStatsC(ctypes.Structure):
@@ -115,6 +121,10 @@ def _lib():
         lib.lsrvt_layout_workspace.restype = S
         lib.lsrvt_layout.argtypes = [P, Dims, P, u32, P, u32, i32, P, P, P, P, P, ctypes.POINTER(u32), P, S, P]
         lib.lsrvt_extract.argtypes = [P, i32, Dims, P, u32, P, P]
+        lib.lsrvt_comoments_workspace.argtypes = [Dims, u32, u32, i32, i32]
+        lib.lsrvt_comoments_workspace.restype = S
+        lib.lsrvt_comoments.argtypes = [P, Dims, P, P, u32, P, u32, i32, P, i32, ctypes.POINTER(MomentsC),
+                                        ctypes.POINTER(MomentsC), ctypes.POINTER(MomentsC), P, S, P]
         lib.lsrvt_seed_workspace.argtypes = [Dims, u32, i32, u32]
         lib.lsrvt_seed_workspace.restype = S
         lib.lsrvt_seed.argtypes = [P, P, Dims, u32, P, P, u32, i32, ctypes.c_uint64, u32, P, u32,
@@ -124,6 +134,7 @@ def _lib():
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
                      "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed",
+                     "lsrvt_comoments",
                      "lsrvt_timing_enable", "lsrvt_timing_read"):
             getattr(lib, name).restype = i32
         _LIB = lib
@@ -618,4 +629,47 @@ def lsrvt_seed(comp, comp_first, n_comp: int, weights=None, mass_lut=None, rho: 
         _check(code, "lsrvt_seed")
         break
     return sites[:int(n_sites.value)]
+
+
+@dataclass
+class Moments:
+    """Joint moments of a set of units (device tensors, float64)."""
+    n: "object"      # int64 [U] (uint64 counts)
+    mean: "object"   # [U, m]
+    m2: "object"     # [U, m(m+1)/2]
+    m3: "object"     # [U, m(m+1)(m+2)/6]
+    m4: "object"     # [U, m(m+1)(m+2)(m+3)/24]
+
+
+def _moments(U, m, dev):
+    torch = _torch()
+    P2, P3, P4 = m * (m + 1) // 2, m * (m + 1) * (m + 2) // 6, m * (m + 1) * (m + 2) * (m + 3) // 24
+    f = lambda k: torch.empty((max(U, 1), k), dtype=torch.float64, device=dev)
+    mo = Moments(torch.empty(max(U, 1), dtype=torch.int64, device=dev), f(m), f(P2), f(P3), f(P4))
+    c = MomentsC(*(ctypes.c_void_p(t.data_ptr()) for t in (mo.n, mo.mean, mo.m2, mo.m3, mo.m4)))
+    return mo, c
+
+
+def lsrvt_comoments(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int, variables,
+                    ws: Workspace | None = None, stream=None):
+    """Joint moments up to fourth order per cell, component and band (Sec. 4.4)."""
+    torch = _torch()
+    _need(cell, torch.int32, "lsrvt_comoments")
+    _need(variables, torch.float32, "lsrvt_comoments")
+    lib = _lib()
+    dims = _dims(cell.shape)
+    m = int(variables.shape[0])
+    S = int(sites.numel())
+    dev = cell.device
+    cm, cc = _moments(S, m, dev)
+    gm, gc = _moments(int(n_comp), m, dev)
+    bm, bc = _moments(int(n_bands), m, dev)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_comoments_workspace(dims, S, int(n_comp), int(n_bands), m))
+    code = lib.lsrvt_comoments(_ptr(cell), dims, _ptr(sites), _ptr(site_comp), S, _ptr(comp_band), int(n_comp),
+                               int(n_bands), _ptr(variables), m, ctypes.byref(cc), ctypes.byref(gc),
+                               ctypes.byref(bc), wptr, wbytes, _stream(stream))
+    _check(code, "lsrvt_comoments")
+    trim = lambda mo, U: Moments(mo.n[:U], mo.mean[:U], mo.m2[:U], mo.m3[:U], mo.m4[:U])
+    return trim(cm, S), trim(gm, int(n_comp)), trim(bm, int(n_bands))
 
