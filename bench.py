@@ -17,6 +17,10 @@ denominator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
+The main line also carries, timed on their own outside the step, the
+on-device stratified initial sites of the same volume ("seeding") and the
+joint moments up to fourth order of the step's cells ("comoments").
+
 Two more modes print their own JSON line instead of the main one:
   --batch   64 independent Fourier volumes (edges 32..192, cubes and 2:1:1
             boxes, 3..10 isovalues, 15 updates) through lsrvt_batch_run on
@@ -342,10 +346,30 @@ def main():
                      "alg_bytes_per_launch": round(alg_bytes_per_launch, 1)},
     }
     out["seeding"] = bench_seeding(L, cc, w, n)
+    out["comoments"] = bench_comoments(L, step, cc, x, wl.n_bands, n)
     if not args.no_cpu_baseline:
         _log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, seeds)
     print(json.dumps(out), flush=True)
+
+
+def bench_comoments(L, step, cc, x, n_bands, n, reps: int = 3):
+    """Joint moments up to fourth order (lsrvt_comoments) of the cells of one
+    step, all 8 variables, timed on their own."""
+    import torch
+    r = step(False)
+    ws = L.Workspace(x.device)
+    L.lsrvt_comoments(r.cell, r.sites, r.site_comp, cc.comp_band, cc.n_comp, n_bands, x, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.lsrvt_comoments(r.cell, r.sites, r.site_comp, cc.comp_band, cc.n_comp, n_bands, x, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    m = int(x.shape[0])
+    units = m + m * (m + 1) // 2 + m * (m + 1) * (m + 2) // 6 + m * (m + 1) * (m + 2) * (m + 3) // 24
+    return {"ms": round(ms, 4), "gvox_s": round(n / (ms / 1e3) / 1e9, 4), "vars": m, "sums_per_voxel": units,
+            "dtype": "f64", "includes": "structured layout of the cells, merges, host synchronisations"}
 
 
 def bench_seeding(L, cc, w, n, reps: int = 5):
