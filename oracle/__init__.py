@@ -28,6 +28,11 @@ ctypes.  Each function cites the passage of the paper it follows:
 * :func:`extract`     -- the raw variables in that order
 * :func:`comoments`   -- Sec. 4.4: centred joint moments of orders 2-4 of
   every unit, direct two-pass float64 numpy (in ``moments.py``)
+* :func:`los_vt`, :func:`los_update`, :func:`los_cvt` -- Eq. 1 with the
+  Euclidean line-of-sight paths of Sec. 3.2.2, the Eq. 2 centroid with
+  masses carried to line-of-sight voxels and the ray-clamped move of
+  Sec. 3.2.3 (in ``los_oracle.c``), with :func:`supercover`, the voxels a
+  segment between two voxel centres touches
 * :func:`seed_stratified` -- Sec. 3.2.1, Eq. 3 and Eq. 4: stratified initial
   sites (numpy and exact Python integers, in ``seeding.py``, with the
   Philox4x32-10 generator it draws from)
@@ -42,7 +47,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "lsrvt_oracle.c")
+_SRCS = [os.path.join(_HERE, "lsrvt_oracle.c"), os.path.join(_HERE, "los_oracle.c")]
 _LIB = os.path.join(_HERE, "liblsrvt_oracle.so")
 
 NONE_ID = 0xFFFFFFFF
@@ -57,11 +62,12 @@ class OracleError(RuntimeError):
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (no fused multiply-add contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS)
+    if force or stale:
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(
             ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
-             "-o", tmp, _SRC, "-lm"]
+             "-o", tmp, *_SRCS, "-lm"]
         )
         os.replace(tmp, _LIB)
     return _LIB
@@ -84,8 +90,15 @@ def _load():
         lib.oracle_update.argtypes = [P, i32, i32, i32, P, P, u32, P]
         lib.oracle_cvt.argtypes = [P, i32, i32, i32, P, u32, P, i32, P, P, P, P]
         lib.oracle_stats.argtypes = [P, i64, u32, P, i32, P, i32, P, P, P, P, P, P, P]
+        lib.oracle_supercover.argtypes = [P, P, P, i64]
+        lib.oracle_supercover.restype = i64
+        lib.oracle_los_vt.argtypes = [P, i32, i32, i32, P, P, u32, P, P, P, P, P]
+        lib.oracle_los_update.argtypes = [P, i32, i32, i32, P, P, P, u32, P, P, P]
+        lib.oracle_los_cvt.argtypes = [P, i32, i32, i32, P, u32, P, i32, P, P, P, P, P, P]
+        lib.oracle_los_clamp.argtypes = [P, i32, i32, i32, P, P, P]
         for f in (lib.oracle_bands, lib.oracle_components, lib.oracle_vt, lib.oracle_vt_unpruned,
-                  lib.oracle_update, lib.oracle_cvt, lib.oracle_stats):
+                  lib.oracle_update, lib.oracle_cvt, lib.oracle_stats, lib.oracle_los_vt,
+                  lib.oracle_los_update, lib.oracle_los_cvt, lib.oracle_los_clamp):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -295,6 +308,106 @@ def extract(variables: np.ndarray, perm) -> np.ndarray:
     x = np.asarray(variables)
     return x.reshape(x.shape[0], -1)[:, np.asarray(perm, dtype=np.int64)]
 
+
+
+# --------------------------------------------------------------------------
+# Euclidean line-of-sight tessellation and site update (los_oracle.c)
+SITE_FLAG = 0x80000000
+
+
+def supercover(a, b) -> np.ndarray:
+    """Voxels whose closed unit cube meets the segment between the centres
+    of voxels a and b, as int32[k, 3] (x, y, z), a first."""
+    A = np.ascontiguousarray(a, dtype=np.int32)
+    B = np.ascontiguousarray(b, dtype=np.int32)
+    cap = int(np.abs(B.astype(np.int64) - A).sum()) * 7 + 2
+    out = np.empty((cap, 3), dtype=np.int32)
+    k = _load().oracle_supercover(_ptr(A), _ptr(B), _ptr(out), cap)
+    if k < 0:
+        raise OracleError(ELIMIT, "supercover")
+    return out[:k].copy()
+
+
+@dataclass
+class LosVT:
+    dist: np.ndarray   # float64[nz, ny, nx]  path length (+inf: no path)
+    src: np.ndarray    # uint32[nz, ny, nx]   voxel source, SITE_FLAG | s, or NONE
+    phi: np.ndarray    # uint32[nz, ny, nx]   line-of-sight voxel of the path
+    cell: np.ndarray   # uint32[nz, ny, nx]   site of phi
+    sweeps: tuple      # sweeps run by stage 1 and stage 2
+
+
+def los_vt(comp: np.ndarray, site_q, anchor) -> LosVT:
+    """Restricted Voronoi regions with Euclidean line-of-sight paths (Eq. 1,
+    Sec. 3.2.2).  site_q int32[S, 3] in 1/256 voxel, anchor uint32[S]."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    q = np.ascontiguousarray(site_q, dtype=np.int32).reshape(-1, 3)
+    a = np.ascontiguousarray(anchor, dtype=np.uint32)
+    dist = np.empty(c.shape, dtype=np.float64)
+    src = np.empty(c.shape, dtype=np.uint32)
+    phi = np.empty(c.shape, dtype=np.uint32)
+    cell = np.empty(c.shape, dtype=np.uint32)
+    sw = np.zeros(2, dtype=np.int32)
+    _check(_load().oracle_los_vt(_ptr(c), nx, ny, nz, _ptr(q), _ptr(a), len(a), _ptr(dist), _ptr(src),
+                                 _ptr(phi), _ptr(cell), _ptr(sw)), "los_vt")
+    return LosVT(dist, src, phi, cell, (int(sw[0]), int(sw[1])))
+
+
+def los_update(comp: np.ndarray, cell: np.ndarray, phi: np.ndarray, site_q, anchor, weights=None):
+    """Eq. 2 target with masses carried to line-of-sight voxels, then the
+    ray-clamped move (Sec. 3.2.3).  Returns (site_q, anchor, target_q);
+    target_q rows of a zero-mass cell are INT32_MIN."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    q = np.array(site_q, dtype=np.int32, copy=True).reshape(-1, 3)
+    a = np.array(anchor, dtype=np.uint32, copy=True)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint16)
+    t = np.empty_like(q)
+    _check(_load().oracle_los_update(_ptr(c), nx, ny, nz, _ptr(w), _ptr(np.ascontiguousarray(cell, dtype=np.uint32)),
+                                     _ptr(np.ascontiguousarray(phi, dtype=np.uint32)), len(a), _ptr(q), _ptr(a),
+                                     _ptr(t)), "los_update")
+    return q, a, t
+
+
+def los_clamp(comp: np.ndarray, x_q, anchor: int, target_q):
+    """The ray-clamped move of one site from x_q (Q8, inside the closed cube
+    of voxel `anchor`) towards target_q.  Returns (new x_q, new anchor)."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    X = np.array(x_q, dtype=np.int32).reshape(3).copy()
+    A = np.array([anchor], dtype=np.uint32)
+    T = np.array(target_q, dtype=np.int32).reshape(3).copy()
+    _check(_load().oracle_los_clamp(_ptr(c), nx, ny, nz, _ptr(X), _ptr(A), _ptr(T)), "los_clamp")
+    return X, int(A[0])
+
+
+@dataclass
+class LosCVT:
+    site_q: np.ndarray  # int32[S, 3]
+    anchor: np.ndarray  # uint32[S]
+    dist: np.ndarray
+    src: np.ndarray
+    phi: np.ndarray
+    cell: np.ndarray
+
+
+def los_cvt(comp: np.ndarray, seeds, weights=None, iters: int = 0) -> LosCVT:
+    """Lloyd loop with the line-of-sight tessellation: T x (VT + update) and a
+    final VT; sites start at the centres of the seed voxels."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32)
+    nx, ny, nz = _dims(c.shape)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint32)
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.uint16)
+    q = np.empty((len(sd), 3), dtype=np.int32)
+    a = np.empty(len(sd), dtype=np.uint32)
+    dist = np.empty(c.shape, dtype=np.float64)
+    src = np.empty(c.shape, dtype=np.uint32)
+    phi = np.empty(c.shape, dtype=np.uint32)
+    cell = np.empty(c.shape, dtype=np.uint32)
+    _check(_load().oracle_los_cvt(_ptr(c), nx, ny, nz, _ptr(sd), len(sd), _ptr(w), int(iters), _ptr(q), _ptr(a),
+                                  _ptr(dist), _ptr(src), _ptr(phi), _ptr(cell)), "los_cvt")
+    return LosCVT(q, a, dist, src, phi, cell)
 
 from .seeding import philox4x32, seed_stratified  # noqa: E402,F401
 from .moments import Moments, comoments, tuples  # noqa: E402,F401
