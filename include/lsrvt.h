@@ -413,6 +413,76 @@ int32_t lsrvt_seed(const uint32_t *d_comp, const uint32_t *d_comp_first, lsrvt_d
                    uint32_t *h_n_pairs, void *d_work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Euclidean line-of-sight tessellation (Eq. 1 with the paths of
+ * Sec. 3.2.2), the geodesically weighted site update (Eq. 2, Sec. 3.2.3) and
+ * their Lloyd loop.
+ *
+ * Sites are continuous points in fixed point with 8 fraction bits (Q8:
+ * x_q = 256 x, int32[S][3], x fastest), each with an anchor voxel whose
+ * closed unit cube holds it.  A voxel is the closed unit cube centred on its
+ * integer coordinates; a segment is clear when every voxel whose closed
+ * cube meets it lies in the component.
+ *
+ * lsrvt_los_vt: every component voxel v gets a path to a site: src[v] =
+ * LSRVT_LOS_SITE | s when v sees site s (the segment from v to the anchor of
+ * s is clear; the leg length is |x_v - x_s|), else the voxel u where the path
+ * continues (the segment v-u is clear, length |x_v - x_u| + dist[u]).  Paths
+ * grow by synchronous sweeps: v looks at each face neighbour w of its
+ * component holding a path and considers the path through src(w) (with its
+ * ray test), the path through w (dist[w] + 1) and its own path re-measured.
+ * Stage 1 allows paths through sites only; stage 2 all three; each stage
+ * ends with the first sweep that changes nothing.  A voxel takes a new path
+ * only when the shortest valid one is shorter by a relative 2^-40, and then
+ * the preferred path within 2^-40 of that one (a site, lowest id, else the
+ * lowest voxel index); each anchor starts with the site of smallest
+ * (length, id) that sits in it.  Lengths are float64: sqrt of exact integer
+ * squared lengths, correctly rounded, so results are deterministic.
+ *   d_comp     uint32[N]      component per voxel, LSRVT_NONE outside
+ *   d_site_q   int32[S][3]    Q8 positions;  d_anchor uint32[S] anchors
+ *   d_dist     float64[N]     out: path length, +inf where no path
+ *   d_src      uint32[N]      out: source code, LSRVT_NONE where no path
+ *   d_phi      uint32[N]      out: the line-of-sight voxel of the path
+ *                             (phi(v) of Eq. 2), LSRVT_NONE where no path
+ *   d_cell     uint32[N]      out: the site of phi(v), LSRVT_NONE
+ *   h_sweeps   int32[2] or NULL: sweeps run by stage 1 and stage 2
+ * LSRVT_EINVAL when an anchor is outside the volume or its component or
+ * does not hold its site; LSRVT_ELIMIT for S >= 2^31 or a stage that has not
+ * converged after 100000 sweeps.  Synchronises the stream after every batch
+ * of 8 sweeps.  Workspace: lsrvt_los_workspace(dims, n_sites).
+ *
+ * lsrvt_los_update: M = sum m_v and S = sum m_v x_phi(v) over each cell
+ * (exact uint64; m_v the uint16 weight, 1 without weights); the target is
+ * round-half-up(256 S / M) in Q8.  The site then walks the segment from its
+ * position towards the target starting in its anchor, and stops at the first
+ * point where the segment touches the closed cube of a voxel outside its
+ * component or the volume, among the cubes it can move into (none behind
+ * the anchor on an axis it moves along, none beside it on an axis it does
+ * not move along); the position becomes x + trunc(t (target - x)) per axis
+ * and the anchor the voxel the walk stopped in.  A cell of zero mass keeps
+ * its site.  d_site_q and d_anchor are updated in place; d_target_q
+ * (int32[S][3] or NULL) receives the targets, INT32_MIN for empty cells.
+ * LSRVT_EINVAL for a cell id >= S.  Synchronises the stream once.
+ *
+ * lsrvt_los_cvt: sites start at the centres of the seed voxels (anchor =
+ * seed), then iters x (lsrvt_los_vt + lsrvt_los_update) and a final
+ * lsrvt_los_vt whose outputs are returned; *h_sweeps (may be NULL) receives
+ * the total number of sweeps.  LSRVT_EINVAL for a seed outside the volume or
+ * outside every component.
+ */
+#define LSRVT_LOS_SITE 0x80000000u
+size_t lsrvt_los_workspace(lsrvt_dims dims, uint32_t n_sites);
+int32_t lsrvt_los_vt(const uint32_t *d_comp, lsrvt_dims dims, const int32_t *d_site_q, const uint32_t *d_anchor,
+                     uint32_t n_sites, double *d_dist, uint32_t *d_src, uint32_t *d_phi, uint32_t *d_cell,
+                     int32_t *h_sweeps, void *d_work, size_t work_bytes, void *stream);
+int32_t lsrvt_los_update(const uint32_t *d_comp, lsrvt_dims dims, const uint16_t *d_weights,
+                         const uint32_t *d_cell, const uint32_t *d_phi, uint32_t n_sites, int32_t *d_site_q,
+                         uint32_t *d_anchor, int32_t *d_target_q, void *d_work, size_t work_bytes, void *stream);
+int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d_seeds, uint32_t n_sites,
+                      const uint16_t *d_weights, int32_t iters, int32_t *d_site_q, uint32_t *d_anchor,
+                      double *d_dist, uint32_t *d_src, uint32_t *d_phi, uint32_t *d_cell, int32_t *h_sweeps,
+                      void *d_work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Benchmark instrumentation of the Voronoi level kernel (the dominant kernel
  * of the Lloyd loop; one launch per breadth-first level).  While enabled,
  * every batch of back-to-back level launches is bracketed by one hipEvent

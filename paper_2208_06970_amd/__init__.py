@@ -36,8 +36,8 @@ EXPORTS = (
     "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
     "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
     "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed_workspace", "lsrvt_seed",
-    "lsrvt_comoments_workspace", "lsrvt_comoments",
-    "lsrvt_timing_enable", "lsrvt_timing_read",
+    "lsrvt_comoments_workspace", "lsrvt_comoments", "lsrvt_los_workspace", "lsrvt_los_vt", "lsrvt_los_update",
+    "lsrvt_los_cvt", "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
 
@@ -129,12 +129,17 @@ def _lib():
         lib.lsrvt_seed_workspace.restype = S
         lib.lsrvt_seed.argtypes = [P, P, Dims, u32, P, P, u32, i32, ctypes.c_uint64, u32, P, u32,
                                    ctypes.POINTER(u32), ctypes.POINTER(u32), P, S, P]
+        lib.lsrvt_los_workspace.argtypes = [Dims, u32]
+        lib.lsrvt_los_workspace.restype = S
+        lib.lsrvt_los_vt.argtypes = [P, Dims, P, P, u32, P, P, P, P, P, P, S, P]
+        lib.lsrvt_los_update.argtypes = [P, Dims, P, P, P, u32, P, P, P, P, S, P]
+        lib.lsrvt_los_cvt.argtypes = [P, Dims, P, u32, P, i32, P, P, P, P, P, P, P, P, S, P]
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
                      "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed",
-                     "lsrvt_comoments",
+                     "lsrvt_comoments", "lsrvt_los_vt", "lsrvt_los_update", "lsrvt_los_cvt",
                      "lsrvt_timing_enable", "lsrvt_timing_read"):
             getattr(lib, name).restype = i32
         _LIB = lib
@@ -673,3 +678,100 @@ def lsrvt_comoments(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int
     trim = lambda mo, U: Moments(mo.n[:U], mo.mean[:U], mo.m2[:U], mo.m3[:U], mo.m4[:U])
     return trim(cm, S), trim(gm, int(n_comp)), trim(bm, int(n_bands))
 
+
+
+# --------------------------------------------------------------------------
+# Euclidean line-of-sight tessellation (Sec. 3.2.2) and site update (Eq. 2,
+# Sec. 3.2.3)
+LOS_SITE = 0x80000000
+
+
+@dataclass
+class LosVT:
+    dist: "object"   # float64 [nz, ny, nx]
+    src: "object"    # int32 (uint32 bits) [nz, ny, nx]: voxel, LOS_SITE | s, or NONE
+    phi: "object"    # int32 (uint32 bits) [nz, ny, nx]
+    cell: "object"   # int32 (uint32 bits) [nz, ny, nx]
+    sweeps: tuple    # sweeps of stage 1 and stage 2 (lsrvt_los_vt) or total (lsrvt_los_cvt)
+
+
+def _los_out(comp):
+    torch = _torch()
+    e = lambda dt: torch.empty(comp.shape, dtype=dt, device=comp.device)
+    return e(torch.float64), e(torch.int32), e(torch.int32), e(torch.int32)
+
+
+def lsrvt_los_vt(comp, site_q, anchor, ws: Workspace | None = None, stream=None) -> LosVT:
+    """Restricted Voronoi regions with Euclidean line-of-sight paths.  site_q
+    int32 [S, 3] in 1/256 voxel (x, y, z), anchor int32 [S] voxel indices."""
+    torch = _torch()
+    _need(comp, torch.int32, "lsrvt_los_vt")
+    _need(site_q, torch.int32, "lsrvt_los_vt")
+    _need(anchor, torch.int32, "lsrvt_los_vt")
+    S = int(anchor.numel())
+    if site_q.numel() != 3 * S:
+        raise LsrvtError(EINVAL, "lsrvt_los_vt", "site_q must be [S, 3]")
+    lib = _lib()
+    dims = _dims(comp.shape)
+    dist, src, phi, cell = _los_out(comp)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_los_workspace(dims, S))
+    sw = (ctypes.c_int32 * 2)()
+    code = lib.lsrvt_los_vt(_ptr(comp), dims, _ptr(site_q), _ptr(anchor), S, _ptr(dist), _ptr(src), _ptr(phi),
+                            _ptr(cell), sw, wptr, wbytes, _stream(stream))
+    _check(code, "lsrvt_los_vt")
+    return LosVT(dist, src, phi, cell, (int(sw[0]), int(sw[1])))
+
+
+def lsrvt_los_update(comp, cell, phi, site_q, anchor, weights=None, ws: Workspace | None = None, stream=None):
+    """Eq. 2 target with masses carried to line-of-sight voxels, then the
+    ray-clamped move; site_q and anchor are updated in place.  Returns the
+    targets, int32 [S, 3] (INT32_MIN rows for empty cells)."""
+    torch = _torch()
+    for t, dt in ((comp, torch.int32), (cell, torch.int32), (phi, torch.int32), (site_q, torch.int32),
+                  (anchor, torch.int32)):
+        _need(t, dt, "lsrvt_los_update")
+    if weights is not None:
+        _need(weights, torch.int16, "lsrvt_los_update")
+    S = int(anchor.numel())
+    lib = _lib()
+    dims = _dims(comp.shape)
+    target = torch.empty((max(S, 1), 3), dtype=torch.int32, device=comp.device)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_los_workspace(dims, S))
+    code = lib.lsrvt_los_update(_ptr(comp), dims, _ptr(weights), _ptr(cell), _ptr(phi), S, _ptr(site_q),
+                                _ptr(anchor), _ptr(target), wptr, wbytes, _stream(stream))
+    _check(code, "lsrvt_los_update")
+    return target[:S]
+
+
+@dataclass
+class LosCVT:
+    site_q: "object"  # int32 [S, 3]
+    anchor: "object"  # int32 [S]
+    vt: LosVT
+
+
+def lsrvt_los_cvt(comp, seeds, weights=None, iters: int = 0, ws: Workspace | None = None, stream=None) -> LosCVT:
+    """Lloyd loop with the line-of-sight tessellation: sites start at the
+    centres of the seed voxels; iters x (VT + update), then a final VT."""
+    torch = _torch()
+    _need(comp, torch.int32, "lsrvt_los_cvt")
+    _need(seeds, torch.int32, "lsrvt_los_cvt")
+    if weights is not None:
+        _need(weights, torch.int16, "lsrvt_los_cvt")
+    S = int(seeds.numel())
+    lib = _lib()
+    dims = _dims(comp.shape)
+    dev = comp.device
+    site_q = torch.empty((max(S, 1), 3), dtype=torch.int32, device=dev)
+    anchor = torch.empty(max(S, 1), dtype=torch.int32, device=dev)
+    dist, src, phi, cell = _los_out(comp)
+    ws = _ws(ws)
+    wptr, wbytes = ws.get(lib.lsrvt_los_workspace(dims, S))
+    sw = ctypes.c_int32(0)
+    code = lib.lsrvt_los_cvt(_ptr(comp), dims, _ptr(seeds), S, _ptr(weights), int(iters), _ptr(site_q),
+                             _ptr(anchor), _ptr(dist), _ptr(src), _ptr(phi), _ptr(cell), ctypes.byref(sw), wptr,
+                             wbytes, _stream(stream))
+    _check(code, "lsrvt_los_cvt")
+    return LosCVT(site_q[:S], anchor[:S], LosVT(dist, src, phi, cell, (int(sw.value),)))

@@ -1,0 +1,643 @@
+// Euclidean line-of-sight Voronoi tessellation and the geodesically weighted
+// site update (Sec. 3.1 with Eq. 1 and Eq. 2; Sec. 3.2.2 and Sec. 3.2.3).
+//
+// State per voxel v: the path length d[v] (float64), its source src[v] (a
+// voxel index, or LSRVT_LOS_SITE | s when v sees its site s directly) and,
+// after the relaxation, phi[v] (the line-of-sight voxel of the path) and
+// cell[v] (the site of phi[v]).  Sites are continuous points kept in fixed
+// point with 8 fraction bits plus an anchor voxel.
+//
+// The relaxation is synchronous: a sweep reads the state the previous sweep
+// left and writes proposals; an apply pass then installs the proposals.  A
+// sweep re-evaluates a voxel only if something it reads changed in the
+// previous sweep (itself, a face neighbour, its source, or the source of a
+// face neighbour): every other voxel would recompute exactly what it computed
+// before, so the sweep equals a full synchronous sweep.
+//
+// Rounding makes a path through a voxel on the straight line to the site as
+// long as the straight line, or an ulp shorter, so a voxel takes a new path
+// only when the shortest valid candidate is shorter by a relative 2^-40, and
+// then takes the preferred candidate within 2^-40 of that shortest one (the
+// site itself first, by id, else the lowest voxel index).
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+
+namespace lsrvt {
+namespace {
+
+constexpr uint32_t kSite = LSRVT_LOS_SITE;
+constexpr int kLosThreads = 256;
+constexpr int kSweepBatch = 8;
+constexpr int32_t kMaxSweeps = 100000;
+constexpr int kPhiRounds = 40;
+constexpr double kShorter = 1.0 - 0x1p-40;
+constexpr double kNear = 1.0 + 0x1p-40;
+
+struct LosArgs {
+  const uint32_t *comp;
+  Geom g;
+  const int32_t *site_q;  // [S][3] Q8
+  const uint32_t *anchor; // [S]
+  uint32_t n_sites;
+  double *d;              // [N] path lengths (the caller's output)
+  uint32_t *src;          // [N] sources (the caller's output)
+  double *pd;             // [N] proposed lengths
+  uint32_t *ps;           // [N] proposed sources
+  uint8_t *chg;           // [2][N] changed in the sweep before / this sweep
+  uint32_t *alive;        // [kSweepBatch] a voxel changed in sweep j of the batch
+  uint32_t *err;
+};
+
+__device__ __forceinline__ void xyz(int64_t v, const Geom &g, int32_t &x, int32_t &y, int32_t &z) {
+  int64_t row = v / g.nx;
+  x = (int32_t)(v - row * g.nx);
+  y = (int32_t)(row % g.ny);
+  z = (int32_t)(row / g.ny);
+}
+
+__device__ __forceinline__ double len_vox(int32_t ax, int32_t ay, int32_t az, int32_t bx, int32_t by, int32_t bz) {
+  int64_t dx = ax - bx, dy = ay - by, dz = az - bz;
+  return sqrt((double)(dx * dx + dy * dy + dz * dz));
+}
+
+__device__ __forceinline__ double len_site(int32_t x, int32_t y, int32_t z, const int32_t *q) {
+  int64_t dx = 256 * (int64_t)x - q[0], dy = 256 * (int64_t)y - q[1], dz = 256 * (int64_t)z - q[2];
+  return sqrt((double)(dx * dx + dy * dy + dz * dz)) / 256.0;
+}
+
+// True when every voxel whose closed cube meets the segment between the
+// centres of a and b belongs to component c.  Plane crossings of axis i
+// happen at t = (2k + 1) / (2 L_i); they are ordered by cross-multiplication
+// ((2k + 1) L_j < 2^31 under the extent limit), and at a crossing shared by
+// several axes every combination of their steps is touched.  The walk stays
+// in the bounding box of a and b, so every read is in bounds.
+__device__ bool ray_clear(const uint32_t *__restrict__ comp, const Geom &g, int32_t ax, int32_t ay, int32_t az,
+                          int32_t bx, int32_t by, int32_t bz, uint32_t c) {
+  const uint32_t L[3] = {(uint32_t)abs(bx - ax), (uint32_t)abs(by - ay), (uint32_t)abs(bz - az)};
+  const int64_t stp[3] = {bx > ax ? 1 : -1, (by > ay ? 1 : -1) * (int64_t)g.nx,
+                          (bz > az ? 1 : -1) * (int64_t)g.nx * g.ny};
+  uint32_t m[3] = {0, 0, 0};
+  int64_t cur = ax + (int64_t)g.nx * (ay + (int64_t)g.ny * az);
+  for (;;) {
+    int best = -1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (m[i] >= L[i]) continue;
+      if (best < 0 || (2 * m[i] + 1) * L[best] < (2 * m[best] + 1) * L[i]) best = i;
+    }
+    if (best < 0) return true;
+    uint32_t tied = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+      if (m[i] < L[i] && (2 * m[i] + 1) * L[best] == (2 * m[best] + 1) * L[i]) tied |= 1u << i;
+    for (uint32_t sub = tied; sub; sub = (sub - 1) & tied) {
+      int64_t q = cur;
+      if (sub & 1u) q += stp[0];
+      if (sub & 2u) q += stp[1];
+      if (sub & 4u) q += stp[2];
+      if (comp[q] != c) return false;
+    }
+    if (tied & 1u) { cur += stp[0]; m[0] += 1; }
+    if (tied & 2u) { cur += stp[1]; m[1] += 1; }
+    if (tied & 4u) { cur += stp[2]; m[2] += 1; }
+  }
+}
+
+__device__ __forceinline__ uint32_t pref(uint32_t code) { return code ^ kSite; }
+
+// ---------------------------------------------------------------- anchors
+__global__ void k_los_check(const uint32_t *__restrict__ comp, Geom g, const int32_t *__restrict__ q,
+                            const uint32_t *__restrict__ anchor, uint32_t S, uint32_t *err) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  uint32_t a = anchor[s];
+  if ((int64_t)a >= g.n || comp[a] == kNone) { err[0] = 1u; return; }
+  int32_t x, y, z;
+  xyz(a, g, x, y, z);
+  const int32_t *p = q + 3 * (size_t)s;
+  if (abs(256 * x - p[0]) > 128 || abs(256 * y - p[1]) > 128 || abs(256 * z - p[2]) > 128) err[0] = 1u;
+}
+
+// Each anchor holds the site with the smallest (length, id): the smallest
+// length by an atomic min on its bit pattern (non-negative doubles order as
+// their bits), then the smallest id among the sites that reach it.
+__global__ void k_anchor_reset(LosArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.n_sites) return;
+  uint32_t a = A.anchor[s];
+  reinterpret_cast<unsigned long long *>(A.pd)[a] = 0x7FF0000000000000ull;
+  A.ps[a] = kNone;
+}
+
+__global__ void k_anchor_len(LosArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.n_sites) return;
+  uint32_t a = A.anchor[s];
+  int32_t x, y, z;
+  xyz(a, A.g, x, y, z);
+  double d = len_site(x, y, z, A.site_q + 3 * (size_t)s);
+  atomicMin(reinterpret_cast<unsigned long long *>(A.pd) + a, (unsigned long long)__double_as_longlong(d));
+}
+
+__global__ void k_anchor_id(LosArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.n_sites) return;
+  uint32_t a = A.anchor[s];
+  int32_t x, y, z;
+  xyz(a, A.g, x, y, z);
+  double d = len_site(x, y, z, A.site_q + 3 * (size_t)s);
+  if (d == A.pd[a]) atomicMin(A.ps + a, s);
+}
+
+__global__ void k_anchor_set(LosArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.n_sites) return;
+  uint32_t a = A.anchor[s];
+  if (A.ps[a] != s) return;
+  A.d[a] = A.pd[a];
+  A.src[a] = kSite | s;
+  A.chg[a] = 1;  // plane 0 is the "changed before" plane of the first sweep
+}
+
+// ---------------------------------------------------------------- sweeps
+// One synchronous sweep of stage 1 (paths only through sites) or stage 2.
+// `cur` selects the plane of chg holding the previous sweep's changes.
+template <int Stage>
+__global__ void __launch_bounds__(kLosThreads) k_los_sweep(LosArgs A, int cur, int slot, int all_dirty) {
+  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+  const Geom g = A.g;
+  const uint8_t *__restrict__ before = A.chg + (size_t)cur * g.n;
+  uint8_t *__restrict__ now = A.chg + (size_t)(cur ^ 1) * g.n;
+  bool changed = false;
+  if (v < g.n) {
+    const uint32_t c = A.comp[v];
+    if (c != kNone) {
+      int32_t x, y, z;
+      xyz(v, g, x, y, z);
+      int64_t nb[6];
+      int k = 0;
+      if (x > 0) nb[k++] = v - 1;
+      if (x < g.nx - 1) nb[k++] = v + 1;
+      if (y > 0) nb[k++] = v - g.nx;
+      if (y < g.ny - 1) nb[k++] = v + g.nx;
+      if (z > 0) nb[k++] = v - (int64_t)g.nx * g.ny;
+      if (z < g.nz - 1) nb[k++] = v + (int64_t)g.nx * g.ny;
+      const uint32_t sv = A.src[v];
+      uint32_t sw[6];
+      bool dirty = all_dirty || before[v];
+      if (sv != kNone && !(sv & kSite)) dirty = dirty || before[sv];
+      for (int i = 0; i < k; ++i) {
+        const int64_t w = nb[i];
+        sw[i] = A.comp[w] == c ? A.src[w] : kNone;
+        dirty = dirty || before[w];
+        if (sw[i] != kNone && !(sw[i] & kSite)) dirty = dirty || before[sw[i]];
+      }
+      if (dirty) {
+        double cd[13];
+        uint32_t cc[13];
+        uint32_t ray[13];
+        int nc = 0;
+        if (Stage == 2 && sv != kNone && !(sv & kSite)) {
+          int32_t ux, uy, uz;
+          xyz(sv, g, ux, uy, uz);
+          cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[sv];
+          cc[nc] = sv;
+          ray[nc++] = kNone;
+        }
+        for (int i = 0; i < k; ++i) {
+          const uint32_t u = sw[i];
+          if (u == kNone) continue;
+          if (u & kSite) {
+            const uint32_t s = u & ~kSite;
+            cd[nc] = len_site(x, y, z, A.site_q + 3 * (size_t)s);
+            cc[nc] = u;
+            ray[nc++] = A.anchor[s];
+          } else if (Stage == 2 && (int64_t)u != v) {
+            int32_t ux, uy, uz;
+            xyz(u, g, ux, uy, uz);
+            cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[u];
+            cc[nc] = u;
+            ray[nc++] = u;
+          }
+          if (Stage == 2) {
+            cd[nc] = A.d[nb[i]] + 1.0;
+            cc[nc] = (uint32_t)nb[i];
+            ray[nc++] = kNone;
+          }
+        }
+        const double dh = A.d[v];
+        // validity: 0 unknown, 1 valid, 2 invalid (not shorter, or blocked)
+        uint8_t val[13];
+        for (int i = 0; i < nc; ++i) val[i] = cd[i] < dh ? 0 : 2;
+        // the shortest valid candidate, checking rays shortest first
+        double dmin = __builtin_inf();
+        for (;;) {
+          int bi = -1;
+          for (int i = 0; i < nc; ++i)
+            if (val[i] == 0 && (bi < 0 || cd[i] < cd[bi])) bi = i;
+          if (bi < 0) break;
+          bool ok = true;
+          if (ray[bi] != kNone) {
+            int32_t ux, uy, uz;
+            xyz(ray[bi], g, ux, uy, uz);
+            ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
+          }
+          val[bi] = ok ? 1 : 2;
+          if (ok) { dmin = cd[bi]; break; }
+        }
+        if (dmin < dh * kShorter) {
+          const double lim = dmin * kNear;
+          int sel = -1;
+          for (int i = 0; i < nc; ++i) {
+            if (val[i] == 2 || cd[i] > lim) continue;
+            if (val[i] == 0) {
+              bool ok = true;
+              if (ray[i] != kNone) {
+                int32_t ux, uy, uz;
+                xyz(ray[i], g, ux, uy, uz);
+                ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
+              }
+              val[i] = ok ? 1 : 2;
+              if (!ok) continue;
+            }
+            if (sel < 0 || pref(cc[i]) < pref(cc[sel]) || (cc[i] == cc[sel] && cd[i] < cd[sel])) sel = i;
+          }
+          A.pd[v] = cd[sel];
+          A.ps[v] = cc[sel];
+          changed = true;
+        }
+      }
+    }
+    now[v] = changed ? 1 : 0;
+  }
+  if (__ballot(changed) != 0ull && lane_id() == 0) A.alive[slot] = 1u;
+}
+
+__global__ void k_los_apply(LosArgs A, int plane) {
+  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+  if (v >= A.g.n) return;
+  if (A.chg[(size_t)plane * A.g.n + v]) {
+    A.d[v] = A.pd[v];
+    A.src[v] = A.ps[v];
+  }
+}
+
+// ---------------------------------------------------------------- phi, cells
+__global__ void k_phi_init(const uint32_t *__restrict__ src, int64_t n, uint32_t *__restrict__ phi) {
+  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t s = src[v];
+  phi[v] = s == kNone ? kNone : (s & kSite) ? (uint32_t)v : s;
+}
+
+// Pointer jumping towards the line-of-sight voxel of each path; any value
+// read (old or new) lies on the same path, so in-place updates are safe.
+__global__ void k_phi_jump(const uint32_t *__restrict__ src, int64_t n, uint32_t *phi, uint32_t *flag) {
+  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+  bool moved = false;
+  if (v < n) {
+    const uint32_t p = phi[v];
+    if (p != kNone && !(src[p] & kSite)) {
+      phi[v] = phi[p];
+      moved = true;
+    }
+  }
+  if (__ballot(moved) != 0ull && lane_id() == 0) flag[0] = 1u;
+}
+
+__global__ void k_phi_cell(const uint32_t *__restrict__ src, const uint32_t *__restrict__ phi, int64_t n,
+                           uint32_t *__restrict__ cell) {
+  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t p = phi[v];
+  cell[v] = p == kNone ? kNone : (src[p] & ~kSite);
+}
+
+// ---------------------------------------------------------------- update
+// M and S = sum m x_phi per site: lanes of a wave with the same cell are
+// summed by a segmented scan first (a wave covers consecutive voxels of a
+// row, mostly one or two cells), then the last lane of a run adds them.
+__global__ void __launch_bounds__(kLosThreads) k_los_accum(const uint32_t *__restrict__ cell,
+                                                           const uint32_t *__restrict__ phi,
+                                                           const uint16_t *__restrict__ w, Geom g, uint32_t S,
+                                                           unsigned long long *acc, uint32_t *err) {
+  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+  uint32_t s = kNone;
+  uint64_t m = 0, sx = 0, sy = 0, sz = 0;
+  if (v < g.n) {
+    s = cell[v];
+    if (s != kNone) {
+      if (s >= S) { err[0] = 1u; s = kNone; }
+      else {
+        m = w ? w[v] : 1u;
+        int32_t x, y, z;
+        xyz(phi[v], g, x, y, z);
+        sx = m * (uint64_t)x;
+        sy = m * (uint64_t)y;
+        sz = m * (uint64_t)z;
+      }
+    }
+  }
+  const int lane = lane_id();
+  // segmented inclusive scan; a run starts where the cell differs from the
+  // previous lane's, and a lane stops adding once its range holds a start
+  const uint32_t prev = __shfl_up(s, 1, kWave);
+  uint32_t head = (lane == 0 || prev != s) ? 1u : 0u;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t ho = __shfl_up(head, o, kWave);
+    const uint64_t mo = __shfl_up(m, o, kWave), xo = __shfl_up(sx, o, kWave);
+    const uint64_t yo = __shfl_up(sy, o, kWave), zo = __shfl_up(sz, o, kWave);
+    if (lane >= o && !head) { m += mo; sx += xo; sy += yo; sz += zo; head = ho; }
+  }
+  const uint32_t next = __shfl_down(s, 1, kWave);
+  const bool last = lane == kWave - 1 || next != s;
+  if (s != kNone && last && m != 0) {
+    unsigned long long *a = acc + 4 * (size_t)s;
+    atomicAdd(a + 0, (unsigned long long)m);
+    atomicAdd(a + 1, (unsigned long long)sx);
+    atomicAdd(a + 2, (unsigned long long)sy);
+    atomicAdd(a + 3, (unsigned long long)sz);
+  }
+}
+
+// Target X_c = round-half-up(256 S / M) per axis, then the walk from the
+// anchor towards it, stopping where the segment first touches the closed
+// cube of a voxel outside the component among the cubes it can move into.
+__global__ void k_los_move(const uint32_t *__restrict__ comp, Geom g, uint32_t S,
+                           const unsigned long long *__restrict__ acc, int32_t *q, uint32_t *anchor,
+                           int32_t *target) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint64_t M = acc[4 * (size_t)s];
+  int32_t *X = q + 3 * (size_t)s;
+  if (M == 0) {
+    if (target) target[3 * (size_t)s] = target[3 * (size_t)s + 1] = target[3 * (size_t)s + 2] = INT32_MIN;
+    return;
+  }
+  int64_t T[3];
+  for (int i = 0; i < 3; ++i) {
+    const uint64_t Si = acc[4 * (size_t)s + 1 + i];
+    const uint64_t qq = Si / M, r = Si % M;
+    T[i] = (int64_t)(256 * qq + (512 * r + M) / (2 * M));
+    if (target) target[3 * (size_t)s + i] = (int32_t)T[i];
+  }
+  const uint32_t a0 = anchor[s];
+  const uint32_t c = comp[a0];
+  int32_t cv[3];
+  xyz(a0, g, cv[0], cv[1], cv[2]);
+  const int32_t ext[3] = {g.nx, g.ny, g.nz};
+  int64_t D[3], num[3], den[3];
+  int32_t step[3];
+  bool moving = false;
+  for (int i = 0; i < 3; ++i) {
+    D[i] = T[i] - X[i];
+    step[i] = D[i] > 0 ? 1 : -1;
+    den[i] = D[i] < 0 ? -D[i] : D[i];
+    num[i] = (256 * (int64_t)cv[i] + 128 * step[i] - X[i]) * step[i];
+    moving = moving || D[i] != 0;
+  }
+  if (!moving) return;
+  for (;;) {
+    int best = -1;
+    for (int i = 0; i < 3; ++i) {
+      if (den[i] == 0 || num[i] >= den[i]) continue;
+      if (best < 0 || num[i] * den[best] < num[best] * den[i]) best = i;
+    }
+    if (best < 0) break;
+    uint32_t tied = 0;
+    for (int i = 0; i < 3; ++i)
+      if (den[i] != 0 && num[i] < den[i] && num[i] * den[best] == num[best] * den[i]) tied |= 1u << i;
+    bool blocked = false;
+    for (uint32_t sub = tied; sub && !blocked; sub = (sub - 1) & tied) {
+      int32_t p[3] = {cv[0], cv[1], cv[2]};
+      for (int i = 0; i < 3; ++i)
+        if (sub & (1u << i)) p[i] += step[i];
+      if (p[0] < 0 || p[1] < 0 || p[2] < 0 || p[0] >= ext[0] || p[1] >= ext[1] || p[2] >= ext[2])
+        blocked = true;
+      else if (comp[p[0] + (int64_t)g.nx * (p[1] + (int64_t)g.ny * p[2])] != c)
+        blocked = true;
+    }
+    if (blocked) {
+      const int64_t tn = num[best], td = den[best];
+      for (int i = 0; i < 3; ++i) X[i] = (int32_t)(X[i] + (tn * D[i]) / td);
+      anchor[s] = (uint32_t)(cv[0] + (int64_t)g.nx * (cv[1] + (int64_t)g.ny * cv[2]));
+      return;
+    }
+    for (int i = 0; i < 3; ++i)
+      if (tied & (1u << i)) { cv[i] += step[i]; num[i] += 256; }
+  }
+  for (int i = 0; i < 3; ++i) X[i] = (int32_t)T[i];
+  anchor[s] = (uint32_t)(cv[0] + (int64_t)g.nx * (cv[1] + (int64_t)g.ny * cv[2]));
+}
+
+__global__ void k_los_seed(const uint32_t *__restrict__ comp, Geom g, const uint32_t *__restrict__ seeds,
+                           uint32_t S, int32_t *q, uint32_t *anchor, uint32_t *err) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t v = seeds[s];
+  if ((int64_t)v >= g.n || comp[v] == kNone) { err[0] = 1u; return; }
+  int32_t x, y, z;
+  xyz(v, g, x, y, z);
+  q[3 * (size_t)s + 0] = 256 * x;
+  q[3 * (size_t)s + 1] = 256 * y;
+  q[3 * (size_t)s + 2] = 256 * z;
+  anchor[s] = v;
+}
+
+// ---------------------------------------------------------------- host side
+struct LosWork {
+  double *pd;
+  uint32_t *ps;
+  uint8_t *chg;
+  uint32_t *ctl;  // [0] err, [1] phi flag, [2..2+kSweepBatch) alive
+  unsigned long long *acc;
+};
+
+template <class C>
+void los_layout(C &cv, const Geom &g, uint32_t S, LosWork *W) {
+  double *pd = cv.template take<double>((size_t)g.n);
+  uint32_t *ps = cv.template take<uint32_t>((size_t)g.n);
+  uint8_t *chg = cv.template take<uint8_t>(2 * (size_t)g.n);
+  uint32_t *ctl = cv.template take<uint32_t>(64);
+  unsigned long long *acc = cv.template take<unsigned long long>(4 * (size_t)(S ? S : 1));
+  if (W) *W = LosWork{pd, ps, chg, ctl, acc};
+}
+
+int32_t read_err(const uint32_t *d_err, hipStream_t s) {
+  uint32_t e = 0;
+  LSRVT_HIP(hipMemcpyAsync(&e, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  LSRVT_HIP(hipStreamSynchronize(s));
+  return e ? LSRVT_EINVAL : LSRVT_OK;
+}
+
+int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const uint32_t *d_anchor, uint32_t S,
+               double *d_dist, uint32_t *d_src, uint32_t *d_phi, uint32_t *d_cell, int32_t *sweeps,
+               const LosWork &W, hipStream_t s) {
+  int32_t rc;
+  const unsigned gs = grid_for(S, 256, 1 << 20);
+  const unsigned gv = (unsigned)((g.n + kLosThreads - 1) / kLosThreads);
+  LosArgs A{d_comp, g, d_q, d_anchor, S, d_dist, d_src, W.pd, W.ps, W.chg, W.ctl + 2, W.ctl};
+  if ((rc = fill<uint32_t>(W.ctl, 2, 0u, s))) return rc;
+  if (S) {
+    hipLaunchKernelGGL(k_los_check, dim3(gs), dim3(256), 0, s, d_comp, g, d_q, d_anchor, S, W.ctl);
+    LSRVT_LAUNCHED();
+    if ((rc = read_err(W.ctl, s))) return rc;
+  }
+  if ((rc = fill<double>(d_dist, g.n, __builtin_inf(), s))) return rc;
+  if ((rc = fill<uint32_t>(d_src, g.n, kNone, s))) return rc;
+  if ((rc = fill<uint8_t>(W.chg, 2 * g.n, 0, s))) return rc;
+  if (S) {
+    hipLaunchKernelGGL(k_anchor_reset, dim3(gs), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_anchor_len, dim3(gs), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_anchor_id, dim3(gs), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_anchor_set, dim3(gs), dim3(256), 0, s, A);
+    LSRVT_LAUNCHED();
+  }
+  int cur = 0;  // plane of chg that holds the previous sweep's changes
+  for (int stage = 1; stage <= 2; ++stage) {
+    int32_t done = 0;
+    bool first = true;
+    for (;;) {
+      if (done >= kMaxSweeps) return LSRVT_ELIMIT;
+      if ((rc = fill<uint32_t>(W.ctl + 2, kSweepBatch, 0u, s))) return rc;
+      for (int j = 0; j < kSweepBatch; ++j) {
+        if (stage == 1)
+          hipLaunchKernelGGL(k_los_sweep<1>, dim3(gv), dim3(kLosThreads), 0, s, A, cur, j, first ? 1 : 0);
+        else
+          hipLaunchKernelGGL(k_los_sweep<2>, dim3(gv), dim3(kLosThreads), 0, s, A, cur, j, first ? 1 : 0);
+        hipLaunchKernelGGL(k_los_apply, dim3(gv), dim3(kLosThreads), 0, s, A, cur ^ 1);
+        cur ^= 1;
+        first = false;
+      }
+      LSRVT_LAUNCHED();
+      uint32_t alive[kSweepBatch];
+      LSRVT_HIP(hipMemcpyAsync(alive, W.ctl + 2, sizeof(alive), hipMemcpyDeviceToHost, s));
+      LSRVT_HIP(hipStreamSynchronize(s));
+      int j = 0;
+      while (j < kSweepBatch && alive[j]) ++j;
+      if (j < kSweepBatch) {  // sweep j changed nothing: the stage has converged
+        done += j + 1;
+        break;
+      }
+      done += kSweepBatch;
+    }
+    if (sweeps) sweeps[stage - 1] = done;
+  }
+  hipLaunchKernelGGL(k_phi_init, dim3(gv), dim3(kLosThreads), 0, s, d_src, g.n, d_phi);
+  LSRVT_LAUNCHED();
+  for (int r = 0;; r += 4) {
+    if (r >= kPhiRounds) return LSRVT_ELIMIT;
+    if ((rc = fill<uint32_t>(W.ctl + 1, 1, 0u, s))) return rc;
+    for (int j = 0; j < 4; ++j)
+      hipLaunchKernelGGL(k_phi_jump, dim3(gv), dim3(kLosThreads), 0, s, d_src, g.n, d_phi, W.ctl + 1);
+    LSRVT_LAUNCHED();
+    uint32_t f = 0;
+    LSRVT_HIP(hipMemcpyAsync(&f, W.ctl + 1, sizeof(f), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    if (!f) break;
+  }
+  hipLaunchKernelGGL(k_phi_cell, dim3(gv), dim3(kLosThreads), 0, s, d_src, d_phi, g.n, d_cell);
+  LSRVT_LAUNCHED();
+  return LSRVT_OK;
+}
+
+int32_t los_update(const uint32_t *d_comp, const Geom &g, const uint16_t *d_w, const uint32_t *d_cell,
+                   const uint32_t *d_phi, uint32_t S, int32_t *d_q, uint32_t *d_anchor, int32_t *d_target,
+                   const LosWork &W, hipStream_t s) {
+  int32_t rc;
+  if (S == 0) return LSRVT_OK;
+  const unsigned gv = (unsigned)((g.n + kLosThreads - 1) / kLosThreads);
+  if ((rc = fill<uint32_t>(W.ctl, 1, 0u, s))) return rc;
+  if ((rc = fill<unsigned long long>(W.acc, 4 * (int64_t)S, 0ull, s))) return rc;
+  hipLaunchKernelGGL(k_los_accum, dim3(gv), dim3(kLosThreads), 0, s, d_cell, d_phi, d_w, g, S, W.acc, W.ctl);
+  hipLaunchKernelGGL(k_los_move, dim3(grid_for(S, 256, 1 << 20)), dim3(256), 0, s, d_comp, g, S, W.acc, d_q,
+                     d_anchor, d_target);
+  LSRVT_LAUNCHED();
+  return read_err(W.ctl, s);
+}
+
+}  // namespace
+}  // namespace lsrvt
+
+using namespace lsrvt;
+
+extern "C" size_t lsrvt_los_workspace(lsrvt_dims dims, uint32_t n_sites) {
+  Geom g;
+  if (make_geom(dims, g) != LSRVT_OK || n_sites >= kSite) return 0;
+  Sizer sz;
+  los_layout(sz, g, n_sites, nullptr);
+  return sz.off;
+}
+
+static int32_t los_prepare(lsrvt_dims dims, uint32_t S, void *d_work, size_t work_bytes, Geom &g, LosWork &W) {
+  int32_t rc = make_geom(dims, g);
+  if (rc) return rc;
+  if (S >= kSite) return LSRVT_ELIMIT;
+  if ((rc = check_work(d_work, work_bytes, lsrvt_los_workspace(dims, S)))) return rc;
+  Carve cv(d_work, work_bytes);
+  los_layout(cv, g, S, &W);
+  return cv.ok ? LSRVT_OK : LSRVT_EWORKSPACE;
+}
+
+extern "C" int32_t lsrvt_los_vt(const uint32_t *d_comp, lsrvt_dims dims, const int32_t *d_site_q,
+                                const uint32_t *d_anchor, uint32_t n_sites, double *d_dist, uint32_t *d_src,
+                                uint32_t *d_phi, uint32_t *d_cell, int32_t *h_sweeps, void *d_work,
+                                size_t work_bytes, void *stream) {
+  if (!d_comp || !d_dist || !d_src || !d_phi || !d_cell || (n_sites && (!d_site_q || !d_anchor)))
+    return LSRVT_EINVAL;
+  Geom g;
+  LosWork W;
+  int32_t rc = los_prepare(dims, n_sites, d_work, work_bytes, g, W);
+  if (rc) return rc;
+  return los_vt(d_comp, g, d_site_q, d_anchor, n_sites, d_dist, d_src, d_phi, d_cell, h_sweeps, W,
+                as_stream(stream));
+}
+
+extern "C" int32_t lsrvt_los_update(const uint32_t *d_comp, lsrvt_dims dims, const uint16_t *d_weights,
+                                    const uint32_t *d_cell, const uint32_t *d_phi, uint32_t n_sites,
+                                    int32_t *d_site_q, uint32_t *d_anchor, int32_t *d_target_q, void *d_work,
+                                    size_t work_bytes, void *stream) {
+  if (!d_comp || !d_cell || !d_phi || (n_sites && (!d_site_q || !d_anchor))) return LSRVT_EINVAL;
+  Geom g;
+  LosWork W;
+  int32_t rc = los_prepare(dims, n_sites, d_work, work_bytes, g, W);
+  if (rc) return rc;
+  return los_update(d_comp, g, d_weights, d_cell, d_phi, n_sites, d_site_q, d_anchor, d_target_q, W,
+                    as_stream(stream));
+}
+
+extern "C" int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d_seeds,
+                                 uint32_t n_sites, const uint16_t *d_weights, int32_t iters, int32_t *d_site_q,
+                                 uint32_t *d_anchor, double *d_dist, uint32_t *d_src, uint32_t *d_phi,
+                                 uint32_t *d_cell, int32_t *h_sweeps, void *d_work, size_t work_bytes,
+                                 void *stream) {
+  if (!d_comp || !d_dist || !d_src || !d_phi || !d_cell || iters < 0 ||
+      (n_sites && (!d_seeds || !d_site_q || !d_anchor)))
+    return LSRVT_EINVAL;
+  Geom g;
+  LosWork W;
+  int32_t rc = los_prepare(dims, n_sites, d_work, work_bytes, g, W);
+  if (rc) return rc;
+  hipStream_t s = as_stream(stream);
+  if (h_sweeps) *h_sweeps = 0;
+  if (n_sites) {
+    if ((rc = fill<uint32_t>(W.ctl, 1, 0u, s))) return rc;
+    hipLaunchKernelGGL(k_los_seed, dim3(grid_for(n_sites, 256, 1 << 20)), dim3(256), 0, s, d_comp, g, d_seeds,
+                       n_sites, d_site_q, d_anchor, W.ctl);
+    LSRVT_LAUNCHED();
+    if ((rc = read_err(W.ctl, s))) return rc;
+  }
+  for (int32_t t = 0; t <= iters; ++t) {
+    int32_t sw[2] = {0, 0};
+    rc = los_vt(d_comp, g, d_site_q, d_anchor, n_sites, d_dist, d_src, d_phi, d_cell, sw, W, s);
+    if (rc) return rc;
+    if (h_sweeps) *h_sweeps += sw[0] + sw[1];
+    if (t == iters) break;
+    rc = los_update(d_comp, g, d_weights, d_cell, d_phi, n_sites, d_site_q, d_anchor, nullptr, W, s);
+    if (rc) return rc;
+  }
+  return LSRVT_OK;
+}

@@ -99,3 +99,24 @@ def test_comoments_host_validation_without_gpu(lib):
     assert call(9, mo, mo, mo) == L.EINVAL
     assert call(4, mo, bad, mo) == L.EINVAL
     assert call(4, mo, mo, mo) == L.EWORKSPACE
+
+
+def test_los_host_validation_without_gpu(lib):
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(4096)
+    d = L.Dims(32, 32, 32)
+    assert lib.lsrvt_los_workspace(d, 100) > 32 ** 3 * 14
+    assert lib.lsrvt_los_workspace(d, 1 << 31) == 0            # site ids must leave the LOS flag bit free
+    assert lib.lsrvt_los_workspace(L.Dims(0, 1, 1), 10) == 0
+    sw = (ctypes.c_int32 * 2)()
+    vt = lambda q, out, S=10, wb=16: lib.lsrvt_los_vt(fake, d, q, fake, S, out, fake, fake, fake, sw, fake, wb, nul)
+    assert vt(fake, nul) == L.EINVAL                             # no distance output
+    assert vt(nul, fake) == L.EINVAL                             # sites without positions
+    assert vt(fake, fake, S=1 << 31) == L.ELIMIT
+    assert vt(fake, fake) == L.EWORKSPACE
+    assert lib.lsrvt_los_update(fake, d, nul, fake, nul, 10, fake, fake, nul, fake, 16, nul) == L.EINVAL
+    assert lib.lsrvt_los_update(fake, d, nul, fake, fake, 10, fake, fake, nul, fake, 16, nul) == L.EWORKSPACE
+    cvt = lambda iters, wb=16: lib.lsrvt_los_cvt(fake, d, fake, 10, nul, iters, fake, fake, fake, fake, fake, fake,
+                                                 nul, fake, wb, nul)
+    assert cvt(-1) == L.EINVAL
+    assert cvt(2) == L.EWORKSPACE
