@@ -45,16 +45,22 @@ struct LosArgs {
   uint32_t *src;          // [N] sources (the caller's output)
   double *pd;             // [N] proposed lengths
   uint32_t *ps;           // [N] proposed sources
-  uint8_t *chg;           // [2][N] changed in the sweep before / this sweep
+  uint8_t *chg;           // [N] changed in this sweep
+  uint8_t *flag;          // [N] v or its source changed in the sweep before
+  uint32_t *list;         // [N] voxels to evaluate in this sweep
+  uint32_t *count;        // length of list
   uint32_t *alive;        // [kSweepBatch] a voxel changed in sweep j of the batch
   uint32_t *err;
 };
 
+// Coordinates of voxel v (v < 2^31, so 32-bit division is exact).
 __device__ __forceinline__ void xyz(int64_t v, const Geom &g, int32_t &x, int32_t &y, int32_t &z) {
-  int64_t row = v / g.nx;
-  x = (int32_t)(v - row * g.nx);
-  y = (int32_t)(row % g.ny);
-  z = (int32_t)(row / g.ny);
+  const uint32_t u = (uint32_t)v, nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+  const uint32_t row = u / nx;
+  const uint32_t zz = row / ny;
+  x = (int32_t)(u - row * nx);
+  y = (int32_t)(row - zz * ny);
+  z = (int32_t)zz;
 }
 
 __device__ __forceinline__ double len_vox(int32_t ax, int32_t ay, int32_t az, int32_t bx, int32_t by, int32_t bz) {
@@ -158,129 +164,185 @@ __global__ void k_anchor_set(LosArgs A) {
   if (A.ps[a] != s) return;
   A.d[a] = A.pd[a];
   A.src[a] = kSite | s;
-  A.chg[a] = 1;  // plane 0 is the "changed before" plane of the first sweep
+  A.flag[a] = 1;  // the anchors' neighbourhoods are evaluated in the first sweep
 }
 
 // ---------------------------------------------------------------- sweeps
-// One synchronous sweep of stage 1 (paths only through sites) or stage 2.
-// `cur` selects the plane of chg holding the previous sweep's changes.
-template <int Stage>
-__global__ void __launch_bounds__(kLosThreads) k_los_sweep(LosArgs A, int cur, int slot, int all_dirty) {
-  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
+// A sweep is three launches.  mark: every component voxel whose flag or a
+// face neighbour's flag is set (or every one, in the first sweep of a stage)
+// is listed, and the change plane is cleared.  eval: each listed voxel
+// evaluates its candidates against the state of the previous sweep and
+// writes a proposal if it changes.  apply: proposals are installed and flag
+// is set for each voxel that changed or whose source changed.  A voxel left
+// out reads nothing that changed since it was last evaluated, so it would
+// compute the same result: the sweep equals a full synchronous sweep.
+constexpr int kMarkPer = 16;  // voxels per thread in mark and apply
+
+__global__ void __launch_bounds__(kLosThreads) k_los_mark(LosArgs A, int all_dirty) {
+  __shared__ uint32_t part[kLosThreads];
+  __shared__ uint32_t base;
   const Geom g = A.g;
-  const uint8_t *__restrict__ before = A.chg + (size_t)cur * g.n;
-  uint8_t *__restrict__ now = A.chg + (size_t)(cur ^ 1) * g.n;
-  bool changed = false;
-  if (v < g.n) {
-    const uint32_t c = A.comp[v];
-    if (c != kNone) {
-      int32_t x, y, z;
-      xyz(v, g, x, y, z);
-      int64_t nb[6];
-      int k = 0;
-      if (x > 0) nb[k++] = v - 1;
-      if (x < g.nx - 1) nb[k++] = v + 1;
-      if (y > 0) nb[k++] = v - g.nx;
-      if (y < g.ny - 1) nb[k++] = v + g.nx;
-      if (z > 0) nb[k++] = v - (int64_t)g.nx * g.ny;
-      if (z < g.nz - 1) nb[k++] = v + (int64_t)g.nx * g.ny;
-      const uint32_t sv = A.src[v];
-      uint32_t sw[6];
-      bool dirty = all_dirty || before[v];
-      if (sv != kNone && !(sv & kSite)) dirty = dirty || before[sv];
-      for (int i = 0; i < k; ++i) {
-        const int64_t w = nb[i];
-        sw[i] = A.comp[w] == c ? A.src[w] : kNone;
-        dirty = dirty || before[w];
-        if (sw[i] != kNone && !(sw[i] & kSite)) dirty = dirty || before[sw[i]];
-      }
-      if (dirty) {
-        double cd[13];
-        uint32_t cc[13];
-        uint32_t ray[13];
-        int nc = 0;
-        if (Stage == 2 && sv != kNone && !(sv & kSite)) {
-          int32_t ux, uy, uz;
-          xyz(sv, g, ux, uy, uz);
-          cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[sv];
-          cc[nc] = sv;
-          ray[nc++] = kNone;
-        }
-        for (int i = 0; i < k; ++i) {
-          const uint32_t u = sw[i];
-          if (u == kNone) continue;
-          if (u & kSite) {
-            const uint32_t s = u & ~kSite;
-            cd[nc] = len_site(x, y, z, A.site_q + 3 * (size_t)s);
-            cc[nc] = u;
-            ray[nc++] = A.anchor[s];
-          } else if (Stage == 2 && (int64_t)u != v) {
-            int32_t ux, uy, uz;
-            xyz(u, g, ux, uy, uz);
-            cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[u];
-            cc[nc] = u;
-            ray[nc++] = u;
-          }
-          if (Stage == 2) {
-            cd[nc] = A.d[nb[i]] + 1.0;
-            cc[nc] = (uint32_t)nb[i];
-            ray[nc++] = kNone;
-          }
-        }
-        const double dh = A.d[v];
-        // validity: 0 unknown, 1 valid, 2 invalid (not shorter, or blocked)
-        uint8_t val[13];
-        for (int i = 0; i < nc; ++i) val[i] = cd[i] < dh ? 0 : 2;
-        // the shortest valid candidate, checking rays shortest first
-        double dmin = __builtin_inf();
-        for (;;) {
-          int bi = -1;
-          for (int i = 0; i < nc; ++i)
-            if (val[i] == 0 && (bi < 0 || cd[i] < cd[bi])) bi = i;
-          if (bi < 0) break;
-          bool ok = true;
-          if (ray[bi] != kNone) {
-            int32_t ux, uy, uz;
-            xyz(ray[bi], g, ux, uy, uz);
-            ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
-          }
-          val[bi] = ok ? 1 : 2;
-          if (ok) { dmin = cd[bi]; break; }
-        }
-        if (dmin < dh * kShorter) {
-          const double lim = dmin * kNear;
-          int sel = -1;
-          for (int i = 0; i < nc; ++i) {
-            if (val[i] == 2 || cd[i] > lim) continue;
-            if (val[i] == 0) {
-              bool ok = true;
-              if (ray[i] != kNone) {
-                int32_t ux, uy, uz;
-                xyz(ray[i], g, ux, uy, uz);
-                ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
-              }
-              val[i] = ok ? 1 : 2;
-              if (!ok) continue;
-            }
-            if (sel < 0 || pref(cc[i]) < pref(cc[sel]) || (cc[i] == cc[sel] && cd[i] < cd[sel])) sel = i;
-          }
-          A.pd[v] = cd[sel];
-          A.ps[v] = cc[sel];
-          changed = true;
-        }
-      }
-    }
-    now[v] = changed ? 1 : 0;
+  const int64_t chunk = (int64_t)blockIdx.x * kLosThreads * kMarkPer;
+  uint32_t bits = 0, cnt = 0;
+#pragma unroll 4
+  for (int j = 0; j < kMarkPer; ++j) {
+    const int64_t v = chunk + (int64_t)j * kLosThreads + threadIdx.x;
+    if (v >= g.n) break;
+    A.chg[v] = 0;
+    if (A.comp[v] == kNone) continue;
+    int32_t x, y, z;
+    xyz(v, g, x, y, z);
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny;
+    // every load is issued (clamped to v at the volume's faces), then combined
+    const uint32_t f = (uint32_t)A.flag[v] | A.flag[x > 0 ? v - 1 : v] | A.flag[x < g.nx - 1 ? v + 1 : v] |
+                       A.flag[y > 0 ? v - sy : v] | A.flag[y < g.ny - 1 ? v + sy : v] |
+                       A.flag[z > 0 ? v - sz : v] | A.flag[z < g.nz - 1 ? v + sz : v];
+    const bool dirty = all_dirty || f != 0;
+    if (dirty) { bits |= 1u << j; ++cnt; }
   }
+  // block-wide exclusive scan of the per-thread counts, one atomic per block
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = 1; o < kLosThreads; o <<= 1) {
+    const uint32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += t;
+    __syncthreads();
+  }
+  if (threadIdx.x == kLosThreads - 1) base = part[kLosThreads - 1] ? atomicAdd(A.count, part[kLosThreads - 1]) : 0u;
+  __syncthreads();
+  uint32_t at = base + part[threadIdx.x] - cnt;
+  for (int j = 0; j < kMarkPer && bits; ++j)
+    if (bits & (1u << j)) {
+      A.list[at++] = (uint32_t)(chunk + (int64_t)j * kLosThreads + threadIdx.x);
+      bits &= ~(1u << j);
+    }
+}
+
+template <int Stage>
+__device__ __forceinline__ bool los_eval(const LosArgs &A, int64_t v) {
+  const Geom g = A.g;
+  const uint32_t c = A.comp[v];
+  int32_t x, y, z;
+  xyz(v, g, x, y, z);
+  int64_t nb[6];
+  int k = 0;
+  if (x > 0) nb[k++] = v - 1;
+  if (x < g.nx - 1) nb[k++] = v + 1;
+  if (y > 0) nb[k++] = v - g.nx;
+  if (y < g.ny - 1) nb[k++] = v + g.nx;
+  if (z > 0) nb[k++] = v - (int64_t)g.nx * g.ny;
+  if (z < g.nz - 1) nb[k++] = v + (int64_t)g.nx * g.ny;
+  const uint32_t sv = A.src[v];
+  double cd[13];
+  uint32_t cc[13];
+  uint32_t ray[13];
+  int nc = 0;
+  if (Stage == 2 && sv != kNone && !(sv & kSite)) {
+    int32_t ux, uy, uz;
+    xyz(sv, g, ux, uy, uz);
+    cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[sv];
+    cc[nc] = sv;
+    ray[nc++] = kNone;
+  }
+  for (int i = 0; i < k; ++i) {
+    const int64_t w = nb[i];
+    if (A.comp[w] != c) continue;
+    const uint32_t u = A.src[w];
+    if (u == kNone) continue;
+    if (u & kSite) {
+      const uint32_t s = u & ~kSite;
+      cd[nc] = len_site(x, y, z, A.site_q + 3 * (size_t)s);
+      cc[nc] = u;
+      ray[nc++] = A.anchor[s];
+    } else if (Stage == 2 && (int64_t)u != v) {
+      int32_t ux, uy, uz;
+      xyz(u, g, ux, uy, uz);
+      cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[u];
+      cc[nc] = u;
+      ray[nc++] = u;
+    }
+    if (Stage == 2) {
+      cd[nc] = A.d[w] + 1.0;
+      cc[nc] = (uint32_t)w;
+      ray[nc++] = kNone;
+    }
+  }
+  const double dh = A.d[v];
+  // validity: 0 unknown, 1 valid, 2 invalid (not shorter, or blocked)
+  uint8_t val[13];
+  for (int i = 0; i < nc; ++i) val[i] = cd[i] < dh ? 0 : 2;
+  // the shortest valid candidate, checking rays shortest first
+  double dmin = __builtin_inf();
+  for (;;) {
+    int bi = -1;
+    for (int i = 0; i < nc; ++i)
+      if (val[i] == 0 && (bi < 0 || cd[i] < cd[bi])) bi = i;
+    if (bi < 0) break;
+    bool ok = true;
+    if (ray[bi] != kNone) {
+      int32_t ux, uy, uz;
+      xyz(ray[bi], g, ux, uy, uz);
+      ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
+      // the same segment decides every candidate aimed at the same voxel
+      for (int i = 0; i < nc; ++i)
+        if (val[i] == 0 && ray[i] == ray[bi]) val[i] = ok ? 1 : 2;
+    }
+    val[bi] = ok ? 1 : 2;
+    if (ok) { dmin = cd[bi]; break; }
+  }
+  if (!(dmin < dh * kShorter)) return false;
+  const double lim = dmin * kNear;
+  int sel = -1;
+  for (int i = 0; i < nc; ++i) {
+    if (val[i] == 2 || cd[i] > lim) continue;
+    if (val[i] == 0) {
+      bool ok = true;
+      if (ray[i] != kNone) {
+        int32_t ux, uy, uz;
+        xyz(ray[i], g, ux, uy, uz);
+        ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
+      }
+      for (int j = i; j < nc; ++j)
+        if (val[j] == 0 && ray[j] == ray[i]) val[j] = ok ? 1 : 2;
+      val[i] = ok ? 1 : 2;
+      if (!ok) continue;
+    }
+    if (sel < 0 || pref(cc[i]) < pref(cc[sel]) || (cc[i] == cc[sel] && cd[i] < cd[sel])) sel = i;
+  }
+  A.pd[v] = cd[sel];
+  A.ps[v] = cc[sel];
+  A.chg[v] = 1;
+  return true;
+}
+
+// One synchronous sweep of stage 1 (paths only through sites) or stage 2
+// over the listed voxels; slot names the sweep in the batch.
+template <int Stage>
+__global__ void __launch_bounds__(kLosThreads) k_los_eval(LosArgs A, int slot) {
+  const uint32_t n = *A.count;
+  bool changed = false;
+  for (uint32_t i = blockIdx.x * kLosThreads + threadIdx.x; i < n; i += gridDim.x * kLosThreads)
+    changed = los_eval<Stage>(A, A.list[i]) || changed;
   if (__ballot(changed) != 0ull && lane_id() == 0) A.alive[slot] = 1u;
 }
 
-__global__ void k_los_apply(LosArgs A, int plane) {
-  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
-  if (v >= A.g.n) return;
-  if (A.chg[(size_t)plane * A.g.n + v]) {
-    A.d[v] = A.pd[v];
-    A.src[v] = A.ps[v];
+__global__ void __launch_bounds__(kLosThreads) k_los_apply(LosArgs A) {
+  const Geom g = A.g;
+  const int64_t chunk = (int64_t)blockIdx.x * kLosThreads * kMarkPer;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *A.count = 0u;  // eval of this sweep has finished
+#pragma unroll 4
+  for (int j = 0; j < kMarkPer; ++j) {
+    const int64_t v = chunk + (int64_t)j * kLosThreads + threadIdx.x;
+    if (v >= g.n) break;
+    uint32_t s = A.src[v];
+    const uint8_t ch = A.chg[v];
+    if (ch) {
+      A.d[v] = A.pd[v];
+      s = A.ps[v];
+      A.src[v] = s;
+    }
+    A.flag[v] = (ch || (s != kNone && !(s & kSite) && A.chg[s])) ? 1 : 0;
   }
 }
 
@@ -452,7 +514,9 @@ struct LosWork {
   double *pd;
   uint32_t *ps;
   uint8_t *chg;
-  uint32_t *ctl;  // [0] err, [1] phi flag, [2..2+kSweepBatch) alive
+  uint8_t *flag;
+  uint32_t *list;
+  uint32_t *ctl;  // [0] err, [1] phi flag, [2..2+kSweepBatch) alive, [2+kSweepBatch] list length
   unsigned long long *acc;
 };
 
@@ -460,10 +524,12 @@ template <class C>
 void los_layout(C &cv, const Geom &g, uint32_t S, LosWork *W) {
   double *pd = cv.template take<double>((size_t)g.n);
   uint32_t *ps = cv.template take<uint32_t>((size_t)g.n);
-  uint8_t *chg = cv.template take<uint8_t>(2 * (size_t)g.n);
+  uint8_t *chg = cv.template take<uint8_t>((size_t)g.n);
+  uint8_t *flag = cv.template take<uint8_t>((size_t)g.n);
+  uint32_t *list = cv.template take<uint32_t>((size_t)g.n);
   uint32_t *ctl = cv.template take<uint32_t>(64);
   unsigned long long *acc = cv.template take<unsigned long long>(4 * (size_t)(S ? S : 1));
-  if (W) *W = LosWork{pd, ps, chg, ctl, acc};
+  if (W) *W = LosWork{pd, ps, chg, flag, list, ctl, acc};
 }
 
 int32_t read_err(const uint32_t *d_err, hipStream_t s) {
@@ -479,7 +545,10 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
   int32_t rc;
   const unsigned gs = grid_for(S, 256, 1 << 20);
   const unsigned gv = (unsigned)((g.n + kLosThreads - 1) / kLosThreads);
-  LosArgs A{d_comp, g, d_q, d_anchor, S, d_dist, d_src, W.pd, W.ps, W.chg, W.ctl + 2, W.ctl};
+  LosArgs A{d_comp, g,    d_q,     d_anchor, S, d_dist, d_src, W.pd, W.ps, W.chg, W.flag, W.list,
+            W.ctl + 2 + kSweepBatch, W.ctl + 2, W.ctl};
+  const unsigned gm = (unsigned)((g.n + (int64_t)kLosThreads * kMarkPer - 1) / ((int64_t)kLosThreads * kMarkPer));
+  const unsigned ge = 2048;
   if ((rc = fill<uint32_t>(W.ctl, 2, 0u, s))) return rc;
   if (S) {
     hipLaunchKernelGGL(k_los_check, dim3(gs), dim3(256), 0, s, d_comp, g, d_q, d_anchor, S, W.ctl);
@@ -488,7 +557,8 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
   }
   if ((rc = fill<double>(d_dist, g.n, __builtin_inf(), s))) return rc;
   if ((rc = fill<uint32_t>(d_src, g.n, kNone, s))) return rc;
-  if ((rc = fill<uint8_t>(W.chg, 2 * g.n, 0, s))) return rc;
+  if ((rc = fill<uint8_t>(W.flag, g.n, 0, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl + 2 + kSweepBatch, 1, 0u, s))) return rc;
   if (S) {
     hipLaunchKernelGGL(k_anchor_reset, dim3(gs), dim3(256), 0, s, A);
     hipLaunchKernelGGL(k_anchor_len, dim3(gs), dim3(256), 0, s, A);
@@ -496,7 +566,6 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
     hipLaunchKernelGGL(k_anchor_set, dim3(gs), dim3(256), 0, s, A);
     LSRVT_LAUNCHED();
   }
-  int cur = 0;  // plane of chg that holds the previous sweep's changes
   for (int stage = 1; stage <= 2; ++stage) {
     int32_t done = 0;
     bool first = true;
@@ -504,12 +573,13 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
       if (done >= kMaxSweeps) return LSRVT_ELIMIT;
       if ((rc = fill<uint32_t>(W.ctl + 2, kSweepBatch, 0u, s))) return rc;
       for (int j = 0; j < kSweepBatch; ++j) {
+        // the first sweep of stage 2 re-evaluates everything: new candidates
+        hipLaunchKernelGGL(k_los_mark, dim3(gm), dim3(kLosThreads), 0, s, A, (first && stage == 2) ? 1 : 0);
         if (stage == 1)
-          hipLaunchKernelGGL(k_los_sweep<1>, dim3(gv), dim3(kLosThreads), 0, s, A, cur, j, first ? 1 : 0);
+          hipLaunchKernelGGL(k_los_eval<1>, dim3(ge), dim3(kLosThreads), 0, s, A, j);
         else
-          hipLaunchKernelGGL(k_los_sweep<2>, dim3(gv), dim3(kLosThreads), 0, s, A, cur, j, first ? 1 : 0);
-        hipLaunchKernelGGL(k_los_apply, dim3(gv), dim3(kLosThreads), 0, s, A, cur ^ 1);
-        cur ^= 1;
+          hipLaunchKernelGGL(k_los_eval<2>, dim3(ge), dim3(kLosThreads), 0, s, A, j);
+        hipLaunchKernelGGL(k_los_apply, dim3(gm), dim3(kLosThreads), 0, s, A);
         first = false;
       }
       LSRVT_LAUNCHED();
