@@ -34,6 +34,7 @@ constexpr int32_t kMaxSweeps = 100000;
 constexpr int kPhiRounds = 40;
 constexpr double kShorter = 1.0 - 0x1p-40;
 constexpr double kNear = 1.0 + 0x1p-40;
+constexpr int kMarkPer = 16;  // voxels per thread in mark and apply (a chunk: 4096 voxels)
 
 struct LosArgs {
   const uint32_t *comp;
@@ -47,6 +48,7 @@ struct LosArgs {
   uint32_t *ps;           // [N] proposed sources
   uint8_t *chg;           // [N] changed in this sweep
   uint8_t *flag;          // [N] v or its source changed in the sweep before
+  uint8_t *chunk_any;     // [chunks] some flag of the chunk is set
   uint32_t *list;         // [N] voxels to evaluate in this sweep
   uint32_t *count;        // length of list
   uint32_t *alive;        // [kSweepBatch] a voxel changed in sweep j of the batch
@@ -165,6 +167,7 @@ __global__ void k_anchor_set(LosArgs A) {
   A.d[a] = A.pd[a];
   A.src[a] = kSite | s;
   A.flag[a] = 1;  // the anchors' neighbourhoods are evaluated in the first sweep
+  A.chunk_any[a / ((uint32_t)kLosThreads * kMarkPer)] = 1;
 }
 
 // ---------------------------------------------------------------- sweeps
@@ -176,13 +179,36 @@ __global__ void k_anchor_set(LosArgs A) {
 // is set for each voxel that changed or whose source changed.  A voxel left
 // out reads nothing that changed since it was last evaluated, so it would
 // compute the same result: the sweep equals a full synchronous sweep.
-constexpr int kMarkPer = 16;  // voxels per thread in mark and apply
 
 __global__ void __launch_bounds__(kLosThreads) k_los_mark(LosArgs A, int all_dirty) {
   __shared__ uint32_t part[kLosThreads];
   __shared__ uint32_t base;
+  __shared__ uint32_t live;
   const Geom g = A.g;
-  const int64_t chunk = (int64_t)blockIdx.x * kLosThreads * kMarkPer;
+  const int64_t C = (int64_t)kLosThreads * kMarkPer;
+  const int64_t chunk = (int64_t)blockIdx.x * C;
+  if (!all_dirty) {
+    // A voxel of this chunk can be dirty only if a flag is set in the chunk
+    // or in a chunk that holds one of its face neighbours (offsets 1, nx and
+    // nx*ny).  Any change of the chunk itself in the sweep before set a flag
+    // here, so a skipped chunk has nothing to clear either.
+    if (threadIdx.x == 0) {
+      const int64_t nch = (g.n + C - 1) / C;
+      const int64_t off[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+      uint32_t any = A.chunk_any[blockIdx.x];
+      for (int k = 0; k < 3 && !any; ++k)
+        for (int sgn = -1; sgn <= 1 && !any; sgn += 2) {
+          int64_t lo = (chunk + sgn * off[k]) / C, hi = (chunk + C - 1 + sgn * off[k]) / C;
+          if (chunk + sgn * off[k] < 0) lo = 0;
+          lo = lo < 0 ? 0 : lo;
+          hi = hi >= nch ? nch - 1 : hi;
+          for (int64_t b = lo; b <= hi && !any; ++b) any = A.chunk_any[b];
+        }
+      live = any;
+    }
+    __syncthreads();
+    if (!live) return;
+  }
   uint32_t bits = 0, cnt = 0;
 #pragma unroll 4
   for (int j = 0; j < kMarkPer; ++j) {
@@ -219,99 +245,121 @@ __global__ void __launch_bounds__(kLosThreads) k_los_mark(LosArgs A, int all_dir
     }
 }
 
+// The segment from voxel (x, y, z) to the ray target of candidate code cc
+// (the voxel itself, or the anchor of a site) is clear.
+__device__ __forceinline__ bool clear_to(const LosArgs &A, int32_t x, int32_t y, int32_t z, uint32_t cc, uint32_t c) {
+  const uint32_t t = (cc & kSite) ? A.anchor[cc & ~kSite] : cc;
+  int32_t ux, uy, uz;
+  xyz(t, A.g, ux, uy, uz);
+  return ray_clear(A.comp, A.g, x, y, z, ux, uy, uz, c);
+}
+
 template <int Stage>
-__device__ __forceinline__ bool los_eval(const LosArgs &A, int64_t v) {
+__device__ __forceinline__ bool los_eval(const LosArgs &A, uint32_t v) {
   const Geom g = A.g;
   const uint32_t c = A.comp[v];
   int32_t x, y, z;
   xyz(v, g, x, y, z);
-  int64_t nb[6];
-  int k = 0;
-  if (x > 0) nb[k++] = v - 1;
-  if (x < g.nx - 1) nb[k++] = v + 1;
-  if (y > 0) nb[k++] = v - g.nx;
-  if (y < g.ny - 1) nb[k++] = v + g.nx;
-  if (z > 0) nb[k++] = v - (int64_t)g.nx * g.ny;
-  if (z < g.nz - 1) nb[k++] = v + (int64_t)g.nx * g.ny;
+  const uint32_t sy = (uint32_t)g.nx, sz = (uint32_t)g.nx * (uint32_t)g.ny;
   const uint32_t sv = A.src[v];
-  double cd[13];
-  uint32_t cc[13];
-  uint32_t ray[13];
-  int nc = 0;
+  const double dh = A.d[v];
+  // candidates: length cd, source code cc; bit i of need: a ray must be
+  // clear; known/ok: validity decided / valid (not shorter counts invalid)
+  // Fixed slots, so every index is a compile-time constant: stage 1 has the
+  // path through the site of neighbour i in slot i; stage 2 has the path
+  // through src(w_i) in slot 2i, through w_i in slot 2i + 1, and the voxel's
+  // own path re-measured in slot 12.  Bit i of `have` marks a candidate.
+  constexpr int kCand = Stage == 1 ? 6 : 13;
+  double cd[kCand];
+  uint32_t cc[kCand];
+  uint32_t need = 0, have = 0;
+#pragma unroll
+  for (int i = 0; i < kCand; ++i) { cd[i] = 0.0; cc[i] = 0u; }
   if (Stage == 2 && sv != kNone && !(sv & kSite)) {
     int32_t ux, uy, uz;
     xyz(sv, g, ux, uy, uz);
-    cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[sv];
-    cc[nc] = sv;
-    ray[nc++] = kNone;
+    cd[kCand - 1] = len_vox(x, y, z, ux, uy, uz) + A.d[sv];
+    cc[kCand - 1] = sv;
+    have |= 1u << (kCand - 1);
   }
-  for (int i = 0; i < k; ++i) {
-    const int64_t w = nb[i];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const bool in = i == 0 ? x > 0 : i == 1 ? x < g.nx - 1 : i == 2 ? y > 0 : i == 3 ? y < g.ny - 1
+                  : i == 4 ? z > 0 : z < g.nz - 1;
+    if (!in) continue;
+    const uint32_t w = i == 0 ? v - 1 : i == 1 ? v + 1 : i == 2 ? v - sy : i == 3 ? v + sy : i == 4 ? v - sz : v + sz;
     if (A.comp[w] != c) continue;
     const uint32_t u = A.src[w];
     if (u == kNone) continue;
+    constexpr int kStep = Stage == 1 ? 1 : 2;
     if (u & kSite) {
-      const uint32_t s = u & ~kSite;
-      cd[nc] = len_site(x, y, z, A.site_q + 3 * (size_t)s);
-      cc[nc] = u;
-      ray[nc++] = A.anchor[s];
-    } else if (Stage == 2 && (int64_t)u != v) {
+      cd[kStep * i] = len_site(x, y, z, A.site_q + 3 * (size_t)(u & ~kSite));
+      cc[kStep * i] = u;
+      need |= 1u << (kStep * i);
+      have |= 1u << (kStep * i);
+    } else if (Stage == 2 && u != v) {
       int32_t ux, uy, uz;
       xyz(u, g, ux, uy, uz);
-      cd[nc] = len_vox(x, y, z, ux, uy, uz) + A.d[u];
-      cc[nc] = u;
-      ray[nc++] = u;
+      cd[kStep * i] = len_vox(x, y, z, ux, uy, uz) + A.d[u];
+      cc[kStep * i] = u;
+      need |= 1u << (kStep * i);
+      have |= 1u << (kStep * i);
     }
     if (Stage == 2) {
-      cd[nc] = A.d[w] + 1.0;
-      cc[nc] = (uint32_t)w;
-      ray[nc++] = kNone;
+      cd[2 * i + 1] = A.d[w] + 1.0;
+      cc[2 * i + 1] = w;
+      have |= 1u << (2 * i + 1);
     }
   }
-  const double dh = A.d[v];
-  // validity: 0 unknown, 1 valid, 2 invalid (not shorter, or blocked)
-  uint8_t val[13];
-  for (int i = 0; i < nc; ++i) val[i] = cd[i] < dh ? 0 : 2;
-  // the shortest valid candidate, checking rays shortest first
+  // Every loop below runs over the compile-time bound kCand (fully
+  // unrolled), so the candidate arrays stay in registers.
+  uint32_t known = 0, ok = 0;
+#pragma unroll
+  for (int i = 0; i < kCand; ++i)
+    if ((have & (1u << i)) && !(cd[i] < dh)) known |= 1u << i;
+  // decides the candidate with code bc and every other undecided one with
+  // the same code that needs a ray (the same segment)
+  auto decide = [&](int bi, uint32_t bc, bool bneed) {
+    bool good = true;
+    if (bneed) {
+      good = clear_to(A, x, y, z, bc, c);
+#pragma unroll
+      for (int j = 0; j < kCand; ++j)
+        if ((have & (1u << j)) && !(known & (1u << j)) && (need & (1u << j)) && cc[j] == bc) {
+          known |= 1u << j;
+          if (good) ok |= 1u << j;
+        }
+    }
+    known |= 1u << bi;
+    if (good) ok |= 1u << bi;
+    return good;
+  };
+  // the shortest valid candidate, deciding shortest first
   double dmin = __builtin_inf();
   for (;;) {
     int bi = -1;
-    for (int i = 0; i < nc; ++i)
-      if (val[i] == 0 && (bi < 0 || cd[i] < cd[bi])) bi = i;
+    double bd = 0.0;
+    uint32_t bc = 0;
+#pragma unroll
+    for (int i = 0; i < kCand; ++i)
+      if ((have & (1u << i)) && !(known & (1u << i)) && (bi < 0 || cd[i] < bd)) { bi = i; bd = cd[i]; bc = cc[i]; }
     if (bi < 0) break;
-    bool ok = true;
-    if (ray[bi] != kNone) {
-      int32_t ux, uy, uz;
-      xyz(ray[bi], g, ux, uy, uz);
-      ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
-      // the same segment decides every candidate aimed at the same voxel
-      for (int i = 0; i < nc; ++i)
-        if (val[i] == 0 && ray[i] == ray[bi]) val[i] = ok ? 1 : 2;
-    }
-    val[bi] = ok ? 1 : 2;
-    if (ok) { dmin = cd[bi]; break; }
+    if (decide(bi, bc, (need >> bi) & 1u)) { dmin = bd; break; }
   }
   if (!(dmin < dh * kShorter)) return false;
   const double lim = dmin * kNear;
-  int sel = -1;
-  for (int i = 0; i < nc; ++i) {
-    if (val[i] == 2 || cd[i] > lim) continue;
-    if (val[i] == 0) {
-      bool ok = true;
-      if (ray[i] != kNone) {
-        int32_t ux, uy, uz;
-        xyz(ray[i], g, ux, uy, uz);
-        ok = ray_clear(A.comp, g, x, y, z, ux, uy, uz, c);
-      }
-      for (int j = i; j < nc; ++j)
-        if (val[j] == 0 && ray[j] == ray[i]) val[j] = ok ? 1 : 2;
-      val[i] = ok ? 1 : 2;
-      if (!ok) continue;
-    }
-    if (sel < 0 || pref(cc[i]) < pref(cc[sel]) || (cc[i] == cc[sel] && cd[i] < cd[sel])) sel = i;
+  bool got = false;
+  double sd = 0.0;
+  uint32_t sc = 0;
+#pragma unroll
+  for (int i = 0; i < kCand; ++i) {
+    if (!(have & (1u << i)) || cd[i] > lim) continue;
+    if (!(known & (1u << i))) decide(i, cc[i], (need >> i) & 1u);
+    if (!(ok & (1u << i))) continue;
+    if (!got || pref(cc[i]) < pref(sc) || (cc[i] == sc && cd[i] < sd)) { got = true; sd = cd[i]; sc = cc[i]; }
   }
-  A.pd[v] = cd[sel];
-  A.ps[v] = cc[sel];
+  A.pd[v] = sd;
+  A.ps[v] = sc;
   A.chg[v] = 1;
   return true;
 }
@@ -331,6 +379,7 @@ __global__ void __launch_bounds__(kLosThreads) k_los_apply(LosArgs A) {
   const Geom g = A.g;
   const int64_t chunk = (int64_t)blockIdx.x * kLosThreads * kMarkPer;
   if (blockIdx.x == 0 && threadIdx.x == 0) *A.count = 0u;  // eval of this sweep has finished
+  int any = 0;
 #pragma unroll 4
   for (int j = 0; j < kMarkPer; ++j) {
     const int64_t v = chunk + (int64_t)j * kLosThreads + threadIdx.x;
@@ -342,8 +391,12 @@ __global__ void __launch_bounds__(kLosThreads) k_los_apply(LosArgs A) {
       s = A.ps[v];
       A.src[v] = s;
     }
-    A.flag[v] = (ch || (s != kNone && !(s & kSite) && A.chg[s])) ? 1 : 0;
+    const int f = (ch || (s != kNone && !(s & kSite) && A.chg[s])) ? 1 : 0;
+    A.flag[v] = (uint8_t)f;
+    any |= f;
   }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) A.chunk_any[blockIdx.x] = any ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- phi, cells
@@ -515,6 +568,7 @@ struct LosWork {
   uint32_t *ps;
   uint8_t *chg;
   uint8_t *flag;
+  uint8_t *chunk_any;
   uint32_t *list;
   uint32_t *ctl;  // [0] err, [1] phi flag, [2..2+kSweepBatch) alive, [2+kSweepBatch] list length
   unsigned long long *acc;
@@ -526,10 +580,11 @@ void los_layout(C &cv, const Geom &g, uint32_t S, LosWork *W) {
   uint32_t *ps = cv.template take<uint32_t>((size_t)g.n);
   uint8_t *chg = cv.template take<uint8_t>((size_t)g.n);
   uint8_t *flag = cv.template take<uint8_t>((size_t)g.n);
+  uint8_t *chunk_any = cv.template take<uint8_t>((size_t)(g.n / ((int64_t)kLosThreads * kMarkPer) + 1));
   uint32_t *list = cv.template take<uint32_t>((size_t)g.n);
   uint32_t *ctl = cv.template take<uint32_t>(64);
   unsigned long long *acc = cv.template take<unsigned long long>(4 * (size_t)(S ? S : 1));
-  if (W) *W = LosWork{pd, ps, chg, flag, list, ctl, acc};
+  if (W) *W = LosWork{pd, ps, chg, flag, chunk_any, list, ctl, acc};
 }
 
 int32_t read_err(const uint32_t *d_err, hipStream_t s) {
@@ -545,8 +600,8 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
   int32_t rc;
   const unsigned gs = grid_for(S, 256, 1 << 20);
   const unsigned gv = (unsigned)((g.n + kLosThreads - 1) / kLosThreads);
-  LosArgs A{d_comp, g,    d_q,     d_anchor, S, d_dist, d_src, W.pd, W.ps, W.chg, W.flag, W.list,
-            W.ctl + 2 + kSweepBatch, W.ctl + 2, W.ctl};
+  LosArgs A{d_comp, g,      d_q,         d_anchor, S, d_dist, d_src, W.pd, W.ps, W.chg, W.flag, W.chunk_any,
+            W.list, W.ctl + 2 + kSweepBatch, W.ctl + 2, W.ctl};
   const unsigned gm = (unsigned)((g.n + (int64_t)kLosThreads * kMarkPer - 1) / ((int64_t)kLosThreads * kMarkPer));
   const unsigned ge = 2048;
   if ((rc = fill<uint32_t>(W.ctl, 2, 0u, s))) return rc;
@@ -557,7 +612,11 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
   }
   if ((rc = fill<double>(d_dist, g.n, __builtin_inf(), s))) return rc;
   if ((rc = fill<uint32_t>(d_src, g.n, kNone, s))) return rc;
+  // mark skips chunks with no flag nearby, so it does not clear the change
+  // plane everywhere: start every pass with it clear
+  if ((rc = fill<uint8_t>(W.chg, g.n, 0, s))) return rc;
   if ((rc = fill<uint8_t>(W.flag, g.n, 0, s))) return rc;
+  if ((rc = fill<uint8_t>(W.chunk_any, gm, 0, s))) return rc;
   if ((rc = fill<uint32_t>(W.ctl + 2 + kSweepBatch, 1, 0u, s))) return rc;
   if (S) {
     hipLaunchKernelGGL(k_anchor_reset, dim3(gs), dim3(256), 0, s, A);
