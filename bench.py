@@ -18,8 +18,10 @@ denominator.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
 The main line also carries, timed on their own outside the step, the
-on-device stratified initial sites of the same volume ("seeding") and the
-joint moments up to fourth order of the step's cells ("comoments").
+on-device stratified initial sites of the same volume ("seeding"), the
+joint moments up to fourth order of the step's cells ("comoments") and the
+Lloyd loop with the Euclidean line-of-sight tessellation and the ray-clamped
+site update on the same components, sites and T ("los").
 
 Two more modes print their own JSON line instead of the main one:
   --batch   64 independent Fourier volumes (edges 32..192, cubes and 2:1:1
@@ -347,6 +349,7 @@ def main():
     }
     out["seeding"] = bench_seeding(L, cc, w, n)
     out["comoments"] = bench_comoments(L, step, cc, x, wl.n_bands, n)
+    out["los"] = bench_los(L, cc, sd, w, n, wl.iters)
     if not args.no_cpu_baseline:
         _log("timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(wl, seeds)
@@ -370,6 +373,26 @@ def bench_comoments(L, step, cc, x, n_bands, n, reps: int = 3):
     units = m + m * (m + 1) // 2 + m * (m + 1) * (m + 2) // 6 + m * (m + 1) * (m + 2) * (m + 3) // 24
     return {"ms": round(ms, 4), "gvox_s": round(n / (ms / 1e3) / 1e9, 4), "vars": m, "sums_per_voxel": units,
             "dtype": "f64", "includes": "structured layout of the cells, merges, host synchronisations"}
+
+
+def bench_los(L, cc, sd, w, n, iters):
+    """The Lloyd loop with the Euclidean line-of-sight tessellation
+    (lsrvt_los_cvt: T updates, T + 1 passes) on the step's components, sites
+    and weights, one call timed on its own after a single-pass warm-up."""
+    import torch
+    ws = L.Workspace(w.device)
+    r = L.lsrvt_los_cvt(cc.comp, sd, w, 0, ws=ws)
+    torch.cuda.synchronize()
+    one_pass_sweeps = r.vt.sweeps[0]
+    _log("los: timing the line-of-sight Lloyd loop")
+    t0 = time.perf_counter()
+    r = L.lsrvt_los_cvt(cc.comp, sd, w, iters, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"ms": round(ms, 3), "iters": iters, "ms_per_pass": round(ms / (iters + 1), 3),
+            "gvox_per_iter_s": round(n * iters / (ms / 1e3) / 1e9, 4), "sweeps": int(r.vt.sweeps[0]),
+            "sweeps_first_pass": int(one_pass_sweeps), "dtype": "f64 lengths, exact integer update",
+            "includes": "host synchronisation every 8 sweeps"}
 
 
 def bench_seeding(L, cc, w, n, reps: int = 5):

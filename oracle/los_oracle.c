@@ -14,7 +14,7 @@
  *    the segment; grazing an edge or a corner of an outside voxel blocks).
  *  - A site is a continuous point X_s, kept in fixed point with 8 fraction
  *    bits (Q8: X = 256 x), plus an anchor voxel: the voxel the site sits in,
- *    the one "classified and activated" first.  Line of sight between a voxel
+ *    the voxel where its region starts growing.  Line of sight between a voxel
  *    v and the site is tested on the segment from v to the anchor's centre;
  *    the length of that leg is |x_v - X_s|.
  *  - Path lengths are float64: sqrt of an exact integer squared length
