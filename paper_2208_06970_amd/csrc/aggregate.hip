@@ -513,15 +513,15 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
           if (h) atomicAdd(&A.hist_c[(int64_t)c * m * A.B + i], h);
         }
     }
-    const float fn = (float)n;
     const double dn = (double)n;
     for (int j = t; j < m; j += kAggThreads) {
       float mean = 0.0f;
       double mean64 = 0.0;
       if (n) {
-        float sj = th[j] + tl[j];
-        mean = K[j] + sj / fn;
+        // the compensated pair (th, tl) is exact in float64; the float32
+        // output is the float64 result rounded once
         mean64 = (double)K[j] + ((double)th[j] + (double)tl[j]) / dn;
+        mean = (float)mean64;
       }
       A.mean32[(int64_t)s * m + j] = mean;
       A.mean64[(int64_t)s * m + j] = mean64;
@@ -533,14 +533,14 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_finalize(FinArgs A) {
       float c32 = 0.0f;
       double c64 = 0.0;
       if (n) {
+        // C = S_jk - S_j S_k / n cancels when the site's value is far from the
+        // cell mean, so it is formed in float64 from the exact pairs and the
+        // float32 output is that result rounded once
         const int uq = m + p;
-        float sj = th[j] + tl[j], sk = th[k] + tl[k];
-        float tt = sj * (sk / fn);
-        c32 = (th[uq] - tt) + tl[uq];
-        if (j == k && c32 < 0.0f) c32 = 0.0f;
         double dj = (double)th[j] + (double)tl[j], dk = (double)th[k] + (double)tl[k];
         c64 = ((double)th[uq] + (double)tl[uq]) - dj * dk / dn;
         if (j == k && c64 < 0.0) c64 = 0.0;
+        c32 = (float)c64;
       }
       A.c64[(int64_t)s * A.P + p] = c64;
       if (j == k) A.m2_32[(int64_t)s * m + j] = c32;

@@ -20,7 +20,9 @@ Workloads (all arrays are C-order [nz, ny, nx], linear index x + nx*(y + ny*z)):
   per 4096 weight-scaled voxels; 20 updates; 8 variables of the same spectrum,
   32-bin histograms and the full 8x8 covariance.
 * ``flame``   1024x512x512 combustion-shaped sheet (mixture fraction Z,
-  temperature T, 16 species), 10 isovalues of Z, weight = |grad T|.
+  temperature T, 16 species), 10 isovalues of Z, weight = |grad T|, 30
+  updates, 18 variables with 32-bin histograms and the full covariance; its
+  sites come from ``flame_sites`` (independent draws, no global sort).
 
 Wave vectors are rounded to integers (cycles per box edge) so that a field is
 one inverse FFT of a sparse spectrum; the field is then periodic on its box.
@@ -219,3 +221,128 @@ def fourier_workload(shape=(256, 256, 256), seed: int = 2, iters: int = 20, n_is
 def workload_sites(wl: Workload, comp: np.ndarray, n_comp: int) -> np.ndarray:
     """Initial sites for a workload from its component labels (seed 7919 * seed + 1)."""
     return seed_sites(comp, n_comp, wl.weights, wl.rho, 7919 * wl.seed + 1)
+
+
+def _modes_separable(shape, seed: int, n_modes: int, kmin: float, kmax: float, L: float) -> np.ndarray:
+    """The mode sum of ``fourier_field`` (same draws, integer wave vectors
+    kappa) evaluated separably: for each distinct kappa_z a (y, x) plane
+    P = sum of a e^{i phi} e^{2 pi i (ky y / ny + kx x / nx)} over its modes,
+    then f[z] = Re sum_kz e^{2 pi i kz z / nz} P_kz as two real matrix
+    products.  Float32, not normalised."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = (int(v) for v in shape)
+    kmag = rng.uniform(kmin, kmax, size=n_modes)
+    d = rng.normal(size=(n_modes, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    phase = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
+    kv = kmag[:, None] * d
+    kint = np.rint(kv * (np.array([nx, ny, nz], dtype=np.float64) / L)).astype(np.int64)
+    amp = kmag ** (-5.0 / 6.0)
+    kzs = np.unique(kint[:, 2])
+    P = np.zeros((len(kzs), ny, nx), dtype=np.complex64)
+    ey = lambda k: np.exp(2j * math.pi * k * np.arange(ny) / ny).astype(np.complex64)
+    ex = lambda k: np.exp(2j * math.pi * k * np.arange(nx) / nx).astype(np.complex64)
+    for m in range(n_modes):
+        j = int(np.searchsorted(kzs, kint[m, 2]))
+        c = np.complex64(amp[m] * np.exp(1j * phase[m]))
+        P[j] += np.outer(c * ey(kint[m, 1]), ex(kint[m, 0]))
+    E = np.exp(2j * math.pi * np.outer(np.arange(nz), kzs) / nz).astype(np.complex64)
+    Pf = P.reshape(len(kzs), ny * nx)
+    c = np.ascontiguousarray  # contiguous real and imaginary parts: BLAS products
+    f = c(E.real) @ c(Pf.real)
+    f -= c(E.imag) @ c(Pf.imag)
+    return f.reshape(nz, ny, nx)
+
+
+def flame_fields(shape=(512, 512, 1024), seed: int = 4, n_species: int = 16, n_modes: int = 512):
+    """Combustion-shaped fields on a box (nz, ny, nx): a thin wrinkled flame
+    sheet across y.  s = (y/(ny-1) - 1/2) + 0.05 n with n the mode sum of
+    ``fourier_field`` (512 modes, |k| in [1, 64] cycles per 512 voxels)
+    rescaled to [-1, 1]; mixture fraction Z = (1 + tanh(s / 0.02)) / 2;
+    temperature T = 300 + 1700 exp(-((Z - 0.3) / 0.1)^2); species
+    Y_i = exp(-((Z - z_i) / w_i)^2) + 0.02 g_i with z_i = (i - 1/2) / n_species,
+    w_i cycling 0.05, 0.1, 0.15, 0.2 (exponents clamped at -80), and g_i one
+    N(0, 1) float32 field (numpy
+    PCG64 ``default_rng(seed + 100)``) rolled by 7919 (i + 1) voxels in linear
+    order.  Returns float32 [2 + n_species, nz, ny, nx] = (Z, T, Y_1, ...)."""
+    nz, ny, nx = (int(v) for v in shape)
+    s = _modes_separable(shape, seed, n_modes, 1.0, 64.0, 512.0)
+    lo, hi = float(s.min()), float(s.max())
+    s -= np.float32(lo)
+    s *= np.float32(2.0 * 0.05 / (hi - lo)) if hi > lo else np.float32(0.0)
+    s -= np.float32(0.05)
+    s += (np.arange(ny, dtype=np.float32) / np.float32(max(ny - 1, 1)) - np.float32(0.5))[None, :, None]
+    out = np.empty((2 + n_species,) + (nz, ny, nx), dtype=np.float32)
+    Z = out[0]
+    s /= np.float32(0.02)
+    np.tanh(s, out=Z)
+    del s
+    Z += 1.0
+    Z *= 0.5
+    t = out[1]
+    np.subtract(Z, np.float32(0.3), out=t)
+    t /= np.float32(0.1)
+    np.square(t, out=t)
+    np.negative(t, out=t)
+    np.exp(t, out=t)
+    t *= 1700.0
+    t += 300.0
+    widths = (0.05, 0.1, 0.15, 0.2)
+    g = np.random.default_rng(seed + 100).standard_normal(size=Z.size, dtype=np.float32)
+    g *= np.float32(0.02)
+    rolled = np.empty_like(g)
+    n = g.size
+    for i in range(n_species):
+        zi = np.float32((i + 0.5) / n_species)
+        wi = np.float32(widths[i % 4])
+        y = out[2 + i]
+        np.subtract(Z, zi, out=y)
+        y /= wi
+        np.square(y, out=y)
+        np.negative(y, out=y)
+        np.maximum(y, np.float32(-80.0), out=y)  # no subnormal results (< 2e-35 change)
+        np.exp(y, out=y)
+        k = (7919 * (i + 1)) % n  # rolled = np.roll(g, k), without a new array
+        rolled[k:] = g[:n - k]
+        rolled[:k] = g[n - k:]
+        y += rolled.reshape(Z.shape)
+    return out
+
+
+def flame_sites(comp: np.ndarray, n_comp: int, weights: np.ndarray, rho: float, seed: int) -> np.ndarray:
+    """Initial sites for large volumes: every voxel is drawn independently with
+    probability min(1, w_v / (rho * mean w)) (uniform numbers from numpy PCG64
+    ``default_rng(seed)``, one per voxel in linear order), and a component
+    that drew no voxel gets its first voxel.  Ids ordered by (component,
+    linear index).  uint32 linear indices."""
+    c = np.ascontiguousarray(comp, dtype=np.uint32).ravel()
+    w = np.ascontiguousarray(weights).ravel()
+    rng = np.random.default_rng(seed)
+    p = w.astype(np.float32) / np.float32(rho * float(w.mean(dtype=np.float64)))
+    u = rng.random(size=c.size, dtype=np.float32)
+    pick = np.flatnonzero((u < p) & (c != 0xFFFFFFFF))
+    del u, p
+    have = np.zeros(n_comp, dtype=bool)
+    have[c[pick]] = True
+    miss = np.flatnonzero(~have)
+    if len(miss):
+        # first voxel of each component without a site
+        first = np.full(n_comp, np.iinfo(np.int64).max, dtype=np.int64)
+        lab = np.flatnonzero(c != 0xFFFFFFFF)
+        np.minimum.at(first, c[lab], lab)
+        pick = np.concatenate([pick, first[miss]])
+    order = np.lexsort((pick, c[pick]))
+    return pick[order].astype(np.uint32)
+
+
+def flame_workload(shape=(512, 512, 1024), seed: int = 4, iters: int = 30, n_bins: int = 32,
+                   rho: float = 4096.0) -> Workload:
+    """The combustion-shaped workload: 1024 x 512 x 512 (nx, ny, nz), 10
+    isovalues of Z at 0.05 .. 0.95, weight = |grad T| as uint16, 18 variables
+    (Z, T, 16 species) with 32-bin histograms and the full 18 x 18 covariance,
+    30 updates, one site per 4096 weight-scaled voxels."""
+    v = flame_fields(shape, seed)
+    iso = np.array([0.05 + 0.1 * i for i in range(10)], dtype=np.float32)
+    w = gradient_weight(v[1])
+    edges = histogram_edges(v, n_bins)
+    return Workload("flame", v[0], iso, w, v, edges, iters, rho, seed, True, {"n_species": 16})
