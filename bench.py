@@ -99,13 +99,8 @@ def cpu_baseline(wl, seeds, T_sample=2):
 
 def _fourier_job_inputs(shape, seed, n_iso, n_vars, n_bins, rho, n_modes=128):
     """Host arrays of one Fourier job (field, isovalues, weights, variables, edges)."""
-    import numpy as np
     import synth
-    f = synth.fourier_field(shape, seed, n_modes=n_modes)
-    iso = synth.quantile_isovalues(f, [(i + 1) / (n_iso + 1) for i in range(n_iso)])
-    w = synth.gradient_weight(f)
-    x = np.stack([synth.fourier_field(shape, 1000 * seed + 1 + j, n_modes=n_modes) for j in range(n_vars)])
-    return f, iso, w, np.ascontiguousarray(x), synth.histogram_edges(x, n_bins)
+    return synth.fourier_job(shape, seed, n_iso, n_vars, n_bins, n_modes)
 
 
 def _device_job(shape, seed, n_iso, n_vars, n_bins, rho, iters):
@@ -131,17 +126,8 @@ def bench_batch(args):
     import numpy as np
     import torch
     import paper_2208_06970_amd as L
-    rng = np.random.default_rng(3)
-    specs = []
-    for j in range(args.batch_jobs):
-        e = int(rng.choice(np.arange(32, 193, 16)))
-        if rng.random() < 0.5:
-            shape = (e, e, e)
-        else:
-            shape = [e // 2, e // 2, e // 2]
-            shape[int(rng.integers(0, 3))] = e
-            shape = tuple(shape)
-        specs.append((shape, 3000 + j, int(rng.integers(3, 11))))
+    import synth
+    specs = synth.batch_specs(args.batch_jobs, 3)
     _log(f"batch: generating {len(specs)} volumes")
     jobs = [_device_job(sh, sd, k, 8, 32, 4096.0, 15) for sh, sd, k in specs]
     vox_iters = sum(j["voxels"] * j["iters"] for j in jobs)

@@ -346,3 +346,32 @@ def flame_workload(shape=(512, 512, 1024), seed: int = 4, iters: int = 30, n_bin
     w = gradient_weight(v[1])
     edges = histogram_edges(v, n_bins)
     return Workload("flame", v[0], iso, w, v, edges, iters, rho, seed, True, {"n_species": 16})
+
+
+def batch_specs(n_jobs: int = 64, seed: int = 3):
+    """The uneven batch: per job (shape, seed, isovalue count).  Long edge
+    e from {32, 48, ..., 192}; a cube, or by coin a 2:1:1 box with the long
+    axis random; 3..10 isovalues; job seeds 3000 + j."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for j in range(n_jobs):
+        e = int(rng.choice(np.arange(32, 193, 16)))
+        if rng.random() < 0.5:
+            shape = (e, e, e)
+        else:
+            sh = [e // 2, e // 2, e // 2]
+            sh[int(rng.integers(0, 3))] = e
+            shape = tuple(sh)
+        specs.append((shape, 3000 + j, int(rng.integers(3, 11))))
+    return specs
+
+
+def fourier_job(shape, seed: int, n_iso: int, n_vars: int = 8, n_bins: int = 32, n_modes: int = 128):
+    """Host arrays of one batch or serving job: a Fourier field, isovalues at
+    quantiles, |grad| weights, n_vars Fourier variables (seeds 1000 seed + 1 + j)
+    and their histogram edges."""
+    f = fourier_field(shape, seed, n_modes=n_modes)
+    iso = quantile_isovalues(f, [(i + 1) / (n_iso + 1) for i in range(n_iso)])
+    w = gradient_weight(f)
+    x = np.stack([fourier_field(shape, 1000 * seed + 1 + j, n_modes=n_modes) for j in range(n_vars)])
+    return f, iso, w, np.ascontiguousarray(x), histogram_edges(x, n_bins)

@@ -97,3 +97,60 @@ def test_batch_capacity_and_validation():
         assert small.status == L.ECAPACITY and small.n_comp == d["cc"].n_comp
         assert ok.status == 0
     L.lsrvt_batch_run([], n_streams=2)
+
+
+def test_batch_fullsize_64_volumes():
+    """The 64-volume batch at full size (edges 32..192, cubes and 2:1:1 boxes,
+    3..10 isovalues, T = 15, 8 variables, 32-bin histograms, covariance; 87 M
+    voxels) on 4 streams: every job bit-identical to its calls alone; bands
+    and components of every job equal the oracle's; cells, sites and cell
+    statistics equal the oracle's on the jobs of at most 2^20 voxels (the
+    larger ones through properties that hold at any size)."""
+    from tests.test_gpu_stats import _check_level
+    specs = synth.batch_specs(64, 3)
+    data = []
+    for shape, seed, k in specs:
+        f, iso, w, x, e = synth.fourier_job(shape, seed, k)
+        band = oracle.bands(f, iso)
+        cc = oracle.components(band, k + 1)
+        seeds = synth.seed_sites(cc.comp, cc.n_comp, w, 4096.0, 7919 * seed + 1)
+        data.append(dict(f=f, iso=iso, w=w, x=x, edges=e, seeds=seeds, iters=15, cov=True, cc=cc, band=band))
+    banner(f"batch full: {len(data)} volumes, {sum(d['f'].size for d in data)} voxels")
+    jobs = [L.BatchJob(field=dev(d["f"]), iso=d["iso"], seeds=dev(d["seeds"]), weights=dev(d["w"]), iters=15,
+                       variables=dev(d["x"]), edges=dev(d["edges"]), cov=True, cap_comp=int(d["cc"].n_comp) + 16)
+            for d in data]
+    L.lsrvt_batch_run(jobs, n_streams=4)
+    n_oracle = 0
+    for i, (d, j) in enumerate(zip(data, jobs)):
+        assert j.status == 0 and j.n_comp == d["cc"].n_comp, i
+        np.testing.assert_array_equal(host(j.band), d["band"])
+        np.testing.assert_array_equal(host(j.comp, np.uint32), d["cc"].comp)
+        band, cc, r, st = _alone(d)
+        np.testing.assert_array_equal(host(j.cell), host(r.cell))
+        S = len(d["seeds"])
+        np.testing.assert_array_equal(host(j.sites)[:S], host(r.sites))
+        for lvl, (a, b) in enumerate(zip(j.stats, st)):
+            units = j.n_comp if lvl == 1 else None
+            for key in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov"):
+                ga = host(getattr(a, key))
+                ga = ga[:units] if units is not None else ga
+                assert np.array_equal(ga, host(getattr(b, key))), (i, lvl, key)
+        cell = host(j.cell, np.uint32)
+        sites = host(j.sites, np.uint32)[:S]
+        site_comp = host(j.site_comp, np.uint32)[:S]
+        if d["f"].size <= (1 << 20):
+            want = oracle.cvt(d["cc"].comp, d["seeds"], d["w"], 15)
+            np.testing.assert_array_equal(cell, want.cell, err_msg=f"job {i}")
+            np.testing.assert_array_equal(sites, want.sites, err_msg=f"job {i}")
+            _check_level(f"job {i} cells", j.stats[0], oracle.stats(want.cell, S, d["x"], d["edges"], cov=True), 8)
+            n_oracle += 1
+        else:
+            cf, comp = cell.ravel(), d["cc"].comp.ravel()
+            lab = cf != oracle.NONE_ID
+            np.testing.assert_array_equal(site_comp[cf[lab]], comp[lab])
+            seeded = np.zeros(d["cc"].n_comp, dtype=bool)
+            seeded[site_comp] = True
+            np.testing.assert_array_equal(lab, seeded[comp])
+            owner = cf[sites]
+            assert np.all((owner == np.arange(S)) | (sites[owner] == sites))
+    print(f"jobs checked against the oracle's Lloyd loop: {n_oracle} of {len(jobs)}")
