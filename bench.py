@@ -219,8 +219,8 @@ def main():
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); a multi-GPU layout is "
+              "not built.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
