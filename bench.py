@@ -90,8 +90,15 @@ def cpu_baseline(wl, seeds, T_sample=2):
     oracle.stats(band_unit.astype(np.uint32), wl.n_bands, wl.variables, wl.edges, cov=True)
     dt = time.perf_counter() - t0
     n = wl.field.size
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n * T_sample / dt / 1e9, "unit": "Gvoxels/s per Lloyd iteration", "cores": 1,
-            "kind": "oracle", "seconds": round(dt, 3),
+            "kind": "oracle", "seconds": round(dt, 3), "host_cpu": model,
+            "host_threads": len(os.sched_getaffinity(0)),
             "sample": f"same {wl.field.shape[2]}x{wl.field.shape[1]}x{wl.field.shape[0]} volume, full pipeline "
                       f"(isobands, components, Lloyd loop, three-level statistics) with {T_sample} updates "
                       f"instead of {wl.iters}; single-threaded C"}
