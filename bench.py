@@ -15,7 +15,7 @@ value = voxels * T / step time, in Gvoxels/s per Lloyd iteration, with the
 whole step (isobands, components, final pass and statistics included) in the
 denominator.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--flame | --batch | --serve]
 
 The main line also carries, timed on their own outside the step, the
 on-device stratified initial sites of the same volume ("seeding"), the
@@ -23,7 +23,10 @@ joint moments up to fourth order of the step's cells ("comoments") and the
 Lloyd loop with the Euclidean line-of-sight tessellation and the ray-clamped
 site update on the same components, sites and T ("los").
 
-Two more modes print their own JSON line instead of the main one:
+Three more modes print their own JSON line instead of the main one:
+  --flame   the combustion-shaped 1024 x 512 x 512 volume (10 isovalues of
+            the mixture fraction, |grad T| weights, 30 updates, 18 variables
+            with 32-bin histograms and the 18 x 18 covariance), whole step;
   --batch   64 independent Fourier volumes (edges 32..192, cubes and 2:1:1
             boxes, 3..10 isovalues, 15 updates) through lsrvt_batch_run on
             several streams, against the same jobs run one at a time;
@@ -218,6 +221,7 @@ def main():
     ap.add_argument("--batch-jobs", type=int, default=64)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--serve", action="store_true", help="Poisson serving loop (own JSON line)")
+    ap.add_argument("--flame", action="store_true", help="1024x512x512 combustion-shaped volume (own JSON line)")
     ap.add_argument("--serve-jobs", type=int, default=24)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--rates", type=float, nargs="*", default=[5.0, 20.0, 50.0])
@@ -242,6 +246,9 @@ def main():
         return
     if args.serve:
         bench_serve(args)
+        return
+    if args.flame:
+        bench_flame(args)
         return
     if args.copy_mib:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
@@ -366,6 +373,69 @@ def bench_comoments(L, step, cc, x, n_bands, n, reps: int = 3):
     units = m + m * (m + 1) // 2 + m * (m + 1) * (m + 2) // 6 + m * (m + 1) * (m + 2) * (m + 3) // 24
     return {"ms": round(ms, 4), "gvox_s": round(n / (ms / 1e3) / 1e9, 4), "vars": m, "sums_per_voxel": units,
             "dtype": "f64", "includes": "structured layout of the cells, merges, host synchronisations"}
+
+
+def bench_flame(args):
+    """The whole step on the combustion-shaped 1024 x 512 x 512 volume."""
+    import numpy as np
+    import torch
+    import paper_2208_06970_amd as L
+    import synth
+    _log("flame: generating the 1024x512x512 workload")
+    wl = synth.flame_workload()
+    n = wl.field.size
+    f = torch.from_numpy(wl.field).cuda()
+    w = torch.from_numpy(wl.weights.view(np.int16)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(wl.variables)).cuda()
+    e = torch.from_numpy(wl.edges).cuda()
+    band, _ = L.lsrvt_isobands(f, wl.iso)
+    cc = L.lsrvt_components(band, wl.n_bands)
+    seeds = synth.flame_sites(cc.comp.cpu().numpy().view(np.uint32), cc.n_comp, wl.weights, wl.rho, wl.seed)
+    sd = torch.from_numpy(seeds.view(np.int32)).cuda()
+    _log(f"flame: comps={cc.n_comp} sites={len(seeds)}")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    ph = np.zeros(4)
+
+    def step(record):
+        if record:
+            ev[0].record()
+        b, _ = L.lsrvt_isobands(f, wl.iso)
+        if record:
+            ev[1].record()
+        c = L.lsrvt_components(b, wl.n_bands)
+        if record:
+            ev[2].record()
+        r = L.lsrvt_cvt(b, c.comp, sd, w, wl.iters, want_mean_ds=False)
+        if record:
+            ev[3].record()
+        L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, c.comp_band, c.n_comp, wl.n_bands, x, e, cov=True)
+        if record:
+            ev[4].record()
+            torch.cuda.synchronize()
+            for k in range(4):
+                ph[k] += ev[k].elapsed_time(ev[k + 1])
+
+    steps = max(1, min(args.steps, 3))
+    step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(True)
+        _log(f"flame: step {i + 1}/{steps} done")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ph /= steps
+    print(json.dumps({"metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
+                      "value": round(n * wl.iters / (ms / 1e3) / 1e9, 4), "unit": "Gvoxels/s", "n_gpus": 1,
+                      "steps": steps, "warmup": 1, "ms_per_step": round(ms, 3), "higher_is_better": True,
+                      "dtype": "u32", "data": "synthetic",
+                      "config": {"workload": "flame 1024x512x512, 10 isovalues of Z, |grad T| uint16 weights, T=30, "
+                                             "18 vars, 32-bin hist, 18x18 cov", "voxels": n, "iters": wl.iters,
+                                 "sites": int(len(seeds)), "components": int(cc.n_comp)},
+                      "phases_ms": {k: round(float(v), 3) for k, v in zip(("isobands", "components", "lloyd",
+                                                                             "aggregate"), ph)},
+                      "lloyd_gvox_per_iter_s": round(n * wl.iters / (ph[2] / 1e3) / 1e9, 4),
+                      "stats_gvox_s": round(n / (ph[3] / 1e3) / 1e9, 4)}), flush=True)
 
 
 def bench_los(L, cc, sd, w, n, iters):
