@@ -233,3 +233,25 @@ def test_los_fullsize_properties():
             continue
         wx, wa_ = oracle.los_clamp(comp, q0h[s_], int(a0h[s_]), tg[s_])
         assert np.array_equal(nq[s_], wx) and na[s_] == wa_, s_
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 1, 37), (1, 23, 1), (5, 1, 9), (3, 70, 2)])
+def test_los_degenerate_shapes(shape):
+    """One voxel, lines along x and y, one-voxel-thick slabs: the walks and
+    neighbour checks at every face of the volume."""
+    rng = np.random.default_rng(sum(shape))
+    n = int(np.prod(shape))
+    comp = np.where(rng.random(shape) < 0.15, NONE, rng.integers(0, 2, shape)).astype(np.uint32)
+    if n == 1:
+        comp[...] = 0
+    cand = np.flatnonzero(comp.ravel() != NONE)
+    seeds = np.sort(rng.choice(cand, min(len(cand), 3), replace=False)).astype(np.uint32)
+    w = rng.integers(1, 9, shape).astype(np.uint16)
+    banner(f"los degenerate: {shape} S={len(seeds)}")
+    want = oracle.los_cvt(comp, seeds, w, 3)
+    got = L.lsrvt_los_cvt(dev(comp), dev(seeds), dev(w), 3)
+    np.testing.assert_array_equal(host(got.site_q), want.site_q)
+    np.testing.assert_array_equal(host(got.anchor, np.uint32), want.anchor)
+    np.testing.assert_array_equal(host(got.vt.dist), want.dist)
+    np.testing.assert_array_equal(host(got.vt.src, np.uint32), want.src)
+    np.testing.assert_array_equal(host(got.vt.cell, np.uint32), want.cell)
