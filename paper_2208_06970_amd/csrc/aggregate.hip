@@ -227,15 +227,8 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
               }
               bin = a - 1;
             }
-            // one LDS atomic per distinct bin of the wave
-            uint64_t rem = __ballot(bin >= 0);
-            while (rem) {
-              const int leader = __ffsll((unsigned long long)rem) - 1;
-              const int b0 = __builtin_amdgcn_readlane(bin, leader);
-              const uint64_t same = __ballot(bin == b0);
-              rem &= ~same;
-              if (lane == leader) atomicAdd(&hist_l[j * B + b0], (uint32_t)__popcll(same));
-            }
+            // one LDS atomic per lane; the LDS serialises lanes that hit one bin
+            if (bin >= 0) atomicAdd(&hist_l[j * B + bin], 1u);
           }
         }
       }
@@ -383,15 +376,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell_wave(CellArgs A) {
             }
             bin = a - 1;
           }
-          uint64_t rem = __ballot(bin >= 0);
-          while (rem) {
-            const int leader = __ffsll((unsigned long long)rem) - 1;
-            const int b0 = __builtin_amdgcn_readlane(bin, leader);
-            const uint64_t same = __ballot(bin == b0);
-            rem &= ~same;
-            if (lane == leader) hist_l[j * B + b0] += (uint32_t)__popcll(same);
-            wave_sync();
-          }
+          if (bin >= 0) atomicAdd(&hist_l[j * B + bin], 1u);
         }
       }
     }
