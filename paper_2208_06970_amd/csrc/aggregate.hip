@@ -554,6 +554,18 @@ __global__ __launch_bounds__(256) void k_band_int(BandIntArgs A) {
   const int64_t cols = 1 + 2 * (int64_t)m + (int64_t)m * B;
   const uint32_t q0 = blockIdx.x * 256u;
   const uint32_t q1 = q0 + 256u < A.n_comp ? q0 + 256u : A.n_comp;
+  const int nq = (int)(q1 - q0);
+  // the run's components and their bands, staged once (the order -> band
+  // chain of loads would otherwise repeat for every column)
+  __shared__ uint32_t cs[256];
+  __shared__ int bs[256];
+  if ((int)threadIdx.x < nq) {
+    const uint32_t c = A.order[q0 + threadIdx.x];
+    cs[threadIdx.x] = c;
+    bs[threadIdx.x] = A.comp_band[c];
+  }
+  __syncthreads();
+  constexpr int kAhead = 8;  // loads issued together per column
   for (int64_t col = threadIdx.x; col < cols; col += 256) {
     const int kind = col == 0 ? 0 : col <= m ? 1 : col <= 2 * m ? 2 : 3;
     const int64_t sub = kind == 1 ? col - 1 : kind == 2 ? col - 1 - m : col - 1 - 2 * m;
@@ -571,24 +583,33 @@ __global__ __launch_bounds__(256) void k_band_int(BandIntArgs A) {
         if (acc) atomicAdd(&A.hist_b[(int64_t)band * m * B + sub], (uint32_t)acc);
       }
     };
-    for (uint32_t q = q0; q < q1; ++q) {
-      const uint32_t c = A.order[q];
-      const int bc = A.comp_band[c];
-      if (bc != band) {
-        flush();
-        band = bc;
-        acc = kind == 1 ? 0xFFFFFFFFull : 0ull;
+    for (int q = 0; q < nq; q += kAhead) {
+      uint64_t v[kAhead];
+#pragma unroll
+      for (int k = 0; k < kAhead; ++k) {
+        v[k] = 0;
+        if (q + k >= nq) continue;
+        const uint32_t c = cs[q + k];
+        v[k] = kind == 0 ? (uint64_t)A.cnt_c[c]
+             : kind == 1 ? (uint64_t)A.kmin_c[(int64_t)c * m + sub]
+             : kind == 2 ? (uint64_t)A.kmax_c[(int64_t)c * m + sub]
+                         : (uint64_t)A.hist_c[(int64_t)c * m * B + sub];
       }
-      if (kind == 0) {
-        acc += A.cnt_c[c];
-      } else if (kind == 1) {
-        uint32_t v = A.kmin_c[(int64_t)c * m + sub];
-        if (v < acc) acc = v;
-      } else if (kind == 2) {
-        uint32_t v = A.kmax_c[(int64_t)c * m + sub];
-        if (v > acc) acc = v;
-      } else {
-        acc += A.hist_c[(int64_t)c * m * B + sub];
+#pragma unroll
+      for (int k = 0; k < kAhead; ++k) {
+        if (q + k >= nq) break;
+        const int bc = bs[q + k];
+        if (bc != band) {
+          flush();
+          band = bc;
+          acc = kind == 1 ? 0xFFFFFFFFull : 0ull;
+        }
+        if (kind == 0 || kind == 3)
+          acc += v[k];
+        else if (kind == 1)
+          acc = v[k] < acc ? v[k] : acc;
+        else
+          acc = v[k] > acc ? v[k] : acc;
       }
     }
     flush();
