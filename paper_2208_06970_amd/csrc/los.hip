@@ -431,50 +431,91 @@ __global__ void k_phi_cell(const uint32_t *__restrict__ src, const uint32_t *__r
 }
 
 // ---------------------------------------------------------------- update
-// M and S = sum m x_phi per site: lanes of a wave with the same cell are
-// summed by a segmented scan first (a wave covers consecutive voxels of a
-// row, mostly one or two cells), then the last lane of a run adds them.
-__global__ void __launch_bounds__(kLosThreads) k_los_accum(const uint32_t *__restrict__ cell,
-                                                           const uint32_t *__restrict__ phi,
-                                                           const uint16_t *__restrict__ w, Geom g, uint32_t S,
-                                                           unsigned long long *acc, uint32_t *err) {
-  const int64_t v = (int64_t)blockIdx.x * kLosThreads + threadIdx.x;
-  uint32_t s = kNone;
-  uint64_t m = 0, sx = 0, sy = 0, sz = 0;
-  if (v < g.n) {
-    s = cell[v];
-    if (s != kNone) {
-      if (s >= S) { err[0] = 1u; s = kNone; }
-      else {
+// M and S = sum m x_phi per site.  One workgroup per 64 x 8 x 8 tile, one
+// wave per row of 64 voxels along x: a segmented scan sums each run of equal
+// cell, the last lane of a run adds it into an LDS table keyed by cell, and
+// the table is flushed with one set of global atomics per distinct cell of
+// the tile (a run that finds the table full adds straight to global memory).
+// The sums are integers, so the order of the additions does not matter.
+constexpr int kAccTX = 64, kAccTY = 8, kAccTZ = 8;
+constexpr int kAccCap = 512;
+
+__global__ void __launch_bounds__(256) k_los_accum(const uint32_t *__restrict__ cell,
+                                                   const uint32_t *__restrict__ phi,
+                                                   const uint16_t *__restrict__ w, Geom g, uint32_t S,
+                                                   unsigned long long *acc, uint32_t *err) {
+  __shared__ uint32_t tkey[kAccCap];
+  __shared__ unsigned long long tM[kAccCap], tX[kAccCap], tY[kAccCap], tZ[kAccCap];
+  const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
+  const int ntx = (g.nx + kAccTX - 1) / kAccTX, nty = (g.ny + kAccTY - 1) / kAccTY;
+  const int ntz = (g.nz + kAccTZ - 1) / kAccTZ;
+  const int64_t ntiles = (int64_t)ntx * nty * ntz;
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int i = t; i < kAccCap; i += 256) {
+      tkey[i] = kNone;
+      tM[i] = tX[i] = tY[i] = tZ[i] = 0ull;
+    }
+    __syncthreads();
+    const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
+    const int x = tx * kAccTX + lane;
+    for (int r = wid; r < kAccTY * kAccTZ; r += 256 / kWave) {
+      const int y = ty * kAccTY + (r % kAccTY), z = tz * kAccTZ + (r / kAccTY);
+      if (y >= g.ny || z >= g.nz) continue;  // uniform across the wave
+      const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      uint32_t s = x < g.nx ? cell[v] : kNone;
+      if (s != kNone && s >= S) {
+        err[0] = 1u;
+        s = kNone;
+      }
+      uint64_t m = 0, sx = 0, sy = 0, sz = 0;
+      if (s != kNone) {
         m = w ? w[v] : 1u;
-        int32_t x, y, z;
-        xyz(phi[v], g, x, y, z);
-        sx = m * (uint64_t)x;
-        sy = m * (uint64_t)y;
-        sz = m * (uint64_t)z;
+        int32_t px, py, pz;
+        xyz(phi[v], g, px, py, pz);
+        sx = m * (uint64_t)px;
+        sy = m * (uint64_t)py;
+        sz = m * (uint64_t)pz;
+      }
+      // segmented inclusive scan; a lane stops adding once its range holds
+      // the start of its run
+      const uint32_t sl_ = __shfl_up(s, 1, kWave), sr = __shfl_down(s, 1, kWave);
+      uint32_t head = (lane == 0 || sl_ != s) ? 1u : 0u;
+      const bool tail = lane == kWave - 1 || sr != s;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t ho = __shfl_up(head, d, kWave);
+        const uint64_t mo = __shfl_up(m, d, kWave), xo = __shfl_up(sx, d, kWave);
+        const uint64_t yo = __shfl_up(sy, d, kWave), zo = __shfl_up(sz, d, kWave);
+        if (lane >= d && !head) { m += mo; sx += xo; sy += yo; sz += zo; head = ho; }
+      }
+      if (tail && s != kNone && m) {
+        const int sl = lds_slot<kAccCap>(tkey, s);
+        if (sl >= 0) {
+          atomicAdd(&tM[sl], (unsigned long long)m);
+          atomicAdd(&tX[sl], (unsigned long long)sx);
+          atomicAdd(&tY[sl], (unsigned long long)sy);
+          atomicAdd(&tZ[sl], (unsigned long long)sz);
+        } else {
+          unsigned long long *a = acc + 4 * (size_t)s;
+          atomicAdd(a + 0, (unsigned long long)m);
+          atomicAdd(a + 1, (unsigned long long)sx);
+          atomicAdd(a + 2, (unsigned long long)sy);
+          atomicAdd(a + 3, (unsigned long long)sz);
+        }
       }
     }
-  }
-  const int lane = lane_id();
-  // segmented inclusive scan; a run starts where the cell differs from the
-  // previous lane's, and a lane stops adding once its range holds a start
-  const uint32_t prev = __shfl_up(s, 1, kWave);
-  uint32_t head = (lane == 0 || prev != s) ? 1u : 0u;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t ho = __shfl_up(head, o, kWave);
-    const uint64_t mo = __shfl_up(m, o, kWave), xo = __shfl_up(sx, o, kWave);
-    const uint64_t yo = __shfl_up(sy, o, kWave), zo = __shfl_up(sz, o, kWave);
-    if (lane >= o && !head) { m += mo; sx += xo; sy += yo; sz += zo; head = ho; }
-  }
-  const uint32_t next = __shfl_down(s, 1, kWave);
-  const bool last = lane == kWave - 1 || next != s;
-  if (s != kNone && last && m != 0) {
-    unsigned long long *a = acc + 4 * (size_t)s;
-    atomicAdd(a + 0, (unsigned long long)m);
-    atomicAdd(a + 1, (unsigned long long)sx);
-    atomicAdd(a + 2, (unsigned long long)sy);
-    atomicAdd(a + 3, (unsigned long long)sz);
+    __syncthreads();
+    for (int i = t; i < kAccCap; i += 256) {
+      const uint32_t c = tkey[i];
+      if (c != kNone && tM[i]) {
+        unsigned long long *a = acc + 4 * (size_t)c;
+        atomicAdd(a + 0, tM[i]);
+        atomicAdd(a + 1, tX[i]);
+        atomicAdd(a + 2, tY[i]);
+        atomicAdd(a + 3, tZ[i]);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -678,10 +719,12 @@ int32_t los_update(const uint32_t *d_comp, const Geom &g, const uint16_t *d_w, c
                    const LosWork &W, hipStream_t s) {
   int32_t rc;
   if (S == 0) return LSRVT_OK;
-  const unsigned gv = (unsigned)((g.n + kLosThreads - 1) / kLosThreads);
   if ((rc = fill<uint32_t>(W.ctl, 1, 0u, s))) return rc;
   if ((rc = fill<unsigned long long>(W.acc, 4 * (int64_t)S, 0ull, s))) return rc;
-  hipLaunchKernelGGL(k_los_accum, dim3(gv), dim3(kLosThreads), 0, s, d_cell, d_phi, d_w, g, S, W.acc, W.ctl);
+  const int64_t ntiles = (int64_t)((g.nx + kAccTX - 1) / kAccTX) * ((g.ny + kAccTY - 1) / kAccTY) *
+                         ((g.nz + kAccTZ - 1) / kAccTZ);
+  hipLaunchKernelGGL(k_los_accum, dim3((unsigned)std::min<int64_t>(ntiles, 65535)), dim3(256), 0, s, d_cell, d_phi,
+                     d_w, g, S, W.acc, W.ctl);
   hipLaunchKernelGGL(k_los_move, dim3(grid_for(S, 256, 1 << 20)), dim3(256), 0, s, d_comp, g, S, W.acc, d_q,
                      d_anchor, d_target);
   LSRVT_LAUNCHED();
