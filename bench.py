@@ -340,6 +340,7 @@ def main():
         "phases_ms": phases,
         "lloyd_gvox_per_iter_s": round(n * wl.iters / (phases["lloyd"] / 1e3) / 1e9, 4) if phases["lloyd"] else None,
         "stats_gvox_s": round(n / (phases["aggregate"] / 1e3) / 1e9, 4) if phases["aggregate"] else None,
+        "end_to_end_gvox_s": round(n / (ms_per_step / 1e3) / 1e9, 4),
         "stats_dtype": "f32 compensated per cell, f64 merges",
         "roofline": {"bound": "hbm", "kernel": "k_bfs_level", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
