@@ -13,9 +13,12 @@
 //     an FMA).  Lanes own units, so the order of every sum is fixed.
 //     Histograms and extrema are integer / compare operations and go through
 //     LDS and then global atomics;
-//  4. per cell, the item partials are combined in item order; mean, M2 and
-//     co-moments are formed in float32 (cell outputs) and expanded to
-//     float64 for the merges;
+//  4. per cell, the item partials are combined in item order; the
+//     compensated float32 pair of every unit is exact in float64, where the
+//     cell's mean, M2 and co-moments are formed once (a constant amount of
+//     work per cell, and the inputs the float64 merges need); the float32
+//     cell outputs are those values rounded once.  Every sum over voxels is
+//     float32;
 //  5. Chan et al.'s pairwise merge in float64: cells of a component in site
 //     id order, then components of a band in component id order.  Counts,
 //     extrema and histograms merge exactly with atomics.

@@ -71,11 +71,21 @@ struct BFSArgs {
                            // bit t of word k is row (t & 15) + 16 (4 (t >> 4) + k)
   uint16_t *yf;        // [2][nbricks][32] y = 0 face rows (0..15), y = 15 face rows (16..31) of the frontier, by z
   uint32_t *cell;      // [N] site id of every reached voxel (NONE elsewhere)
+  uint32_t *dist;      // [N] level at which each voxel was reached (its hop distance to its site)
   uint32_t *act;       // [2][nbricks]: act[L & 1][b] == L when brick b takes part in level L
   uint32_t *alive;     // [3]: alive[L % 3] != 0 when some brick takes part in level L
   uint32_t *hist;      // [kHistLen] alive flag of every level
   uint32_t *err;
+  // incremental passes only
+  uint16_t *inv;       // [nbricks][256] voxels whose site moved in the last update
+  uint32_t *bnd;       // [nbricks][4096] kept voxels next to an invalid one: dist << 12 | x + 16 row
+  uint32_t *bcnt;      // [nbricks] entries of bnd
+  uint32_t *wake;      // [nbricks] next level at which the brick injects kept voxels (NONE: none)
 };
+
+// Entries of the kept-voxel lists hold the level in 20 bits; a pass whose
+// lists would need more runs as a full pass.
+constexpr uint32_t kMaxBndLevel = (1u << 20) - 1;
 
 __device__ __forceinline__ int64_t brick_row_base(const Geom &g, int x0, int y, int z) {
   return x0 + (int64_t)g.nx * (y + (int64_t)g.ny * z);
@@ -133,6 +143,53 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict_
   }
 }
 
+struct BrickPos {
+  uint32_t b, row, lx;
+  int bx, by, bz;
+};
+
+__device__ __forceinline__ BrickPos brick_pos(const BFSArgs &A, uint32_t v) {
+  const uint32_t x = v % (uint32_t)A.g.nx, r = v / (uint32_t)A.g.nx;
+  const uint32_t y = r % (uint32_t)A.g.ny, z = r / (uint32_t)A.g.ny;
+  BrickPos p;
+  p.bx = (int)(x / BX);
+  p.by = (int)(y / BY);
+  p.bz = (int)(z / BZ);
+  p.b = (uint32_t)p.bx + (uint32_t)A.bg.nbx * ((uint32_t)p.by + (uint32_t)A.bg.nby * (uint32_t)p.bz);
+  p.row = (y % BY) + BY * (z % BZ);
+  p.lx = x % BX;
+  return p;
+}
+
+// Bit of voxel (row, lx) of brick b in a 16-bit row array, read through the
+// 32-bit word that holds it.
+__device__ __forceinline__ bool row_bit(const uint16_t *rows, const BrickPos &p) {
+  return (rows[(size_t)p.b * kRows + p.row] >> p.lx) & 1u;
+}
+
+__device__ __forceinline__ void or_row_bit(uint16_t *rows, const BrickPos &p) {
+  const size_t w = ((size_t)p.b * kRows + p.row) >> 1;
+  atomicOr(reinterpret_cast<uint32_t *>(rows) + w, (1u << p.lx) << ((p.row & 1u) * 16u));
+}
+
+// Puts a voxel into the frontier of level 0 (rows and packed faces) and
+// marks its brick and the six neighbours for level 1.
+__device__ void frontier0(const BFSArgs &A, const BrickPos &p) {
+  or_row_bit(A.fr, p);
+  const uint32_t ly = p.row & 15u, lz = p.row >> 4;
+  if (p.lx == 0 || p.lx == BX - 1) {
+    const uint32_t lane = ly + 16u * (lz >> 2), k = lz & 3u;
+    atomicOr(&A.xf[(size_t)p.b * 8 + (p.lx ? 4 : 0) + k], 1ull << lane);
+  }
+  if (ly == 0 || ly == BY - 1) {
+    const size_t yi = (size_t)p.b * 32 + (ly ? 16 : 0) + lz;
+    atomicOr(reinterpret_cast<uint32_t *>(A.yf) + (yi >> 1), (1u << p.lx) << ((yi & 1u) * 16u));
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) mark_brick(A, p.bx, p.by, p.bz, k, 1u);
+  A.alive[1] = 1u;
+}
+
 // Level 0: every site reaches its own voxel; co-located sites keep the lowest id.
 __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -142,44 +199,91 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
     atomicOr(A.err, 1u);
     return;
   }
-  uint32_t x = v % (uint32_t)A.g.nx, r = v / (uint32_t)A.g.nx;
-  uint32_t y = r % (uint32_t)A.g.ny, z = r / (uint32_t)A.g.ny;
-  int bx = x / BX, by = y / BY, bz = z / BZ;
-  uint32_t b = bx + A.bg.nbx * (by + A.bg.nby * bz);
-  const uint32_t ly = y % BY, lz = z % BZ, lx = x % BX;
-  const uint32_t row = ly + BY * lz;
+  const BrickPos p = brick_pos(A, v);
   atomicMin(&A.cell[v], s);
-  // 16-bit rows are updated through the 32-bit word that holds them (parity 0 = level 0)
-  const size_t w = ((size_t)b * kRows + row) >> 1;
-  const uint32_t bit = (1u << lx) << ((row & 1u) * 16u);
-  atomicOr(reinterpret_cast<uint32_t *>(A.vis) + w, bit);
-  atomicOr(reinterpret_cast<uint32_t *>(A.fr) + w, bit);
-  if (lx == 0 || lx == BX - 1) {
-    const uint32_t lane = ly + 16u * (lz >> 2), k = lz & 3u;
-    atomicOr(&A.xf[(size_t)b * 8 + (lx ? 4 : 0) + k], 1ull << lane);
+  A.dist[v] = 0u;
+  or_row_bit(A.vis, p);
+  frontier0(A, p);
+}
+
+// ----------------------------------------------------------------------------
+// Incremental passes.  After an update only the sites that moved can change
+// the regions.  A voxel whose site did not move keeps a key (distance, id)
+// that is still the best over the sites that did not move, so the new key is
+// the better of that one and the best over the moved sites; voxels whose site
+// moved ("invalid") know neither.  The pass is the same level-synchronous
+// search, restricted: its frontier at level L holds the voxels changed at
+// level L - 1 and the kept voxels of distance L - 1 that touch an invalid
+// voxel ("boundary", injected from per-brick lists at their level).  An
+// invalid voxel reached at level L takes the smallest id of its frontier
+// neighbours, as in a full pass: every neighbour at distance L - 1 is in the
+// frontier (it changed, or it was kept and touches this invalid voxel).  A
+// kept voxel reached at level L takes (L, id) only when that key is smaller
+// than its own: a kept neighbour at distance L - 1 offers a key it already
+// beats, so leaving such neighbours out of the frontier changes nothing.  A
+// kept voxel that changes joins the frontier, so changes spread as far as
+// they reach, and the result is the full pass's.
+
+// Invalid rows: voxels whose site moved.  One voxel per lane, ballots per row.
+__global__ __launch_bounds__(kVTThreads) void k_inc_reset(const uint32_t *__restrict__ cell,
+                                                          const uint8_t *__restrict__ moved, Geom g, VTGrid bg,
+                                                          uint16_t *__restrict__ inv) {
+  const int64_t slots = bg.nbricks * kRows * BX;
+  const int lane = lane_id();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i - lane < slots;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    bool p = false;
+    const int64_t row = i >> 4;
+    if (i < slots) {
+      const int64_t b = row / kRows;
+      const int t = (int)(row % kRows);
+      const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+      const int x = bx * BX + (int)(i & 15), y = by * BY + (t & 15), z = bz * BZ + (t >> 4);
+      if (x < g.nx && y < g.ny && z < g.nz) {
+        const uint32_t c = cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)];
+        p = c != kNone && moved[c] != 0;
+      }
+    }
+    const uint64_t m = __ballot(p);
+    if (i < slots && (lane & 15) == 0) inv[row] = (uint16_t)((m >> lane) & 0xFFFFu);
   }
-  if (ly == 0 || ly == BY - 1) {
-    const size_t yi = (size_t)b * 32 + (ly ? 16 : 0) + lz;
-    atomicOr(reinterpret_cast<uint32_t *>(A.yf) + (yi >> 1), (1u << lx) << ((yi & 1u) * 16u));
+}
+
+// Level 0 of an incremental pass, step 1: a site voxel changes when it is
+// invalid or holds a larger key than (0, s); such voxels are cleared and
+// flagged as changed (every writer stores the same values).
+__global__ void k_inc_site_a(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t v = sites[s];
+  if ((int64_t)v >= A.g.n) {
+    atomicOr(A.err, 1u);
+    return;
   }
-#pragma unroll
-  for (int k = 0; k < 7; ++k) mark_brick(A, bx, by, bz, k, 1u);
-  A.alive[1] = 1u;
+  const BrickPos p = brick_pos(A, v);
+  if (row_bit(A.inv, p) || A.dist[v] != 0u || A.cell[v] > s) {
+    A.cell[v] = kNone;
+    A.dist[v] = 0u;
+    or_row_bit(A.vis, p);
+  }
+}
+
+// Step 2: every site on a changed voxel takes part in the minimum; changed
+// site voxels form the frontier of level 0.
+__global__ void k_inc_site_b(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t v = sites[s];
+  if ((int64_t)v >= A.g.n) return;
+  const BrickPos p = brick_pos(A, v);
+  if (!row_bit(A.vis, p)) return;
+  atomicMin(&A.cell[v], s);
+  frontier0(A, p);
 }
 
 constexpr int kLvlThreads = 64;  // one wave per brick
 constexpr int kNewCap = 1024;    // new voxels per brick and level shared out through LDS
 
-// Level L: a voxel not reached yet is reached now when a same-band face
-// neighbour was reached at level L - 1; it takes the smallest id among those
-// neighbours (Eq. 1 with ties to the lower id).  One wave per brick: lane t
-// owns the four rows ly = t & 15, lz = 4 (t >> 4) + k (k = 0..3), so the y-
-// and z-neighbour rows inside the brick come from other lanes' registers,
-// and the rows beyond the brick's faces from the neighbours' packed face
-// words; every load of the brick's masks is issued at once.  The new voxels
-// are then listed in LDS and shared out one per lane, whatever row they are
-// in.  A brick that reached anything marks itself and its six neighbours
-// for level L + 1.
 // Ids of the six face neighbours of new voxel v, the sources among them
 // flagged by a0..a5 (x-, x+, y-, y+, z-, z+; at least one is set).  All six
 // loads are issued unconditionally so that they are in flight together; a
@@ -203,7 +307,48 @@ __device__ __forceinline__ void gather6(const uint32_t *cell, int64_t v, int64_t
   g[5] = cell[a5 ? n5 : f];
 }
 
-__device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *lst, uint32_t *dmp) {
+__device__ __forceinline__ uint32_t min_id6(const uint32_t m0, const uint32_t m1, const uint32_t m2, const uint32_t g[6]) {
+  uint32_t id = (m0 & 1u) ? g[0] : kNone;
+  id = min(id, ((m0 >> 16) & 1u) ? g[1] : kNone);
+  id = min(id, (m1 & 1u) ? g[2] : kNone);
+  id = min(id, ((m1 >> 16) & 1u) ? g[3] : kNone);
+  id = min(id, (m2 & 1u) ? g[4] : kNone);
+  id = min(id, ((m2 >> 16) & 1u) ? g[5] : kNone);
+  return id;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor(v, o, kWave));
+  return v;
+}
+
+// LDS of one level workgroup (one wave).
+struct LvlLds {
+  uint16_t lst[kNewCap];   // listed candidates: x | row << 4
+  uint32_t dmp[3 * kRows]; // per row: source directions of its candidates
+  uint32_t inv[kRows];     // incremental: invalid voxels of candidate rows
+  uint32_t acc[kRows];     // incremental: candidates that took a new key
+  uint32_t inj[kRows];     // incremental: kept voxels injected at this level
+};
+
+// Level L: a candidate is a voxel that has not changed yet in this pass and
+// has a same-band face neighbour in the frontier of level L - 1; its key
+// would be (L, smallest id among those neighbours).  In a full pass every
+// voxel is invalid and every candidate takes its key (Eq. 1 with ties to the
+// lower id).  In an incremental pass a kept candidate takes it only when it
+// is smaller than its own (distance, id).  One wave per brick: lane t owns
+// the four rows ly = t & 15, lz = 4 (t >> 4) + k (k = 0..3), so the y- and
+// z-neighbour rows inside the brick come from other lanes' registers, and
+// the rows beyond the brick's faces from the neighbours' packed face words;
+// every load of the brick's masks is issued at once.  Candidates are listed
+// in LDS and shared out one per lane, whatever row they are in.  The
+// frontier the brick writes for level L holds its changed voxels and, in an
+// incremental pass, its kept voxels of distance L that touch an invalid one;
+// when it is not empty the brick marks itself and its six neighbours for
+// level L + 1.
+template <bool INC>
+__device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
   const int t = threadIdx.x;
   const int ly = t & 15, g4 = (t >> 4) * 4;
   const size_t pin = (size_t)((L - 1) & 1), pout = (size_t)(L & 1);
@@ -221,7 +366,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
   const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby), bz = (int)(b / ((uint32_t)A.bg.nbx * A.bg.nby));
   const int64_t rb = (int64_t)b * kRows;
   const bool hym = ly == 0 && by > 0, hyp = ly == BY - 1 && by < A.bg.nby - 1;
-  uint32_t F[4], V[4], XM[4], XP[4], YM[4], YP[4], E[4][3];
+  uint32_t F[4], V[4], I[4], XM[4], XP[4], YM[4], YP[4], E[4][3];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = ly + 16 * (g4 + k);
@@ -229,6 +374,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
     for (int j = 0; j < 3; ++j) E[k][j] = A.eq[(rb + r) * 3 + j];
     F[k] = fin[rb + r];
     V[k] = A.vis[rb + r];
+    I[k] = INC ? (uint32_t)A.inv[rb + r] : 0xFFFFu;
     const unsigned long long xm = bx > 0 ? xin[(size_t)(b - 1) * 8 + 4 + k] : 0ull;
     const unsigned long long xp = bx < A.bg.nbx - 1 ? xin[(size_t)(b + 1) * 8 + k] : 0ull;
     XM[k] = (uint32_t)(xm >> t) & 1u;
@@ -239,7 +385,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
   const uint32_t ZM = (g4 == 0 && bz > 0) ? fin[(b - bsz) * kRows + 240 + ly] : 0u;
   const uint32_t ZP = (g4 == 12 && bz < A.bg.nbz - 1) ? fin[(b + bsz) * kRows + ly] : 0u;
   const uint32_t zlo = __shfl(F[3], lm16, kWave), zhi = __shfl(F[0], lp16, kWave);
-  uint32_t nw[4], c = 0;
+  uint32_t cand[4], c = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = ly + 16 * (g4 + k);
@@ -254,13 +400,36 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
     const uint32_t d0 = sxm & E[k][0] & 0xFFFFu, d1 = sxp & (E[k][0] >> 16);
     const uint32_t d2 = fym & E[k][1] & 0xFFFFu, d3 = fyp & (E[k][1] >> 16);
     const uint32_t d4 = fzm & E[k][2] & 0xFFFFu, d5 = fzp & (E[k][2] >> 16);
-    nw[k] = (d0 | d1 | d2 | d3 | d4 | d5) & ~V[k] & 0xFFFFu;
-    if (nw[k]) {
-      dmp[r] = d0 | (d1 << 16);
-      dmp[kRows + r] = d2 | (d3 << 16);
-      dmp[2 * kRows + r] = d4 | (d5 << 16);
+    cand[k] = (d0 | d1 | d2 | d3 | d4 | d5) & ~V[k] & 0xFFFFu;
+    if (cand[k]) {
+      S.dmp[r] = d0 | (d1 << 16);
+      S.dmp[kRows + r] = d2 | (d3 << 16);
+      S.dmp[2 * kRows + r] = d4 | (d5 << 16);
+      if (INC) S.inv[r] = I[k];
     }
-    c += (uint32_t)__popc(nw[k]);
+    c += (uint32_t)__popc(cand[k]);
+  }
+  // kept voxels of distance L that touch an invalid voxel join the frontier
+  uint32_t inj[4] = {0u, 0u, 0u, 0u};
+  if (INC && __builtin_amdgcn_readfirstlane(A.wake[b]) == L) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) S.inj[ly + 16 * (g4 + k)] = 0u;
+    __syncthreads();
+    const uint32_t cnt = A.bcnt[b];
+    const uint32_t *list = A.bnd + (size_t)b * (kRows * BX);
+    uint32_t nxt = kNone;
+    for (uint32_t i = t; i < cnt; i += kWave) {
+      const uint32_t e = list[i], d = e >> 12;
+      if (d == L)
+        atomicOr(&S.inj[(e & 0xFFFu) >> 4], 1u << (e & 15u));
+      else if (d > L)
+        nxt = min(nxt, d);
+    }
+    nxt = wave_min_u32(nxt);
+    if (t == 0) A.wake[b] = nxt;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) inj[k] = S.inj[ly + 16 * (g4 + k)] & ~V[k];
   }
   uint32_t inc = c;
 #pragma unroll
@@ -269,104 +438,128 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, uint16_t *ls
     if (t >= o) inc += v;
   }
   const uint32_t total = __shfl(inc, kWave - 1, kWave);
-  // nothing new: the frontier words of this parity stay stale, which is
-  // harmless (see above)
-  if (total == 0) return;
-  if (t < 7) mark_brick(A, bx, by, bz, t, L + 1);
-  if (t == 0) A.alive[(L + 1) % 3] = 1u;
   const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
-  if (total <= (uint32_t)kNewCap) {
+  uint32_t nw[4] = {0u, 0u, 0u, 0u};
+  if (total > 0 && total <= (uint32_t)kNewCap) {
     uint32_t p = inc - c;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      uint32_t bits = nw[k];
+      uint32_t bits = cand[k];
       const uint32_t r = (uint32_t)(ly + 16 * (g4 + k));
+      if (INC) S.acc[r] = 0u;
       while (bits) {
         const uint32_t x = (uint32_t)(__ffs(bits) - 1);
         bits &= bits - 1;
-        lst[p++] = (uint16_t)(x | (r << 4));
+        S.lst[p++] = (uint16_t)(x | (r << 4));
       }
     }
     __syncthreads();
-    // ids of the listed voxels, two per lane at a time
+    // keys of the listed voxels, two per lane at a time
     for (uint32_t e = t; e < total; e += 2 * kWave) {
       int64_t v[2];
-      uint32_t g[2][6], m[2][3];
+      uint32_t g[2][6], m[2][3], ob[2], od[2], oc[2], ri[2], xi[2];
       bool have[2];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const uint32_t ee = e + (uint32_t)u * kWave;
         have[u] = ee < total;
-        const uint32_t idx = lst[have[u] ? ee : 0u];
+        const uint32_t idx = S.lst[have[u] ? ee : 0u];
         const uint32_t r = idx >> 4, x = idx & 15u;
+        ri[u] = r;
+        xi[u] = x;
         v[u] = vb + x + sy * (int64_t)(r & 15u) + sz * (int64_t)(r >> 4);
-        m[u][0] = dmp[r] >> x;
-        m[u][1] = dmp[kRows + r] >> x;
-        m[u][2] = dmp[2 * kRows + r] >> x;
+        m[u][0] = S.dmp[r] >> x;
+        m[u][1] = S.dmp[kRows + r] >> x;
+        m[u][2] = S.dmp[2 * kRows + r] >> x;
         gather6(A.cell, v[u], sy, sz, m[u][0] & 1u, (m[u][0] >> 16) & 1u, m[u][1] & 1u, (m[u][1] >> 16) & 1u,
                 m[u][2] & 1u, (m[u][2] >> 16) & 1u, g[u]);
+        ob[u] = INC ? (S.inv[r] >> x) & 1u : 1u;
+        od[u] = 0u;
+        oc[u] = 0u;
+        if (!ob[u]) {  // a kept voxel: its own key
+          od[u] = A.dist[v[u]];
+          oc[u] = A.cell[v[u]];
+        }
       }
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        uint32_t id = (m[u][0] & 1u) ? g[u][0] : kNone;
-        id = min(id, ((m[u][0] >> 16) & 1u) ? g[u][1] : kNone);
-        id = min(id, (m[u][1] & 1u) ? g[u][2] : kNone);
-        id = min(id, ((m[u][1] >> 16) & 1u) ? g[u][3] : kNone);
-        id = min(id, (m[u][2] & 1u) ? g[u][4] : kNone);
-        id = min(id, ((m[u][2] >> 16) & 1u) ? g[u][5] : kNone);
-        if (have[u]) A.cell[v[u]] = id;
+        const uint32_t id = min_id6(m[u][0], m[u][1], m[u][2], g[u]);
+        const bool ok = ob[u] || L < od[u] || (L == od[u] && id < oc[u]);
+        if (have[u] && ok) {
+          A.cell[v[u]] = id;
+          A.dist[v[u]] = L;
+          if (INC) atomicOr(&S.acc[ri[u]], 1u << xi[u]);
+        }
       }
     }
-  } else {
-    // more new voxels than the list holds: each lane takes its own rows
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nw[k] = INC ? S.acc[ly + 16 * (g4 + k)] : cand[k];
+  } else if (total > 0) {
+    // more candidates than the list holds: each lane takes its own rows
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      uint32_t bits = nw[k];
+      uint32_t bits = cand[k];
       const int r = ly + 16 * (g4 + k);
       const int64_t base = vb + sy * (int64_t)(r & 15) + sz * (int64_t)(r >> 4);
-      const uint32_t m0 = dmp[r], m1 = dmp[kRows + r], m2 = dmp[2 * kRows + r];
+      const uint32_t m0 = S.dmp[r], m1 = S.dmp[kRows + r], m2 = S.dmp[2 * kRows + r];
       while (bits) {
         const int x = __ffs(bits) - 1;
         bits &= bits - 1;
         const int64_t v = base + x;
-        const uint32_t a0 = (m0 >> x) & 1u, a1 = (m0 >> (16 + x)) & 1u, a2 = (m1 >> x) & 1u;
-        const uint32_t a3 = (m1 >> (16 + x)) & 1u, a4 = (m2 >> x) & 1u, a5 = (m2 >> (16 + x)) & 1u;
         uint32_t gg[6];
-        gather6(A.cell, v, sy, sz, a0, a1, a2, a3, a4, a5, gg);
-        uint32_t id = a0 ? gg[0] : kNone;
-        id = min(id, a1 ? gg[1] : kNone);
-        id = min(id, a2 ? gg[2] : kNone);
-        id = min(id, a3 ? gg[3] : kNone);
-        id = min(id, a4 ? gg[4] : kNone);
-        id = min(id, a5 ? gg[5] : kNone);
-        A.cell[v] = id;
+        gather6(A.cell, v, sy, sz, (m0 >> x) & 1u, (m0 >> (16 + x)) & 1u, (m1 >> x) & 1u, (m1 >> (16 + x)) & 1u,
+                (m2 >> x) & 1u, (m2 >> (16 + x)) & 1u, gg);
+        const uint32_t id = min_id6(m0 >> x, m1 >> x, m2 >> x, gg);
+        bool ok = true;
+        if (INC && !((I[k] >> x) & 1u)) {
+          const uint32_t od = A.dist[v], oc = A.cell[v];
+          ok = L < od || (L == od && id < oc);
+        }
+        if (ok) {
+          A.cell[v] = id;
+          A.dist[v] = L;
+          nw[k] |= 1u << x;
+        }
       }
     }
   }
+  uint32_t out[4], any = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    out[k] = nw[k] | inj[k];
+    any |= out[k];
+  }
+  // nothing reached or injected: the frontier words of this parity stay
+  // stale, which is harmless (see above)
+  if (__ballot(any != 0u) == 0ull) return;
+  if (t < 7) mark_brick(A, bx, by, bz, t, L + 1);
+  if (t == 0) A.alive[(L + 1) % 3] = 1u;
   // this level's frontier: rows, and the packed faces the neighbours read
   unsigned long long xw = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = ly + 16 * (g4 + k);
     if (nw[k]) A.vis[rb + r] = (uint16_t)(V[k] | nw[k]);
-    fout[rb + r] = (uint16_t)nw[k];
-    const unsigned long long lo_k = __ballot(nw[k] & 1u), hi_k = __ballot((nw[k] >> 15) & 1u);
+    fout[rb + r] = (uint16_t)out[k];
+    const unsigned long long lo_k = __ballot(out[k] & 1u), hi_k = __ballot((out[k] >> 15) & 1u);
     if (t == k) xw = lo_k;
     if (t == 4 + k) xw = hi_k;
-    if (ly == 0) yout[(size_t)b * 32 + g4 + k] = (uint16_t)nw[k];
-    if (ly == BY - 1) yout[(size_t)b * 32 + 16 + g4 + k] = (uint16_t)nw[k];
+    if (ly == 0) yout[(size_t)b * 32 + g4 + k] = (uint16_t)out[k];
+    if (ly == BY - 1) yout[(size_t)b * 32 + 16 + g4 + k] = (uint16_t)out[k];
   }
   if (t < 8) xout[(size_t)b * 8 + t] = xw;
-  __syncthreads();  // the LDS list and masks are reused by the next brick
+  __syncthreads();  // the LDS lists and masks are reused by the next brick
 }
 
-// One BFS level per launch over the bricks marked for it.  Workgroup 0
-// records whether level L is alive and clears the flag of level L + 2 (level
-// L + 1 sets it), so launches may be enqueued past the last level: they find
-// no marked brick and return.
+// One BFS level per launch over the bricks marked for it (and, in an
+// incremental pass, the bricks that inject kept voxels at this level).
+// Workgroup 0 records whether level L is alive and clears the flag of level
+// L + 2 (level L + 1 sets it), so launches may be enqueued past the last
+// level: they find no marked brick and return.
+template <bool INC>
 __global__ __launch_bounds__(kLvlThreads) void k_bfs_level(BFSArgs A, uint32_t L) {
-  __shared__ uint16_t lst[kNewCap];
-  __shared__ uint32_t dmp[3 * kRows];
+  __shared__ LvlLds S;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     A.hist[L % kHistLen] = A.alive[L % 3];
     A.alive[(L + 2) % 3] = 0u;
@@ -378,9 +571,131 @@ __global__ __launch_bounds__(kLvlThreads) void k_bfs_level(BFSArgs A, uint32_t L
   for (int64_t i = blockIdx.x; i < 8 * per; i += gridDim.x) {
     const int64_t b = (i & 7) * per + (i >> 3);
     if (b >= A.bg.nbricks) continue;
-    if (__builtin_amdgcn_readfirstlane(act[b]) != L) continue;
-    bfs_brick(A, L, (uint32_t)b, lst, dmp);
+    bool go = __builtin_amdgcn_readfirstlane(act[b]) == L;
+    if (INC && !go) go = __builtin_amdgcn_readfirstlane(A.wake[b]) == L;
+    if (!go) continue;
+    bfs_brick<INC>(A, L, (uint32_t)b, S);
   }
+}
+
+// Incremental pass set-up: per brick, the kept voxels (not invalid, not yet
+// changed) with a same-band face neighbour that is invalid.  Those of
+// distance 0 (sites) go into the frontier of level 0 at once; the others are
+// listed as (distance << 12 | x + 16 row), and the brick's wake level is
+// their smallest distance.  One wave per brick, rows as in the level kernel.
+__global__ __launch_bounds__(kLvlThreads) void k_bnd_build(BFSArgs A) {
+  __shared__ uint16_t lst[kRows * BX];
+  __shared__ uint32_t cnt_s;
+  const int t = threadIdx.x;
+  const int ly = t & 15, g4 = (t >> 4) * 4;
+  const int lm1 = (t + kWave - 1) & (kWave - 1), lp1 = (t + 1) & (kWave - 1);
+  const int lm16 = (t + kWave - 16) & (kWave - 1), lp16 = (t + 16) & (kWave - 1);
+  const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
+  const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
+  for (int64_t b = blockIdx.x; b < A.bg.nbricks; b += gridDim.x) {
+    const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby),
+              bz = (int)(b / ((int64_t)A.bg.nbx * A.bg.nby));
+    const int64_t rb = b * kRows;
+    const bool hym = ly == 0 && by > 0, hyp = ly == BY - 1 && by < A.bg.nby - 1;
+    uint32_t I[4], V[4], XM[4], XP[4], YM[4], YP[4], E[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = ly + 16 * (g4 + k);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) E[k][j] = A.eq[(rb + r) * 3 + j];
+      I[k] = A.inv[rb + r];
+      V[k] = A.vis[rb + r];
+      XM[k] = bx > 0 ? ((uint32_t)A.inv[(b - 1) * kRows + r] >> 15) & 1u : 0u;
+      XP[k] = bx < A.bg.nbx - 1 ? (uint32_t)A.inv[(b + 1) * kRows + r] & 1u : 0u;
+      YM[k] = hym ? A.inv[(b - bsy) * kRows + 15 + 16 * (g4 + k)] : 0u;
+      YP[k] = hyp ? A.inv[(b + bsy) * kRows + 16 * (g4 + k)] : 0u;
+    }
+    const uint32_t ZM = (g4 == 0 && bz > 0) ? A.inv[(b - bsz) * kRows + 240 + ly] : 0u;
+    const uint32_t ZP = (g4 == 12 && bz < A.bg.nbz - 1) ? A.inv[(b + bsz) * kRows + ly] : 0u;
+    const uint32_t zlo = __shfl(I[3], lm16, kWave), zhi = __shfl(I[0], lp16, kWave);
+    uint32_t bm[4], c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t up = __shfl(I[k], lm1, kWave), dn = __shfl(I[k], lp1, kWave);
+      const uint32_t fym = ly > 0 ? up : YM[k];
+      const uint32_t fyp = ly < BY - 1 ? dn : YP[k];
+      const uint32_t fzm = k > 0 ? I[k - 1] : (g4 > 0 ? zlo : ZM);
+      const uint32_t fzp = k < 3 ? I[k + 1] : (g4 < 12 ? zhi : ZP);
+      const uint32_t sxm = (I[k] << 1) | XM[k];
+      const uint32_t sxp = (I[k] >> 1) | (XP[k] << 15);
+      const uint32_t adj = (sxm & E[k][0] & 0xFFFFu) | (sxp & (E[k][0] >> 16)) | (fym & E[k][1] & 0xFFFFu) |
+                           (fyp & (E[k][1] >> 16)) | (fzm & E[k][2] & 0xFFFFu) | (fzp & (E[k][2] >> 16));
+      bm[k] = adj & ~I[k] & ~V[k] & 0xFFFFu;
+      c += (uint32_t)__popc(bm[k]);
+    }
+    uint32_t inc = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t v = __shfl_up(inc, o, kWave);
+      if (t >= o) inc += v;
+    }
+    const uint32_t total = __shfl(inc, kWave - 1, kWave);
+    if (total == 0) {
+      if (t == 0) {
+        A.bcnt[b] = 0u;
+        A.wake[b] = kNone;
+      }
+      continue;
+    }
+    uint32_t p = inc - c;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t bits = bm[k];
+      const uint32_t r = (uint32_t)(ly + 16 * (g4 + k));
+      while (bits) {
+        const uint32_t x = (uint32_t)(__ffs(bits) - 1);
+        bits &= bits - 1;
+        lst[p++] = (uint16_t)(x | (r << 4));
+      }
+    }
+    if (t == 0) cnt_s = 0u;
+    __syncthreads();
+    const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
+    uint32_t *list = A.bnd + (size_t)b * (kRows * BX);
+    uint32_t nxt = kNone;
+    for (uint32_t e = t; e < total; e += kWave) {
+      const uint32_t idx = lst[e];
+      const uint32_t r = idx >> 4, x = idx & 15u;
+      const uint32_t d = A.dist[vb + x + sy * (int64_t)(r & 15u) + sz * (int64_t)(r >> 4)];
+      if (d == 0u) {
+        BrickPos q;
+        q.b = (uint32_t)b;
+        q.row = r;
+        q.lx = x;
+        q.bx = bx;
+        q.by = by;
+        q.bz = bz;
+        frontier0(A, q);
+      } else if (d > kMaxBndLevel) {
+        atomicOr(A.err, 4u);
+      } else {
+        list[atomicAdd(&cnt_s, 1u)] = (d << 12) | idx;
+        nxt = min(nxt, d);
+      }
+    }
+    nxt = wave_min_u32(nxt);
+    __syncthreads();
+    if (t == 0) {
+      A.bcnt[b] = cnt_s;
+      A.wake[b] = nxt;
+    }
+    __syncthreads();
+  }
+}
+
+// Smallest wake level over all bricks (the next level at which some brick
+// injects kept voxels), atomically into *out, which holds NONE beforehand.
+__global__ __launch_bounds__(256) void k_wake_min(const uint32_t *__restrict__ wake, int64_t nb, uint32_t *out) {
+  uint32_t m = kNone;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x)
+    m = min(m, wake[i]);
+  m = wave_min_u32(m);
+  if (lane_id() == 0 && m != kNone) atomicMin(out, m);
 }
 
 // ----------------------------------------------------------------------------
@@ -489,12 +804,15 @@ __device__ __forceinline__ double move_len(uint32_t a, uint32_t b, Geom g) {
   return sqrt(dx * dx + dy * dy + dz * dz);
 }
 
+// moved[s] records whether site s moved (the next Voronoi pass is
+// incremental over the moved sites).
 __global__ void k_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Sums sums, uint32_t *sites, double *ds,
-                       uint32_t *fb_list, uint32_t *fb_cnt) {
+                       uint8_t *moved, uint32_t *fb_list, uint32_t *fb_cnt) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   uint64_t M = sums.M[s];
   uint32_t old = sites[s];
+  moved[s] = 0;
   if (M == 0) {
     if (ds) ds[s] = 0.0;
     return;
@@ -503,6 +821,7 @@ __global__ void k_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Su
   uint32_t q = (uint32_t)(qx + (uint64_t)g.nx * (qy + (uint64_t)g.ny * qz));
   if (cell[q] == s) {
     sites[s] = q;
+    moved[s] = q != old;
     if (ds) ds[s] = move_len(old, q, g);
   } else {
     uint32_t pos = atomicAdd(fb_cnt, 1u);
@@ -512,8 +831,8 @@ __global__ void k_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Su
 
 // Exact nearest in-cell voxel by growing cubes; one workgroup per site.
 __global__ __launch_bounds__(256) void k_snap_fallback(const uint32_t *__restrict__ cell, Geom g, Sums sums,
-                                                       uint32_t *sites, double *ds, const uint32_t *fb_list,
-                                                       const uint32_t *fb_cnt) {
+                                                       uint32_t *sites, double *ds, uint8_t *moved,
+                                                       const uint32_t *fb_list, const uint32_t *fb_cnt) {
   __shared__ uint64_t r_hi[256], r_lo[256];
   __shared__ uint32_t r_v[256];
   const int t = threadIdx.x;
@@ -582,6 +901,7 @@ __global__ __launch_bounds__(256) void k_snap_fallback(const uint32_t *__restric
       uint32_t old = sites[s];
       if (bestv != kNone) {
         sites[s] = bestv;
+        moved[s] = bestv != old;
         if (ds) ds[s] = move_len(old, bestv, g);
       } else if (ds) {
         ds[s] = 0.0;
@@ -641,9 +961,13 @@ struct CvtWork {
   uint32_t *eq;
   uint16_t *fr, *vis, *yf;
   unsigned long long *xf;
-  uint32_t *act, *ctl;  // brick marks; ctl[0..2] level alive flags, ctl[3] error bits
+  uint32_t *act, *ctl;  // brick marks; ctl[0..2] level alive flags, ctl[3] error bits, ctl[4] next wake level
   uint32_t *fb_list, *fb_cnt, *err;
   uint32_t *hist;
+  uint32_t *dist;            // [N] hop distance of every reached voxel
+  uint16_t *inv;             // [nbricks][256] invalid voxels (incremental passes)
+  uint32_t *bnd, *bcnt, *wake;  // kept-voxel lists per brick, their counts and wake levels
+  uint8_t *moved;            // [S] site moved in the last update
   unsigned long long *sums;  // 4 x S
   double *ds, *mean, *mean_part;
 };
@@ -662,13 +986,14 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   VTGrid bg = vt_grid(g);
   int64_t nb = bg.nbricks;
   size_t s1 = S ? S : 1;
+  const bool inc = iters > 0;  // incremental passes follow the first one
   auto eq = a.template take<uint32_t>(nb * kRows * 3);
   auto fr = a.template take<uint16_t>(2 * nb * kRows);
   auto vis = a.template take<uint16_t>(nb * kRows);
   auto xf = a.template take<unsigned long long>(2 * nb * 8);
   auto yf = a.template take<uint16_t>(2 * nb * 32);
   auto act = a.template take<uint32_t>(2 * nb);
-  auto ctl = a.template take<uint32_t>(4);
+  auto ctl = a.template take<uint32_t>(8);
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
   auto sums = a.template take<unsigned long long>(4 * s1);
@@ -676,6 +1001,12 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto mean = a.template take<double>(iters > 0 ? iters : 1);
   auto mpart = a.template take<double>(kMeanParts);
   auto hist = a.template take<uint32_t>(kHistLen);
+  auto dist = a.template take<uint32_t>(g.n);
+  auto moved = a.template take<uint8_t>(s1);
+  auto inv = a.template take<uint16_t>(inc ? nb * kRows : 1);
+  auto bnd = a.template take<uint32_t>(inc ? nb * kRows * BX : 1);
+  auto bcnt = a.template take<uint32_t>(inc ? nb : 1);
+  auto wake = a.template take<uint32_t>(inc ? nb : 1);
   if (W) {
     W->eq = eq;
     W->fr = fr;
@@ -692,6 +1023,12 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
     W->mean = mean;
     W->mean_part = mpart;
     W->hist = hist;
+    W->dist = dist;
+    W->moved = moved;
+    W->inv = inc ? inv : nullptr;
+    W->bnd = inc ? bnd : nullptr;
+    W->bcnt = inc ? bcnt : nullptr;
+    W->wake = inc ? wake : nullptr;
   }
 }
 
@@ -718,7 +1055,8 @@ int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t
 // Driver state of one Lloyd run: the number of levels of the previous pass,
 // which sizes the first batch of level launches of the next one.
 struct VTState {
-  uint32_t levels = 0;
+  uint32_t levels = 0;      // levels of the last full pass
+  uint32_t inc_levels = 0;  // levels of the first run of the last incremental pass
 };
 
 // Benchmark timing of the level kernel: while enabled, an event pair on the
@@ -762,8 +1100,12 @@ int32_t timed_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> &ev, ui
   return LSRVT_OK;
 }
 
-// Voxels never reached (components without a site) get LSRVT_NONE.
-__global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint16_t *__restrict__ vis, Geom g, VTGrid bg,
+// Voxels never reached get LSRVT_NONE: in a full pass those of components
+// without a site; in an incremental pass the invalid voxels not reached
+// again (none: a moved site stays in its component).
+template <bool INC>
+__global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint16_t *__restrict__ vis,
+                                                             const uint16_t *__restrict__ inv, Geom g, VTGrid bg,
                                                              uint32_t *__restrict__ cell) {
   const int t = threadIdx.x, ly = t & 15, lz = t >> 4;
   for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
@@ -772,6 +1114,7 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint16_t *__r
     if (y >= g.ny || z >= g.nz) continue;
     const int w = g.nx - x0 < BX ? g.nx - x0 : BX;
     uint32_t miss = ~vis[b * kRows + t] & ((1u << w) - 1u);
+    if (INC) miss &= inv[b * kRows + t];
     const int64_t base = brick_row_base(g, x0, y, z);
     while (miss) {
       const int x = __ffs(miss) - 1;
@@ -797,12 +1140,30 @@ int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s
   return LSRVT_OK;
 }
 
-// One restricted Voronoi pass: level 0 at the sites, then launches of the
-// level kernel, enqueued in batches sized by the previous pass (sites move
-// little between passes) until the device reports an empty level.
-int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
-               hipStream_t s) {
-  VTGrid bg = vt_grid(g);
+BFSArgs bfs_args(const Geom &g, uint32_t *cell, CvtWork &W) {
+  BFSArgs A;
+  A.g = g;
+  A.bg = vt_grid(g);
+  A.eq = W.eq;
+  A.fr = W.fr;
+  A.vis = W.vis;
+  A.xf = W.xf;
+  A.yf = W.yf;
+  A.cell = cell;
+  A.dist = W.dist;
+  A.act = W.act;
+  A.alive = W.ctl;
+  A.hist = W.hist;
+  A.err = W.err;
+  A.inv = W.inv;
+  A.bnd = W.bnd;
+  A.bcnt = W.bcnt;
+  A.wake = W.wake;
+  return A;
+}
+
+// Clears the per-pass search state (frontiers, reached rows, marks, flags).
+int32_t clear_pass(const VTGrid &bg, CvtWork &W, hipStream_t s) {
   int32_t rc;
   // 16-bit and 64-bit arrays are cleared as 32-bit words (even lengths)
   if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(W.fr), bg.nbricks * kRows, 0u, s))) return rc;
@@ -811,32 +1172,29 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   if ((rc = fill<uint32_t>(reinterpret_cast<uint32_t *>(W.yf), bg.nbricks * 32, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.ctl, 3, 0u, s))) return rc;
-  BFSArgs A;
-  A.g = g;
-  A.bg = bg;
-  A.eq = W.eq;
-  A.fr = W.fr;
-  A.vis = W.vis;
-  A.xf = W.xf;
-  A.yf = W.yf;
-  A.cell = cell;
-  A.act = W.act;
-  A.alive = W.ctl;
-  A.hist = W.hist;
-  A.err = W.err;
-  if (S) {
-    hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g.n, cell);
-    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
-    LSRVT_LAUNCHED();
-  }
+  return LSRVT_OK;
+}
+
+// Launches of the level kernel from level 1 on, enqueued in batches (the
+// first one sized by the previous pass of the same kind, since sites move
+// little between passes); after each batch the host reads the flags.  An
+// incremental pass whose frontier dies out before every brick has injected
+// its kept voxels continues at the smallest pending wake level.  Sets *redo
+// when a kept-voxel list could not hold a level (the caller then runs a full
+// pass).
+template <bool INC>
+int32_t run_levels(const Geom &g, const BFSArgs &A, CvtWork &W, VTState &st, hipStream_t s, bool *redo) {
+  const VTGrid &bg = A.bg;
   const int64_t max_level = g.n + 2;
-  const unsigned cap = vt_grid_cap(bg);
   const unsigned lgrid = (unsigned)std::min<int64_t>(8 * ((bg.nbricks + 7) / 8), 65528);
+  const unsigned wgrid = (unsigned)std::min<int64_t>((bg.nbricks + 255) / 256, 1024);
   uint32_t L = 0;  // levels enqueued
-  int batch = st.levels ? (int)st.levels + 4 : 16;
-  bool more = S != 0;
-  uint32_t c[4] = {0, 0, 0, 0};
-  while (more) {
+  uint32_t run_end = 0;  // last level of the first run of consecutive launches
+  bool jumped = false;
+  int batch = INC ? (int)std::max<uint32_t>(8, st.inc_levels + 2) : (st.levels ? (int)st.levels + 4 : 16);
+  int32_t rc;
+  uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  while (true) {
     // one event pair around a batch of back-to-back level launches (while
     // timing is on): the launches of a batch run without gaps
     const bool timed = timer().on;
@@ -844,22 +1202,38 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     if (timed && (rc = timed_begin(s, ev))) return rc;
     for (int i = 0; i < batch; ++i) {
       ++L;
-      hipLaunchKernelGGL(k_bfs_level, dim3(lgrid), dim3(kLvlThreads), 0, s, A, L);
+      hipLaunchKernelGGL(k_bfs_level<INC>, dim3(lgrid), dim3(kLvlThreads), 0, s, A, L);
       LSRVT_LAUNCHED();
     }
     if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
+    if (INC) {
+      if ((rc = fill<uint32_t>(W.ctl + 4, 1, kNone, s))) return rc;
+      hipLaunchKernelGGL(k_wake_min, dim3(wgrid), dim3(256), 0, s, W.wake, bg.nbricks, W.ctl + 4);
+      LSRVT_LAUNCHED();
+    }
     LSRVT_HIP(hipMemcpyAsync(c, W.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
     LSRVT_HIP(hipStreamSynchronize(s));
     const uint32_t e = c[3];
+    if (INC && (e & 4u)) {
+      *redo = true;
+      return LSRVT_OK;
+    }
     if (e & 1u) return LSRVT_EINVAL;
     if (e) return LSRVT_EDEVICE;
-    more = c[(L + 1) % 3] != 0;  // bricks marked for the next level?
+    if (!jumped) run_end = L;
+    if (c[(L + 1) % 3] == 0) {  // no brick marked for the next level
+      if (!INC || c[4] == kNone) break;
+      // nothing marked until the next wake level: go there
+      if ((rc = fill<uint32_t>(W.ctl, 3, 0u, s))) return rc;
+      L = c[4] - 1;
+      jumped = true;
+    }
     if ((int64_t)L > max_level) return LSRVT_EDEVICE;
     batch = 8;
   }
-  const uint32_t launched = L;
-  // the number of levels sizes the first batch of the next pass
-  const uint32_t nl = std::min<uint32_t>(L + 1, kHistLen);
+  // the length of the first run of alive levels sizes the first batch of
+  // the next pass of the same kind
+  const uint32_t nl = std::min<uint32_t>(run_end + 1, kHistLen);
   std::vector<uint32_t> h(nl, 0);
   if (nl > 1) {
     LSRVT_HIP(hipMemcpyAsync(h.data(), W.hist, sizeof(uint32_t) * nl, hipMemcpyDeviceToHost, s));
@@ -867,17 +1241,90 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   }
   uint32_t levels = 0;
   while (levels + 1 < nl && h[levels + 1]) ++levels;
-  st.levels = levels;
-  hipLaunchKernelGGL(k_vt_unreached, dim3(cap), dim3(kVTThreads), 0, s, W.vis, g, bg, cell);
+  (INC ? st.inc_levels : st.levels) = levels;
+  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
+  if (debug_levels) fprintf(stderr, "[lsrvt] vt %s levels=%u last=%u\n", INC ? "inc" : "full", levels, L);
+  return LSRVT_OK;
+}
+
+// One restricted Voronoi pass over every voxel: level 0 at the sites, then
+// the level launches until the device reports an empty level.
+int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
+               hipStream_t s) {
+  VTGrid bg = vt_grid(g);
+  int32_t rc;
+  if ((rc = clear_pass(bg, W, s))) return rc;
+  BFSArgs A = bfs_args(g, cell, W);
+  if (S) {
+    hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g.n, cell);
+    hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
+    LSRVT_LAUNCHED();
+    bool redo = false;
+    if ((rc = run_levels<false>(g, A, W, st, s, &redo))) return rc;
+  }
+  hipLaunchKernelGGL(k_vt_unreached<false>, dim3(vt_grid_cap(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
     timer().passes += 1;
     timer().voxels_per_pass = g.n;
   }
+  return LSRVT_OK;
+}
+
+// One incremental pass after an update: cell and dist hold the previous
+// pass's keys and W.moved flags the sites that moved.  The result is that of
+// a full pass with the new sites (see the incremental-pass notes above).
+int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
+                   hipStream_t s) {
+  if (!W.inv || S == 0) return run_vt(g, sites, S, cell, W, st, s);
+  VTGrid bg = vt_grid(g);
+  int32_t rc;
+  if ((rc = clear_pass(bg, W, s))) return rc;
+  BFSArgs A = bfs_args(g, cell, W);
+  const int64_t slots = bg.nbricks * kRows * BX;
+  const unsigned rgrid = (unsigned)std::min<int64_t>((slots + kVTThreads - 1) / kVTThreads, 65535);
+  hipLaunchKernelGGL(k_inc_reset, dim3(rgrid), dim3(kVTThreads), 0, s, cell, W.moved, g, bg, W.inv);
+  hipLaunchKernelGGL(k_inc_site_a, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
+  hipLaunchKernelGGL(k_inc_site_b, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
+  hipLaunchKernelGGL(k_bnd_build, dim3((unsigned)std::min<int64_t>(bg.nbricks, 65535)), dim3(kLvlThreads), 0, s, A);
+  LSRVT_LAUNCHED();
+  bool redo = false;
+  if ((rc = run_levels<true>(g, A, W, st, s, &redo))) return rc;
+  if (redo) {
+    if ((rc = fill<uint32_t>(W.err, 1, 0u, s))) return rc;
+    return run_vt(g, sites, S, cell, W, st, s);
+  }
+  hipLaunchKernelGGL(k_vt_unreached<true>, dim3(vt_grid_cap(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, cell);
+  LSRVT_LAUNCHED();
   static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
-  if (debug_levels) {
-    fprintf(stderr, "[lsrvt] vt levels=%u launches=%u\n", levels, launched);
+  if (debug_levels) {  // sizes of the pass: moved sites, invalid and changed voxels, listed kept voxels
+    std::vector<uint8_t> mv(S);
+    std::vector<uint16_t> iv(bg.nbricks * kRows), vs(bg.nbricks * kRows);
+    std::vector<uint32_t> bc(bg.nbricks);
+    LSRVT_HIP(hipMemcpyAsync(mv.data(), W.moved, S, hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipMemcpyAsync(iv.data(), W.inv, iv.size() * 2, hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipMemcpyAsync(vs.data(), W.vis, vs.size() * 2, hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipMemcpyAsync(bc.data(), W.bcnt, bc.size() * 4, hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    uint64_t nm = 0, ni = 0, nv = 0, nbd = 0, nbk = 0;
+    for (uint8_t m : mv) nm += m != 0;
+    for (size_t i = 0; i < iv.size(); ++i) {
+      ni += __builtin_popcount(iv[i]);
+      nv += __builtin_popcount(vs[i]);
+    }
+    for (uint32_t c : bc) {
+      nbd += c;
+      nbk += c != 0;
+    }
+    fprintf(stderr, "[lsrvt]   moved=%llu invalid=%llu changed=%llu kept-listed=%llu in %llu bricks\n",
+            (unsigned long long)nm, (unsigned long long)ni, (unsigned long long)nv, (unsigned long long)nbd,
+            (unsigned long long)nbk);
+  }
+  if (timer().on) {
+    std::lock_guard<std::mutex> lk(timer().mu);
+    timer().passes += 1;
+    timer().voxels_per_pass = g.n;
   }
   return LSRVT_OK;
 }
@@ -901,9 +1348,10 @@ int32_t run_update(const uint32_t *cell, const Geom &g, const uint16_t *w, uint3
   Sums sm{W.sums, W.sums + S, W.sums + 2 * (size_t)S, W.sums + 3 * (size_t)S};
   const int64_t ntiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
   hipLaunchKernelGGL(k_centroid, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(256), 0, s, cell, w, g, S, sm);
-  hipLaunchKernelGGL(k_snap, dim3((S + 255) / 256), dim3(256), 0, s, cell, g, S, sm, sites, ds, W.fb_list, W.fb_cnt);
-  hipLaunchKernelGGL(k_snap_fallback, dim3(S < 1024 ? S : 1024), dim3(256), 0, s, cell, g, sm, sites, ds, W.fb_list,
+  hipLaunchKernelGGL(k_snap, dim3((S + 255) / 256), dim3(256), 0, s, cell, g, S, sm, sites, ds, W.moved, W.fb_list,
                      W.fb_cnt);
+  hipLaunchKernelGGL(k_snap_fallback, dim3(S < 1024 ? S : 1024), dim3(256), 0, s, cell, g, sm, sites, ds, W.moved,
+                     W.fb_list, W.fb_cnt);
   LSRVT_LAUNCHED();
   return LSRVT_OK;
 }
@@ -979,7 +1427,9 @@ extern "C" int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrv
   if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
   for (int32_t t = 0; t <= iters; ++t) {
-    if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
+    // the first pass covers every voxel; later ones only what the moved sites change
+    if (t == 0 && (rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
+    if (t > 0 && (rc = run_vt_inc(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
     if (t == iters) break;
     if ((rc = run_update(d_cell, g, d_weights, d_sites, n_sites, W.ds, W, s))) return rc;
     hipLaunchKernelGGL(k_mean_ds_part, dim3(kMeanParts), dim3(256), 0, s, W.ds, n_sites, W.mean_part);

@@ -5,12 +5,14 @@ in the launch configuration bench.py times.
 Labels are compared with the oracle element by element for the isobands,
 the components and a 1-update Lloyd loop (the oracle finishes those in
 seconds); the per-cell statistics of that loop's cells within the stated
-tolerances (the merges to components and bands are checked against the
-oracle on smaller volumes).  The 20-update loop bench.py times is checked through
-properties that hold at any size: every labelled voxel's cell is a site of
-its own component, exactly the components without a site stay unlabelled,
-every site lies in its own cell (or a co-located lower id owns its voxel),
-and repeated runs give identical bits.
+tolerances.  The 20-update loop bench.py times is compared bit for bit with
+the oracle's run of Algorithm 1 on the same inputs, through the SHA-256
+digests of its cells, sites and site components that
+``tests/golden/make_golden.py`` wrote from the oracle (160 s on one host
+core); its statistics at every level against the oracle's: cells computed
+here from the (digest-checked) labels, components and bands stored by the
+same script.  Properties that hold at any size and run-to-run determinism
+are checked too.
 """
 import numpy as np
 import pytest
@@ -18,6 +20,7 @@ import pytest
 import oracle
 import paper_2208_06970_amd as L
 import synth
+from tests import golden_util as G
 from tests.gpu_util import banner, dev, host
 from tests.test_gpu_stats import _check_level
 
@@ -94,3 +97,33 @@ def test_fullsize_bench_loop_properties(workload):
     ok = (owner == np.arange(len(sites))) | (sites[owner] == sites)
     assert np.all(ok)
     assert runs[0].mean_ds[-1] < runs[0].mean_ds[0]
+
+
+def test_fullsize_bench_loop_against_oracle(workload):
+    """The bench loop (20 updates) against the oracle's stored run, and the
+    statistics of its cells, components and bands."""
+    wl, band, cc, seeds = workload
+    doc, arrays = G.load("fourier256_t20")
+    assert G.sha(seeds) == doc["seeds_sha256"], "inputs differ from the ones the oracle ran on"
+    banner(f"fullsize: Lloyd loop, {wl.iters} updates, against the oracle's digests")
+    b = dev(band)
+    g = L.lsrvt_components(b, wl.n_bands)
+    r = L.lsrvt_cvt(b, g.comp, dev(seeds), dev(wl.weights), wl.iters)
+    cell = host(r.cell, np.uint32)
+    G.check_labels(cell, doc, "fourier 256^3 T=20")
+    assert G.sha(host(r.sites, np.uint32)) == doc["sites_sha256"]
+    assert G.sha(host(r.site_comp, np.uint32)) == doc["site_comp_sha256"]
+    np.testing.assert_allclose(r.mean_ds, doc["mean_ds"], rtol=1e-12, atol=0)
+    banner("fullsize: statistics of the 20-update cells, components and bands")
+    x = np.ascontiguousarray(wl.variables)
+    cs, gs, bs = L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, g.comp_band, g.n_comp, wl.n_bands, dev(x),
+                                   dev(wl.edges), cov=True)
+    # the labels are the oracle's (their digest matched): its cell statistics
+    _check_level("cell", cs, oracle.stats(cell, len(seeds), x, wl.edges, cov=True), x.shape[0])
+    G.exact_digests_match(gs, doc["comp_exact_sha256"], "component")
+    G.exact_digests_match(bs, doc["band_exact_sha256"], "band")
+    rows = arrays["comp_rows"]
+    _check_level("component (largest 256)", L.LevelStats(*(None if getattr(gs, k) is None else getattr(gs, k)[rows]
+                                                         for k in ("n", "mean", "m2", "vmin", "vmax", "hist", "cov"))),
+                 G.level_stats(arrays, "comp"), x.shape[0])
+    _check_level("band", bs, G.level_stats(arrays, "band"), x.shape[0])

@@ -46,14 +46,39 @@ def _check_level(name, got, want, m, exact_only=False, fp64=False):
     vb = 1e-5 * var_w[nz]
     assert np.all(verr <= vb), f"{name} var: worst ratio {np.max(verr / np.maximum(vb, 1e-300))}"
     assert np.all(host(got.mean)[~nz] == 0) and np.all(host(got.m2)[~nz] == 0)
+    worst = {"mean": _ratio(err, bound), "var": _ratio(verr, vb)}
+    lit = {"mean": _rel(mean[nz], want.mean[nz]), "var": _rel(var_g[nz], var_w[nz])}
     if want.cov is not None:
         cg = host(got.cov).astype(np.float64) / nn[:, None]
         cw = want.cov / nn[:, None]
+        worst["cov"] = lit["cov"] = 0.0
         for p, (j, k) in enumerate(_pairs(m)):
             b = 1e-5 * np.sqrt(var_w[:, j] * var_w[:, k])
             e = np.abs(cg[:, p] - cw[:, p])
             assert np.all(e[nz] <= b[nz]), f"{name} cov({j},{k}): worst {np.max(e[nz] / np.maximum(b[nz], 1e-300))}"
+            worst["cov"] = max(worst["cov"], _ratio(e[nz], b[nz]))
+            lit["cov"] = max(lit["cov"], _rel(cg[nz, p], cw[nz, p]))
+    # worst error as a fraction of the tolerance, and the plain relative error
+    print(f"[precision] {name}: of tolerance " + " ".join(f"{k} {v:.3g}" for k, v in worst.items())
+          + "; relative " + " ".join(f"{k} {v:.3g}" for k, v in lit.items()), flush=True)
     return True
+
+
+def _ratio(err, bound):
+    """Largest err / bound (0 where both are 0)."""
+    if err.size == 0:
+        return 0.0
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(bound > 0, err / np.where(bound > 0, bound, 1.0), np.where(err > 0, np.inf, 0.0))
+    return float(np.max(r))
+
+
+def _rel(got, want):
+    """Largest |got - want| / |want| over the entries with want != 0."""
+    m = want != 0
+    if not np.any(m):
+        return 0.0
+    return float(np.max(np.abs(got[m] - want[m]) / np.abs(want[m])))
 
 
 def _run(shape, seed, m, B, cov, T=3, kind="fourier", rho=128.0, drop_comp_seeds=False, var_gen=None):
