@@ -81,6 +81,7 @@ struct BFSArgs {
   uint32_t *bnd;       // [nbricks][4096] kept voxels next to an invalid one: dist << 12 | x + 16 row
   uint32_t *bcnt;      // [nbricks] entries of bnd
   uint32_t *wake;      // [nbricks] next level at which the brick injects kept voxels (NONE: none)
+  unsigned long long *dbg;  // diagnostics (LSRVT_DEBUG_LEVELS only): brick visits, candidates, ...
 };
 
 // Entries of the kept-voxel lists hold the level in 20 bits; a pass whose
@@ -185,8 +186,12 @@ __device__ void frontier0(const BFSArgs &A, const BrickPos &p) {
     const size_t yi = (size_t)p.b * 32 + (ly ? 16 : 0) + lz;
     atomicOr(reinterpret_cast<uint32_t *>(A.yf) + (yi >> 1), (1u << p.lx) << ((yi & 1u) * 16u));
   }
+  // the brick, and the face neighbours whose shared face the voxel lies on
+  const uint32_t lz2 = p.row >> 4, ly2 = p.row & 15u;
+  const bool on[7] = {true, p.lx == 0, p.lx == BX - 1, ly2 == 0, ly2 == BY - 1, lz2 == 0, lz2 == BZ - 1};
 #pragma unroll
-  for (int k = 0; k < 7; ++k) mark_brick(A, p.bx, p.by, p.bz, k, 1u);
+  for (int k = 0; k < 7; ++k)
+    if (on[k]) mark_brick(A, p.bx, p.by, p.bz, k, 1u);
   A.alive[1] = 1u;
 }
 
@@ -440,6 +445,14 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
   const uint32_t total = __shfl(inc, kWave - 1, kWave);
   const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
   uint32_t nw[4] = {0u, 0u, 0u, 0u};
+  if (A.dbg && t == 0) {
+    atomicAdd(&A.dbg[0], 1ull);
+    atomicAdd(&A.dbg[1], (unsigned long long)total);
+    if (total > (uint32_t)kNewCap) {
+      atomicAdd(&A.dbg[2], 1ull);
+      atomicAdd(&A.dbg[3], (unsigned long long)total);
+    }
+  }
   if (total > 0 && total <= (uint32_t)kNewCap) {
     uint32_t p = inc - c;
 #pragma unroll
@@ -530,10 +543,39 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
     out[k] = nw[k] | inj[k];
     any |= out[k];
   }
+  if (A.dbg) {
+    uint32_t na = 0, ni = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      na += (uint32_t)__popc(nw[k]);
+      ni += (uint32_t)__popc(inj[k]);
+    }
+    na = wave_sum_u32(na);
+    ni = wave_sum_u32(ni);
+    if (t == 0) {
+      atomicAdd(&A.dbg[4], (unsigned long long)na);
+      atomicAdd(&A.dbg[5], (unsigned long long)ni);
+    }
+  }
   // nothing reached or injected: the frontier words of this parity stay
   // stale, which is harmless (see above)
   if (__ballot(any != 0u) == 0ull) return;
-  if (t < 7) mark_brick(A, bx, by, bz, t, L + 1);
+  // the brick works at level L + 1, and so does each face neighbour whose
+  // shared face the frontier touches (only through it can the frontier
+  // reach that neighbour's voxels)
+  uint32_t fxm = 0, fxp = 0, fym = 0, fyp = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    fxm |= out[k] & 1u;
+    fxp |= (out[k] >> 15) & 1u;
+    fym |= ly == 0 ? out[k] : 0u;
+    fyp |= ly == BY - 1 ? out[k] : 0u;
+  }
+  const uint32_t fzm = g4 == 0 ? out[0] : 0u, fzp = g4 == 12 ? out[3] : 0u;
+  const uint32_t mk = 1u | (__ballot(fxm != 0u) ? 2u : 0u) | (__ballot(fxp != 0u) ? 4u : 0u) |
+                      (__ballot(fym != 0u) ? 8u : 0u) | (__ballot(fyp != 0u) ? 16u : 0u) |
+                      (__ballot(fzm != 0u) ? 32u : 0u) | (__ballot(fzp != 0u) ? 64u : 0u);
+  if (t < 7 && ((mk >> t) & 1u)) mark_brick(A, bx, by, bz, t, L + 1);
   if (t == 0) A.alive[(L + 1) % 3] = 1u;
   // this level's frontier: rows, and the packed faces the neighbours read
   unsigned long long xw = 0;
@@ -993,7 +1035,7 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto xf = a.template take<unsigned long long>(2 * nb * 8);
   auto yf = a.template take<uint16_t>(2 * nb * 32);
   auto act = a.template take<uint32_t>(2 * nb);
-  auto ctl = a.template take<uint32_t>(8);
+  auto ctl = a.template take<uint32_t>(8 + 2 * 8);  // flags, then diagnostic counters
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
   auto sums = a.template take<unsigned long long>(4 * s1);
@@ -1159,6 +1201,8 @@ BFSArgs bfs_args(const Geom &g, uint32_t *cell, CvtWork &W) {
   A.bnd = W.bnd;
   A.bcnt = W.bcnt;
   A.wake = W.wake;
+  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
+  A.dbg = debug_levels ? reinterpret_cast<unsigned long long *>(W.ctl + 8) : nullptr;
   return A;
 }
 
@@ -1243,7 +1287,14 @@ int32_t run_levels(const Geom &g, const BFSArgs &A, CvtWork &W, VTState &st, hip
   while (levels + 1 < nl && h[levels + 1]) ++levels;
   (INC ? st.inc_levels : st.levels) = levels;
   static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
-  if (debug_levels) fprintf(stderr, "[lsrvt] vt %s levels=%u last=%u\n", INC ? "inc" : "full", levels, L);
+  if (debug_levels) {
+    unsigned long long d[8];
+    LSRVT_HIP(hipMemcpyAsync(d, W.ctl + 8, sizeof(d), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    fprintf(stderr, "[lsrvt] vt %s levels=%u last=%u visits=%llu cand=%llu big=%llu bigcand=%llu new=%llu inj=%llu\n",
+            INC ? "inc" : "full", levels, L, d[0], d[1], d[2], d[3], d[4], d[5]);
+    if ((rc = fill<unsigned long long>(reinterpret_cast<unsigned long long *>(W.ctl + 8), 8, 0ull, s))) return rc;
+  }
   return LSRVT_OK;
 }
 
@@ -1360,7 +1411,7 @@ int32_t begin(CvtWork &W, const Geom &g, hipStream_t s) {
   int32_t rc;
   VTGrid bg = vt_grid(g);
   if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.ctl, 4, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl, 8 + 2 * 8, 0u, s))) return rc;
   return LSRVT_OK;
 }
 
@@ -1469,3 +1520,4 @@ extern "C" int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *p
   T.passes = 0;
   return LSRVT_OK;
 }
+
