@@ -416,6 +416,11 @@ def lsrvt_aggregate(cell, sites, site_comp, comp_band, n_comp: int, n_bands: int
     return out
 
 
+def lsrvt_components_workspace_bytes(shape, n_bands: int) -> int:
+    """Workspace bytes of lsrvt_components for a volume of `shape` (nz, ny, nx)."""
+    return int(_lib().lsrvt_components_workspace(_dims(shape), int(n_bands)))
+
+
 def lsrvt_cvt_workspace_bytes(shape, n_sites: int, iters: int) -> int:
     """Workspace bytes of lsrvt_cvt for a volume of `shape` (nz, ny, nx)."""
     return int(_lib().lsrvt_cvt_workspace(_dims(shape), int(n_sites), max(int(iters), 0)))

@@ -967,8 +967,10 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     hipLaunchKernelGGL(k_agg_items, dim3((S + 255) / 256), dim3(256), 0, s, W.lay.cnt_rank, S, W.items);
     LSRVT_LAUNCHED();
     if ((rc = ScanU32::run(W.items, S, W.item_off, W.scratch, W.scratch_bytes, s))) return rc;
-    LSRVT_HIP(hipMemcpyAsync(&n_items, W.item_off + S, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    LSRVT_HIP(hipStreamSynchronize(s));
+    {
+      const int32_t rc_ = read_words(W.item_off + S, 1, &n_items, s);
+      if (rc_) return rc_;
+    }
     if ((int64_t)n_items > W.item_cap) return LSRVT_EDEVICE;  // cannot happen: the capacity is an upper bound
   }
 

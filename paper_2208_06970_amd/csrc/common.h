@@ -162,6 +162,10 @@ inline int32_t fill(T *p, int64_t n, T v, hipStream_t s) {
   return LSRVT_OK;
 }
 
+// Reads n <= 64 words of device memory to the host after the work queued on
+// s (synchronises s).  Implemented in readback.hip.
+int32_t read_words(const uint32_t *d_src, int n, uint32_t *h_out, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // Stable counting sort of a u32 index list by an 8-bit key, used for the
 // band ordering of component roots and (per digit) for sorting sites by

@@ -396,8 +396,10 @@ extern "C" int32_t lsrvt_components(const uint8_t *d_band, lsrvt_dims dims, int3
                      L.roots, L.root_band);
   LSRVT_LAUNCHED();
   uint32_t n_comp = 0;
-  LSRVT_HIP(hipMemcpyAsync(&n_comp, L.tile_off + ntiles, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+  {
+    const int32_t rc_ = read_words(L.tile_off + ntiles, 1, &n_comp, s);
+    if (rc_) return rc_;
+  }
   *h_n_comp = n_comp;
   st = StableSort8::run(L.root_band, n_comp, L.pos, L.bucket, rest, rest_bytes, s);
   if (st) return st;

@@ -446,6 +446,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
   const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
   uint32_t nw[4] = {0u, 0u, 0u, 0u};
   if (A.dbg && t == 0) {
+    atomicAdd(reinterpret_cast<uint32_t *>(A.dbg + 8) + (L % kHistLen), 1u);
     atomicAdd(&A.dbg[0], 1ull);
     atomicAdd(&A.dbg[1], (unsigned long long)total);
     if (total > (uint32_t)kNewCap) {
@@ -1035,7 +1036,7 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto xf = a.template take<unsigned long long>(2 * nb * 8);
   auto yf = a.template take<uint16_t>(2 * nb * 32);
   auto act = a.template take<uint32_t>(2 * nb);
-  auto ctl = a.template take<uint32_t>(8 + 2 * 8);  // flags, then diagnostic counters
+  auto ctl = a.template take<uint32_t>(8 + 2 * 8 + kHistLen);  // flags, diagnostic counters, visits per level
   auto fbl = a.template take<uint32_t>(s1);
   auto fbc = a.template take<uint32_t>(4);
   auto sums = a.template take<unsigned long long>(4 * s1);
@@ -1255,8 +1256,7 @@ int32_t run_levels(const Geom &g, const BFSArgs &A, CvtWork &W, VTState &st, hip
       hipLaunchKernelGGL(k_wake_min, dim3(wgrid), dim3(256), 0, s, W.wake, bg.nbricks, W.ctl + 4);
       LSRVT_LAUNCHED();
     }
-    LSRVT_HIP(hipMemcpyAsync(c, W.ctl, sizeof(c), hipMemcpyDeviceToHost, s));
-    LSRVT_HIP(hipStreamSynchronize(s));
+    if ((rc = read_words(W.ctl, 8, c, s))) return rc;
     const uint32_t e = c[3];
     if (INC && (e & 4u)) {
       *redo = true;
@@ -1293,7 +1293,13 @@ int32_t run_levels(const Geom &g, const BFSArgs &A, CvtWork &W, VTState &st, hip
     LSRVT_HIP(hipStreamSynchronize(s));
     fprintf(stderr, "[lsrvt] vt %s levels=%u last=%u visits=%llu cand=%llu big=%llu bigcand=%llu new=%llu inj=%llu\n",
             INC ? "inc" : "full", levels, L, d[0], d[1], d[2], d[3], d[4], d[5]);
-    if ((rc = fill<unsigned long long>(reinterpret_cast<unsigned long long *>(W.ctl + 8), 8, 0ull, s))) return rc;
+    std::vector<uint32_t> pv(std::min<uint32_t>(L + 1, kHistLen));
+    LSRVT_HIP(hipMemcpyAsync(pv.data(), W.ctl + 24, pv.size() * 4, hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    fprintf(stderr, "[lsrvt]   visits per level:");
+    for (size_t i = 1; i < pv.size(); ++i) fprintf(stderr, " %u", pv[i]);
+    fprintf(stderr, "\n");
+    if ((rc = fill<uint32_t>(W.ctl + 8, 2 * 8 + kHistLen, 0u, s))) return rc;
   }
   return LSRVT_OK;
 }
@@ -1383,8 +1389,8 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
 // Errors a run reported on the device (synchronises).
 int32_t vt_errors(CvtWork &W, hipStream_t s) {
   uint32_t e = 0;
-  LSRVT_HIP(hipMemcpyAsync(&e, W.err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+  int32_t rc = read_words(W.err, 1, &e, s);
+  if (rc) return rc;
   if (e & 1u) return LSRVT_EINVAL;
   if (e) return LSRVT_EDEVICE;
   return LSRVT_OK;
@@ -1411,7 +1417,7 @@ int32_t begin(CvtWork &W, const Geom &g, hipStream_t s) {
   int32_t rc;
   VTGrid bg = vt_grid(g);
   if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.ctl, 8 + 2 * 8, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl, 8 + 2 * 8 + kHistLen, 0u, s))) return rc;
   return LSRVT_OK;
 }
 

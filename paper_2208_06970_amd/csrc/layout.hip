@@ -293,8 +293,10 @@ int32_t layout_voxels(const uint32_t *cell, const Geom &g, uint32_t S, LayoutWor
   LSRVT_LAUNCHED();
   if ((rc = ScanU32::run(W.tile_nd, T, W.pair_off, W.scratch, W.scratch_bytes, s))) return rc;
   uint32_t P = 0;
-  LSRVT_HIP(hipMemcpyAsync(&P, W.pair_off + T, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+  {
+    const int32_t rc_ = read_words(W.pair_off + T, 1, &P, s);
+    if (rc_) return rc_;
+  }
   if ((int64_t)P > W.pair_cap) return LSRVT_EDEVICE;  // cannot happen: the capacity is an upper bound
   // 2. the pairs, in tile order
   hipLaunchKernelGGL(k_lay_small<kPassPairs>, dim3(grid), dim3(kWave), 0, s, A);
@@ -421,8 +423,10 @@ extern "C" int32_t lsrvt_layout(const uint32_t *d_cell, lsrvt_dims dims, const u
                      d_comp_off, d_band_off);
   LSRVT_LAUNCHED();
   uint32_t placed = 0;
-  LSRVT_HIP(hipMemcpyAsync(&placed, W.cell_off + n_sites, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+  {
+    const int32_t rc_ = read_words(W.cell_off + n_sites, 1, &placed, s);
+    if (rc_) return rc_;
+  }
   if (h_n_placed) *h_n_placed = placed;
   return LSRVT_OK;
 }

@@ -630,8 +630,10 @@ void los_layout(C &cv, const Geom &g, uint32_t S, LosWork *W) {
 
 int32_t read_err(const uint32_t *d_err, hipStream_t s) {
   uint32_t e = 0;
-  LSRVT_HIP(hipMemcpyAsync(&e, d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+  {
+    const int32_t rc_ = read_words(d_err, 1, &e, s);
+    if (rc_) return rc_;
+  }
   return e ? LSRVT_EINVAL : LSRVT_OK;
 }
 
@@ -684,8 +686,10 @@ int32_t los_vt(const uint32_t *d_comp, const Geom &g, const int32_t *d_q, const 
       }
       LSRVT_LAUNCHED();
       uint32_t alive[kSweepBatch];
-      LSRVT_HIP(hipMemcpyAsync(alive, W.ctl + 2, sizeof(alive), hipMemcpyDeviceToHost, s));
-      LSRVT_HIP(hipStreamSynchronize(s));
+      {
+        const int32_t rc_ = read_words(W.ctl + 2, kSweepBatch, alive, s);
+        if (rc_) return rc_;
+      }
       int j = 0;
       while (j < kSweepBatch && alive[j]) ++j;
       if (j < kSweepBatch) {  // sweep j changed nothing: the stage has converged

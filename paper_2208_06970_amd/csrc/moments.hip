@@ -424,8 +424,10 @@ int32_t merge_groups(const uint32_t *goff, uint32_t G, const MergeIn &in, const 
   LSRVT_LAUNCHED();
   if ((rc = ScanU32::run(W.nchunk, G, W.choff, W.scratch, W.scratch_bytes, s))) return rc;
   uint32_t J = 0;
-  LSRVT_HIP(hipMemcpyAsync(&J, W.choff + G, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  LSRVT_HIP(hipStreamSynchronize(s));
+  {
+    const int32_t rc_ = read_words(W.choff + G, 1, &J, s);
+    if (rc_) return rc_;
+  }
   hipLaunchKernelGGL(k_mom_jobs, dim3((G + 255) / 256), dim3(256), 0, s, goff, G, W.choff, W.job_lo, W.job_hi);
   const unsigned grid1 = (unsigned)std::min<int64_t>(((int64_t)J + 3) / 4, 65535);
   if (J)

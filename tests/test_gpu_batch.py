@@ -103,10 +103,14 @@ def test_batch_fullsize_64_volumes():
     """The 64-volume batch at full size (edges 32..192, cubes and 2:1:1 boxes,
     3..10 isovalues, T = 15, 8 variables, 32-bin histograms, covariance; 87 M
     voxels) on 4 streams: every job bit-identical to its calls alone; bands
-    and components of every job equal the oracle's; cells, sites and cell
-    statistics equal the oracle's on the jobs of at most 2^20 voxels (the
-    larger ones through properties that hold at any size)."""
+    and components of every job equal the oracle's; cells, sites and site
+    components of every job equal the oracle's run of Algorithm 1 (SHA-256
+    digests written from the oracle by tests/golden/make_golden.py); cell
+    statistics of every job against the oracle's on the (digest-checked)
+    labels."""
+    from tests import golden_util as G
     from tests.test_gpu_stats import _check_level
+    gold, _ = G.load("batch64_t15")
     specs = synth.batch_specs(64, 3)
     data = []
     for shape, seed, k in specs:
@@ -138,19 +142,12 @@ def test_batch_fullsize_64_volumes():
         cell = host(j.cell, np.uint32)
         sites = host(j.sites, np.uint32)[:S]
         site_comp = host(j.site_comp, np.uint32)[:S]
-        if d["f"].size <= (1 << 20):
-            want = oracle.cvt(d["cc"].comp, d["seeds"], d["w"], 15)
-            np.testing.assert_array_equal(cell, want.cell, err_msg=f"job {i}")
-            np.testing.assert_array_equal(sites, want.sites, err_msg=f"job {i}")
-            _check_level(f"job {i} cells", j.stats[0], oracle.stats(want.cell, S, d["x"], d["edges"], cov=True), 8)
-            n_oracle += 1
-        else:
-            cf, comp = cell.ravel(), d["cc"].comp.ravel()
-            lab = cf != oracle.NONE_ID
-            np.testing.assert_array_equal(site_comp[cf[lab]], comp[lab])
-            seeded = np.zeros(d["cc"].n_comp, dtype=bool)
-            seeded[site_comp] = True
-            np.testing.assert_array_equal(lab, seeded[comp])
-            owner = cf[sites]
-            assert np.all((owner == np.arange(S)) | (sites[owner] == sites))
+        g = gold["jobs"][i]
+        assert list(d["f"].shape) == g["shape"] and G.sha(d["seeds"]) == g["seeds_sha256"], f"job {i} inputs"
+        G.check_labels(cell, g, f"job {i}")
+        assert G.sha(sites) == g["sites_sha256"], f"job {i} sites"
+        assert G.sha(site_comp) == g["site_comp_sha256"], f"job {i} site components"
+        # the labels are the oracle's (their digest matched): its cell statistics
+        _check_level(f"job {i} cells", j.stats[0], oracle.stats(cell, S, d["x"], d["edges"], cov=True), 8)
+        n_oracle += 1
     print(f"jobs checked against the oracle's Lloyd loop: {n_oracle} of {len(jobs)}")
