@@ -149,6 +149,23 @@ int32_t lsrvt_update(const uint32_t *d_cell, lsrvt_dims dims, const uint16_t *d_
                      size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * lsrvt_update without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops that forbid
+ * allocation).  Same arguments, semantics and results as lsrvt_update; its
+ * scratch (per-site sums, fallback list, moved flags: 37 bytes per site) is
+ * a fixed device array inside the library, one per GPU, held until the
+ * process ends.  Allocates nothing and does not synchronise.
+ * Limit: n_sites <= LSRVT_UPDATE_NOALLOC_MAX_SITES, else ELIMIT (nothing is
+ * launched).  Every call on one GPU shares that GPU's scratch, so calls that
+ * overlap on one GPU (different streams, or host threads) race: serialise
+ * them.  The scratch keeps the last call's contents; each call clears what
+ * it needs itself.
+ */
+#define LSRVT_UPDATE_NOALLOC_MAX_SITES (1u << 18)
+int32_t lsrvt_update_noalloc(const uint32_t *d_cell, lsrvt_dims dims, const uint16_t *d_weights,
+                             uint32_t *d_sites, uint32_t n_sites, double *d_ds, void *stream);
+
+/* ------------------------------------------------------------------------
  * The Lloyd loop of Algorithm 1 with a fixed number of updates:
  * sites_0 = seeds; for t < iters: cells_t = VT(sites_t),
  * sites_{t+1} = update(cells_t); the output cells are VT(sites_iters).

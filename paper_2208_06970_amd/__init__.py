@@ -33,7 +33,7 @@ STATS_COV = 2
 
 EXPORTS = (
     "lsrvt_status_string", "lsrvt_version", "lsrvt_isobands", "lsrvt_components_workspace",
-    "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt_workspace", "lsrvt_cvt",
+    "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_update_noalloc", "lsrvt_cvt_workspace", "lsrvt_cvt",
     "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
     "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed_workspace", "lsrvt_seed",
     "lsrvt_comoments_workspace", "lsrvt_comoments", "lsrvt_los_workspace", "lsrvt_los_vt", "lsrvt_los_update",
@@ -106,6 +106,7 @@ def _lib():
         lib.lsrvt_components.argtypes = [P, Dims, i32, P, u32, P, P, P, P, P, P, S, P]
         lib.lsrvt_vt.argtypes = [P, Dims, P, u32, P, P, S, P]
         lib.lsrvt_update.argtypes = [P, Dims, P, P, u32, P, P, S, P]
+        lib.lsrvt_update_noalloc.argtypes = [P, Dims, P, P, u32, P, P]
         lib.lsrvt_cvt_workspace.argtypes = [Dims, u32, i32]
         lib.lsrvt_cvt_workspace.restype = S
         lib.lsrvt_cvt.argtypes = [P, P, Dims, P, u32, P, i32, P, P, P, P, P, S, P]
@@ -137,7 +138,8 @@ def _lib():
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
-        for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_cvt",
+        for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_update_noalloc",
+                     "lsrvt_cvt",
                      "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed",
                      "lsrvt_comoments", "lsrvt_los_vt", "lsrvt_los_update", "lsrvt_los_cvt",
                      "lsrvt_timing_enable", "lsrvt_timing_read"):
@@ -310,6 +312,28 @@ def lsrvt_update(cell, sites, weights=None, ds=None, ws: Workspace | None = None
     code = lib.lsrvt_update(_ptr(cell), dims, _ptr(weights), _ptr(sites), sites.numel(), _ptr(ds), wptr, wbytes,
                             _stream(stream))
     _check(code, "lsrvt_update")
+    return sites, ds
+
+
+UPDATE_NOALLOC_MAX_SITES = 1 << 18
+
+
+def lsrvt_update_noalloc(cell, sites, weights=None, ds=None, stream=None):
+    """lsrvt_update without a workspace (the library's fixed per-GPU scratch;
+    at most UPDATE_NOALLOC_MAX_SITES sites).  ``ds`` must be given by callers
+    that cannot allocate; returns (sites, ds)."""
+    torch = _torch()
+    _need(cell, torch.int32, "lsrvt_update_noalloc")
+    _need(sites, torch.int32, "lsrvt_update_noalloc")
+    if weights is not None:
+        _need(weights, torch.int16, "lsrvt_update_noalloc")
+    lib = _lib()
+    dims = _dims(cell.shape)
+    if ds is None:
+        ds = torch.empty(sites.numel(), dtype=torch.float64, device=cell.device)
+    code = lib.lsrvt_update_noalloc(_ptr(cell), dims, _ptr(weights), _ptr(sites), sites.numel(), _ptr(ds),
+                                    _stream(stream))
+    _check(code, "lsrvt_update_noalloc")
     return sites, ds
 
 

@@ -1527,3 +1527,67 @@ extern "C" int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *p
   return LSRVT_OK;
 }
 
+// ----------------------------------------------------------------------------
+// The site update for callers that cannot allocate device memory (code under
+// graph capture, serving loops that forbid allocation): its scratch (per-site
+// uint64 sums, the fallback list and counter, the moved flags) lives in a
+// file-scope device array of fixed size, one copy per GPU, held until the
+// process ends.  Host code never passes the array's name to a kernel: its
+// device address is looked up once per device (with that device current)
+// and kept.
+namespace lsrvt {
+
+constexpr uint32_t kNoAllocSites = LSRVT_UPDATE_NOALLOC_MAX_SITES;
+constexpr size_t kNoAllocSums = (size_t)4 * kNoAllocSites * sizeof(unsigned long long);
+constexpr size_t kNoAllocList = (size_t)kNoAllocSites * sizeof(uint32_t);
+constexpr size_t kNoAllocBytes = kNoAllocSums + kNoAllocList + 256 + kNoAllocSites;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+struct ScratchTable {
+  std::mutex mu;
+  std::vector<unsigned char *> ptr;  // device address of `scratch` per device (nullptr: not looked up)
+};
+
+ScratchTable &scratch_table() {
+  static ScratchTable t;
+  return t;
+}
+
+int32_t scratch_ptr(unsigned char **out) {
+  int dev = 0;
+  LSRVT_HIP(hipGetDevice(&dev));
+  ScratchTable &T = scratch_table();
+  std::lock_guard<std::mutex> lk(T.mu);
+  if ((size_t)dev >= T.ptr.size()) T.ptr.resize((size_t)dev + 1, nullptr);
+  if (!T.ptr[dev]) {
+    void *p = nullptr;
+    LSRVT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return LSRVT_EDEVICE;
+    T.ptr[dev] = static_cast<unsigned char *>(p);
+  }
+  *out = T.ptr[dev];
+  return LSRVT_OK;
+}
+
+}  // namespace
+}  // namespace lsrvt
+
+extern "C" int32_t lsrvt_update_noalloc(const uint32_t *d_cell, lsrvt_dims dims, const uint16_t *d_weights,
+                                        uint32_t *d_sites, uint32_t n_sites, double *d_ds, void *stream) {
+  Geom g;
+  int32_t rc = make_geom(dims, g);
+  if (rc) return rc;
+  if (!d_cell || (n_sites && !d_sites)) return LSRVT_EINVAL;
+  if (n_sites > kNoAllocSites) return LSRVT_ELIMIT;
+  unsigned char *base = nullptr;
+  if ((rc = scratch_ptr(&base))) return rc;
+  CvtWork W{};
+  W.sums = reinterpret_cast<unsigned long long *>(base);
+  W.fb_list = reinterpret_cast<uint32_t *>(base + kNoAllocSums);
+  W.fb_cnt = reinterpret_cast<uint32_t *>(base + kNoAllocSums + kNoAllocList);
+  W.moved = base + kNoAllocSums + kNoAllocList + 256;
+  return run_update(d_cell, g, d_weights, d_sites, n_sites, d_ds, W, as_stream(stream));
+}
