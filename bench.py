@@ -6,34 +6,37 @@ T + 1 restricted geodesic Voronoi passes) -> statistics of every cell merged to
 components and bands.  The initial sites are an input of the Lloyd loop; they
 are drawn once before timing from the (deterministic) components.
 
-Default workload: the 256^3 turbulence-like Fourier field (8 isovalues at
-quantiles, |grad f| saliency weights as uint16, one site per 4096
-weight-scaled voxels, 20 updates, 8 statistics variables with 32-bin
-histograms and the full 8x8 covariance).
+Default workload (the largest configuration that fits one GPU): the
+combustion-shaped 1024 x 512 x 512 volume, a thin wrinkled flame sheet
+standing in for the paper's DNS flame data (10 isovalues of the mixture
+fraction Z, |grad T| saliency weights as uint16, one site per 4096
+weight-scaled voxels, 30 updates, 18 statistics variables (Z, T, 16 species)
+with 32-bin histograms and the full 18 x 18 covariance).
 
 value = voxels * T / step time, in Gvoxels/s per Lloyd iteration, with the
 whole step (isobands, components, final pass and statistics included) in the
 denominator.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--flame | --batch | --serve]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+                       [--fourier | --batch | --serve]
 
-The main line also carries, timed on their own outside the step, the
-on-device stratified initial sites of the same volume ("seeding"), the
-joint moments up to fourth order of the step's cells ("comoments") and the
-Lloyd loop with the Euclidean line-of-sight tessellation and the ray-clamped
-site update on the same components, sites and T ("los").
+The main line also carries, as extra keys, the 256^3 Fourier workload's step
+("fourier256"), the 64-volume batch through lsrvt_batch_run against one job
+at a time ("batch") and a short Poisson serving run against serial plain
+launches ("serve"), unless --no-extras.
 
-Three more modes print their own JSON line instead of the main one:
-  --flame   the combustion-shaped 1024 x 512 x 512 volume (10 isovalues of
-            the mixture fraction, |grad T| weights, 30 updates, 18 variables
-            with 32-bin histograms and the 18 x 18 covariance), whole step;
+Modes that print their own JSON line instead of the main one:
+  --fourier the 256^3 Fourier workload (8 isovalues, |grad f| weights, 20
+            updates, 8 variables), with the joint moments, on-device seeding
+            and line-of-sight Lloyd loop timed beside it;
   --batch   64 independent Fourier volumes (edges 32..192, cubes and 2:1:1
-            boxes, 3..10 isovalues, 15 updates) through lsrvt_batch_run on
-            several streams, against the same jobs run one at a time;
-  --serve   a Poisson stream of jobs (edges 64..192 per axis, 3..12
-            isovalues, 10..30 updates, 4..8 variables) through the serving
-            loop with HBM-footprint admission, against one slot; reports
-            p50/p99 latency and throughput per arrival rate.
+            boxes, 3..10 isovalues, 15 updates) through lsrvt_batch_run,
+            against the same jobs run one at a time;
+  --serve   a Poisson stream of jobs of the serving configuration's sizes
+            (edges 64..512 per axis, 3..12 isovalues, 10..30 updates, 4..16
+            variables) through the serving loop with HBM-footprint admission,
+            against serial plain launches; p50/p99 latency and throughput per
+            arrival rate.
 """
 from __future__ import annotations
 
@@ -50,7 +53,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 VT_BYTES_PER_VOXEL = 5           # one Voronoi pass must read the band (1 B) and write the cell (4 B)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bfs_level_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 CVT_SOURCE = os.path.join(ROOT, "paper_2208_06970_amd", "csrc", "cvt.hip")
 
 
@@ -63,11 +66,12 @@ def _source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic_per_launch():
-    """HBM bytes per launch of the Voronoi level kernel from committed rocprofv3 counters,
-    or None when they are missing or the kernel source changed since."""
+def _traffic_per_launch(workload: str):
+    """HBM bytes per launch of the Voronoi level kernel on `workload` from the
+    committed rocprofv3 counter summary, or None when it is missing or the
+    kernel source changed since the counters were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(PROFILES, f"k_bfs_level_traffic_{workload}.json")) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -76,35 +80,224 @@ def _traffic_per_launch():
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, seeds, T_sample=2):
-    """The oracle as it stands, single-threaded, on the same volume with
-    T_sample updates (a bounded sample of the step)."""
-    import oracle
-    import numpy as np
-    t0 = time.perf_counter()
-    band = oracle.bands(wl.field, wl.iso)
-    cc = oracle.components(band, wl.n_bands)
-    r = oracle.cvt(cc.comp, seeds, wl.weights, T_sample)
-    S = len(seeds)
-    oracle.stats(r.cell, S, wl.variables, wl.edges, cov=True)
-    comp_unit = np.where(r.cell == oracle.NONE_ID, oracle.NONE_ID, r.site_comp[np.minimum(r.cell, S - 1)])
-    oracle.stats(comp_unit.astype(np.uint32), cc.n_comp, wl.variables, wl.edges, cov=True)
-    band_unit = np.where(r.cell == oracle.NONE_ID, oracle.NONE_ID, band.astype(np.uint32))
-    oracle.stats(band_unit.astype(np.uint32), wl.n_bands, wl.variables, wl.edges, cov=True)
-    dt = time.perf_counter() - t0
-    n = wl.field.size
+def _host_cpu():
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
             model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n * T_sample / dt / 1e9, "unit": "Gvoxels/s per Lloyd iteration", "cores": 1,
-            "kind": "oracle", "seconds": round(dt, 3), "host_cpu": model,
-            "host_threads": len(os.sched_getaffinity(0)),
-            "sample": f"same {wl.field.shape[2]}x{wl.field.shape[1]}x{wl.field.shape[0]} volume, full pipeline "
-                      f"(isobands, components, Lloyd loop, three-level statistics) with {T_sample} updates "
-                      f"instead of {wl.iters}; single-threaded C"}
+    return model
+
+
+def cpu_baseline(field, iso, weights, variables, edges, rho, seed, iters, sample_desc, T_sample=2):
+    """The oracle as it stands, single-threaded, on a bounded sample: every
+    phase timed on its own (isobands, components, T_sample + 1 Voronoi passes,
+    T_sample updates, three levels of statistics), the per-voxel rate of a
+    step with `iters` updates formed from the per-phase times (the fixed
+    phases counted once, the Voronoi pass iters + 1 times and the update iters
+    times, as in the GPU step)."""
+    import numpy as np
+    import oracle
+    import synth
+    t = {}
+    t0 = time.perf_counter()
+    band = oracle.bands(field, iso)
+    t["isobands"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cc = oracle.components(band, len(iso) + 1)
+    t["components"] = time.perf_counter() - t0
+    sites = synth.flame_sites(cc.comp, cc.n_comp, weights, rho, seed)
+    t_vt, t_up = [], []
+    s = sites.copy()
+    for k in range(T_sample + 1):
+        t0 = time.perf_counter()
+        cell = oracle.vt(cc.comp, s)
+        t_vt.append(time.perf_counter() - t0)
+        if k == T_sample:
+            break
+        t0 = time.perf_counter()
+        s, _ = oracle.update(cell, s, weights)
+        t_up.append(time.perf_counter() - t0)
+    S = len(sites)
+    site_comp = cc.comp.ravel()[sites]
+    t0 = time.perf_counter()
+    oracle.stats(cell, S, variables, edges, cov=True)
+    cu = np.where(cell == oracle.NONE_ID, oracle.NONE_ID, site_comp[np.minimum(cell, S - 1)]).astype(np.uint32)
+    oracle.stats(cu, cc.n_comp, variables, edges, cov=True)
+    bu = np.where(cell == oracle.NONE_ID, oracle.NONE_ID, band.astype(np.uint32))
+    oracle.stats(bu, len(iso) + 1, variables, edges, cov=True)
+    t["statistics"] = time.perf_counter() - t0
+    t["vt_pass"] = float(np.mean(t_vt))
+    t["update"] = float(np.mean(t_up))
+    step = t["isobands"] + t["components"] + (iters + 1) * t["vt_pass"] + iters * t["update"] + t["statistics"]
+    n = field.size
+    return {"value": n * iters / step / 1e9, "unit": "Gvoxels/s per Lloyd iteration", "cores": 1, "kind": "oracle",
+            "seconds": round(sum(v for k, v in t.items() if k not in ("vt_pass", "update")) + sum(t_vt) + sum(t_up), 3),
+            "phase_seconds": {k: round(v, 4) for k, v in t.items()},
+            "lloyd_iter_gvox_s": round(n / (t["vt_pass"] + t["update"]) / 1e9, 6),
+            "host_cpu": _host_cpu(), "host_threads": len(os.sched_getaffinity(0)),
+            "sample": sample_desc + f"; {T_sample} updates timed per phase, the step formed for T={iters}; "
+                                    "single-threaded C"}
+
+
+class Step:
+    """One whole step of the hot path on device-resident inputs, with
+    per-phase hipEvent timing."""
+
+    def __init__(self, f, iso, n_bands, sd, w, iters, x, e):
+        import torch
+        self.f, self.iso, self.n_bands, self.sd, self.w, self.iters, self.x, self.e = f, iso, n_bands, sd, w, iters, x, e
+        self.ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        self.ph = [0.0] * 4
+        self.n = 0
+
+    def __call__(self, record):
+        import torch
+        import paper_2208_06970_amd as L
+        if record:
+            self.ev[0].record()
+        b, _ = L.lsrvt_isobands(self.f, self.iso)
+        if record:
+            self.ev[1].record()
+        c = L.lsrvt_components(b, self.n_bands)
+        if record:
+            self.ev[2].record()
+        r = L.lsrvt_cvt(b, c.comp, self.sd, self.w, self.iters, want_mean_ds=False)
+        if record:
+            self.ev[3].record()
+        L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, c.comp_band, c.n_comp, self.n_bands, self.x, self.e, cov=True)
+        if record:
+            self.ev[4].record()
+            torch.cuda.synchronize()
+            for k in range(4):
+                self.ph[k] += self.ev[k].elapsed_time(self.ev[k + 1])
+            self.n += 1
+        return r, c
+
+    def phases(self):
+        return {k: round(v / max(self.n, 1), 4) for k, v in zip(("isobands", "components", "lloyd", "aggregate"),
+                                                                 self.ph)}
+
+
+def timed_steps(step, steps, warmup, label):
+    """Warm-up, then exactly `steps` timed steps bracketed by synchronisations;
+    also the Voronoi level kernel's own time (hipEvents on its stream)."""
+    import torch
+    import paper_2208_06970_amd as L
+    for i in range(warmup):
+        step(False)
+        _log(f"{label}: warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    L.lsrvt_timing_read()                      # discard anything recorded so far
+    L.lsrvt_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(True)
+        _log(f"{label}: step {i + 1}/{steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    L.lsrvt_timing_enable(False)
+    return dt * 1e3 / steps, L.lsrvt_timing_read()
+
+
+def roofline(timing, workload):
+    vt_ms, vt_launches, vt_passes, vox_per_pass = timing
+    alg_bytes_per_launch = VT_BYTES_PER_VOXEL * vox_per_pass * vt_passes / max(vt_launches, 1)
+    avg_launch_s = vt_ms / 1e3 / max(vt_launches, 1)
+    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    return {"bound": "hbm", "kernel": "k_bfs_level", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": _traffic_per_launch(workload),
+            "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": vt_launches, "passes": vt_passes,
+            "alg_bytes_per_launch": round(alg_bytes_per_launch, 1)}
+
+
+def bench_flame(args):
+    """The main line: the whole step on the combustion-shaped 1024 x 512 x 512 volume."""
+    import numpy as np
+    import torch
+    import paper_2208_06970_amd as L
+    import synth
+    _log("flame: generating the 1024x512x512 workload")
+    wl = synth.flame_workload()
+    n = wl.field.size
+    f = torch.from_numpy(wl.field).cuda()
+    w = torch.from_numpy(wl.weights.view(np.int16)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(wl.variables)).cuda()
+    e = torch.from_numpy(wl.edges).cuda()
+    band, _ = L.lsrvt_isobands(f, wl.iso)
+    cc = L.lsrvt_components(band, wl.n_bands)
+    seeds = synth.flame_sites(cc.comp.cpu().numpy().view(np.uint32), cc.n_comp, wl.weights, wl.rho, wl.seed)
+    sd = torch.from_numpy(seeds.view(np.int32)).cuda()
+    _log(f"flame: comps={cc.n_comp} sites={len(seeds)}")
+    step = Step(f, wl.iso, wl.n_bands, sd, w, wl.iters, x, e)
+    ms, timing = timed_steps(step, args.steps, args.warmup, "flame")
+    ph = step.phases()
+    out = {
+        "metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
+        "value": round(n * wl.iters / (ms / 1e3) / 1e9, 4), "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "flame 1024x512x512 (combustion-shaped sheet), 10 isovalues of Z, |grad T| uint16 "
+                               "weights, 1 site / 4096 weighted voxels, T=30, 18 vars (Z, T, 16 species), "
+                               "32-bin hist, 18x18 cov",
+                   "voxels": n, "iters": wl.iters, "sites": int(len(seeds)), "components": int(cc.n_comp),
+                   "parallelism": "single GPU"},
+        "phases_ms": ph,
+        "lloyd_gvox_per_iter_s": round(n * wl.iters / (ph["lloyd"] / 1e3) / 1e9, 4) if ph["lloyd"] else None,
+        "stats_gvox_s": round(n / (ph["aggregate"] / 1e3) / 1e9, 4) if ph["aggregate"] else None,
+        "end_to_end_gvox_s": round(n / (ms / 1e3) / 1e9, 4),
+        "stats_dtype": "f32 compensated per cell, f64 merges",
+        "roofline": roofline(timing, "flame"),
+    }
+    del x, e
+    if not args.no_cpu_baseline:
+        _log("flame: timing the oracle on a bounded sample")
+        z = 16
+        out["cpu_baseline"] = cpu_baseline(
+            np.ascontiguousarray(wl.field[:z]), wl.iso, np.ascontiguousarray(wl.weights[:z]),
+            np.ascontiguousarray(wl.variables[:, :z]), wl.edges, wl.rho, wl.seed, wl.iters,
+            f"the first {z} z-planes of the same 1024x512x512 fields (1024x512x{z}, {n * z // 512} voxels, its own "
+            f"components and sites)")
+    return out
+
+
+def bench_fourier(args, extras=True):
+    """The 256^3 Fourier workload's whole step; with `extras`, the joint
+    moments, on-device seeding and the line-of-sight Lloyd loop beside it."""
+    import numpy as np
+    import torch
+    import paper_2208_06970_amd as L
+    import synth
+    _log("fourier: generating the 256^3 workload")
+    wl = synth.fourier_workload(shape=(args.size,) * 3)
+    n = wl.field.size
+    f = torch.from_numpy(wl.field).cuda()
+    w = torch.from_numpy(wl.weights.view(np.int16)).cuda()
+    x = torch.from_numpy(np.ascontiguousarray(wl.variables)).cuda()
+    e = torch.from_numpy(wl.edges).cuda()
+    band, _ = L.lsrvt_isobands(f, wl.iso)
+    cc = L.lsrvt_components(band, wl.n_bands)
+    seeds = synth.workload_sites(wl, cc.comp.cpu().numpy().view(np.uint32), cc.n_comp)
+    sd = torch.from_numpy(seeds.view(np.int32)).cuda()
+    step = Step(f, wl.iso, wl.n_bands, sd, w, wl.iters, x, e)
+    ms, timing = timed_steps(step, args.steps, args.warmup, "fourier")
+    ph = step.phases()
+    out = {"value": round(n * wl.iters / (ms / 1e3) / 1e9, 4), "unit": "Gvoxels/s per Lloyd iteration",
+           "ms_per_step": round(ms, 3), "steps": args.steps,
+           "config": {"workload": f"fourier {args.size}^3, 512 modes k^-5/3, 8 isovalues, |grad| uint16 weights, "
+                                  f"1 site / 4096 weighted voxels, T={wl.iters}, 8 vars, 32-bin hist, 8x8 cov",
+                      "voxels": n, "iters": wl.iters, "sites": int(len(seeds)), "components": int(cc.n_comp)},
+           "phases_ms": ph,
+           "lloyd_gvox_per_iter_s": round(n * wl.iters / (ph["lloyd"] / 1e3) / 1e9, 4) if ph["lloyd"] else None,
+           "stats_gvox_s": round(n / (ph["aggregate"] / 1e3) / 1e9, 4) if ph["aggregate"] else None,
+           "roofline": roofline(timing, "fourier256")}
+    if extras:
+        out["seeding"] = bench_seeding(L, cc, w, n)
+        out["comoments"] = bench_comoments(L, step, cc, x, wl.n_bands, n)
+        out["los"] = bench_los(L, cc, sd, w, n, wl.iters)
+    return out
 
 
 def _fourier_job_inputs(shape, seed, n_iso, n_vars, n_bins, rho, n_modes=128):
@@ -159,55 +352,90 @@ def bench_batch(args):
 
     res = {}
     ws = L.Workspace()
+    reps = max(1, min(args.steps, 3))
     for name, fn in (("serial", serial), ("batched", lambda: L.lsrvt_batch_run(make(), n_streams=args.streams, ws=ws))):
         fn()
         torch.cuda.synchronize()
         ts = []
-        for _ in range(args.steps):
+        for _ in range(reps):
             t0 = time.perf_counter()
             fn()
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         res[name] = float(np.median(ts))
         _log(f"batch {name}: {res[name] * 1e3:.1f} ms")
-    print(json.dumps({"metric": "Gvoxels/s per Lloyd iteration, 64-volume batch (whole path per job)",
-                      "unit": "Gvoxels/s", "higher_is_better": True, "n_gpus": 1, "steps": args.steps,
-                      "value": round(vox_iters / res["batched"] / 1e9, 4),
-                      "serial_value": round(vox_iters / res["serial"] / 1e9, 4),
-                      "ms_batched": round(res["batched"] * 1e3, 3), "ms_serial": round(res["serial"] * 1e3, 3),
-                      "speedup": round(res["serial"] / res["batched"], 3), "streams": args.streams,
-                      "config": {"workload": "64 Fourier volumes, edges 32..192 (cubes and 2:1:1), 3..10 isovalues, "
-                                             "T=15, 8 vars, 32-bin hist, 8x8 cov", "voxels": int(sum(j["voxels"] for j in jobs))},
-                      "dtype": "u32", "data": "synthetic"}), flush=True)
+    return {"metric": "Gvoxels/s per Lloyd iteration, 64-volume batch (whole path per job)",
+            "unit": "Gvoxels/s", "value": round(vox_iters / res["batched"] / 1e9, 4),
+            "serial_value": round(vox_iters / res["serial"] / 1e9, 4),
+            "ms_batched": round(res["batched"] * 1e3, 3), "ms_serial": round(res["serial"] * 1e3, 3),
+            "speedup": round(res["serial"] / res["batched"], 3), "streams": args.streams, "reps": reps,
+            "config": {"workload": "64 Fourier volumes, edges 32..192 (cubes and 2:1:1), 3..10 isovalues, "
+                                   "T=15, 8 vars, 32-bin hist, 8x8 cov", "voxels": int(sum(j["voxels"] for j in jobs))}}
 
 
-def bench_serve(args):
-    """Poisson arrivals through the serving loop, several slots vs one slot."""
+def serving_jobs(n, seed=5000, pool=6, max_edge=512):
+    """Jobs of the serving configuration: per request, edges uniform in
+    64..max_edge per axis, 3..12 isovalues, 10..30 updates, 4..16 variables.
+    The fields come from a pool of `pool` generated Fourier volumes (one per
+    drawn shape, reused by later requests with their own isovalue count,
+    update count and variable count) so that generating inputs stays within
+    the benchmark's time; each request's variables are smooth functions of
+    its field computed on the device."""
     import numpy as np
+    import torch
+    import paper_2208_06970_amd as L
     import paper_2208_06970_amd.serve as srv
-    rng = np.random.default_rng(5)
-    specs = []
-    for j in range(args.serve_jobs):
-        shape = tuple(int(v) for v in rng.integers(64, 193, size=3))
-        specs.append((shape, 5000 + j, int(rng.integers(3, 13)), int(rng.integers(4, 9)), int(rng.integers(10, 31))))
-    _log(f"serve: generating {len(specs)} jobs")
-    made = [_device_job(sh, sd, k, m, 32, 4096.0, t) for sh, sd, k, m, t in specs]
-    jobs = [srv.Job(field=d["field"], iso=d["iso"], seeds=d["seeds"], weights=d["weights"], iters=d["iters"],
-                    variables=d["variables"], edges=d["edges"], cov=True, cap_comp=d["cap_comp"]) for d in made]
+    import synth
+    rng = np.random.default_rng(seed)
+    vols = []
+    for p in range(pool):
+        shape = tuple(int(v) for v in rng.integers(64, max_edge + 1, size=3))
+        f = synth.fourier_field(shape, seed + p, n_modes=64)
+        w = synth.gradient_weight(f)
+        vols.append((f, torch.from_numpy(f).cuda(), torch.from_numpy(w.view(np.int16)).cuda(), w))
+    jobs = []
+    for i in range(n):
+        f, fd, wd, w = vols[int(rng.integers(0, pool))]
+        K, T, m = int(rng.integers(3, 13)), int(rng.integers(10, 31)), int(rng.integers(4, 17))
+        iso = synth.quantile_isovalues(f, [(k + 1) / (K + 1) for k in range(K)])
+        band, _ = L.lsrvt_isobands(fd, iso)
+        cc = L.lsrvt_components(band, K + 1)
+        seeds = synth.seed_sites(cc.comp.cpu().numpy().view(np.uint32), cc.n_comp, w, 4096.0, 7919 * (seed + i) + 1)
+        x = torch.stack([torch.sin(fd * (2.0 + j) + 0.5 * j) * (1.0 + j) for j in range(m)]).contiguous()
+        lo = x.reshape(m, -1).min(dim=1).values.cpu().numpy()
+        hi = x.reshape(m, -1).max(dim=1).values.cpu().numpy()
+        edges = np.stack([np.linspace(float(a), float(b), 33) for a, b in zip(lo, hi)]).astype(np.float32)
+        jobs.append(srv.Job(field=fd, iso=iso, seeds=torch.from_numpy(seeds.view(np.int32)).cuda(), weights=wd,
+                            iters=T, variables=x, edges=torch.from_numpy(edges).cuda(), cov=True,
+                            cap_comp=int(cc.n_comp) + 16))
+    return jobs
+
+
+def bench_serve(args, rates=None, n_jobs=None):
+    """Poisson arrivals through the serving loop against serial plain launches."""
+    import paper_2208_06970_amd.serve as srv
+    rates = rates or args.rates
+    n_jobs = n_jobs or args.serve_jobs
+    _log(f"serve: generating {n_jobs} jobs")
+    jobs = serving_jobs(n_jobs, pool=args.serve_pool)
     budget = int(args.budget_gib * 2**30)
     srv.serve(jobs[:2], [0.0, 0.0], slots=2, budget_bytes=budget)  # warm-up
+    vox = [j.voxels for j in jobs]
     out = {"metric": "p50/p99 request latency and throughput, Poisson job stream", "unit": "ms / Gvoxels/s",
-           "n_gpus": 1, "data": "synthetic", "dtype": "u32",
-           "config": {"workload": f"{len(jobs)} jobs, edges 64..192 per axis, 3..12 isovalues, T=10..30, 4..8 vars, "
-                                  f"32-bin hist, cov", "budget_gib": args.budget_gib, "slots": args.slots},
+           "config": {"workload": f"{len(jobs)} jobs per rate, edges 64..512 per axis (fields from a pool of "
+                                  f"{args.serve_pool} volumes), 3..12 isovalues, T=10..30, 4..16 vars, 32-bin hist, cov",
+                      "mean_voxels": int(sum(vox) / len(vox)), "budget_gib": args.budget_gib, "slots": args.slots},
            "rates": {}}
-    for rate in args.rates:
+    for rate in rates:
         arr = srv.poisson_arrivals(len(jobs), rate, 5)
         a = srv.serve(jobs, arr, slots=args.slots, budget_bytes=budget).summary()
-        b = srv.serve(jobs, arr, slots=1, budget_bytes=budget).summary()
-        out["rates"][str(rate)] = {"served": a, "one_slot": b}
-        _log(f"serve rate {rate}: {a['p50_ms']} / {a['p99_ms']} ms (one slot {b['p50_ms']} / {b['p99_ms']})")
-    print(json.dumps(out), flush=True)
+        b = srv.serial(jobs, arr).summary()
+        out["rates"][str(rate)] = {"served": a, "serial": {k: b[k] for k in ("makespan_s", "jobs_per_s",
+                                                                               "gvox_iter_per_s", "p50_ms", "p99_ms",
+                                                                               "mean_ms")}}
+        _log(f"serve rate {rate}: p50/p99 {a['p50_ms']} / {a['p99_ms']} ms, {a['gvox_iter_per_s']} Gvox/s "
+             f"(serial {b['p50_ms']} / {b['p99_ms']} ms, {b['gvox_iter_per_s']} Gvox/s)")
+    return out
 
 
 def main():
@@ -216,15 +444,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="main line without the c2/batch/serve keys")
     ap.add_argument("--size", type=int, default=256, help="edge of the cubic Fourier volume")
+    ap.add_argument("--fourier", action="store_true", help="256^3 Fourier workload (own JSON line)")
     ap.add_argument("--batch", action="store_true", help="64-volume batch vs serial (own JSON line)")
     ap.add_argument("--batch-jobs", type=int, default=64)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--serve", action="store_true", help="Poisson serving loop (own JSON line)")
-    ap.add_argument("--flame", action="store_true", help="1024x512x512 combustion-shaped volume (own JSON line)")
-    ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--serve-jobs", type=int, default=40)
+    ap.add_argument("--serve-pool", type=int, default=6)
     ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--rates", type=float, nargs="*", default=[5.0, 20.0, 50.0])
+    ap.add_argument("--rates", type=float, nargs="*", default=[5.0, 10.0, 20.0, 50.0, 100.0, 200.0])
     ap.add_argument("--budget-gib", type=float, default=96.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration) and exit")
@@ -234,22 +464,8 @@ def main():
               "not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import paper_2208_06970_amd as L
-    import synth
-
     torch.cuda.set_device(0)
-    if args.batch:
-        bench_batch(args)
-        return
-    if args.serve:
-        bench_serve(args)
-        return
-    if args.flame:
-        bench_flame(args)
-        return
     if args.copy_mib:
         src = torch.ones(args.copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -258,110 +474,42 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4, "launches": 3}), flush=True)
         return
-    _log("generating workload")
-    wl = synth.fourier_workload(shape=(args.size,) * 3)
-    n = wl.field.size
-    f = torch.from_numpy(wl.field).cuda()
-    w = torch.from_numpy(wl.weights.view(np.int16)).cuda()
-    x = torch.from_numpy(np.ascontiguousarray(wl.variables)).cuda()
-    e = torch.from_numpy(wl.edges).cuda()
-    band, _ = L.lsrvt_isobands(f, wl.iso)
-    cc = L.lsrvt_components(band, wl.n_bands)
-    seeds = synth.workload_sites(wl, cc.comp.cpu().numpy().view(np.uint32), cc.n_comp)
-    sd = torch.from_numpy(seeds.view(np.int32)).cuda()
-    _log(f"volume {wl.field.shape} comps={cc.n_comp} sites={len(seeds)}")
-
-    ev = {k: torch.cuda.Event(enable_timing=True) for k in ("t0", "t1", "t2", "t3", "t4")}
-    phase_ms = {"isobands": 0.0, "components": 0.0, "lloyd": 0.0, "aggregate": 0.0}
-
-    def step(record):
-        if record:
-            ev["t0"].record()
-        b, _ = L.lsrvt_isobands(f, wl.iso)
-        if record:
-            ev["t1"].record()
-        c = L.lsrvt_components(b, wl.n_bands)
-        if record:
-            ev["t2"].record()
-        r = L.lsrvt_cvt(b, c.comp, sd, w, wl.iters, want_mean_ds=False)
-        if record:
-            ev["t3"].record()
-        L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, c.comp_band, c.n_comp, wl.n_bands, x, e, cov=True)
-        if record:
-            ev["t4"].record()
-            torch.cuda.synchronize()
-            phase_ms["isobands"] += ev["t0"].elapsed_time(ev["t1"])
-            phase_ms["components"] += ev["t1"].elapsed_time(ev["t2"])
-            phase_ms["lloyd"] += ev["t2"].elapsed_time(ev["t3"])
-            phase_ms["aggregate"] += ev["t3"].elapsed_time(ev["t4"])
-        return r
-
-    for i in range(args.warmup):
-        step(False)
-        _log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    L.lsrvt_timing_read()                      # discard anything recorded so far
-    L.lsrvt_timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(True)
-        _log(f"step {i + 1}/{args.steps} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    L.lsrvt_timing_enable(False)
-    vt_ms, vt_launches, vt_passes, vox_per_pass = L.lsrvt_timing_read()
-
-    ms_per_step = dt * 1e3 / args.steps
-    value = n * wl.iters / (ms_per_step / 1e3) / 1e9
-    phases = {k: round(v / args.steps, 4) for k, v in phase_ms.items()}
-    # roofline of the dominant kernel: the Voronoi level kernel, HBM-bound
-    alg_bytes_per_launch = VT_BYTES_PER_VOXEL * vox_per_pass * vt_passes / max(vt_launches, 1)
-    avg_launch_s = vt_ms / 1e3 / max(vt_launches, 1)
-    achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    traffic = _traffic_per_launch()
-    out = {
-        "metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
-        "value": round(value, 4),
-        "unit": "Gvoxels/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"fourier {args.size}^3, 512 modes k^-5/3, 8 isovalues, |grad| uint16 weights, "
-                               f"1 site / 4096 weighted voxels, T={wl.iters}, 8 vars, 32-bin hist, 8x8 cov",
-                   "voxels": n, "iters": wl.iters, "sites": int(len(seeds)), "components": int(cc.n_comp),
-                   "parallelism": "single GPU"},
-        "phases_ms": phases,
-        "lloyd_gvox_per_iter_s": round(n * wl.iters / (phases["lloyd"] / 1e3) / 1e9, 4) if phases["lloyd"] else None,
-        "stats_gvox_s": round(n / (phases["aggregate"] / 1e3) / 1e9, 4) if phases["aggregate"] else None,
-        "end_to_end_gvox_s": round(n / (ms_per_step / 1e3) / 1e9, 4),
-        "stats_dtype": "f32 compensated per cell, f64 merges",
-        "roofline": {"bound": "hbm", "kernel": "k_bfs_level", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": traffic,
-                     "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": vt_launches, "passes": vt_passes,
-                     "alg_bytes_per_launch": round(alg_bytes_per_launch, 1)},
-    }
-    out["seeding"] = bench_seeding(L, cc, w, n)
-    out["comoments"] = bench_comoments(L, step, cc, x, wl.n_bands, n)
-    out["los"] = bench_los(L, cc, sd, w, n, wl.iters)
-    if not args.no_cpu_baseline:
-        _log("timing the oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(wl, seeds)
+    if args.batch:
+        out = bench_batch(args)
+        out.update(n_gpus=1, steps=args.steps, higher_is_better=True, dtype="u32", data="synthetic")
+        print(json.dumps(out), flush=True)
+        return
+    if args.serve:
+        out = bench_serve(args)
+        out.update(n_gpus=1, dtype="u32", data="synthetic")
+        print(json.dumps(out), flush=True)
+        return
+    if args.fourier:
+        f = bench_fourier(args)
+        out = {"metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
+               "n_gpus": 1, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
+        out.update(f)
+        print(json.dumps(out), flush=True)
+        return
+    out = bench_flame(args)
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        fargs = argparse.Namespace(**vars(args))
+        fargs.steps, fargs.warmup = min(args.steps, 3), 1
+        out["fourier256"] = bench_fourier(fargs, extras=False)
+        torch.cuda.empty_cache()
+        out["batch"] = bench_batch(fargs)
+        torch.cuda.empty_cache()
+        out["serve"] = bench_serve(fargs, rates=[10.0, 50.0], n_jobs=24)
     print(json.dumps(out), flush=True)
 
 
 def bench_comoments(L, step, cc, x, n_bands, n, reps: int = 3):
     """Joint moments up to fourth order (lsrvt_comoments) of the cells of one
-    step, all 8 variables, timed on their own."""
+    step, all variables, timed on their own."""
     import torch
-    r = step(False)
+    r, _ = step(False)
     ws = L.Workspace(x.device)
     L.lsrvt_comoments(r.cell, r.sites, r.site_comp, cc.comp_band, cc.n_comp, n_bands, x, ws=ws)
     torch.cuda.synchronize()
@@ -374,69 +522,6 @@ def bench_comoments(L, step, cc, x, n_bands, n, reps: int = 3):
     units = m + m * (m + 1) // 2 + m * (m + 1) * (m + 2) // 6 + m * (m + 1) * (m + 2) * (m + 3) // 24
     return {"ms": round(ms, 4), "gvox_s": round(n / (ms / 1e3) / 1e9, 4), "vars": m, "sums_per_voxel": units,
             "dtype": "f64", "includes": "structured layout of the cells, merges, host synchronisations"}
-
-
-def bench_flame(args):
-    """The whole step on the combustion-shaped 1024 x 512 x 512 volume."""
-    import numpy as np
-    import torch
-    import paper_2208_06970_amd as L
-    import synth
-    _log("flame: generating the 1024x512x512 workload")
-    wl = synth.flame_workload()
-    n = wl.field.size
-    f = torch.from_numpy(wl.field).cuda()
-    w = torch.from_numpy(wl.weights.view(np.int16)).cuda()
-    x = torch.from_numpy(np.ascontiguousarray(wl.variables)).cuda()
-    e = torch.from_numpy(wl.edges).cuda()
-    band, _ = L.lsrvt_isobands(f, wl.iso)
-    cc = L.lsrvt_components(band, wl.n_bands)
-    seeds = synth.flame_sites(cc.comp.cpu().numpy().view(np.uint32), cc.n_comp, wl.weights, wl.rho, wl.seed)
-    sd = torch.from_numpy(seeds.view(np.int32)).cuda()
-    _log(f"flame: comps={cc.n_comp} sites={len(seeds)}")
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    ph = np.zeros(4)
-
-    def step(record):
-        if record:
-            ev[0].record()
-        b, _ = L.lsrvt_isobands(f, wl.iso)
-        if record:
-            ev[1].record()
-        c = L.lsrvt_components(b, wl.n_bands)
-        if record:
-            ev[2].record()
-        r = L.lsrvt_cvt(b, c.comp, sd, w, wl.iters, want_mean_ds=False)
-        if record:
-            ev[3].record()
-        L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, c.comp_band, c.n_comp, wl.n_bands, x, e, cov=True)
-        if record:
-            ev[4].record()
-            torch.cuda.synchronize()
-            for k in range(4):
-                ph[k] += ev[k].elapsed_time(ev[k + 1])
-
-    steps = max(1, min(args.steps, 3))
-    step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        step(True)
-        _log(f"flame: step {i + 1}/{steps} done")
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    ph /= steps
-    print(json.dumps({"metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
-                      "value": round(n * wl.iters / (ms / 1e3) / 1e9, 4), "unit": "Gvoxels/s", "n_gpus": 1,
-                      "steps": steps, "warmup": 1, "ms_per_step": round(ms, 3), "higher_is_better": True,
-                      "dtype": "u32", "data": "synthetic",
-                      "config": {"workload": "flame 1024x512x512, 10 isovalues of Z, |grad T| uint16 weights, T=30, "
-                                             "18 vars, 32-bin hist, 18x18 cov", "voxels": n, "iters": wl.iters,
-                                 "sites": int(len(seeds)), "components": int(cc.n_comp)},
-                      "phases_ms": {k: round(float(v), 3) for k, v in zip(("isobands", "components", "lloyd",
-                                                                             "aggregate"), ph)},
-                      "lloyd_gvox_per_iter_s": round(n * wl.iters / (ph[2] / 1e3) / 1e9, 4),
-                      "stats_gvox_s": round(n / (ph[3] / 1e3) / 1e9, 4)}), flush=True)
 
 
 def bench_los(L, cc, sd, w, n, iters):

@@ -507,8 +507,9 @@ int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d
  * for the recorded events and returns, since the previous read: the summed
  * milliseconds of those batches, the number of level launches in them, the
  * number of Voronoi passes they belong to and the voxels of one pass; then
- * it resets the totals.  Process-global state, meant for benchmarks, not for
- * concurrent production use.
+ * it resets the totals.  The state is per host thread: enabling, recording
+ * and reading all refer to the calling thread's own record, so calls made
+ * from other threads (other streams) are neither timed nor disturbed.
  */
 int32_t lsrvt_timing_enable(int32_t enable);
 int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass);

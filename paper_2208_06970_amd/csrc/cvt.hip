@@ -70,8 +70,8 @@ struct BFSArgs {
   unsigned long long *xf;  // [2][nbricks][8] x = 0 face (words 0..3), x = 15 face (4..7) of the frontier;
                            // bit t of word k is row (t & 15) + 16 (4 (t >> 4) + k)
   uint16_t *yf;        // [2][nbricks][32] y = 0 face rows (0..15), y = 15 face rows (16..31) of the frontier, by z
-  uint32_t *cell;      // [N] site id of every reached voxel (NONE elsewhere)
-  uint32_t *dist;      // [N] level at which each voxel was reached (its hop distance to its site)
+  uint32_t *cell;      // [nbricks][4096] site id of every reached voxel, brick-major (x + 16 y + 256 z in the brick)
+  uint32_t *dist;      // [nbricks][4096] level at which each voxel was reached (its hop distance), brick-major
   uint32_t *act;       // [2][nbricks]: act[L & 1][b] == L when brick b takes part in level L
   uint32_t *alive;     // [3]: alive[L % 3] != 0 when some brick takes part in level L
   uint32_t *hist;      // [kHistLen] alive flag of every level
@@ -147,6 +147,7 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict_
 struct BrickPos {
   uint32_t b, row, lx;
   int bx, by, bz;
+  size_t bi;  // brick-major index: b * 4096 + lx + 16 * row
 };
 
 __device__ __forceinline__ BrickPos brick_pos(const BFSArgs &A, uint32_t v) {
@@ -159,6 +160,7 @@ __device__ __forceinline__ BrickPos brick_pos(const BFSArgs &A, uint32_t v) {
   p.b = (uint32_t)p.bx + (uint32_t)A.bg.nbx * ((uint32_t)p.by + (uint32_t)A.bg.nby * (uint32_t)p.bz);
   p.row = (y % BY) + BY * (z % BZ);
   p.lx = x % BX;
+  p.bi = (size_t)p.b * (kRows * BX) + p.lx + BX * p.row;
   return p;
 }
 
@@ -205,8 +207,8 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
     return;
   }
   const BrickPos p = brick_pos(A, v);
-  atomicMin(&A.cell[v], s);
-  A.dist[v] = 0u;
+  atomicMin(&A.cell[p.bi], s);
+  A.dist[p.bi] = 0u;
   or_row_bit(A.vis, p);
   frontier0(A, p);
 }
@@ -229,8 +231,9 @@ __global__ void k_bfs_init(const uint32_t *__restrict__ sites, uint32_t S, BFSAr
 // kept voxel that changes joins the frontier, so changes spread as far as
 // they reach, and the result is the full pass's.
 
-// Invalid rows: voxels whose site moved.  One voxel per lane, ballots per row.
-__global__ __launch_bounds__(kVTThreads) void k_inc_reset(const uint32_t *__restrict__ cell,
+// Invalid rows: voxels whose site moved.  One voxel per lane, ballots per row
+// (the slot index is the brick-major index of the cells).
+__global__ __launch_bounds__(kVTThreads) void k_inc_reset(const uint32_t *__restrict__ cellb,
                                                           const uint8_t *__restrict__ moved, Geom g, VTGrid bg,
                                                           uint16_t *__restrict__ inv) {
   const int64_t slots = bg.nbricks * kRows * BX;
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(kVTThreads) void k_inc_reset(const uint32_t *__rest
       const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
       const int x = bx * BX + (int)(i & 15), y = by * BY + (t & 15), z = bz * BZ + (t >> 4);
       if (x < g.nx && y < g.ny && z < g.nz) {
-        const uint32_t c = cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)];
+        const uint32_t c = cellb[i];
         p = c != kNone && moved[c] != 0;
       }
     }
@@ -266,9 +269,9 @@ __global__ void k_inc_site_a(const uint32_t *__restrict__ sites, uint32_t S, BFS
     return;
   }
   const BrickPos p = brick_pos(A, v);
-  if (row_bit(A.inv, p) || A.dist[v] != 0u || A.cell[v] > s) {
-    A.cell[v] = kNone;
-    A.dist[v] = 0u;
+  if (row_bit(A.inv, p) || A.dist[p.bi] != 0u || A.cell[p.bi] > s) {
+    A.cell[p.bi] = kNone;
+    A.dist[p.bi] = 0u;
     or_row_bit(A.vis, p);
   }
 }
@@ -282,23 +285,33 @@ __global__ void k_inc_site_b(const uint32_t *__restrict__ sites, uint32_t S, BFS
   if ((int64_t)v >= A.g.n) return;
   const BrickPos p = brick_pos(A, v);
   if (!row_bit(A.vis, p)) return;
-  atomicMin(&A.cell[v], s);
+  atomicMin(&A.cell[p.bi], s);
   frontier0(A, p);
 }
 
 constexpr int kLvlThreads = 64;  // one wave per brick
 constexpr int kNewCap = 1024;    // new voxels per brick and level shared out through LDS
 
-// Ids of the six face neighbours of new voxel v, the sources among them
-// flagged by a0..a5 (x-, x+, y-, y+, z-, z+; at least one is set).  All six
-// loads are issued unconditionally so that they are in flight together; a
-// direction that is not a source reads the first source again, which hits
-// the line that load brings in.
-__device__ __forceinline__ void gather6(const uint32_t *cell, int64_t v, int64_t sy, int64_t sz, uint32_t a0,
-                                        uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4, uint32_t a5,
-                                        uint32_t g[6]) {
-  const int64_t n0 = v - 1, n1 = v + 1, n2 = v - sy, n3 = v + sy, n4 = v - sz, n5 = v + sz;
-  int64_t f = a5 ? n5 : v;
+// Ids of the six face neighbours of new voxel (lx, row) of brick b, the
+// sources among them flagged by a0..a5 (x-, x+, y-, y+, z-, z+; at least one
+// is set), read from the brick-major cell array.  A source across a brick
+// face lies in the neighbour brick (which exists: edges join voxels of the
+// volume only).  All six loads are issued unconditionally so that they are in
+// flight together; a direction that is not a source reads the first source
+// again, which hits the line that load brings in.
+__device__ __forceinline__ void gather6(const uint32_t *cell, size_t b, uint32_t lx, uint32_t row, size_t bsy,
+                                        size_t bsz, uint32_t a0, uint32_t a1, uint32_t a2, uint32_t a3, uint32_t a4,
+                                        uint32_t a5, uint32_t g[6]) {
+  constexpr size_t kB = (size_t)kRows * BX;
+  const uint32_t ly = row & 15u, lz = row >> 4;
+  const size_t v = b * kB + lx + BX * row;
+  const size_t n0 = lx > 0 ? v - 1 : (b - 1) * kB + 15 + BX * row;
+  const size_t n1 = lx < 15 ? v + 1 : (b + 1) * kB + BX * row;
+  const size_t n2 = ly > 0 ? v - 16 : (b - bsy) * kB + lx + 16 * 15 + 256 * lz;
+  const size_t n3 = ly < 15 ? v + 16 : (b + bsy) * kB + lx + 256 * lz;
+  const size_t n4 = lz > 0 ? v - 256 : (b - bsz) * kB + lx + 16 * ly + 256 * 15;
+  const size_t n5 = lz < 15 ? v + 256 : (b + bsz) * kB + lx + 16 * ly;
+  size_t f = a5 ? n5 : v;
   f = a4 ? n4 : f;
   f = a3 ? n3 : f;
   f = a2 ? n2 : f;
@@ -364,7 +377,6 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
   unsigned long long *xout = A.xf + pout * nbk * 8;
   const uint16_t *yin = A.yf + pin * nbk * 32;
   uint16_t *yout = A.yf + pout * nbk * 32;
-  const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
   const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
   const int lm1 = (t + kWave - 1) & (kWave - 1), lp1 = (t + 1) & (kWave - 1);
   const int lm16 = (t + kWave - 16) & (kWave - 1), lp16 = (t + 16) & (kWave - 1);
@@ -443,7 +455,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
     if (t >= o) inc += v;
   }
   const uint32_t total = __shfl(inc, kWave - 1, kWave);
-  const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
+  const size_t vb = (size_t)b * (kRows * BX);  // the brick's first cell (brick-major arrays)
   uint32_t nw[4] = {0u, 0u, 0u, 0u};
   if (A.dbg && t == 0) {
     atomicAdd(reinterpret_cast<uint32_t *>(A.dbg + 8) + (L % kHistLen), 1u);
@@ -470,7 +482,7 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
     __syncthreads();
     // keys of the listed voxels, two per lane at a time
     for (uint32_t e = t; e < total; e += 2 * kWave) {
-      int64_t v[2];
+      size_t v[2];
       uint32_t g[2][6], m[2][3], ob[2], od[2], oc[2], ri[2], xi[2];
       bool have[2];
 #pragma unroll
@@ -481,12 +493,12 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
         const uint32_t r = idx >> 4, x = idx & 15u;
         ri[u] = r;
         xi[u] = x;
-        v[u] = vb + x + sy * (int64_t)(r & 15u) + sz * (int64_t)(r >> 4);
+        v[u] = vb + x + BX * r;
         m[u][0] = S.dmp[r] >> x;
         m[u][1] = S.dmp[kRows + r] >> x;
         m[u][2] = S.dmp[2 * kRows + r] >> x;
-        gather6(A.cell, v[u], sy, sz, m[u][0] & 1u, (m[u][0] >> 16) & 1u, m[u][1] & 1u, (m[u][1] >> 16) & 1u,
-                m[u][2] & 1u, (m[u][2] >> 16) & 1u, g[u]);
+        gather6(A.cell, b, x, r, (size_t)bsy, (size_t)bsz, m[u][0] & 1u, (m[u][0] >> 16) & 1u, m[u][1] & 1u,
+                (m[u][1] >> 16) & 1u, m[u][2] & 1u, (m[u][2] >> 16) & 1u, g[u]);
         ob[u] = INC ? (S.inv[r] >> x) & 1u : 1u;
         od[u] = 0u;
         oc[u] = 0u;
@@ -515,15 +527,15 @@ __device__ void bfs_brick(const BFSArgs &A, uint32_t L, uint32_t b, LvlLds &S) {
     for (int k = 0; k < 4; ++k) {
       uint32_t bits = cand[k];
       const int r = ly + 16 * (g4 + k);
-      const int64_t base = vb + sy * (int64_t)(r & 15) + sz * (int64_t)(r >> 4);
+      const size_t base = vb + BX * (size_t)r;
       const uint32_t m0 = S.dmp[r], m1 = S.dmp[kRows + r], m2 = S.dmp[2 * kRows + r];
       while (bits) {
         const int x = __ffs(bits) - 1;
         bits &= bits - 1;
-        const int64_t v = base + x;
+        const size_t v = base + x;
         uint32_t gg[6];
-        gather6(A.cell, v, sy, sz, (m0 >> x) & 1u, (m0 >> (16 + x)) & 1u, (m1 >> x) & 1u, (m1 >> (16 + x)) & 1u,
-                (m2 >> x) & 1u, (m2 >> (16 + x)) & 1u, gg);
+        gather6(A.cell, b, (uint32_t)x, (uint32_t)r, (size_t)bsy, (size_t)bsz, (m0 >> x) & 1u, (m0 >> (16 + x)) & 1u,
+                (m1 >> x) & 1u, (m1 >> (16 + x)) & 1u, (m2 >> x) & 1u, (m2 >> (16 + x)) & 1u, gg);
         const uint32_t id = min_id6(m0 >> x, m1 >> x, m2 >> x, gg);
         bool ok = true;
         if (INC && !((I[k] >> x) & 1u)) {
@@ -633,7 +645,6 @@ __global__ __launch_bounds__(kLvlThreads) void k_bnd_build(BFSArgs A) {
   const int ly = t & 15, g4 = (t >> 4) * 4;
   const int lm1 = (t + kWave - 1) & (kWave - 1), lp1 = (t + 1) & (kWave - 1);
   const int lm16 = (t + kWave - 16) & (kWave - 1), lp16 = (t + 16) & (kWave - 1);
-  const int64_t sy = A.g.nx, sz = (int64_t)A.g.nx * A.g.ny;
   const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
   for (int64_t b = blockIdx.x; b < A.bg.nbricks; b += gridDim.x) {
     const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby),
@@ -698,13 +709,13 @@ __global__ __launch_bounds__(kLvlThreads) void k_bnd_build(BFSArgs A) {
     }
     if (t == 0) cnt_s = 0u;
     __syncthreads();
-    const int64_t vb = (int64_t)bx * BX + sy * ((int64_t)by * BY) + sz * ((int64_t)bz * BZ);
+    const size_t vb = (size_t)b * (kRows * BX);
     uint32_t *list = A.bnd + (size_t)b * (kRows * BX);
     uint32_t nxt = kNone;
     for (uint32_t e = t; e < total; e += kWave) {
       const uint32_t idx = lst[e];
       const uint32_t r = idx >> 4, x = idx & 15u;
-      const uint32_t d = A.dist[vb + x + sy * (int64_t)(r & 15u) + sz * (int64_t)(r >> 4)];
+      const uint32_t d = A.dist[vb + x + BX * r];
       if (d == 0u) {
         BrickPos q;
         q.b = (uint32_t)b;
@@ -1007,7 +1018,8 @@ struct CvtWork {
   uint32_t *act, *ctl;  // brick marks; ctl[0..2] level alive flags, ctl[3] error bits, ctl[4] next wake level
   uint32_t *fb_list, *fb_cnt, *err;
   uint32_t *hist;
-  uint32_t *dist;            // [N] hop distance of every reached voxel
+  uint32_t *cellb;           // [nbricks][4096] cells, brick-major (the search's own copy)
+  uint32_t *dist;            // [nbricks][4096] hop distance of every reached voxel, brick-major
   uint16_t *inv;             // [nbricks][256] invalid voxels (incremental passes)
   uint32_t *bnd, *bcnt, *wake;  // kept-voxel lists per brick, their counts and wake levels
   uint8_t *moved;            // [S] site moved in the last update
@@ -1044,7 +1056,8 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto mean = a.template take<double>(iters > 0 ? iters : 1);
   auto mpart = a.template take<double>(kMeanParts);
   auto hist = a.template take<uint32_t>(kHistLen);
-  auto dist = a.template take<uint32_t>(g.n);
+  auto cellb = a.template take<uint32_t>(nb * kRows * BX);
+  auto dist = a.template take<uint32_t>(nb * kRows * BX);
   auto moved = a.template take<uint8_t>(s1);
   auto inv = a.template take<uint16_t>(inc ? nb * kRows : 1);
   auto bnd = a.template take<uint32_t>(inc ? nb * kRows * BX : 1);
@@ -1066,6 +1079,7 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
     W->mean = mean;
     W->mean_part = mpart;
     W->hist = hist;
+    W->cellb = cellb;
     W->dist = dist;
     W->moved = moved;
     W->inv = inc ? inv : nullptr;
@@ -1114,8 +1128,10 @@ struct KernelTimer {
   uint64_t passes = 0;
   int64_t voxels_per_pass = 0;
 };
+// one timer per host thread: calls issued from different threads (streams)
+// never share instrumentation state
 KernelTimer &timer() {
-  static KernelTimer t;
+  thread_local KernelTimer t;
   return t;
 }
 
@@ -1143,36 +1159,46 @@ int32_t timed_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t> &ev, ui
   return LSRVT_OK;
 }
 
-// Voxels never reached get LSRVT_NONE: in a full pass those of components
-// without a site; in an incremental pass the invalid voxels not reached
-// again (none: a moved site stays in its component).
+// End of a pass: the brick-major cells are written to the caller's C-order
+// cell array, row by row (16 contiguous voxels), with LSRVT_NONE for voxels
+// never reached: in a full pass those of components without a site; in an
+// incremental pass the invalid voxels not reached again (none: a moved site
+// stays in its component), whose brick-major entry is set to NONE as well.
 template <bool INC>
-__global__ __launch_bounds__(kVTThreads) void k_vt_unreached(const uint16_t *__restrict__ vis,
-                                                             const uint16_t *__restrict__ inv, Geom g, VTGrid bg,
-                                                             uint32_t *__restrict__ cell) {
-  const int t = threadIdx.x, ly = t & 15, lz = t >> 4;
-  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
+__global__ __launch_bounds__(kVTThreads) void k_vt_finish(const uint16_t *__restrict__ vis,
+                                                          const uint16_t *__restrict__ inv, Geom g, VTGrid bg,
+                                                          uint32_t *__restrict__ cellb, uint32_t *__restrict__ cell) {
+  const int t = threadIdx.x;
+  const int lx = t & 15;
+  for (int64_t rr = (int64_t)blockIdx.x * (kVTThreads / BX) + (t >> 4); rr < bg.nbricks * kRows;
+       rr += (int64_t)gridDim.x * (kVTThreads / BX)) {
+    const int64_t b = rr / kRows;
+    const int row = (int)(rr % kRows);
     const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-    const int x0 = bx * BX, y = by * BY + ly, z = bz * BZ + lz;
-    if (y >= g.ny || z >= g.nz) continue;
-    const int w = g.nx - x0 < BX ? g.nx - x0 : BX;
-    uint32_t miss = ~vis[b * kRows + t] & ((1u << w) - 1u);
-    if (INC) miss &= inv[b * kRows + t];
-    const int64_t base = brick_row_base(g, x0, y, z);
-    while (miss) {
-      const int x = __ffs(miss) - 1;
-      miss &= miss - 1;
-      cell[base + x] = kNone;
+    const int x = bx * BX + lx, y = by * BY + (row & 15), z = bz * BZ + (row >> 4);
+    if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+    const size_t bi = (size_t)rr * BX + lx;
+    bool miss = !((vis[rr] >> lx) & 1u);
+    if (INC) miss = miss && ((inv[rr] >> lx) & 1u);
+    uint32_t c = cellb[bi];
+    if (miss) {
+      c = kNone;
+      cellb[bi] = kNone;
     }
+    cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = c;
   }
 }
 
-__global__ void k_sites_clear(const uint32_t *__restrict__ sites, uint32_t S, int64_t n, uint32_t *cell) {
+// Site voxels cleared before level 0 of a full pass (brick-major cells).
+__global__ void k_sites_clear(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s < S && (int64_t)sites[s] < n) cell[sites[s]] = kNone;
+  if (s < S && (int64_t)sites[s] < A.g.n) A.cell[brick_pos(A, sites[s]).bi] = kNone;
 }
 
-unsigned vt_grid_cap(const VTGrid &bg) { return (unsigned)(bg.nbricks < 65535 ? bg.nbricks : 65535); }
+unsigned finish_grid(const VTGrid &bg) {
+  const int64_t g = (bg.nbricks * kRows + kVTThreads / BX - 1) / (kVTThreads / BX);
+  return (unsigned)(g < 65535 ? g : 65535);
+}
 
 int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s) {
   VTGrid bg = vt_grid(g);
@@ -1183,7 +1209,7 @@ int32_t vt_prepare(const uint8_t *band, const Geom &g, CvtWork &W, hipStream_t s
   return LSRVT_OK;
 }
 
-BFSArgs bfs_args(const Geom &g, uint32_t *cell, CvtWork &W) {
+BFSArgs bfs_args(const Geom &g, CvtWork &W) {
   BFSArgs A;
   A.g = g;
   A.bg = vt_grid(g);
@@ -1192,7 +1218,7 @@ BFSArgs bfs_args(const Geom &g, uint32_t *cell, CvtWork &W) {
   A.vis = W.vis;
   A.xf = W.xf;
   A.yf = W.yf;
-  A.cell = cell;
+  A.cell = W.cellb;
   A.dist = W.dist;
   A.act = W.act;
   A.alive = W.ctl;
@@ -1311,15 +1337,16 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   VTGrid bg = vt_grid(g);
   int32_t rc;
   if ((rc = clear_pass(bg, W, s))) return rc;
-  BFSArgs A = bfs_args(g, cell, W);
+  BFSArgs A = bfs_args(g, W);
   if (S) {
-    hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, g.n, cell);
+    hipLaunchKernelGGL(k_sites_clear, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
     hipLaunchKernelGGL(k_bfs_init, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
     LSRVT_LAUNCHED();
     bool redo = false;
     if ((rc = run_levels<false>(g, A, W, st, s, &redo))) return rc;
   }
-  hipLaunchKernelGGL(k_vt_unreached<false>, dim3(vt_grid_cap(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, cell);
+  hipLaunchKernelGGL(k_vt_finish<false>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, W.cellb,
+                     cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
@@ -1338,10 +1365,10 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
   VTGrid bg = vt_grid(g);
   int32_t rc;
   if ((rc = clear_pass(bg, W, s))) return rc;
-  BFSArgs A = bfs_args(g, cell, W);
+  BFSArgs A = bfs_args(g, W);
   const int64_t slots = bg.nbricks * kRows * BX;
   const unsigned rgrid = (unsigned)std::min<int64_t>((slots + kVTThreads - 1) / kVTThreads, 65535);
-  hipLaunchKernelGGL(k_inc_reset, dim3(rgrid), dim3(kVTThreads), 0, s, cell, W.moved, g, bg, W.inv);
+  hipLaunchKernelGGL(k_inc_reset, dim3(rgrid), dim3(kVTThreads), 0, s, W.cellb, W.moved, g, bg, W.inv);
   hipLaunchKernelGGL(k_inc_site_a, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
   hipLaunchKernelGGL(k_inc_site_b, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
   hipLaunchKernelGGL(k_bnd_build, dim3((unsigned)std::min<int64_t>(bg.nbricks, 65535)), dim3(kLvlThreads), 0, s, A);
@@ -1352,7 +1379,8 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
     if ((rc = fill<uint32_t>(W.err, 1, 0u, s))) return rc;
     return run_vt(g, sites, S, cell, W, st, s);
   }
-  hipLaunchKernelGGL(k_vt_unreached<true>, dim3(vt_grid_cap(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, cell);
+  hipLaunchKernelGGL(k_vt_finish<true>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, W.cellb,
+                     cell);
   LSRVT_LAUNCHED();
   static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
   if (debug_levels) {  // sizes of the pass: moved sites, invalid and changed voxels, listed kept voxels

@@ -394,7 +394,10 @@ class ServeReport:
 def serve(jobs: list, arrivals: list, slots: int, budget_bytes: int, keep_results: bool = False,
           cancel_ids=()) -> ServeReport:
     """Run `jobs` arriving at `arrivals` (seconds from the start, nondecreasing)
-    on `slots` streams under `budget_bytes` of device memory."""
+    on `slots` streams under `budget_bytes` of device memory.  With
+    `keep_results` the outputs of each finished job are handed to the caller
+    (job.result) and from then on are the caller's memory, outside the
+    budget; otherwise they are dropped when the job ends."""
     import torch
     if len(jobs) != len(arrivals):
         raise ValueError("one arrival time per job")
@@ -441,8 +444,13 @@ def serve(jobs: list, arrivals: list, slots: int, budget_bytes: int, keep_result
                 go_on = sched.phase_done(req, now, err)
                 if not go_on:
                     work[slot] = None
-                    if req.status in (QUEUED, FAILED, CANCELLED):
-                        req.state.clear()   # a deferred job starts again from its first phase
+                    # a deferred job starts again from its first phase; the
+                    # outputs of a finished job are handed over (kept) or dropped
+                    if req.status != DONE or not keep_results:
+                        if req.status == DONE:
+                            req.state = {"_dropped": True}
+                        else:
+                            req.state.clear()
                 for r in sched.admit(now):
                     work[r.slot] = r
                 lock.notify_all()
@@ -476,6 +484,7 @@ def serve(jobs: list, arrivals: list, slots: int, budget_bytes: int, keep_result
         j.arrival, j.start, j.done, j.status = r.arrival, r.start, r.done, r.status
         j.result = ({"band": r.state["band"], "comp": r.state["comp"], "cvt": r.state["cvt"],
                      "stats": r.state["stats"]} if keep_results and r.status == DONE else {})
+        r.state = {}
     failed = [r for r in reqs if r.status == FAILED]
     done = [r for r in reqs if r.status == DONE]
     makespan = (max(r.done for r in done) - min(r.arrival for r in done)) if done else 0.0
