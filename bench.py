@@ -353,7 +353,10 @@ def bench_batch(args):
     res = {}
     ws = L.Workspace()
     reps = max(1, min(args.steps, 3))
-    for name, fn in (("serial", serial), ("batched", lambda: L.lsrvt_batch_run(make(), n_streams=args.streams, ws=ws))):
+    from paper_2208_06970_amd import autotune
+    streams = autotune.batch_streams(make, key=f"fourier-batch-{len(jobs)}", ws=ws)
+    _log(f"batch: autotuned streams = {streams}")
+    for name, fn in (("serial", serial), ("batched", lambda: L.lsrvt_batch_run(make(), n_streams=streams, ws=ws))):
         fn()
         torch.cuda.synchronize()
         ts = []
@@ -368,7 +371,9 @@ def bench_batch(args):
             "unit": "Gvoxels/s", "value": round(vox_iters / res["batched"] / 1e9, 4),
             "serial_value": round(vox_iters / res["serial"] / 1e9, 4),
             "ms_batched": round(res["batched"] * 1e3, 3), "ms_serial": round(res["serial"] * 1e3, 3),
-            "speedup": round(res["serial"] / res["batched"], 3), "streams": args.streams, "reps": reps,
+            "speedup": round(res["serial"] / res["batched"], 3), "streams": streams, "reps": reps,
+            "form": "labels and statistics per job on autotuned streams; Lloyd loops of all jobs in lockstep, "
+                    "one launch per phase over all jobs",
             "config": {"workload": "64 Fourier volumes, edges 32..192 (cubes and 2:1:1), 3..10 isovalues, "
                                    "T=15, 8 vars, 32-bin hist, 8x8 cov", "voxels": int(sum(j["voxels"] for j in jobs))}}
 
@@ -419,6 +424,11 @@ def bench_serve(args, rates=None, n_jobs=None):
     _log(f"serve: generating {n_jobs} jobs")
     jobs = serving_jobs(n_jobs, pool=args.serve_pool)
     budget = int(args.budget_gib * 2**30)
+    from paper_2208_06970_amd import autotune
+    import paper_2208_06970_amd as L
+    for j in jobs:  # the Voronoi schedule of every job class, tuned before timing
+        band, _ = L.lsrvt_isobands(j.field, j.iso)
+        autotune.vt_engine(band, j.seeds, len(j.iso) + 1)
     srv.serve(jobs[:2], [0.0, 0.0], slots=2, budget_bytes=budget)  # warm-up
     vox = [j.voxels for j in jobs]
     out = {"metric": "p50/p99 request latency and throughput, Poisson job stream", "unit": "ms / Gvoxels/s",

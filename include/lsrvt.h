@@ -500,6 +500,26 @@ int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d
                       void *d_work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Schedule of the Voronoi passes of lsrvt_vt and lsrvt_cvt (Eq. 1): both
+ * compute the same regions bit for bit.
+ *   LSRVT_VT_AUTO     the library's choice from the volume and site count
+ *                     (the brick relaxation when there are at least 1024
+ *                     voxels per site, the level search otherwise)
+ *   LSRVT_VT_LEVELS   level-synchronous breadth-first search, one launch per
+ *                     level, over 16^3 bricks of bit masks
+ *   LSRVT_VT_BRICKS   brick relaxation: rounds of launches over marked 16^3
+ *                     bricks, each relaxed to its own fixed point in LDS
+ * The setting belongs to the calling host thread (calls from other threads
+ * are not affected).  Returns the previous setting, or -1 (and changes
+ * nothing) for an unknown value.  The autotuner of the Python package picks
+ * it per job class by measurement.
+ */
+#define LSRVT_VT_AUTO 0
+#define LSRVT_VT_LEVELS 1
+#define LSRVT_VT_BRICKS 2
+int32_t lsrvt_set_vt_engine(int32_t engine);
+
+/* ------------------------------------------------------------------------
  * Benchmark instrumentation of the Voronoi level kernel (the dominant kernel
  * of the Lloyd loop; one launch per breadth-first level).  While enabled,
  * every batch of back-to-back level launches is bracketed by one hipEvent

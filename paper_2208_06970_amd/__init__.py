@@ -37,7 +37,7 @@ EXPORTS = (
     "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
     "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed_workspace", "lsrvt_seed",
     "lsrvt_comoments_workspace", "lsrvt_comoments", "lsrvt_los_workspace", "lsrvt_los_vt", "lsrvt_los_update",
-    "lsrvt_los_cvt", "lsrvt_timing_enable", "lsrvt_timing_read",
+    "lsrvt_los_cvt", "lsrvt_set_vt_engine", "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
 
@@ -135,6 +135,8 @@ def _lib():
         lib.lsrvt_los_vt.argtypes = [P, Dims, P, P, u32, P, P, P, P, P, P, S, P]
         lib.lsrvt_los_update.argtypes = [P, Dims, P, P, P, u32, P, P, P, P, S, P]
         lib.lsrvt_los_cvt.argtypes = [P, Dims, P, u32, P, i32, P, P, P, P, P, P, P, P, S, P]
+        lib.lsrvt_set_vt_engine.argtypes = [i32]
+        lib.lsrvt_set_vt_engine.restype = i32
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
@@ -612,6 +614,19 @@ def lsrvt_extract(variables, perm, out=None, stream=None):
         out = torch.empty((m, k), dtype=torch.float32, device=variables.device)
     _check(_lib().lsrvt_extract(_ptr(variables), m, dims, _ptr(perm), k, _ptr(out), _stream(stream)), "lsrvt_extract")
     return out
+
+
+VT_AUTO, VT_LEVELS, VT_BRICKS = 0, 1, 2
+
+
+def lsrvt_set_vt_engine(engine: int) -> int:
+    """Schedule of the Voronoi passes for calls from this host thread
+    (VT_AUTO, VT_LEVELS or VT_BRICKS; same regions either way); returns the
+    previous setting."""
+    prev = int(_lib().lsrvt_set_vt_engine(int(engine)))
+    if prev < 0:
+        raise LsrvtError(EINVAL, "lsrvt_set_vt_engine", f"unknown engine {engine}")
+    return prev
 
 
 def lsrvt_timing_enable(enable: bool = True) -> None:

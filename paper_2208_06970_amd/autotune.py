@@ -1,0 +1,170 @@
+"""Autotuner for the schedule choices of the hot path, with an on-disk cache.
+
+Two choices are tuned by measurement on the GPU at hand:
+
+* the schedule of the Voronoi passes (``lsrvt_set_vt_engine``): the
+  level-synchronous search or the brick relaxation.  Both give the same
+  regions; which is faster depends on the volume's shape and how many voxels
+  each site holds (wide cells mean many levels per pass but few relaxation
+  rounds).  Tuned per job class by timing one Voronoi pass with each.
+* the number of streams of ``lsrvt_batch_run``'s per-job phases (labels and
+  statistics), tuned per batch by timing the whole batch.
+
+A job class is (GPU name, log2 of the voxel count, log2 of voxels per site,
+band count bucket).  Results are kept in a JSON file (``LSRVT_AUTOTUNE_CACHE``,
+by default ``~/.cache/lsrvt/autotune.json``), read once per process and
+rewritten atomically (write to a temporary file, then rename) under a lock
+file, so concurrent processes share it safely.  Nothing here changes what is
+computed: every candidate gives bit-identical results.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import tempfile
+import threading
+import time
+
+import numpy as np
+
+from . import (VT_BRICKS, VT_LEVELS, lsrvt_set_vt_engine, lsrvt_vt)
+
+_LOCK = threading.Lock()
+_CACHE = None
+
+
+def cache_path() -> str:
+    return os.environ.get("LSRVT_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "lsrvt", "autotune.json"))
+
+
+def _device_name() -> str:
+    import torch
+    try:
+        return torch.cuda.get_device_properties(torch.cuda.current_device()).name.replace(" ", "_")
+    except Exception:  # pragma: no cover
+        return "unknown"
+
+
+def _load() -> dict:
+    global _CACHE
+    if _CACHE is None:
+        try:
+            with open(cache_path()) as fh:
+                _CACHE = json.load(fh)
+        except (OSError, ValueError):
+            _CACHE = {}
+    return _CACHE
+
+
+def _store(key: str, value) -> None:
+    """Record key -> value in memory and on disk (merged with what other
+    processes wrote meanwhile)."""
+    cache = _load()
+    cache[key] = value
+    path = cache_path()
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        import fcntl
+        with open(path + ".lock", "w") as lk:
+            fcntl.flock(lk, fcntl.LOCK_EX)
+            try:
+                with open(path) as fh:
+                    disk = json.load(fh)
+            except (OSError, ValueError):
+                disk = {}
+            disk[key] = value
+            fd, tmp = tempfile.mkstemp(dir=os.path.dirname(path), prefix=".autotune")
+            with os.fdopen(fd, "w") as fh:
+                json.dump(disk, fh, indent=1, sort_keys=True)
+            os.replace(tmp, path)
+            fcntl.flock(lk, fcntl.LOCK_UN)
+    except OSError:  # a read-only home: keep the in-memory result
+        pass
+
+
+def job_class(shape, n_sites: int, n_bands: int) -> str:
+    n = int(np.prod(shape))
+    vps = n / max(int(n_sites), 1)
+    return (f"vt:{_device_name()}:n2^{int(round(math.log2(max(n, 1))))}:"
+            f"vps2^{int(round(math.log2(max(vps, 1.0))))}:bands{min(int(n_bands), 16)}")
+
+
+def _time_vt(band, sites, engine: int, reps: int = 2) -> float:
+    import torch
+    prev = lsrvt_set_vt_engine(engine)
+    try:
+        lsrvt_vt(band, sites)  # warm-up (and workspace sizing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            lsrvt_vt(band, sites)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+    finally:
+        lsrvt_set_vt_engine(prev)
+
+
+def vt_engine(band, sites, n_bands: int, tune: bool = True) -> int | None:
+    """The faster Voronoi schedule for this job's class: from the cache, or
+    measured now (one pass with each schedule) when `tune`; None when the
+    class is unknown and `tune` is False."""
+    key = job_class(tuple(band.shape), int(sites.numel()), n_bands)
+    with _LOCK:
+        hit = _load().get(key)
+    if hit is not None:
+        return int(hit["engine"])
+    if not tune:
+        return None
+    times = {e: _time_vt(band, sites, e) for e in (VT_LEVELS, VT_BRICKS)}
+    best = min(times, key=times.get)
+    with _LOCK:
+        _store(key, {"engine": best, "ms": {str(k): round(v * 1e3, 4) for k, v in times.items()}})
+    return best
+
+
+class engine_for:
+    """Context manager: run the enclosed calls of this thread with the tuned
+    Voronoi schedule of the job (band, sites)."""
+
+    def __init__(self, band, sites, n_bands: int, tune: bool = True):
+        self.engine = vt_engine(band, sites, n_bands, tune)
+        self.prev = None
+
+    def __enter__(self):
+        if self.engine is not None:
+            self.prev = lsrvt_set_vt_engine(self.engine)
+        return self
+
+    def __exit__(self, *exc):
+        if self.prev is not None:
+            lsrvt_set_vt_engine(self.prev)
+        return False
+
+
+def batch_streams(make_jobs, candidates=(2, 4, 8), key: str | None = None, ws=None) -> int:
+    """The number of streams for lsrvt_batch_run: cached under `key`, or
+    measured by running the batch (make_jobs() -> list of BatchJob) with each
+    candidate."""
+    import torch
+    from . import lsrvt_batch_run
+    if key is not None:
+        with _LOCK:
+            hit = _load().get(f"batch:{_device_name()}:{key}")
+        if hit is not None:
+            return int(hit["streams"])
+    times = {}
+    for n in candidates:
+        lsrvt_batch_run(make_jobs(), n_streams=n, ws=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lsrvt_batch_run(make_jobs(), n_streams=n, ws=ws)
+        torch.cuda.synchronize()
+        times[n] = time.perf_counter() - t0
+    best = min(times, key=times.get)
+    if key is not None:
+        with _LOCK:
+            _store(f"batch:{_device_name()}:{key}", {"streams": best,
+                                                     "ms": {str(k): round(v * 1e3, 3) for k, v in times.items()}})
+    return best

@@ -162,6 +162,22 @@ inline int32_t fill(T *p, int64_t n, T v, hipStream_t s) {
   return LSRVT_OK;
 }
 
+// The Lloyd loops of many jobs in lockstep, one launch per phase over all
+// jobs (cvt.hip); used by lsrvt_batch_run.
+struct CvtBatchJob {
+  lsrvt_dims dims;
+  const uint8_t *band;
+  const uint32_t *comp;
+  const uint32_t *seeds;
+  uint32_t n_sites;
+  const uint16_t *weights;
+  int32_t iters;
+  uint32_t *cell, *sites, *site_comp;
+};
+size_t cvt_batch_header(int32_t n);
+size_t cvt_batch_job_workspace(lsrvt_dims dims, uint32_t n_sites, int32_t iters);
+int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, int32_t *status, hipStream_t s);
+
 // Reads n <= 64 words of device memory to the host after the work queued on
 // s (synchronises s).  Implemented in readback.hip.
 int32_t read_words(const uint32_t *d_src, int n, uint32_t *h_out, hipStream_t s);

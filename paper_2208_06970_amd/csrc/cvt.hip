@@ -106,7 +106,7 @@ __device__ __forceinline__ void mark_brick(const BFSArgs &A, int bx, int by, int
 // too); voxels outside the volume have no edges.  One voxel per lane, so a
 // wave covers four rows of a brick and the band reads are coalesced.  Bands
 // do not change during a Lloyd loop, so this runs once per call.
-__global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict__ band, Geom g, VTGrid bg,
+__device__ __forceinline__ void d_vt_eq(const uint8_t *__restrict__ band, Geom g, VTGrid bg,
                                                       uint32_t *__restrict__ eq) {
   const int64_t slots = bg.nbricks * kRows * BX;
   const int lane = lane_id();
@@ -143,6 +143,9 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict_
     }
   }
 }
+__global__ __launch_bounds__(kVTThreads) void k_vt_eq(const uint8_t *__restrict__ band, Geom g, VTGrid bg,
+                                                      uint32_t *__restrict__ eq) { d_vt_eq(band, g, bg, eq); }
+
 
 struct BrickPos {
   uint32_t b, row, lx;
@@ -753,6 +756,353 @@ __global__ __launch_bounds__(256) void k_wake_min(const uint32_t *__restrict__ w
 }
 
 // ----------------------------------------------------------------------------
+// Brick relaxation engine (an alternative schedule for the same regions).
+//
+// The regions of Eq. 1 with ties to the lower id are the unique fixed point
+// of key(v) = min(key(v), min over same-band face neighbours w of
+// key(w) + (1, 0)), keys (distance, id) compared lexicographically and
+// packed as distance << 32 | id, started from (0, s) at the sites and
+// "unreached" elsewhere.  Any order of such relaxations that starts from
+// keys that are lengths of real paths (upper bounds) and stops when nothing
+// changes reaches that fixed point, so the result is the level search's, bit
+// for bit.  Here a round is one launch over the bricks marked for it: a
+// workgroup loads a brick's keys into LDS, takes the offers of the six face
+// neighbours (their stored keys plus one hop), relaxes the brick to its own
+// fixed point by line sweeps along x, y and z (forward and backward, with the
+// same-band edge masks) until a sweep round changes nothing, stores the keys
+// that changed, and marks for the next round each face neighbour whose shared
+// face changed.  A brick reads its neighbours' keys while they may be
+// written in the same round: every value it can see is a real path length,
+// and a neighbour that lowers a face key after the read marks it again, so
+// the rounds end exactly at the fixed point.  An incremental pass starts from
+// the previous keys with the voxels of moved sites set to unreached, and
+// marks the bricks that hold such voxels or a changed site.
+constexpr int kBRThreads = 256;
+constexpr int kBRRow = BX + 1;  // LDS row stride (u64): padding against bank conflicts
+constexpr unsigned long long kOneHop = 1ull << 32;
+
+struct BRArgs {
+  Geom g;
+  VTGrid bg;
+  const uint32_t *eq;              // [nbricks][256][3] same-band edge masks (as the level search)
+  unsigned long long *key;         // [nbricks][4096] brick-major keys, kInfKey = unreached
+  unsigned long long *xface;       // [nbricks][2][256] keys of the x = 0 and x = 15 voxels of every row
+  uint32_t *mark;                  // [2][nbricks]: mark[r & 1][b] == r when brick b works in round r
+  uint32_t *list;                  // [nbricks] bricks of the current round
+  uint32_t *ctl;                   // [0] list length, [3] error bits
+  uint32_t *alive;                 // [3] round alive flags (by r % 3); shared by the jobs of a batch
+  uint32_t *hist;                  // [kHistLen] bricks that worked in each round
+  unsigned long long *dbg;         // diagnostics (LSRVT_DEBUG_LEVELS only): processings, sweep rounds
+};
+
+__device__ __forceinline__ void br_mark(const BRArgs &A, int bx, int by, int bz, int k, uint32_t r) {
+  const int qx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
+  const int qy = by + (k == 3 ? -1 : k == 4 ? 1 : 0);
+  const int qz = bz + (k == 5 ? -1 : k == 6 ? 1 : 0);
+  if (qx >= 0 && qy >= 0 && qz >= 0 && qx < A.bg.nbx && qy < A.bg.nby && qz < A.bg.nbz)
+    A.mark[(size_t)(r & 1) * A.bg.nbricks + (size_t)(qx + A.bg.nbx * (qy + A.bg.nby * qz))] = r;
+}
+
+// Site keys of a pass: (0, s) wherever it is smaller than the stored key
+// (every voxel of a full pass is unreached); a site voxel that changes
+// marks its brick, and the face neighbours whose face it lies on, for round
+// 1 (its packed x-face copy follows).
+__device__ __forceinline__ void d_br_sites(const uint32_t *__restrict__ sites, uint32_t S, BRArgs A) {
+  uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t v = sites[s];
+  if ((int64_t)v >= A.g.n) {
+    atomicOr(&A.ctl[3], 1u);
+    return;
+  }
+  const uint32_t x = v % (uint32_t)A.g.nx, rr = v / (uint32_t)A.g.nx;
+  const uint32_t y = rr % (uint32_t)A.g.ny, z = rr / (uint32_t)A.g.ny;
+  const int bx = (int)(x / BX), by = (int)(y / BY), bz = (int)(z / BZ);
+  const size_t b = (size_t)bx + (size_t)A.bg.nbx * ((size_t)by + (size_t)A.bg.nby * (size_t)bz);
+  const uint32_t lx = x % BX, ly = y % BY, lz = z % BZ;
+  const uint32_t row = ly + BY * lz;
+  const unsigned long long k = (unsigned long long)s;
+  const unsigned long long old = atomicMin(&A.key[b * (kRows * BX) + lx + BX * row], k);
+  if (k >= old) return;
+  if (lx == 0) atomicMin(&A.xface[b * 512 + row], k);
+  if (lx == BX - 1) atomicMin(&A.xface[b * 512 + 256 + row], k);
+  const bool on[7] = {true, lx == 0, lx == BX - 1, ly == 0, ly == BY - 1, lz == 0, lz == BZ - 1};
+#pragma unroll
+  for (int q = 0; q < 7; ++q)
+    if (on[q]) br_mark(A, bx, by, bz, q, 1u);
+  A.alive[1] = 1u;
+}
+__global__ void k_br_sites(const uint32_t *__restrict__ sites, uint32_t S, BRArgs A) { d_br_sites(sites, S, A); }
+
+
+// Incremental pass set-up: voxels whose site moved become unreached (keys
+// and packed faces), and their bricks are marked for round 1.  One thread
+// per voxel slot (the slot index is the brick-major index).
+__device__ __forceinline__ void d_br_reset(const uint8_t *__restrict__ moved, BRArgs A) {
+  const int64_t slots = A.bg.nbricks * kRows * BX;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long k = A.key[i];
+    if (k == kInfKey) continue;
+    const uint32_t id = (uint32_t)(k & 0xFFFFFFFFull);
+    if (!moved[id]) continue;
+    A.key[i] = kInfKey;
+    const int64_t b = i / (kRows * BX);
+    const int loc = (int)(i % (kRows * BX));
+    const int lx = loc & 15, row = loc >> 4;
+    if (lx == 0) A.xface[b * 512 + row] = kInfKey;
+    if (lx == BX - 1) A.xface[b * 512 + 256 + row] = kInfKey;
+    A.mark[(size_t)1 * A.bg.nbricks + b] = 1u;  // round 1 has parity 1
+    A.alive[1] = 1u;
+  }
+}
+__global__ __launch_bounds__(256) void k_br_reset(const uint8_t *__restrict__ moved, BRArgs A) { d_br_reset(moved, A); }
+
+
+// The bricks marked for round r, listed (one counter atomic per block).
+__device__ __forceinline__ void d_br_list(BRArgs A, uint32_t r) {
+  __shared__ uint32_t base_s;
+  __shared__ uint32_t wcount[256 / kWave];
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  if (blockIdx.x == 0 && t == 0) A.alive[(r + 2) % 3] = 0u;  // round r + 2 sets its flag during round r + 1
+  const uint32_t *mk = A.mark + (size_t)(r & 1) * A.bg.nbricks;
+  for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < A.bg.nbricks; b0 += (int64_t)gridDim.x * 256) {
+    const int64_t b = b0 + t;
+    const bool on = b < A.bg.nbricks && mk[b] == r;
+    const uint64_t bal = __ballot(on);
+    if (lane == 0) wcount[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    if (t == 0) {
+      uint32_t tot = 0;
+      for (int q = 0; q < 256 / kWave; ++q) tot += wcount[q];
+      base_s = tot ? atomicAdd(&A.ctl[0], tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t off = base_s;
+    for (int q = 0; q < w; ++q) off += wcount[q];
+    if (on) A.list[off + (uint32_t)__popcll(bal & lanemask_lt())] = (uint32_t)b;
+    __syncthreads();
+  }
+}
+__global__ __launch_bounds__(256) void k_br_list(BRArgs A, uint32_t r) { d_br_list(A, r); }
+
+
+__device__ __forceinline__ int br_at(int lx, int row) { return row * kBRRow + lx; }
+
+// One round over the listed bricks.  LDS holds the brick's keys (rows padded
+// against bank conflicts), its edge masks and a changed bit per voxel.
+__device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
+  __shared__ unsigned long long K[kRows * kBRRow];
+  __shared__ uint32_t E[kRows][3];
+  __shared__ uint32_t chg[kRows];  // bit lx of row: the voxel's key changed in this processing
+  __shared__ uint8_t dx[kRows], dy[kRows], dz[kRows];  // lines to sweep along x (by row), y (lx, lz), z (lx, ly)
+  __shared__ uint32_t flags[8];
+  const int t = threadIdx.x;
+  const uint32_t count = A.ctl[0];
+  const size_t kB = (size_t)kRows * BX;
+  const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
+  if (blockIdx.x == 0 && t == 0) A.hist[r % kHistLen] = count;  // bricks that work in round r
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+    const int64_t b = A.list[item];
+    const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby),
+              bz = (int)(b / ((int64_t)A.bg.nbx * A.bg.nby));
+    // keys (16 per thread, coalesced) and edge masks
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int loc = i * kBRThreads + t;
+      K[br_at(loc & 15, loc >> 4)] = A.key[(size_t)b * kB + loc];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) E[t][j] = A.eq[((size_t)b * kRows + t) * 3 + j];
+    chg[t] = 0u;
+    if (t < 8) flags[t] = 0u;
+    __syncthreads();
+    // offers of the six face neighbours: their keys plus one hop
+    {
+      const int row = t;  // x faces: row t
+      if (bx > 0 && (E[row][0] & 1u)) {
+        const unsigned long long h = A.xface[(size_t)(b - 1) * 512 + 256 + row];
+        if (h != kInfKey && atomicMin(&K[br_at(0, row)], h + kOneHop) > h + kOneHop) atomicOr(&chg[row], 1u);
+      }
+      if (bx < A.bg.nbx - 1 && ((E[row][0] >> 31) & 1u)) {
+        const unsigned long long h = A.xface[(size_t)(b + 1) * 512 + row];
+        if (h != kInfKey && atomicMin(&K[br_at(15, row)], h + kOneHop) > h + kOneHop) atomicOr(&chg[row], 1u << 15);
+      }
+      const int lx = t & 15, hi4 = t >> 4;  // y faces: (lx, lz = hi4); z faces: (lx, ly = hi4)
+      const int rym = 16 * hi4, ryp = 15 + 16 * hi4;
+      if (by > 0 && ((E[rym][1] >> lx) & 1u)) {
+        const unsigned long long h = A.key[(size_t)(b - bsy) * kB + lx + 16 * 15 + 256 * hi4];
+        if (h != kInfKey && atomicMin(&K[br_at(lx, rym)], h + kOneHop) > h + kOneHop) atomicOr(&chg[rym], 1u << lx);
+      }
+      if (by < A.bg.nby - 1 && ((E[ryp][1] >> (16 + lx)) & 1u)) {
+        const unsigned long long h = A.key[(size_t)(b + bsy) * kB + lx + 256 * hi4];
+        if (h != kInfKey && atomicMin(&K[br_at(lx, ryp)], h + kOneHop) > h + kOneHop) atomicOr(&chg[ryp], 1u << lx);
+      }
+      const int rzm = hi4, rzp = hi4 + 16 * 15;
+      if (bz > 0 && ((E[rzm][2] >> lx) & 1u)) {
+        const unsigned long long h = A.key[(size_t)(b - bsz) * kB + lx + 16 * hi4 + 256 * 15];
+        if (h != kInfKey && atomicMin(&K[br_at(lx, rzm)], h + kOneHop) > h + kOneHop) atomicOr(&chg[rzm], 1u << lx);
+      }
+      if (bz < A.bg.nbz - 1 && ((E[rzp][2] >> (16 + lx)) & 1u)) {
+        const unsigned long long h = A.key[(size_t)(b + bsz) * kB + lx + 16 * hi4];
+        if (h != kInfKey && atomicMin(&K[br_at(lx, rzp)], h + kOneHop) > h + kOneHop) atomicOr(&chg[rzp], 1u << lx);
+      }
+    }
+    __syncthreads();
+    // the brick's own fixed point: line sweeps along x, y and z.  A line is
+    // swept again along its axis only after a voxel on it changed (every
+    // line starts dirty); the loop ends when no line is dirty.
+    uint32_t sweeps = 0;
+    dx[t] = dy[t] = dz[t] = 1;
+    __syncthreads();
+    for (;;) {
+      ++sweeps;
+      if (dx[t]) {  // x: thread t sweeps row t
+        dx[t] = 0;
+        unsigned long long k[16];
+        const uint32_t em = E[t][0];
+#pragma unroll
+        for (int x = 0; x < 16; ++x) k[x] = K[br_at(x, t)];
+        uint32_t c = 0;
+#pragma unroll
+        for (int x = 1; x < 16; ++x)
+          if (((em >> x) & 1u) && k[x - 1] != kInfKey && k[x - 1] + kOneHop < k[x]) {
+            k[x] = k[x - 1] + kOneHop;
+            c |= 1u << x;
+          }
+#pragma unroll
+        for (int x = 14; x >= 0; --x)
+          if (((em >> (16 + x)) & 1u) && k[x + 1] != kInfKey && k[x + 1] + kOneHop < k[x]) {
+            k[x] = k[x + 1] + kOneHop;
+            c |= 1u << x;
+          }
+        if (c) {
+          atomicOr(&chg[t], c);
+          const int ly = t & 15, lz = t >> 4;
+#pragma unroll
+          for (int x = 0; x < 16; ++x)
+            if ((c >> x) & 1u) {
+              K[br_at(x, t)] = k[x];
+              dy[x + 16 * lz] = 1;
+              dz[x + 16 * ly] = 1;
+            }
+        }
+      }
+      __syncthreads();
+      if (dy[t]) {  // y: thread t sweeps (lx, lz) = (t & 15, t >> 4) along y
+        dy[t] = 0;
+        const int lx = t & 15, lz = t >> 4;
+        unsigned long long k[16];
+#pragma unroll
+        for (int y = 0; y < 16; ++y) k[y] = K[br_at(lx, y + 16 * lz)];
+        uint32_t c = 0;
+#pragma unroll
+        for (int y = 1; y < 16; ++y)
+          if (((E[y + 16 * lz][1] >> lx) & 1u) && k[y - 1] != kInfKey && k[y - 1] + kOneHop < k[y]) {
+            k[y] = k[y - 1] + kOneHop;
+            c |= 1u << y;
+          }
+#pragma unroll
+        for (int y = 14; y >= 0; --y)
+          if (((E[y + 16 * lz][1] >> (16 + lx)) & 1u) && k[y + 1] != kInfKey && k[y + 1] + kOneHop < k[y]) {
+            k[y] = k[y + 1] + kOneHop;
+            c |= 1u << y;
+          }
+#pragma unroll
+        for (int y = 0; y < 16; ++y)
+          if ((c >> y) & 1u) {
+            K[br_at(lx, y + 16 * lz)] = k[y];
+            atomicOr(&chg[y + 16 * lz], 1u << lx);
+            dx[y + 16 * lz] = 1;
+            dz[lx + 16 * y] = 1;
+          }
+      }
+      __syncthreads();
+      if (dz[t]) {  // z: thread t sweeps (lx, ly) = (t & 15, t >> 4) along z
+        dz[t] = 0;
+        const int lx = t & 15, ly = t >> 4;
+        unsigned long long k[16];
+#pragma unroll
+        for (int z = 0; z < 16; ++z) k[z] = K[br_at(lx, ly + 16 * z)];
+        uint32_t c = 0;
+#pragma unroll
+        for (int z = 1; z < 16; ++z)
+          if (((E[ly + 16 * z][2] >> lx) & 1u) && k[z - 1] != kInfKey && k[z - 1] + kOneHop < k[z]) {
+            k[z] = k[z - 1] + kOneHop;
+            c |= 1u << z;
+          }
+#pragma unroll
+        for (int z = 14; z >= 0; --z)
+          if (((E[ly + 16 * z][2] >> (16 + lx)) & 1u) && k[z + 1] != kInfKey && k[z + 1] + kOneHop < k[z]) {
+            k[z] = k[z + 1] + kOneHop;
+            c |= 1u << z;
+          }
+#pragma unroll
+        for (int z = 0; z < 16; ++z)
+          if ((c >> z) & 1u) {
+            K[br_at(lx, ly + 16 * z)] = k[z];
+            atomicOr(&chg[ly + 16 * z], 1u << lx);
+            dx[ly + 16 * z] = 1;
+            dy[lx + 16 * z] = 1;
+          }
+      }
+      __syncthreads();  // every dirty mark of the z stage is visible before the test
+      if (!__syncthreads_or(dx[t] | dy[t] | dz[t])) break;
+    }
+    // store what changed; note which faces changed
+    uint32_t fc = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int loc = i * kBRThreads + t;
+      const int lx = loc & 15, row = loc >> 4, ly = row & 15, lz = row >> 4;
+      if ((chg[row] >> lx) & 1u) {
+        const unsigned long long k = K[br_at(lx, row)];
+        A.key[(size_t)b * kB + loc] = k;
+        if (lx == 0) A.xface[(size_t)b * 512 + row] = k;
+        if (lx == BX - 1) A.xface[(size_t)b * 512 + 256 + row] = k;
+        fc |= (lx == 0 ? 2u : 0u) | (lx == BX - 1 ? 4u : 0u) | (ly == 0 ? 8u : 0u) | (ly == BY - 1 ? 16u : 0u) |
+              (lz == 0 ? 32u : 0u) | (lz == BZ - 1 ? 64u : 0u);
+      }
+    }
+    if (fc) atomicOr(&flags[0], fc);
+    if (A.dbg && t == 0) {
+      atomicAdd(&A.dbg[0], 1ull);
+      atomicAdd(&A.dbg[1], (unsigned long long)sweeps);
+    }
+    __syncthreads();
+    // a changed face: the neighbour across it (if any) works in round r + 1
+    const uint32_t nb_exists = (bx > 0 ? 2u : 0u) | (bx < A.bg.nbx - 1 ? 4u : 0u) | (by > 0 ? 8u : 0u) |
+                               (by < A.bg.nby - 1 ? 16u : 0u) | (bz > 0 ? 32u : 0u) | (bz < A.bg.nbz - 1 ? 64u : 0u);
+    const uint32_t f = flags[0] & nb_exists;
+    if (t >= 1 && t < 7 && ((f >> t) & 1u)) br_mark(A, bx, by, bz, t, r + 1);
+    if (t == 0 && f) A.alive[(r + 1) % 3] = 1u;
+    __syncthreads();
+  }
+}
+__global__ __launch_bounds__(kBRThreads) void k_br_round(BRArgs A, uint32_t r) { d_br_round(A, r); }
+
+
+// End of a pass: keys to the caller's C-order cells (NONE where unreached),
+// 16 contiguous voxels per row.
+__device__ __forceinline__ void d_br_finish(const unsigned long long *__restrict__ key, Geom g,
+                                                          VTGrid bg, uint32_t *__restrict__ cell) {
+  const int t = threadIdx.x;
+  const int lx = t & 15;
+  for (int64_t rr = (int64_t)blockIdx.x * (kVTThreads / BX) + (t >> 4); rr < bg.nbricks * kRows;
+       rr += (int64_t)gridDim.x * (kVTThreads / BX)) {
+    const int64_t b = rr / kRows;
+    const int row = (int)(rr % kRows);
+    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+    const int x = bx * BX + lx, y = by * BY + (row & 15), z = bz * BZ + (row >> 4);
+    if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
+    const unsigned long long k = key[(size_t)rr * BX + lx];
+    cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = k == kInfKey ? kNone : (uint32_t)(k & 0xFFFFFFFFull);
+  }
+}
+__global__ __launch_bounds__(kVTThreads) void k_br_finish(const unsigned long long *__restrict__ key, Geom g,
+                                                          VTGrid bg, uint32_t *__restrict__ cell) { d_br_finish(key, g, bg, cell); }
+
+
+// ----------------------------------------------------------------------------
 // update
 
 struct Sums {
@@ -768,7 +1118,7 @@ struct Sums {
 constexpr int TX = 64, TY = 8, TZ = 8;
 constexpr int kTabCap = 512;
 
-__global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ cell, const uint16_t *__restrict__ w,
+__device__ __forceinline__ void d_centroid(const uint32_t *__restrict__ cell, const uint16_t *__restrict__ w,
                                                   Geom g, uint32_t S, Sums sums) {
   __shared__ uint32_t tkey[kTabCap];
   __shared__ unsigned long long tM[kTabCap], tX[kTabCap], tY[kTabCap], tZ[kTabCap];
@@ -836,6 +1186,9 @@ __global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ c
     __syncthreads();
   }
 }
+__global__ __launch_bounds__(256) void k_centroid(const uint32_t *__restrict__ cell, const uint16_t *__restrict__ w,
+                                                  Geom g, uint32_t S, Sums sums) { d_centroid(cell, w, g, S, sums); }
+
 
 struct U128 {
   uint64_t hi, lo;
@@ -860,7 +1213,7 @@ __device__ __forceinline__ double move_len(uint32_t a, uint32_t b, Geom g) {
 
 // moved[s] records whether site s moved (the next Voronoi pass is
 // incremental over the moved sites).
-__global__ void k_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Sums sums, uint32_t *sites, double *ds,
+__device__ __forceinline__ void d_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Sums sums, uint32_t *sites, double *ds,
                        uint8_t *moved, uint32_t *fb_list, uint32_t *fb_cnt) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
@@ -882,9 +1235,12 @@ __global__ void k_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Su
     fb_list[pos] = s;
   }
 }
+__global__ void k_snap(const uint32_t *__restrict__ cell, Geom g, uint32_t S, Sums sums, uint32_t *sites, double *ds,
+                       uint8_t *moved, uint32_t *fb_list, uint32_t *fb_cnt) { d_snap(cell, g, S, sums, sites, ds, moved, fb_list, fb_cnt); }
+
 
 // Exact nearest in-cell voxel by growing cubes; one workgroup per site.
-__global__ __launch_bounds__(256) void k_snap_fallback(const uint32_t *__restrict__ cell, Geom g, Sums sums,
+__device__ __forceinline__ void d_snap_fallback(const uint32_t *__restrict__ cell, Geom g, Sums sums,
                                                        uint32_t *sites, double *ds, uint8_t *moved,
                                                        const uint32_t *fb_list, const uint32_t *fb_cnt) {
   __shared__ uint64_t r_hi[256], r_lo[256];
@@ -964,6 +1320,10 @@ __global__ __launch_bounds__(256) void k_snap_fallback(const uint32_t *__restric
     __syncthreads();
   }
 }
+__global__ __launch_bounds__(256) void k_snap_fallback(const uint32_t *__restrict__ cell, Geom g, Sums sums,
+                                                       uint32_t *sites, double *ds, uint8_t *moved,
+                                                       const uint32_t *fb_list, const uint32_t *fb_cnt) { d_snap_fallback(cell, g, sums, sites, ds, moved, fb_list, fb_cnt); }
+
 
 // Mean of ds[0..S) in a fixed order: 256 contiguous chunks summed by 256
 // workgroups, then the chunk sums in order by one workgroup.
@@ -995,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_mean_ds(const double *part, uint32_t S,
   if (threadIdx.x == 0) *out = S ? red[0] / (double)S : 0.0;
 }
 
-__global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, const uint32_t *__restrict__ comp, Geom g,
+__device__ __forceinline__ void d_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, const uint32_t *__restrict__ comp, Geom g,
                              uint32_t *sites, uint32_t *site_comp, uint32_t *err) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
@@ -1007,6 +1367,9 @@ __global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, con
   sites[s] = v;
   site_comp[s] = comp[v];
 }
+__global__ void k_init_sites(const uint32_t *__restrict__ seeds, uint32_t S, const uint32_t *__restrict__ comp, Geom g,
+                             uint32_t *sites, uint32_t *site_comp, uint32_t *err) { d_init_sites(seeds, S, comp, g, sites, site_comp, err); }
+
 
 // ----------------------------------------------------------------------------
 // host side
@@ -1023,6 +1386,8 @@ struct CvtWork {
   uint16_t *inv;             // [nbricks][256] invalid voxels (incremental passes)
   uint32_t *bnd, *bcnt, *wake;  // kept-voxel lists per brick, their counts and wake levels
   uint8_t *moved;            // [S] site moved in the last update
+  unsigned long long *xface; // [nbricks][2][256] packed x faces of the brick relaxation keys
+  uint32_t *brlist;          // [nbricks] bricks of a relaxation round
   unsigned long long *sums;  // 4 x S
   double *ds, *mean, *mean_part;
 };
@@ -1059,6 +1424,8 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
   auto cellb = a.template take<uint32_t>(nb * kRows * BX);
   auto dist = a.template take<uint32_t>(nb * kRows * BX);
   auto moved = a.template take<uint8_t>(s1);
+  auto xface = a.template take<unsigned long long>(nb * 512);
+  auto brlist = a.template take<uint32_t>(nb);
   auto inv = a.template take<uint16_t>(inc ? nb * kRows : 1);
   auto bnd = a.template take<uint32_t>(inc ? nb * kRows * BX : 1);
   auto bcnt = a.template take<uint32_t>(inc ? nb : 1);
@@ -1082,6 +1449,8 @@ void cvt_layout(A &a, const Geom &g, uint32_t S, int32_t iters, CvtWork *W) {
     W->cellb = cellb;
     W->dist = dist;
     W->moved = moved;
+    W->xface = xface;
+    W->brlist = brlist;
     W->inv = inc ? inv : nullptr;
     W->bnd = inc ? bnd : nullptr;
     W->bcnt = inc ? bcnt : nullptr;
@@ -1114,7 +1483,28 @@ int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t
 struct VTState {
   uint32_t levels = 0;      // levels of the last full pass
   uint32_t inc_levels = 0;  // levels of the first run of the last incremental pass
+  uint32_t br_rounds = 0;   // rounds of the last brick relaxation pass
 };
+
+// Which schedule computes the Voronoi passes: the level-synchronous search
+// or the brick relaxation (both give the same regions bit for bit).  The
+// choice is made per host thread (lsrvt_set_vt_engine); by default, the
+// brick relaxation for volumes with many voxels per site (wide cells: many
+// levels per pass, few relaxation rounds) and the level search otherwise.
+enum class VTEngine { Auto = 0, Levels = 1, Bricks = 2 };
+
+thread_local VTEngine t_engine = VTEngine::Auto;
+
+VTEngine vt_engine(const Geom &g, uint32_t S) {
+  VTEngine e = t_engine;
+  if (e == VTEngine::Auto) {
+    static const char *env = getenv("LSRVT_VT_ENGINE");
+    if (env && env[0] == 'l') return VTEngine::Levels;
+    if (env && env[0] == 'b') return VTEngine::Bricks;
+    e = (S == 0 || g.n / (int64_t)S >= 1024) ? VTEngine::Bricks : VTEngine::Levels;
+  }
+  return e;
+}
 
 // Benchmark timing of the level kernel: while enabled, an event pair on the
 // launch stream around every batch of level launches; read back by
@@ -1414,6 +1804,109 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
   return LSRVT_OK;
 }
 
+BRArgs br_args(const Geom &g, CvtWork &W) {
+  BRArgs A;
+  A.g = g;
+  A.bg = vt_grid(g);
+  A.eq = W.eq;
+  A.key = reinterpret_cast<unsigned long long *>(W.cellb);  // spans the cell and distance arrays
+  A.xface = W.xface;
+  A.mark = W.act;
+  A.list = W.brlist;
+  A.ctl = W.ctl;
+  A.alive = W.ctl + 4;
+  A.hist = W.hist;
+  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
+  A.dbg = debug_levels ? reinterpret_cast<unsigned long long *>(W.ctl + 8) : nullptr;
+  return A;
+}
+
+// One Voronoi pass by brick relaxation: a full pass from the sites, or (inc)
+// an incremental one from the previous keys after the update that set
+// W.moved.  Rounds are enqueued in batches (the first sized by the previous
+// pass); after each batch the host reads whether any brick is marked.
+int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st, bool inc,
+               hipStream_t s) {
+  const VTGrid bg = vt_grid(g);
+  BRArgs A = br_args(g, W);
+  int32_t rc;
+  const int64_t nkeys = bg.nbricks * kRows * BX;
+  if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl, 3, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl + 4, 3, 0u, s))) return rc;
+  if (!inc) {
+    if ((rc = fill<unsigned long long>(A.key, nkeys, kInfKey, s))) return rc;
+    if ((rc = fill<unsigned long long>(A.xface, bg.nbricks * 512, kInfKey, s))) return rc;
+  } else {
+    hipLaunchKernelGGL(k_br_reset, dim3((unsigned)std::min<int64_t>((nkeys + 255) / 256, 65535)), dim3(256), 0, s,
+                       W.moved, A);
+    LSRVT_LAUNCHED();
+  }
+  if (S) {
+    hipLaunchKernelGGL(k_br_sites, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
+    LSRVT_LAUNCHED();
+  }
+  const unsigned lgrid = (unsigned)std::min<int64_t>((bg.nbricks + 255) / 256, 4096);
+  const unsigned rgrid = (unsigned)std::min<int64_t>(bg.nbricks, 2048);
+  uint32_t r = 0;
+  int batch = st.br_rounds ? (int)st.br_rounds : 8;
+  uint32_t c[8];
+  const int64_t max_rounds = 4 * g.n + 8;
+  while (true) {
+    const bool timed = timer().on;
+    std::pair<hipEvent_t, hipEvent_t> ev;
+    if (timed && (rc = timed_begin(s, ev))) return rc;
+    for (int i = 0; i < batch; ++i) {
+      ++r;
+      if ((rc = fill<uint32_t>(W.ctl, 1, 0u, s))) return rc;
+      hipLaunchKernelGGL(k_br_list, dim3(lgrid), dim3(256), 0, s, A, r);
+      hipLaunchKernelGGL(k_br_round, dim3(rgrid), dim3(kBRThreads), 0, s, A, r);
+      LSRVT_LAUNCHED();
+    }
+    if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
+    if ((rc = read_words(W.ctl, 8, c, s))) return rc;
+    if (c[3] & 1u) return LSRVT_EINVAL;
+    if (c[3]) return LSRVT_EDEVICE;
+    if (c[4 + (r + 1) % 3] == 0) break;
+    if ((int64_t)r > max_rounds) return LSRVT_EDEVICE;
+    batch = 8;
+  }
+  // the rounds that had work size the first batch of the next pass
+  const uint32_t nl = std::min<uint32_t>(r + 1, kHistLen);
+  std::vector<uint32_t> h(nl, 0);
+  LSRVT_HIP(hipMemcpyAsync(h.data(), W.hist, sizeof(uint32_t) * nl, hipMemcpyDeviceToHost, s));
+  LSRVT_HIP(hipStreamSynchronize(s));
+  uint32_t worked = 0;
+  while (worked + 1 < nl && h[worked + 1]) ++worked;
+  st.br_rounds = worked;
+  static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
+  if (debug_levels) {
+    unsigned long long d[2];
+    LSRVT_HIP(hipMemcpyAsync(d, W.ctl + 8, sizeof(d), hipMemcpyDeviceToHost, s));
+    LSRVT_HIP(hipStreamSynchronize(s));
+    if ((rc = fill<uint32_t>(W.ctl + 8, 4, 0u, s))) return rc;
+    fprintf(stderr, "[lsrvt] br %s processings=%llu sweep rounds=%llu\n", inc ? "inc" : "full", d[0], d[1]);
+    fprintf(stderr, "[lsrvt] br %s rounds=%u launched=%u bricks per round:", inc ? "inc" : "full", worked, r);
+    for (uint32_t i = 1; i < nl; ++i) fprintf(stderr, " %u", h[i]);
+    fprintf(stderr, "\n");
+  }
+  hipLaunchKernelGGL(k_br_finish, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, A.key, g, bg, cell);
+  LSRVT_LAUNCHED();
+  if (timer().on) {
+    std::lock_guard<std::mutex> lk(timer().mu);
+    timer().passes += 1;
+    timer().voxels_per_pass = g.n;
+  }
+  return LSRVT_OK;
+}
+
+// A Voronoi pass with the selected schedule.
+int32_t vt_pass(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st, bool inc,
+                hipStream_t s) {
+  if (vt_engine(g, S) == VTEngine::Bricks) return run_br(g, sites, S, cell, W, st, inc, s);
+  return inc ? run_vt_inc(g, sites, S, cell, W, st, s) : run_vt(g, sites, S, cell, W, st, s);
+}
+
 // Errors a run reported on the device (synchronises).
 int32_t vt_errors(CvtWork &W, hipStream_t s) {
   uint32_t e = 0;
@@ -1449,6 +1942,261 @@ int32_t begin(CvtWork &W, const Geom &g, hipStream_t s) {
   return LSRVT_OK;
 }
 
+
+// ----------------------------------------------------------------------------
+// The Lloyd loops of many jobs in lockstep: every phase of every pass is one
+// launch over all jobs (blockIdx.y = job), with each job's blocks striding
+// over that job's own work.  The Voronoi passes use the brick relaxation
+// (its rounds are shared: round r works on the marked bricks of every job,
+// and the batch ends a pass when no job has a brick marked); a job with fewer
+// updates than the batch's largest simply stops taking part.  Every job's
+// kernels, sums and orders are its own, so its results are bit-identical to
+// its lsrvt_cvt alone.
+struct JobDev {
+  BRArgs A;
+  Geom g;
+  const uint8_t *band;
+  const uint32_t *comp, *seeds;
+  const uint16_t *w;
+  uint32_t *cell, *sites, *site_comp, *eq;
+  uint32_t S;
+  int32_t iters;
+  Sums sums;
+  double *ds;
+  uint8_t *moved;
+  uint32_t *fb_list, *fb_cnt;
+};
+
+__global__ __launch_bounds__(kVTThreads) void kb_vt_eq(const JobDev *J) {
+  const JobDev &j = J[blockIdx.y];
+  d_vt_eq(j.band, j.g, j.A.bg, j.eq);
+}
+
+__global__ void kb_init_sites(const JobDev *J) {
+  const JobDev &j = J[blockIdx.y];
+  d_init_sites(j.seeds, j.S, j.comp, j.g, j.sites, j.site_comp, j.A.ctl + 3);
+}
+
+// Start of pass t: marks and list counters cleared, and for a full pass
+// (t = 0) every key and packed face unreached.  Block (0, 0) clears the
+// shared round flags.
+__global__ __launch_bounds__(256) void kb_pass_clear(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 3) j.A.alive[threadIdx.x] = 0u;
+  if (t > j.iters) return;
+  const int64_t nb = j.A.bg.nbricks, stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < 2 * nb; i += stride) j.A.mark[i] = 0u;
+  if (i0 == 0) j.A.ctl[0] = 0u;
+  if (t == 0) {
+    for (int64_t i = i0; i < nb * kRows * BX; i += stride) j.A.key[i] = kInfKey;
+    for (int64_t i = i0; i < nb * 512; i += stride) j.A.xface[i] = kInfKey;
+  }
+}
+
+__global__ __launch_bounds__(256) void kb_reset(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t > j.iters || t == 0) return;
+  d_br_reset(j.moved, j.A);
+}
+
+__global__ void kb_sites(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t > j.iters) return;
+  d_br_sites(j.sites, j.S, j.A);
+}
+
+__global__ void kb_round_prep(const JobDev *J) {
+  if (threadIdx.x == 0) J[blockIdx.y].A.ctl[0] = 0u;
+}
+
+__global__ __launch_bounds__(256) void kb_list(const JobDev *J, int32_t t, uint32_t r) {
+  const JobDev &j = J[blockIdx.y];
+  if (t > j.iters) return;
+  d_br_list(j.A, r);
+}
+
+__global__ __launch_bounds__(kBRThreads) void kb_round(const JobDev *J, int32_t t, uint32_t r) {
+  const JobDev &j = J[blockIdx.y];
+  if (t > j.iters) return;
+  d_br_round(j.A, r);
+}
+
+__global__ __launch_bounds__(kVTThreads) void kb_finish(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t > j.iters) return;
+  d_br_finish(j.A.key, j.g, j.A.bg, j.cell);
+}
+
+__global__ __launch_bounds__(256) void kb_update_clear(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t >= j.iters) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t i = i0; i < 4 * (int64_t)j.S; i += stride) j.sums.M[i] = 0ull;  // M, Sx, Sy, Sz are contiguous
+  if (i0 == 0) *j.fb_cnt = 0u;
+}
+
+__global__ __launch_bounds__(256) void kb_centroid(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t >= j.iters) return;
+  d_centroid(j.cell, j.w, j.g, j.S, j.sums);
+}
+
+__global__ void kb_snap(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t >= j.iters) return;
+  d_snap(j.cell, j.g, j.S, j.sums, j.sites, j.ds, j.moved, j.fb_list, j.fb_cnt);
+}
+
+__global__ __launch_bounds__(256) void kb_snap_fallback(const JobDev *J, int32_t t) {
+  const JobDev &j = J[blockIdx.y];
+  if (t >= j.iters) return;
+  d_snap_fallback(j.cell, j.g, j.sums, j.sites, j.ds, j.moved, j.fb_list, j.fb_cnt);
+}
+
+}  // namespace
+
+// Bytes of the descriptor block that precedes the jobs' workspaces.
+size_t cvt_batch_header(int32_t n) { return ((size_t)n * sizeof(JobDev) + 256 + 255) & ~size_t(255); }
+
+size_t cvt_batch_job_workspace(lsrvt_dims dims, uint32_t n_sites, int32_t iters) {
+  Geom g;
+  if (make_geom(dims, g)) return 0;
+  return (cvt_workspace(g, n_sites, iters < 0 ? 0 : iters) + 255) & ~size_t(255);
+}
+
+// The Lloyd loops of n jobs in lockstep (see above).  work: the descriptor
+// block, then one cvt workspace per job (cvt_batch_job_workspace each, in
+// order).  status[i] receives each job's status.
+int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, int32_t *status, hipStream_t s) {
+  if (n <= 0) return LSRVT_OK;
+  std::vector<JobDev> hj((size_t)n);
+  uint8_t *base = static_cast<uint8_t *>(work);
+  const size_t head = cvt_batch_header(n);
+  if (bytes < head) return LSRVT_EWORKSPACE;
+  JobDev *dj = reinterpret_cast<JobDev *>(base);
+  uint32_t *alive = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev));
+  size_t off = head;
+  int32_t tmax = 0;
+  int64_t max_keys = 0, max_sites = 0, max_tiles = 0, max_nb = 0, max_slots = 0;
+  std::vector<CvtWork> Ws((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    const CvtBatchJob &b = jobs[i];
+    JobDev &j = hj[(size_t)i];
+    Geom g;
+    int32_t rc = make_geom(b.dims, g);
+    if (rc) return rc;
+    if (b.iters < 0 || !b.band || !b.comp || !b.cell || (b.n_sites && (!b.seeds || !b.sites || !b.site_comp)))
+      return LSRVT_EINVAL;
+    const size_t need = cvt_batch_job_workspace(b.dims, b.n_sites, b.iters);
+    if (off + need > bytes) return LSRVT_EWORKSPACE;
+    CvtWork &W = Ws[(size_t)i];
+    if ((rc = carve_cvt(base + off, need, g, b.n_sites, b.iters, W))) return rc;
+    off += need;
+    j.A = br_args(g, W);
+    j.A.alive = alive;
+    j.A.dbg = nullptr;
+    j.g = g;
+    j.band = b.band;
+    j.comp = b.comp;
+    j.seeds = b.seeds;
+    j.w = b.weights;
+    j.cell = b.cell;
+    j.sites = b.sites;
+    j.site_comp = b.site_comp;
+    j.eq = W.eq;
+    j.S = b.n_sites;
+    j.iters = b.iters;
+    const size_t S = b.n_sites;
+    j.sums = Sums{W.sums, W.sums + S, W.sums + 2 * S, W.sums + 3 * S};
+    j.ds = W.ds;
+    j.moved = W.moved;
+    j.fb_list = W.fb_list;
+    j.fb_cnt = W.fb_cnt;
+    tmax = std::max(tmax, b.iters);
+    const VTGrid bg = vt_grid(g);
+    max_nb = std::max<int64_t>(max_nb, bg.nbricks);
+    max_keys = std::max<int64_t>(max_keys, bg.nbricks * kRows * BX);
+    max_slots = std::max<int64_t>(max_slots, bg.nbricks * kRows);
+    max_sites = std::max<int64_t>(max_sites, (int64_t)S);
+    max_tiles = std::max<int64_t>(max_tiles, (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) *
+                                                 ((g.nz + TZ - 1) / TZ));
+  }
+  int32_t rc;
+  LSRVT_HIP(hipMemcpyAsync(dj, hj.data(), sizeof(JobDev) * (size_t)n, hipMemcpyHostToDevice, s));
+  for (int32_t i = 0; i < n; ++i)
+    if ((rc = fill<uint32_t>(Ws[(size_t)i].ctl, 8 + 2 * 8, 0u, s))) return rc;
+  const unsigned N = (unsigned)n;
+  auto cap = [](int64_t v, int64_t c) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(v, c)); };
+  const unsigned g_sites = cap((max_sites + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(kb_init_sites, dim3(g_sites, N), dim3(256), 0, s, dj);
+  hipLaunchKernelGGL(kb_vt_eq, dim3(cap((max_keys + kVTThreads - 1) / kVTThreads, 65535), N), dim3(kVTThreads), 0, s,
+                     dj);
+  LSRVT_LAUNCHED();
+  const unsigned g_clear = cap((max_keys + 255) / 256, 8192);
+  const unsigned g_list = cap((max_nb + 255) / 256, 4096);
+  const unsigned g_round = cap(max_nb, 2048);
+  const unsigned g_fin = cap((max_slots + kVTThreads / BX - 1) / (kVTThreads / BX), 65535);
+  const unsigned g_tiles = cap(max_tiles, 65535);
+  const unsigned g_fb = cap(max_sites, 1024);
+  uint32_t rounds_hint = 0;
+  for (int32_t t = 0; t <= tmax; ++t) {
+    hipLaunchKernelGGL(kb_pass_clear, dim3(g_clear, N), dim3(256), 0, s, dj, t);
+    if (t > 0) hipLaunchKernelGGL(kb_reset, dim3(g_clear, N), dim3(256), 0, s, dj, t);
+    hipLaunchKernelGGL(kb_sites, dim3(g_sites, N), dim3(256), 0, s, dj, t);
+    LSRVT_LAUNCHED();
+    uint32_t r = 0;
+    int batch = rounds_hint ? (int)rounds_hint : 8;
+    uint32_t c[3];
+    const bool timed = timer().on;
+    while (true) {
+      std::pair<hipEvent_t, hipEvent_t> ev;
+      if (timed && (rc = timed_begin(s, ev))) return rc;
+      for (int k = 0; k < batch; ++k) {
+        ++r;
+        hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, s, dj);
+        hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, s, dj, t, r);
+        hipLaunchKernelGGL(kb_round, dim3(g_round, N), dim3(kBRThreads), 0, s, dj, t, r);
+        LSRVT_LAUNCHED();
+      }
+      if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
+      if ((rc = read_words(alive, 3, c, s))) return rc;
+      if (c[(r + 1) % 3] == 0) break;
+      if (r > (uint32_t)(1u << 30)) return LSRVT_EDEVICE;
+      batch = 8;
+    }
+    rounds_hint = r;
+    hipLaunchKernelGGL(kb_finish, dim3(g_fin, N), dim3(kVTThreads), 0, s, dj, t);
+    if (t < tmax) {
+      hipLaunchKernelGGL(kb_update_clear, dim3(g_sites, N), dim3(256), 0, s, dj, t);
+      hipLaunchKernelGGL(kb_centroid, dim3(g_tiles, N), dim3(256), 0, s, dj, t);
+      hipLaunchKernelGGL(kb_snap, dim3(g_sites, N), dim3(256), 0, s, dj, t);
+      hipLaunchKernelGGL(kb_snap_fallback, dim3(g_fb, N), dim3(256), 0, s, dj, t);
+    }
+    LSRVT_LAUNCHED();
+    if (timed) {
+      std::lock_guard<std::mutex> lk(timer().mu);
+      for (int32_t i = 0; i < n; ++i)
+        if (t <= hj[(size_t)i].iters) {
+          timer().passes += 1;
+          timer().voxels_per_pass = hj[(size_t)i].g.n;
+        }
+    }
+  }
+  // each job's error bits (a seed outside its volume)
+  for (int32_t i0 = 0; i0 < n; i0 += 64) {
+    uint32_t e[64];
+    const int m = std::min<int32_t>(64, n - i0);
+    for (int k = 0; k < m; ++k) {
+      if ((rc = read_words(Ws[(size_t)(i0 + k)].ctl + 3, 1, &e[k], s))) return rc;
+      status[i0 + k] = (e[k] & 1u) ? LSRVT_EINVAL : e[k] ? LSRVT_EDEVICE : LSRVT_OK;
+    }
+  }
+  return LSRVT_OK;
+}
+
+namespace {
 }  // namespace
 
 }  // namespace lsrvt
@@ -1474,7 +2222,7 @@ extern "C" int32_t lsrvt_vt(const uint8_t *d_band, lsrvt_dims dims, const uint32
   if ((rc = begin(W, g, s))) return rc;
   if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
-  if ((rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
+  if ((rc = vt_pass(g, d_sites, n_sites, d_cell, W, st, false, s))) return rc;
   return vt_errors(W, s);
 }
 
@@ -1513,8 +2261,7 @@ extern "C" int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrv
   VTState st;
   for (int32_t t = 0; t <= iters; ++t) {
     // the first pass covers every voxel; later ones only what the moved sites change
-    if (t == 0 && (rc = run_vt(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
-    if (t > 0 && (rc = run_vt_inc(g, d_sites, n_sites, d_cell, W, st, s))) return rc;
+    if ((rc = vt_pass(g, d_sites, n_sites, d_cell, W, st, t > 0, s))) return rc;
     if (t == iters) break;
     if ((rc = run_update(d_cell, g, d_weights, d_sites, n_sites, W.ds, W, s))) return rc;
     hipLaunchKernelGGL(k_mean_ds_part, dim3(kMeanParts), dim3(256), 0, s, W.ds, n_sites, W.mean_part);
@@ -1618,4 +2365,11 @@ extern "C" int32_t lsrvt_update_noalloc(const uint32_t *d_cell, lsrvt_dims dims,
   W.fb_cnt = reinterpret_cast<uint32_t *>(base + kNoAllocSums + kNoAllocList);
   W.moved = base + kNoAllocSums + kNoAllocList + 256;
   return run_update(d_cell, g, d_weights, d_sites, n_sites, d_ds, W, as_stream(stream));
+}
+
+extern "C" int32_t lsrvt_set_vt_engine(int32_t engine) {
+  if (engine < 0 || engine > 2) return -1;
+  const int32_t prev = (int32_t)t_engine;
+  t_engine = (VTEngine)engine;
+  return prev;
 }

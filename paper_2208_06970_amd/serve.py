@@ -333,10 +333,13 @@ def _phase_labels(req, ws, stream):
 
 
 def _phase_lloyd(req, ws, stream):
-    from . import lsrvt_cvt
+    from . import autotune, lsrvt_cvt
     job = req.job
-    r = lsrvt_cvt(req.state["band"], req.state["comp"].comp, job.seeds, job.weights, job.iters, ws=_OneShot(ws),
-                  stream=stream, want_mean_ds=False)
+    # the Voronoi schedule the autotuner found fastest for this job's class
+    # (cached only: no measurement inside the serving loop)
+    with autotune.engine_for(req.state["band"], job.seeds, len(job.iso) + 1, tune=False):
+        r = lsrvt_cvt(req.state["band"], req.state["comp"].comp, job.seeds, job.weights, job.iters, ws=_OneShot(ws),
+                      stream=stream, want_mean_ds=False)
     req.state["cvt"] = r
 
 

@@ -99,16 +99,21 @@ def test_fullsize_bench_loop_properties(workload):
     assert runs[0].mean_ds[-1] < runs[0].mean_ds[0]
 
 
-def test_fullsize_bench_loop_against_oracle(workload):
+@pytest.mark.parametrize("engine", [L.VT_LEVELS, L.VT_BRICKS], ids=["levels", "bricks"])
+def test_fullsize_bench_loop_against_oracle(workload, engine):
     """The bench loop (20 updates) against the oracle's stored run, and the
     statistics of its cells, components and bands."""
     wl, band, cc, seeds = workload
     doc, arrays = G.load("fourier256_t20")
     assert G.sha(seeds) == doc["seeds_sha256"], "inputs differ from the ones the oracle ran on"
-    banner(f"fullsize: Lloyd loop, {wl.iters} updates, against the oracle's digests")
+    banner(f"fullsize: Lloyd loop, {wl.iters} updates, engine {engine}, against the oracle's digests")
     b = dev(band)
     g = L.lsrvt_components(b, wl.n_bands)
-    r = L.lsrvt_cvt(b, g.comp, dev(seeds), dev(wl.weights), wl.iters)
+    prev = L.lsrvt_set_vt_engine(engine)
+    try:
+        r = L.lsrvt_cvt(b, g.comp, dev(seeds), dev(wl.weights), wl.iters)
+    finally:
+        L.lsrvt_set_vt_engine(prev)
     cell = host(r.cell, np.uint32)
     G.check_labels(cell, doc, "fourier 256^3 T=20")
     assert G.sha(host(r.sites, np.uint32)) == doc["sites_sha256"]

@@ -16,6 +16,14 @@ from tests import brute
 from tests.gpu_util import banner, dev, host
 
 pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(params=[L.VT_LEVELS, L.VT_BRICKS], ids=["levels", "bricks"])
+def engine(request):
+    """Run a Voronoi test with each schedule of the passes (same regions)."""
+    prev = L.lsrvt_set_vt_engine(request.param)
+    yield request.param
+    L.lsrvt_set_vt_engine(prev)
 NONE = oracle.NONE_ID
 
 
@@ -108,7 +116,7 @@ def test_components_random_noise_bands():
 @pytest.mark.parametrize("shape,K,seed,S", [((64, 64, 64), 4, 1, 600), ((37, 29, 45), 6, 2, 300),
                                             ((1, 1, 500), 2, 3, 9), ((1, 50, 70), 3, 4, 40),
                                             ((50, 40, 33), 1, 5, 1), ((17, 16, 48), 5, 6, 2000)])
-def test_vt_parity(shape, K, seed, S):
+def test_vt_parity(shape, K, seed, S, engine):
     f = _field(shape, seed, "blobs" if shape == (64, 64, 64) else "fourier")
     iso = synth.quantile_isovalues(f, np.linspace(0, 1, K + 2)[1:-1])
     band_d, _, cc = _labels(f, iso)
@@ -123,7 +131,7 @@ def test_vt_parity(shape, K, seed, S):
         assert not np.any(host(cell, np.uint32) == S - 1)
 
 
-def test_vt_every_voxel_a_site():
+def test_vt_every_voxel_a_site(engine):
     rng = np.random.default_rng(3)
     band = brute.random_bands((6, 17, 19), 2, rng, smooth=True)
     comp = oracle.components(band, 2).comp
@@ -133,7 +141,7 @@ def test_vt_every_voxel_a_site():
     np.testing.assert_array_equal(host(cell, np.uint32), oracle.vt(comp, sites))
 
 
-def test_vt_octants_and_errors():
+def test_vt_octants_and_errors(engine):
     band = np.zeros((10, 10, 10), dtype=np.uint8)
     pts = [(x, y, z) for z in (2, 7) for y in (2, 7) for x in (2, 7)]
     sites = np.array([x + 10 * (y + 10 * z) for x, y, z in pts], dtype=np.uint32)
@@ -187,19 +195,19 @@ def _cvt_case(f, iso, weights, rho, seed, T):
     return got
 
 
-def test_cvt_blobs_64():
+def test_cvt_blobs_64(engine):
     wl = synth.blobs_workload()
     _cvt_case(wl.field, wl.iso, None, wl.rho, 5, wl.iters)
 
 
 @pytest.mark.parametrize("shape,T,seed", [((37, 29, 45), 6, 2), ((48, 20, 33), 0, 3), ((1, 64, 90), 5, 4)])
-def test_cvt_weighted_ragged(shape, T, seed):
+def test_cvt_weighted_ragged(shape, T, seed, engine):
     f = _field(shape, seed)
     iso = synth.quantile_isovalues(f, [0.25, 0.5, 0.75])
     _cvt_case(f, iso, synth.gradient_weight(f), 96.0, seed, T)
 
 
-def test_cvt_errors_and_determinism():
+def test_cvt_errors_and_determinism(engine):
     f = _field((20, 21, 22), 9)
     iso = synth.quantile_isovalues(f, [0.5])
     band_d, _, cc = _labels(f, iso)
