@@ -66,12 +66,12 @@ def _source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic_per_launch(workload: str):
-    """HBM bytes per launch of the Voronoi level kernel on `workload` from the
-    committed rocprofv3 counter summary, or None when it is missing or the
-    kernel source changed since the counters were taken."""
+def _traffic_per_launch(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, or None when it is missing or the kernel
+    source changed since the counters were taken."""
     try:
-        with open(os.path.join(PROFILES, f"k_bfs_level_traffic_{workload}.json")) as f:
+        with open(os.path.join(PROFILES, f"{kernel}_traffic_{workload}.json")) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
@@ -203,14 +203,21 @@ def timed_steps(step, steps, warmup, label):
 
 
 def roofline(timing, workload):
-    vt_ms, vt_launches, vt_passes, vox_per_pass = timing
+    """Roofline of the Voronoi passes' dominant kernel, from the library's own
+    hipEvent brackets: the level kernel (one launch per BFS level) or the
+    relaxation round (one brick-list launch and one round launch per round).
+    Algorithmic bytes of one pass: read the band, write the cell (5 B per
+    voxel), spread over the pass's launches."""
+    vt_ms, vt_launches, vt_passes, vox_per_pass, engines = timing
+    kernel = {1: "k_bfs_level", 2: "k_br_round"}.get(engines, "k_bfs_level+k_br_round")
     alg_bytes_per_launch = VT_BYTES_PER_VOXEL * vox_per_pass * vt_passes / max(vt_launches, 1)
     avg_launch_s = vt_ms / 1e3 / max(vt_launches, 1)
     achieved = alg_bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    return {"bound": "hbm", "kernel": "k_bfs_level", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": _traffic_per_launch(workload),
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": _traffic_per_launch(kernel, workload),
             "avg_launch_us": round(avg_launch_s * 1e6, 3), "launches": vt_launches, "passes": vt_passes,
-            "alg_bytes_per_launch": round(alg_bytes_per_launch, 1)}
+            "alg_bytes_per_launch": round(alg_bytes_per_launch, 1),
+            "pass_ms": round(vt_ms / max(vt_passes, 1), 3)}
 
 
 def bench_flame(args):

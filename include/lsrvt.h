@@ -520,19 +520,23 @@ int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d
 int32_t lsrvt_set_vt_engine(int32_t engine);
 
 /* ------------------------------------------------------------------------
- * Benchmark instrumentation of the Voronoi level kernel (the dominant kernel
- * of the Lloyd loop; one launch per breadth-first level).  While enabled,
- * every batch of back-to-back level launches is bracketed by one hipEvent
- * pair recorded on the stream it is launched on.  lsrvt_timing_read waits
- * for the recorded events and returns, since the previous read: the summed
- * milliseconds of those batches, the number of level launches in them, the
- * number of Voronoi passes they belong to and the voxels of one pass; then
- * it resets the totals.  The state is per host thread: enabling, recording
+ * Benchmark instrumentation of the Voronoi passes' dominant kernel: the
+ * level kernel (one launch per breadth-first level) under LSRVT_VT_LEVELS,
+ * the relaxation round (one brick-list launch and one round launch per
+ * round) under LSRVT_VT_BRICKS.  While enabled, every batch of back-to-back
+ * levels or rounds is bracketed by one hipEvent pair recorded on the stream
+ * it is launched on.  lsrvt_timing_read waits for the recorded events and
+ * returns, since the previous read: the summed milliseconds of those
+ * batches, the number of levels or rounds in them, the number of Voronoi
+ * passes they belong to, the voxels of one pass and which schedules ran
+ * (bit 0 levels, bit 1 bricks); then it resets the totals.  Any output
+ * pointer may be NULL.  The state is per host thread: enabling, recording
  * and reading all refer to the calling thread's own record, so calls made
  * from other threads (other streams) are neither timed nor disturbed.
  */
 int32_t lsrvt_timing_enable(int32_t enable);
-int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass);
+int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass,
+                          int32_t *engines);
 
 #ifdef __cplusplus
 }

@@ -139,7 +139,8 @@ def _lib():
         lib.lsrvt_set_vt_engine.restype = i32
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
-                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64)]
+                                          ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(ctypes.c_int32)]
         for name in ("lsrvt_isobands", "lsrvt_components", "lsrvt_vt", "lsrvt_update", "lsrvt_update_noalloc",
                      "lsrvt_cvt",
                      "lsrvt_aggregate", "lsrvt_batch_run", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed",
@@ -630,16 +631,19 @@ def lsrvt_set_vt_engine(engine: int) -> int:
 
 
 def lsrvt_timing_enable(enable: bool = True) -> None:
-    """Bracket every batch of Voronoi level-kernel launches with a hipEvent pair (benchmarks)."""
+    """Bracket every batch of the Voronoi passes' dominant launches (levels or
+    relaxation rounds) with a hipEvent pair (benchmarks)."""
     _check(_lib().lsrvt_timing_enable(1 if enable else 0), "lsrvt_timing_enable")
 
 
 def lsrvt_timing_read():
-    """(kernel ms, launches, passes, voxels per pass) since the previous read."""
-    ms, la, pa, vx = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64()
-    _check(_lib().lsrvt_timing_read(ctypes.byref(ms), ctypes.byref(la), ctypes.byref(pa), ctypes.byref(vx)),
-           "lsrvt_timing_read")
-    return ms.value, la.value, pa.value, vx.value
+    """(kernel ms, launches, passes, voxels per pass, engines) since the
+    previous read; engines has bit 0 set when level passes ran, bit 1 when
+    relaxation passes ran."""
+    ms, la, pa, vx, en = ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib().lsrvt_timing_read(ctypes.byref(ms), ctypes.byref(la), ctypes.byref(pa), ctypes.byref(vx),
+                                    ctypes.byref(en)), "lsrvt_timing_read")
+    return ms.value, la.value, pa.value, vx.value, en.value
 
 
 def lsrvt_seed(comp, comp_first, n_comp: int, weights=None, mass_lut=None, rho: int = 4096, block: int = 16,

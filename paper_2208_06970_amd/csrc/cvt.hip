@@ -888,15 +888,53 @@ __global__ __launch_bounds__(256) void k_br_list(BRArgs A, uint32_t r) { d_br_li
 
 __device__ __forceinline__ int br_at(int lx, int row) { return row * kBRRow + lx; }
 
-// One round over the listed bricks.  LDS holds the brick's keys (rows padded
-// against bank conflicts), its edge masks and a changed bit per voxel.
+// One line of 16 voxels at K[base + i * st] relaxed forward and backward
+// along its same-band edges (mask bit i: edge from voxel i to i - 1, bit
+// 16 + i: edge to i + 1).  Returns the bits of the voxels whose key dropped;
+// the line is written back only then.  The calling thread owns the line for
+// the whole stage.
+__device__ __forceinline__ uint32_t br_sweep(unsigned long long *K, int base, int st, uint32_t mask) {
+  unsigned long long k[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) k[i] = K[base + i * st];
+  uint32_t c = 0;
+#pragma unroll
+  for (int i = 1; i < 16; ++i) {
+    const unsigned long long o = k[i - 1] + kOneHop;
+    if (((mask >> i) & 1u) && k[i - 1] != kInfKey && o < k[i]) {
+      k[i] = o;
+      c |= 1u << i;
+    }
+  }
+#pragma unroll
+  for (int i = 14; i >= 0; --i) {
+    const unsigned long long o = k[i + 1] + kOneHop;
+    if (((mask >> (16 + i)) & 1u) && k[i + 1] != kInfKey && o < k[i]) {
+      k[i] = o;
+      c |= 1u << i;
+    }
+  }
+  if (c) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) K[base + i * st] = k[i];
+  }
+  return c;
+}
+
+// One round over the listed bricks.  Thread t owns three lines of the
+// brick for the whole processing: row t along x (ly, lz) = (t & 15, t >> 4),
+// the y line (lx, lz) = (t & 15, t >> 4) and the z line (lx, ly) =
+// (t & 15, t >> 4); their edge masks stay in registers.  LDS holds the
+// keys (rows padded against bank conflicts), a changed bit per voxel and a
+// dirty flag per line.
 __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
   __shared__ unsigned long long K[kRows * kBRRow];
-  __shared__ uint32_t E[kRows][3];
-  __shared__ uint32_t chg[kRows];  // bit lx of row: the voxel's key changed in this processing
+  __shared__ uint32_t raw[2][kRows];  // y and z edge masks by row, for the transposition into line masks
+  __shared__ uint32_t chg[kRows];     // bit lx of row: the voxel's key changed in this processing
   __shared__ uint8_t dx[kRows], dy[kRows], dz[kRows];  // lines to sweep along x (by row), y (lx, lz), z (lx, ly)
   __shared__ uint32_t flags[8];
   const int t = threadIdx.x;
+  const int lo4 = t & 15, hi4 = t >> 4;
   const uint32_t count = A.ctl[0];
   const size_t kB = (size_t)kRows * BX;
   const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
@@ -905,154 +943,110 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     const int64_t b = A.list[item];
     const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby),
               bz = (int)(b / ((int64_t)A.bg.nbx * A.bg.nby));
-    // keys (16 per thread, coalesced) and edge masks
+    const bool hxm = bx > 0, hxp = bx < A.bg.nbx - 1, hym = by > 0, hyp = by < A.bg.nby - 1, hzm = bz > 0,
+               hzp = bz < A.bg.nbz - 1;
+    // every global read of the processing, issued together: the brick's keys
+    // (16 per thread, coalesced), its edge masks and the six faces of the
+    // neighbours (a missing neighbour reads the brick itself, unused)
+    unsigned long long kv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) kv[i] = A.key[(size_t)b * kB + i * kBRThreads + t];
+    const uint32_t *eq = A.eq + ((size_t)b * kRows + t) * 3;
+    const uint32_t mx = eq[0], e1 = eq[1], e2 = eq[2];
+    const unsigned long long fxm = A.xface[(size_t)(hxm ? b - 1 : b) * 512 + 256 + t];
+    const unsigned long long fxp = A.xface[(size_t)(hxp ? b + 1 : b) * 512 + t];
+    const unsigned long long fym = A.key[(size_t)(hym ? b - bsy : b) * kB + lo4 + 16 * 15 + 256 * hi4];
+    const unsigned long long fyp = A.key[(size_t)(hyp ? b + bsy : b) * kB + lo4 + 256 * hi4];
+    const unsigned long long fzm = A.key[(size_t)(hzm ? b - bsz : b) * kB + lo4 + 16 * hi4 + 256 * 15];
+    const unsigned long long fzp = A.key[(size_t)(hzp ? b + bsz : b) * kB + lo4 + 16 * hi4];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int loc = i * kBRThreads + t;
-      K[br_at(loc & 15, loc >> 4)] = A.key[(size_t)b * kB + loc];
+      K[br_at(loc & 15, loc >> 4)] = kv[i];
     }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) E[t][j] = A.eq[((size_t)b * kRows + t) * 3 + j];
+    raw[0][t] = e1;
+    raw[1][t] = e2;
     chg[t] = 0u;
+    dx[t] = dy[t] = dz[t] = 1;
     if (t < 8) flags[t] = 0u;
     __syncthreads();
+    // line masks of this thread's y line (lx, lz) and z line (lx, ly), in
+    // the x rows' format (bit i: edge to i - 1, bit 16 + i: edge to i + 1)
+    uint32_t my = 0, mz = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t wy = raw[0][i + 16 * hi4], wz = raw[1][hi4 + 16 * i];
+      my |= ((wy >> lo4) & 1u) << i | ((wy >> (16 + lo4)) & 1u) << (16 + i);
+      mz |= ((wz >> lo4) & 1u) << i | ((wz >> (16 + lo4)) & 1u) << (16 + i);
+    }
     // offers of the six face neighbours: their keys plus one hop
     {
-      const int row = t;  // x faces: row t
-      if (bx > 0 && (E[row][0] & 1u)) {
-        const unsigned long long h = A.xface[(size_t)(b - 1) * 512 + 256 + row];
-        if (h != kInfKey && atomicMin(&K[br_at(0, row)], h + kOneHop) > h + kOneHop) atomicOr(&chg[row], 1u);
-      }
-      if (bx < A.bg.nbx - 1 && ((E[row][0] >> 31) & 1u)) {
-        const unsigned long long h = A.xface[(size_t)(b + 1) * 512 + row];
-        if (h != kInfKey && atomicMin(&K[br_at(15, row)], h + kOneHop) > h + kOneHop) atomicOr(&chg[row], 1u << 15);
-      }
-      const int lx = t & 15, hi4 = t >> 4;  // y faces: (lx, lz = hi4); z faces: (lx, ly = hi4)
-      const int rym = 16 * hi4, ryp = 15 + 16 * hi4;
-      if (by > 0 && ((E[rym][1] >> lx) & 1u)) {
-        const unsigned long long h = A.key[(size_t)(b - bsy) * kB + lx + 16 * 15 + 256 * hi4];
-        if (h != kInfKey && atomicMin(&K[br_at(lx, rym)], h + kOneHop) > h + kOneHop) atomicOr(&chg[rym], 1u << lx);
-      }
-      if (by < A.bg.nby - 1 && ((E[ryp][1] >> (16 + lx)) & 1u)) {
-        const unsigned long long h = A.key[(size_t)(b + bsy) * kB + lx + 256 * hi4];
-        if (h != kInfKey && atomicMin(&K[br_at(lx, ryp)], h + kOneHop) > h + kOneHop) atomicOr(&chg[ryp], 1u << lx);
-      }
-      const int rzm = hi4, rzp = hi4 + 16 * 15;
-      if (bz > 0 && ((E[rzm][2] >> lx) & 1u)) {
-        const unsigned long long h = A.key[(size_t)(b - bsz) * kB + lx + 16 * hi4 + 256 * 15];
-        if (h != kInfKey && atomicMin(&K[br_at(lx, rzm)], h + kOneHop) > h + kOneHop) atomicOr(&chg[rzm], 1u << lx);
-      }
-      if (bz < A.bg.nbz - 1 && ((E[rzp][2] >> (16 + lx)) & 1u)) {
-        const unsigned long long h = A.key[(size_t)(b + bsz) * kB + lx + 16 * hi4];
-        if (h != kInfKey && atomicMin(&K[br_at(lx, rzp)], h + kOneHop) > h + kOneHop) atomicOr(&chg[rzp], 1u << lx);
-      }
+      auto offer = [&](bool has, bool edge, unsigned long long h, int lx, int row) {
+        if (has && edge && h != kInfKey && atomicMin(&K[br_at(lx, row)], h + kOneHop) > h + kOneHop)
+          atomicOr(&chg[row], 1u << lx);
+      };
+      offer(hxm, mx & 1u, fxm, 0, t);
+      offer(hxp, (mx >> 31) & 1u, fxp, 15, t);
+      offer(hym, my & 1u, fym, lo4, 16 * hi4);
+      offer(hyp, (my >> 31) & 1u, fyp, lo4, 15 + 16 * hi4);
+      offer(hzm, mz & 1u, fzm, lo4, hi4);
+      offer(hzp, (mz >> 31) & 1u, fzp, lo4, hi4 + 16 * 15);
     }
     __syncthreads();
     // the brick's own fixed point: line sweeps along x, y and z.  A line is
     // swept again along its axis only after a voxel on it changed (every
     // line starts dirty); the loop ends when no line is dirty.
     uint32_t sweeps = 0;
-    dx[t] = dy[t] = dz[t] = 1;
-    __syncthreads();
     for (;;) {
       ++sweeps;
-      if (dx[t]) {  // x: thread t sweeps row t
+      if (dx[t]) {  // row t = (ly, lz)
         dx[t] = 0;
-        unsigned long long k[16];
-        const uint32_t em = E[t][0];
-#pragma unroll
-        for (int x = 0; x < 16; ++x) k[x] = K[br_at(x, t)];
-        uint32_t c = 0;
-#pragma unroll
-        for (int x = 1; x < 16; ++x)
-          if (((em >> x) & 1u) && k[x - 1] != kInfKey && k[x - 1] + kOneHop < k[x]) {
-            k[x] = k[x - 1] + kOneHop;
-            c |= 1u << x;
-          }
-#pragma unroll
-        for (int x = 14; x >= 0; --x)
-          if (((em >> (16 + x)) & 1u) && k[x + 1] != kInfKey && k[x + 1] + kOneHop < k[x]) {
-            k[x] = k[x + 1] + kOneHop;
-            c |= 1u << x;
-          }
-        if (c) {
-          atomicOr(&chg[t], c);
-          const int ly = t & 15, lz = t >> 4;
-#pragma unroll
-          for (int x = 0; x < 16; ++x)
-            if ((c >> x) & 1u) {
-              K[br_at(x, t)] = k[x];
-              dy[x + 16 * lz] = 1;
-              dz[x + 16 * ly] = 1;
-            }
+        uint32_t c = br_sweep(K, t * kBRRow, 1, mx);
+        chg[t] |= c;  // only this thread touches row t's word in this stage
+        while (c) {
+          const int x = __builtin_ctz(c);
+          c &= c - 1;
+          dy[x + 16 * hi4] = 1;
+          dz[x + 16 * lo4] = 1;
         }
       }
       __syncthreads();
-      if (dy[t]) {  // y: thread t sweeps (lx, lz) = (t & 15, t >> 4) along y
+      if (dy[t]) {  // y line (lx, lz) = (lo4, hi4)
         dy[t] = 0;
-        const int lx = t & 15, lz = t >> 4;
-        unsigned long long k[16];
-#pragma unroll
-        for (int y = 0; y < 16; ++y) k[y] = K[br_at(lx, y + 16 * lz)];
-        uint32_t c = 0;
-#pragma unroll
-        for (int y = 1; y < 16; ++y)
-          if (((E[y + 16 * lz][1] >> lx) & 1u) && k[y - 1] != kInfKey && k[y - 1] + kOneHop < k[y]) {
-            k[y] = k[y - 1] + kOneHop;
-            c |= 1u << y;
-          }
-#pragma unroll
-        for (int y = 14; y >= 0; --y)
-          if (((E[y + 16 * lz][1] >> (16 + lx)) & 1u) && k[y + 1] != kInfKey && k[y + 1] + kOneHop < k[y]) {
-            k[y] = k[y + 1] + kOneHop;
-            c |= 1u << y;
-          }
-#pragma unroll
-        for (int y = 0; y < 16; ++y)
-          if ((c >> y) & 1u) {
-            K[br_at(lx, y + 16 * lz)] = k[y];
-            atomicOr(&chg[y + 16 * lz], 1u << lx);
-            dx[y + 16 * lz] = 1;
-            dz[lx + 16 * y] = 1;
-          }
+        uint32_t c = br_sweep(K, 16 * kBRRow * hi4 + lo4, kBRRow, my);
+        while (c) {
+          const int y = __builtin_ctz(c);
+          c &= c - 1;
+          atomicOr(&chg[y + 16 * hi4], 1u << lo4);
+          dx[y + 16 * hi4] = 1;
+          dz[lo4 + 16 * y] = 1;
+        }
       }
       __syncthreads();
-      if (dz[t]) {  // z: thread t sweeps (lx, ly) = (t & 15, t >> 4) along z
+      if (dz[t]) {  // z line (lx, ly) = (lo4, hi4)
         dz[t] = 0;
-        const int lx = t & 15, ly = t >> 4;
-        unsigned long long k[16];
-#pragma unroll
-        for (int z = 0; z < 16; ++z) k[z] = K[br_at(lx, ly + 16 * z)];
-        uint32_t c = 0;
-#pragma unroll
-        for (int z = 1; z < 16; ++z)
-          if (((E[ly + 16 * z][2] >> lx) & 1u) && k[z - 1] != kInfKey && k[z - 1] + kOneHop < k[z]) {
-            k[z] = k[z - 1] + kOneHop;
-            c |= 1u << z;
-          }
-#pragma unroll
-        for (int z = 14; z >= 0; --z)
-          if (((E[ly + 16 * z][2] >> (16 + lx)) & 1u) && k[z + 1] != kInfKey && k[z + 1] + kOneHop < k[z]) {
-            k[z] = k[z + 1] + kOneHop;
-            c |= 1u << z;
-          }
-#pragma unroll
-        for (int z = 0; z < 16; ++z)
-          if ((c >> z) & 1u) {
-            K[br_at(lx, ly + 16 * z)] = k[z];
-            atomicOr(&chg[ly + 16 * z], 1u << lx);
-            dx[ly + 16 * z] = 1;
-            dy[lx + 16 * z] = 1;
-          }
+        uint32_t c = br_sweep(K, hi4 * kBRRow + lo4, 16 * kBRRow, mz);
+        while (c) {
+          const int z = __builtin_ctz(c);
+          c &= c - 1;
+          atomicOr(&chg[hi4 + 16 * z], 1u << lo4);
+          dx[hi4 + 16 * z] = 1;
+          dy[lo4 + 16 * z] = 1;
+        }
       }
       __syncthreads();  // every dirty mark of the z stage is visible before the test
       if (!__syncthreads_or(dx[t] | dy[t] | dz[t])) break;
     }
-    // store what changed; note which faces changed
+    // store what changed; note which faces changed.  The thread index is
+    // passed through an empty asm statement so that the store addresses are
+    // recomputed here instead of being kept live (in registers) from the
+    // loads at the top across the sweeps.
+    int tt = t;
+    asm volatile("" : "+v"(tt));
     uint32_t fc = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int loc = i * kBRThreads + t;
+      const int loc = i * kBRThreads + tt;
       const int lx = loc & 15, row = loc >> 4, ly = row & 15, lz = row >> 4;
       if ((chg[row] >> lx) & 1u) {
         const unsigned long long k = K[br_at(lx, row)];
@@ -1070,15 +1064,15 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     }
     __syncthreads();
     // a changed face: the neighbour across it (if any) works in round r + 1
-    const uint32_t nb_exists = (bx > 0 ? 2u : 0u) | (bx < A.bg.nbx - 1 ? 4u : 0u) | (by > 0 ? 8u : 0u) |
-                               (by < A.bg.nby - 1 ? 16u : 0u) | (bz > 0 ? 32u : 0u) | (bz < A.bg.nbz - 1 ? 64u : 0u);
+    const uint32_t nb_exists = (hxm ? 2u : 0u) | (hxp ? 4u : 0u) | (hym ? 8u : 0u) | (hyp ? 16u : 0u) |
+                               (hzm ? 32u : 0u) | (hzp ? 64u : 0u);
     const uint32_t f = flags[0] & nb_exists;
     if (t >= 1 && t < 7 && ((f >> t) & 1u)) br_mark(A, bx, by, bz, t, r + 1);
     if (t == 0 && f) A.alive[(r + 1) % 3] = 1u;
     __syncthreads();
   }
 }
-__global__ __launch_bounds__(kBRThreads) void k_br_round(BRArgs A, uint32_t r) { d_br_round(A, r); }
+__global__ __launch_bounds__(kBRThreads, 4) void k_br_round(BRArgs A, uint32_t r) { d_br_round(A, r); }
 
 
 // End of a pass: keys to the caller's C-order cells (NONE where unreached),
@@ -1506,9 +1500,9 @@ VTEngine vt_engine(const Geom &g, uint32_t S) {
   return e;
 }
 
-// Benchmark timing of the level kernel: while enabled, an event pair on the
-// launch stream around every batch of level launches; read back by
-// lsrvt_timing_read.
+// Benchmark timing of the Voronoi passes' dominant kernel (levels or
+// relaxation rounds): while enabled, an event pair on the launch stream
+// around every batch of launches; read back by lsrvt_timing_read.
 struct KernelTimer {
   std::mutex mu;
   bool on = false;
@@ -1517,6 +1511,7 @@ struct KernelTimer {
   uint64_t launches = 0;
   uint64_t passes = 0;
   int64_t voxels_per_pass = 0;
+  int32_t engines = 0;  // bit 0: level passes recorded, bit 1: relaxation passes
 };
 // one timer per host thread: calls issued from different threads (streams)
 // never share instrumentation state
@@ -1741,6 +1736,7 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
     timer().passes += 1;
+    timer().engines |= 1;
     timer().voxels_per_pass = g.n;
   }
   return LSRVT_OK;
@@ -1798,6 +1794,7 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
   }
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
+    timer().engines |= 1;
     timer().passes += 1;
     timer().voxels_per_pass = g.n;
   }
@@ -1896,6 +1893,7 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     std::lock_guard<std::mutex> lk(timer().mu);
     timer().passes += 1;
     timer().voxels_per_pass = g.n;
+    timer().engines |= 2;
   }
   return LSRVT_OK;
 }
@@ -2016,7 +2014,7 @@ __global__ __launch_bounds__(256) void kb_list(const JobDev *J, int32_t t, uint3
   d_br_list(j.A, r);
 }
 
-__global__ __launch_bounds__(kBRThreads) void kb_round(const JobDev *J, int32_t t, uint32_t r) {
+__global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J, int32_t t, uint32_t r) {
   const JobDev &j = J[blockIdx.y];
   if (t > j.iters) return;
   d_br_round(j.A, r);
@@ -2177,6 +2175,7 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
     LSRVT_LAUNCHED();
     if (timed) {
       std::lock_guard<std::mutex> lk(timer().mu);
+      timer().engines |= 2;
       for (int32_t i = 0; i < n; ++i)
         if (t <= hj[(size_t)i].iters) {
           timer().passes += 1;
@@ -2281,7 +2280,8 @@ extern "C" int32_t lsrvt_timing_enable(int32_t enable) {
   return LSRVT_OK;
 }
 
-extern "C" int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass) {
+extern "C" int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *passes, int64_t *voxels_per_pass,
+                                     int32_t *engines) {
   KernelTimer &T = timer();
   std::lock_guard<std::mutex> lk(T.mu);
   for (auto &ev : T.pending) {
@@ -2296,6 +2296,8 @@ extern "C" int32_t lsrvt_timing_read(double *ms, uint64_t *launches, uint64_t *p
   if (launches) *launches = T.launches;
   if (passes) *passes = T.passes;
   if (voxels_per_pass) *voxels_per_pass = T.voxels_per_pass;
+  if (engines) *engines = T.engines;
+  T.engines = 0;
   T.ms = 0.0;
   T.launches = 0;
   T.passes = 0;
