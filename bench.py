@@ -53,6 +53,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 VT_BYTES_PER_VOXEL = 5           # one Voronoi pass must read the band (1 B) and write the cell (4 B)
+LOS_BYTES_PER_VOXEL = 20         # a line-of-sight pass: comp in (4 B); length, source, cell out (8 + 4 + 4 B)
 PROFILES = os.path.join(ROOT, "profiles")
 CVT_SOURCE = os.path.join(ROOT, "paper_2208_06970_amd", "csrc", "cvt.hip")
 
@@ -258,6 +259,10 @@ def bench_flame(args):
         "stats_dtype": "f32 compensated per cell, f64 merges",
         "roofline": roofline(timing, "flame"),
     }
+    if not args.no_extras:
+        _log("flame: joint moments of the step's cells, 18 variables")
+        out["comoments"] = bench_comoments(L, step, cc, x, wl.n_bands, n, reps=1)
+        torch.cuda.empty_cache()
     del x, e
     if not args.no_cpu_baseline:
         _log("flame: timing the oracle on a bounded sample")
@@ -502,7 +507,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.fourier:
-        f = bench_fourier(args)
+        f = bench_fourier(args, extras=not args.no_extras)
         out = {"metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
                "n_gpus": 1, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
                "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
@@ -555,10 +560,19 @@ def bench_los(L, cc, sd, w, n, iters):
     r = L.lsrvt_los_cvt(cc.comp, sd, w, iters, ws=ws)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3
+    # roofline of the whole loop against the bytes a pass must move at the
+    # least: component ids in (4 B), float64 length, source and cell out
+    # (8 + 4 + 4 B) per voxel and pass; the updates ride along in the time
+    alg = LOS_BYTES_PER_VOXEL * n * (iters + 1)
+    achieved = alg / (ms / 1e3) / 1e9
     return {"ms": round(ms, 3), "iters": iters, "ms_per_pass": round(ms / (iters + 1), 3),
             "gvox_per_iter_s": round(n * iters / (ms / 1e3) / 1e9, 4), "sweeps": int(r.vt.sweeps[0]),
             "sweeps_first_pass": int(one_pass_sweeps), "dtype": "f64 lengths, exact integer update",
-            "includes": "host synchronisation every 8 sweeps"}
+            "includes": "host synchronisation every 8 sweeps",
+            "roofline": {"bound": "hbm", "kernel": "line-of-sight pass (k_los_mark, k_los_eval, k_los_apply) and update",
+                         "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                         "alg_bytes_per_voxel_pass": LOS_BYTES_PER_VOXEL, "passes": iters + 1}}
 
 
 def bench_seeding(L, cc, w, n, reps: int = 5):

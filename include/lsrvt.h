@@ -272,9 +272,10 @@ int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, const uint32_t 
  *   mean [U][m], m2 [U][P2], m3 [U][P3], m4 [U][P4] float64; cells are
  *   indexed by site id.
  *   d_cell, d_sites, d_site_comp, d_comp_band: as for lsrvt_aggregate
- *   d_vars        float32[m][N], 1 <= m <= 8
+ *   d_vars        float32[m][N], 1 <= m <= 18 (at m = 18: 171, 1140 and 5985
+ *                 entries of M2, M3 and M4 per unit)
  * Synchronises the stream (layout sizes, merge work lists).  Errors:
- * EINVAL (m outside 1..8, bands outside 1..255, NULL arrays).
+ * EINVAL (m outside 1..18, bands outside 1..255, NULL arrays).
  * Workspace: lsrvt_comoments_workspace(dims, n_sites, n_comp, n_bands, m).
  */
 typedef struct {

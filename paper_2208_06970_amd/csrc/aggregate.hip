@@ -31,6 +31,7 @@ namespace lsrvt {
 namespace {
 
 constexpr int kAggThreads = 256;
+constexpr int kAggMaxThreads = 512;  // k_agg_cell with two lane groups of up to 256 units
 constexpr int kMaxVars = 32;
 constexpr int kMaxPairs = kMaxVars * (kMaxVars + 1) / 2;
 constexpr int64_t kItemVoxels = 4096;
@@ -114,7 +115,7 @@ struct CellArgs {
   const float *vars;  // [m][N]
   const float *edges; // [m][B+1] or null
   int64_t n;
-  int m, B, U, G, P, tile;  // tile: voxels staged in LDS per round (multiple of 256, at most 1024)
+  int m, B, U, G, P, tile;  // tile: voxels staged in LDS per round (1, 2 or 4 times the block size)
   Pairs pairs;
   const uint32_t *item_off;   // [S + 1] by rank
   const uint32_t *item_rank;  // [n_items]
@@ -127,25 +128,62 @@ struct CellArgs {
 
 constexpr int kMaxVPT = 4;  // voxels per thread and round
 
+// Wave-wide min / max by DPP lane moves (quad permutes, row mirrors, row
+// broadcasts; every lane of the wave active): the result is read from the
+// last lane and returned to all lanes.
+#define LSRVT_DPP_STEP(OP, ID, CTRL, RMASK) \
+  v = OP(v, (uint32_t)__builtin_amdgcn_update_dpp((int)(ID), (int)v, CTRL, RMASK, 0xF, false))
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor(v, o, kWave));
-  return v;
+  LSRVT_DPP_STEP(min, 0xFFFFFFFFu, 0xB1, 0xF);   // quad_perm [1,0,3,2]
+  LSRVT_DPP_STEP(min, 0xFFFFFFFFu, 0x4E, 0xF);   // quad_perm [2,3,0,1]
+  LSRVT_DPP_STEP(min, 0xFFFFFFFFu, 0x141, 0xF);  // row_half_mirror
+  LSRVT_DPP_STEP(min, 0xFFFFFFFFu, 0x140, 0xF);  // row_mirror
+  LSRVT_DPP_STEP(min, 0xFFFFFFFFu, 0x142, 0xA);  // row_bcast:15 into rows 1 and 3
+  LSRVT_DPP_STEP(min, 0xFFFFFFFFu, 0x143, 0xC);  // row_bcast:31 into rows 2 and 3
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor(v, o, kWave));
-  return v;
+  LSRVT_DPP_STEP(max, 0u, 0xB1, 0xF);
+  LSRVT_DPP_STEP(max, 0u, 0x4E, 0xF);
+  LSRVT_DPP_STEP(max, 0u, 0x141, 0xF);
+  LSRVT_DPP_STEP(max, 0u, 0x140, 0xF);
+  LSRVT_DPP_STEP(max, 0u, 0x142, 0xA);
+  LSRVT_DPP_STEP(max, 0u, 0x143, 0xC);
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+#undef LSRVT_DPP_STEP
+
+// Histogram bin of x: #{interior edges e_1..e_{B-1} <= x} for ascending
+// edges e_0..e_B (sc = B / (e_B - e_0)).  A guess from the mean edge spacing
+// is kept when the two edges around it confirm it (always, for evenly spaced
+// edges); otherwise bisection.  NaN lands in bin 0, as every comparison with
+// it is false.
+__device__ __forceinline__ int hist_bin(float x, const float *e, int B, float e0, float sc) {
+  const int g = (int)fminf(fmaxf((x - e0) * sc, 0.0f), (float)(B - 1));
+  if ((g == 0 || e[g] <= x) && (g == B - 1 || x < e[g + 1])) return g;
+  int a = 1, b = B;
+  while (a < b) {
+    const int mid = (a + b) >> 1;
+    if (e[mid] <= x)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  return a - 1;
 }
 
-// R = unit slots per lane: with R == 1 the U units are replicated over
-// G = 256 / U lane groups that split the voxels; with R > 1 (more units than
-// lanes) lane t owns units t, t + 256, ... and G = 1.
-template <int R>
-__global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
+// R = unit slots per lane: with R == 1 the U units are replicated over G
+// lane groups that split each staging round's voxels into G contiguous
+// ranges (multiples of four voxels, in order; the workgroup has at least
+// G * U threads); with R > 1 (more units than lanes) lane t owns units t,
+// t + NT, ... and G = 1.  VPT = voxels staged per thread and round (the
+// round holds VPT * NT voxels).
+template <int R, int VPT>
+__global__ __launch_bounds__(kAggMaxThreads) void k_agg_cell(CellArgs A) {
   extern __shared__ uint8_t smem[];
-  const int m = A.m, B = A.B, U = A.U, G = A.G, TL = A.tile, ld = A.tile + 1;
-  float *dv = reinterpret_cast<float *>(smem);                       // [m][TL + 1] values minus the site value
+  const int m = A.m, B = A.B, U = A.U, G = A.G, TL = A.tile, ld = A.tile + 4;
+  const int NT = blockDim.x;
+  float *dv = reinterpret_cast<float *>(smem);                       // [m][TL + 4] values minus the site value
   uint32_t *hist_l = reinterpret_cast<uint32_t *>(dv + m * ld);      // [m*B]
   uint32_t *kmin_l = hist_l + m * B;                                 // [m]
   uint32_t *kmax_l = kmin_l + m;                                     // [m]
@@ -153,11 +191,14 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
   float *ph = K + m;                                                 // [G*U]
   float *pl = ph + G * U;                                            // [G*U]
   float *edg = pl + G * U;                                           // [m][B+1]
+  float *scl = edg + m * (B + 1);                                    // [m] B / (e_B - e_0)
   const int t = threadIdx.x;
   const int lane = lane_id();
   const int grp = R == 1 ? t / U : 0;
-  if (B > 0)
-    for (int i = t; i < m * (B + 1); i += kAggThreads) edg[i] = A.edges[i];
+  if (B > 0) {
+    for (int i = t; i < m * (B + 1); i += NT) edg[i] = A.edges[i];
+    for (int j = t; j < m; j += NT) scl[j] = (float)B / (A.edges[j * (B + 1) + B] - A.edges[j * (B + 1)]);
+  }
 
   const uint32_t n_list = *A.list_cnt;
   for (uint32_t k = blockIdx.x; k < n_list; k += gridDim.x) {
@@ -168,7 +209,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
     const uint32_t start = A.cell_off[r] + part * (uint32_t)kItemVoxels;
     const uint32_t stop = min(A.cell_off[r + 1], start + (uint32_t)kItemVoxels);
 
-    for (int i = t; i < m * B; i += kAggThreads) hist_l[i] = 0;
+    for (int i = t; i < m * B; i += NT) hist_l[i] = 0;
     if (t < m) {
       kmin_l[t] = 0xFFFFFFFFu;
       kmax_l[t] = 0u;
@@ -181,12 +222,12 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
 
     for (uint32_t base = start; base < stop; base += (uint32_t)TL) {
       const int nt = (int)min((uint32_t)TL, stop - base);
-      // stage: thread t owns voxels t, t + 256, ... of the round
-      uint32_t vv[kMaxVPT];
-      bool ok[kMaxVPT];
+      // stage: thread t owns voxels t, t + NT, ... of the round
+      uint32_t vv[VPT];
+      bool ok[VPT];
 #pragma unroll
-      for (int i = 0; i < kMaxVPT; ++i) {
-        const int q = t + i * kAggThreads;
+      for (int i = 0; i < VPT; ++i) {
+        const int q = t + i * NT;
         ok[i] = q < nt;
         vv[i] = ok[i] ? A.perm[base + q] : 0u;
       }
@@ -194,14 +235,14 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
       for (int j = 0; j < m; ++j) {
         const float kj = K[j];
         const float *col = A.vars + (int64_t)j * A.n;
-        float x[kMaxVPT];
+        float x[VPT];
 #pragma unroll
-        for (int i = 0; i < kMaxVPT; ++i) x[i] = ok[i] ? col[vv[i]] : 0.0f;
+        for (int i = 0; i < VPT; ++i) x[i] = ok[i] ? col[vv[i]] : 0.0f;
         uint32_t kmn = 0xFFFFFFFFu, kmx = 0u;
 #pragma unroll
-        for (int i = 0; i < kMaxVPT; ++i) {
+        for (int i = 0; i < VPT; ++i) {
           if (!ok[i]) continue;
-          dv[j * ld + t + i * kAggThreads] = x[i] - kj;
+          dv[j * ld + t + i * NT] = x[i] - kj;
           const uint32_t kk = f2key(x[i]);
           kmn = min(kmn, kk);
           kmx = max(kmx, kk);
@@ -214,43 +255,52 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
         }
         if (B > 0) {
           const float *e = edg + j * (B + 1);
+          const float e0 = e[0], sc = scl[j];
 #pragma unroll
-          for (int i = 0; i < kMaxVPT; ++i) {
-            if (i * kAggThreads >= TL) break;
-            // bin = #{interior edges e_1..e_{B-1} <= x}: upper bound by bisection
-            int bin = -1;
-            if (ok[i]) {
-              int a = 1, b = B;
-              while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (e[mid] <= x[i])
-                  a = mid + 1;
-                else
-                  b = mid;
-              }
-              bin = a - 1;
-            }
+          for (int i = 0; i < VPT; ++i)
             // one LDS atomic per lane; the LDS serialises lanes that hit one bin
-            if (bin >= 0) atomicAdd(&hist_l[j * B + bin], 1u);
-          }
+            if (ok[i]) atomicAdd(&hist_l[j * B + hist_bin(x[i], e, B, e0, sc)], 1u);
         }
       }
       __syncthreads();
+      // this group's voxels of the round: [v0, v1), four at a time
+      const int cs = R == 1 ? ((nt + G - 1) / G + 3) & ~3 : nt;
+      const int v0 = min(nt, grp * cs), v1 = min(nt, v0 + cs);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const int u = R == 1 ? t % U : t + q * kAggThreads;
+        const int u = R == 1 ? t % U : t + q * NT;
         const bool worker = R == 1 ? t < G * U : u < U;
         if (!worker) continue;
         if (u < m) {
           const float *du = dv + u * ld;
-          for (int v = grp; v < nt; v += G) acc(hi[q], lo[q], du[v], 0.0f);
+          int v = v0;
+          for (; v + 4 <= v1; v += 4) {
+            const float4 a = *reinterpret_cast<const float4 *>(du + v);
+            acc(hi[q], lo[q], a.x, 0.0f);
+            acc(hi[q], lo[q], a.y, 0.0f);
+            acc(hi[q], lo[q], a.z, 0.0f);
+            acc(hi[q], lo[q], a.w, 0.0f);
+          }
+          for (; v < v1; ++v) acc(hi[q], lo[q], du[v], 0.0f);
         } else {
           const int p = u - m;
           const float *dj = dv + A.pairs.j[p] * ld, *dk = dv + A.pairs.k[p] * ld;
-          for (int v = grp; v < nt; v += G) {
-            const float a = dj[v], b = dk[v];
-            const float pr = a * b;
-            const float pe = __builtin_fmaf(a, b, -pr);  // exact error of the product
+          int v = v0;
+          for (; v + 4 <= v1; v += 4) {
+            const float4 a = *reinterpret_cast<const float4 *>(dj + v);
+            const float4 b = *reinterpret_cast<const float4 *>(dk + v);
+            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const float pr = av[i] * bv[i];
+              const float pe = __builtin_fmaf(av[i], bv[i], -pr);  // exact error of the product
+              acc(hi[q], lo[q], pr, pe);
+            }
+          }
+          for (; v < v1; ++v) {
+            const float a0 = dj[v], b0 = dk[v];
+            const float pr = a0 * b0;
+            const float pe = __builtin_fmaf(a0, b0, -pr);
             acc(hi[q], lo[q], pr, pe);
           }
         }
@@ -260,7 +310,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
     // combine the lane groups in group order
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      const int u = R == 1 ? t % U : t + q * kAggThreads;
+      const int u = R == 1 ? t % U : t + q * NT;
       const bool worker = R == 1 ? t < G * U : u < U;
       if (worker) {
         ph[grp * U + u] = hi[q];
@@ -268,7 +318,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
       }
     }
     __syncthreads();
-    for (int u = t; u < U; u += kAggThreads) {
+    for (int u = t; u < U; u += NT) {
       float H = 0.0f, Lo = 0.0f;
       for (int gg = 0; gg < G; ++gg) {
         acc(H, Lo, ph[gg * U + u], 0.0f);
@@ -280,7 +330,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell(CellArgs A) {
     // flush exact integer/compare statistics
     if (A.hist) {
       uint32_t *dst = A.hist + (int64_t)s * m * B;
-      for (int i = t; i < m * B; i += kAggThreads)
+      for (int i = t; i < m * B; i += NT)
         if (hist_l[i]) atomicAdd(&dst[i], hist_l[i]);
     }
     if (t < m) {
@@ -364,22 +414,11 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell_wave(CellArgs A) {
       }
       if (B > 0) {
         const float *e = edg + j * (B + 1);
+        const float e0 = e[0], sc = (float)B / (e[B] - e0);
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
           if (i * kWave >= nt) break;
-          int bin = -1;
-          if (ok[i]) {
-            int a = 1, b = B;
-            while (a < b) {
-              const int mid = (a + b) >> 1;
-              if (e[mid] <= x[i])
-                a = mid + 1;
-              else
-                b = mid;
-            }
-            bin = a - 1;
-          }
-          if (bin >= 0) atomicAdd(&hist_l[j * B + bin], 1u);
+          if (ok[i]) atomicAdd(&hist_l[j * B + hist_bin(x[i], e, B, e0, sc)], 1u);
         }
       }
     }
@@ -1024,23 +1063,35 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     A.list = W.big_list;
     A.list_cnt = counts + 1;
     const int R = (U + kAggThreads - 1) / kAggThreads;
-    A.G = R == 1 ? kAggThreads / U : 1;
-    // the largest staging round that keeps the workgroup within 48 KiB of LDS
-    const size_t fixed = sizeof(float) * ((size_t)m * B + 3 * m + 2 * (size_t)A.G * U + (size_t)m * (B + 1));
-    size_t lds = 0;
-    for (int tl = kMaxVPT * kAggThreads; tl >= kAggThreads; tl /= 2) {
-      A.tile = tl;
-      lds = fixed + sizeof(float) * (size_t)m * (tl + 1);
-      if (lds <= 49152) break;
+    // lane groups: 256 / U of them in 256 threads while units fill at most
+    // half the workgroup, else two groups in up to 512 threads (all lanes but
+    // the rounding to whole waves work)
+    int NT = kAggThreads;
+    if (R == 1) {
+      A.G = 2 * U <= kAggThreads ? kAggThreads / U : 2;
+      NT = std::max(kAggThreads, (A.G * U + kWave - 1) / kWave * kWave);
+    } else {
+      A.G = 1;
     }
-    if (lds > 65536 || R > 3) return LSRVT_EINVAL;
-    unsigned grid = n_items < 16384 ? n_items : 16384;
+    // the largest staging round (NT, 2 NT or 4 NT voxels) that keeps the
+    // workgroup within 40 KiB of LDS, so four workgroups share a CU
+    const size_t fixed = sizeof(float) * ((size_t)m * B + 3 * m + 2 * (size_t)A.G * U + (size_t)m * (B + 1) + m);
+    size_t lds = 0;
+    int vpt = kMaxVPT;
+    for (; vpt >= 1; vpt /= 2) {
+      A.tile = vpt * NT;
+      lds = fixed + sizeof(float) * (size_t)m * (A.tile + 4);
+      if (lds <= 40960 || vpt == 1) break;
+    }
+    if (lds > 65536 || R > 3 || NT > kAggMaxThreads) return LSRVT_EINVAL;
+    const unsigned grid = n_items < 16384 ? n_items : 16384;
+    auto launch = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, A); };
     if (R == 1)
-      hipLaunchKernelGGL(k_agg_cell<1>, dim3(grid), dim3(kAggThreads), lds, s, A);
+      vpt == 4 ? launch(k_agg_cell<1, 4>) : vpt == 2 ? launch(k_agg_cell<1, 2>) : launch(k_agg_cell<1, 1>);
     else if (R == 2)
-      hipLaunchKernelGGL(k_agg_cell<2>, dim3(grid), dim3(kAggThreads), lds, s, A);
+      vpt == 4 ? launch(k_agg_cell<2, 4>) : vpt == 2 ? launch(k_agg_cell<2, 2>) : launch(k_agg_cell<2, 1>);
     else
-      hipLaunchKernelGGL(k_agg_cell<3>, dim3(grid), dim3(kAggThreads), lds, s, A);
+      vpt == 4 ? launch(k_agg_cell<3, 4>) : vpt == 2 ? launch(k_agg_cell<3, 2>) : launch(k_agg_cell<3, 1>);
     LSRVT_LAUNCHED();
   }
 

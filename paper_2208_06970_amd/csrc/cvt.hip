@@ -840,19 +840,31 @@ __global__ void k_br_sites(const uint32_t *__restrict__ sites, uint32_t S, BRArg
 // per voxel slot (the slot index is the brick-major index).
 __device__ __forceinline__ void d_br_reset(const uint8_t *__restrict__ moved, BRArgs A) {
   const int64_t slots = A.bg.nbricks * kRows * BX;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += (int64_t)gridDim.x * blockDim.x) {
-    const unsigned long long k = A.key[i];
-    if (k == kInfKey) continue;
-    const uint32_t id = (uint32_t)(k & 0xFFFFFFFFull);
-    if (!moved[id]) continue;
-    A.key[i] = kInfKey;
-    const int64_t b = i / (kRows * BX);
-    const int loc = (int)(i % (kRows * BX));
-    const int lx = loc & 15, row = loc >> 4;
-    if (lx == 0) A.xface[b * 512 + row] = kInfKey;
-    if (lx == BX - 1) A.xface[b * 512 + 256 + row] = kInfKey;
-    A.mark[(size_t)1 * A.bg.nbricks + b] = 1u;  // round 1 has parity 1
-    A.alive[1] = 1u;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  constexpr int kU = 4;  // slots per thread and step: their loads are issued together
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < slots; i0 += kU * stride) {
+    unsigned long long k[kU];
+    uint8_t mv[kU];
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      const int64_t i = i0 + j * stride;
+      k[j] = i < slots ? A.key[i] : kInfKey;
+    }
+#pragma unroll
+    for (int j = 0; j < kU; ++j) mv[j] = k[j] != kInfKey ? moved[(uint32_t)(k[j] & 0xFFFFFFFFull)] : (uint8_t)0;
+#pragma unroll
+    for (int j = 0; j < kU; ++j) {
+      if (!mv[j]) continue;
+      const int64_t i = i0 + j * stride;
+      A.key[i] = kInfKey;
+      const int64_t b = i / (kRows * BX);
+      const int loc = (int)(i % (kRows * BX));
+      const int lx = loc & 15, row = loc >> 4;
+      if (lx == 0) A.xface[b * 512 + row] = kInfKey;
+      if (lx == BX - 1) A.xface[b * 512 + 256 + row] = kInfKey;
+      A.mark[(size_t)1 * A.bg.nbricks + b] = 1u;  // round 1 has parity 1
+      A.alive[1] = 1u;
+    }
   }
 }
 __global__ __launch_bounds__(256) void k_br_reset(const uint8_t *__restrict__ moved, BRArgs A) { d_br_reset(moved, A); }
@@ -935,9 +947,9 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
   __shared__ uint32_t flags[8];
   const int t = threadIdx.x;
   const int lo4 = t & 15, hi4 = t >> 4;
-  const uint32_t count = A.ctl[0];
   const size_t kB = (size_t)kRows * BX;
   const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
+  const uint32_t count = A.ctl[0];
   if (blockIdx.x == 0 && t == 0) A.hist[r % kHistLen] = count;  // bricks that work in round r
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
     const int64_t b = A.list[item];
@@ -1102,6 +1114,116 @@ __global__ __launch_bounds__(kVTThreads) void k_br_finish(const unsigned long lo
 struct Sums {
   unsigned long long *M, *Sx, *Sy, *Sz;
 };
+
+// The centroid sums of the update (Sec. 3.1: mass and mass-weighted
+// position of every cell, exact uint64 integers, so their order does not
+// matter) taken at the end of the Voronoi pass that produces the cells: the
+// pass's last kernel holds every voxel's cell id once anyway, so the sums
+// cost no second read of the cell array.  One workgroup per 16^3 brick
+// stages the brick's cells and weights in LDS; thread t then walks row t
+// (16 voxels along x) and adds every run of equal cell id into an LDS table
+// keyed by cell id (global atomics when the table is full); the table is
+// flushed with one set of global atomics per distinct cell of the brick.
+struct Fuse {
+  const uint16_t *w;  // weights (C order) or null for unit weights
+  uint32_t S;
+  Sums sums;          // zeroed before the pass
+};
+
+constexpr int kFinTab = 256;
+constexpr int kFinRow = BX + 1;  // LDS row stride: the row walks read without bank conflicts
+struct FinLds {
+  uint32_t c[kRows * kFinRow];
+  uint16_t w[kRows * kFinRow];
+  uint32_t tkey[kFinTab];
+  unsigned long long tM[kFinTab], tX[kFinTab], tY[kFinTab], tZ[kFinTab];
+};
+
+__device__ __forceinline__ void fin_clear(FinLds &L) {
+  for (int i = threadIdx.x; i < kFinTab; i += blockDim.x) {
+    L.tkey[i] = kNone;
+    L.tM[i] = L.tX[i] = L.tY[i] = L.tZ[i] = 0ull;
+  }
+}
+
+// After the brick's cells and weights are staged (and a barrier): the row
+// walks and the flush.  Ends with a barrier.
+__device__ __forceinline__ void fin_sums(FinLds &L, const Fuse &F, int bx, int by, int bz, const Geom &g) {
+  const int t = threadIdx.x;
+  const int y = by * BY + (t & 15), z = bz * BZ + (t >> 4);
+  const uint32_t x0 = (uint32_t)(bx * BX);
+  if (y < g.ny && z < g.nz) {
+    uint32_t cur = kNone, m = 0, sx = 0;  // run mass and sum of w * (x - x0): below 2^24
+    auto flush = [&]() {
+      if (cur < F.S && m) {
+        const unsigned long long M = m, X = (unsigned long long)m * x0 + sx, Y = (unsigned long long)m * (uint32_t)y,
+                                 Z = (unsigned long long)m * (uint32_t)z;
+        const int sl = lds_slot<kFinTab>(L.tkey, cur);
+        if (sl >= 0) {
+          atomicAdd(&L.tM[sl], M);
+          atomicAdd(&L.tX[sl], X);
+          atomicAdd(&L.tY[sl], Y);
+          atomicAdd(&L.tZ[sl], Z);
+        } else {
+          atomicAdd(&F.sums.M[cur], M);
+          atomicAdd(&F.sums.Sx[cur], X);
+          atomicAdd(&F.sums.Sy[cur], Y);
+          atomicAdd(&F.sums.Sz[cur], Z);
+        }
+      }
+    };
+#pragma unroll
+    for (int i = 0; i < BX; ++i) {
+      const uint32_t c = L.c[t * kFinRow + i], wv = L.w[t * kFinRow + i];
+      if (c != cur) {
+        flush();
+        cur = c;
+        m = sx = 0;
+      }
+      m += wv;
+      sx += wv * (uint32_t)i;
+    }
+    flush();
+  }
+  __syncthreads();
+  for (int i = t; i < kFinTab; i += blockDim.x) {
+    const uint32_t c = L.tkey[i];
+    if (c != kNone && L.tM[i]) {
+      atomicAdd(&F.sums.M[c], L.tM[i]);
+      atomicAdd(&F.sums.Sx[c], L.tX[i]);
+      atomicAdd(&F.sums.Sy[c], L.tY[i]);
+      atomicAdd(&F.sums.Sz[c], L.tZ[i]);
+    }
+  }
+  __syncthreads();
+}
+
+// End of a relaxation pass followed by an update: the keys to C-order cells
+// (as k_br_finish) and the centroid sums, one workgroup per brick.
+__global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const unsigned long long *__restrict__ key, Geom g,
+                                                               VTGrid bg, uint32_t *__restrict__ cell, Fuse F) {
+  __shared__ FinLds L;
+  const int t = threadIdx.x;
+  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
+    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+    fin_clear(L);
+#pragma unroll 4
+    for (int i = 0; i < BX; ++i) {
+      const int loc = i * kVTThreads + t;
+      const int x = bx * BX + (loc & 15), y = by * BY + ((loc >> 4) & 15), z = bz * BZ + (loc >> 8);
+      const bool in = x < g.nx && y < g.ny && z < g.nz;
+      const unsigned long long k = key[(size_t)b * (kRows * BX) + loc];
+      const uint32_t c = k == kInfKey ? kNone : (uint32_t)(k & 0xFFFFFFFFull);
+      const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      if (in) cell[v] = c;
+      const int li = (loc >> 4) * kFinRow + (loc & 15);
+      L.c[li] = in ? c : kNone;
+      L.w[li] = in ? (F.w ? F.w[v] : (uint16_t)1) : (uint16_t)0;
+    }
+    __syncthreads();
+    fin_sums(L, F, bx, by, bz, g);
+  }
+}
 
 // One workgroup per 64x8x8 tile; each wave takes rows of the tile with one
 // lane per voxel (coalesced loads).  A segmented scan over the lanes sums
@@ -1574,11 +1696,54 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_finish(const uint16_t *__rest
   }
 }
 
+// The same end of a level-search pass with the centroid sums of the update
+// that follows (see k_br_finish_sums), one workgroup per brick.
+template <bool INC>
+__global__ __launch_bounds__(kVTThreads) void k_vt_finish_sums(const uint16_t *__restrict__ vis,
+                                                               const uint16_t *__restrict__ inv, Geom g, VTGrid bg,
+                                                               uint32_t *__restrict__ cellb,
+                                                               uint32_t *__restrict__ cell, Fuse F) {
+  __shared__ FinLds L;
+  const int t = threadIdx.x;
+  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
+    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
+    fin_clear(L);
+#pragma unroll 4
+    for (int i = 0; i < BX; ++i) {
+      const int loc = i * kVTThreads + t;
+      const int lx = loc & 15;
+      const int64_t rr = b * kRows + (loc >> 4);
+      const int x = bx * BX + lx, y = by * BY + ((loc >> 4) & 15), z = bz * BZ + (loc >> 8);
+      const bool in = x < g.nx && y < g.ny && z < g.nz;
+      const size_t bi = (size_t)b * (kRows * BX) + loc;
+      uint32_t c = kNone;
+      if (in) {
+        bool miss = !((vis[rr] >> lx) & 1u);
+        if (INC) miss = miss && ((inv[rr] >> lx) & 1u);
+        c = cellb[bi];
+        if (miss) {
+          c = kNone;
+          cellb[bi] = kNone;
+        }
+      }
+      const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+      if (in) cell[v] = c;
+      const int li = (loc >> 4) * kFinRow + lx;
+      L.c[li] = c;
+      L.w[li] = in ? (F.w ? F.w[v] : (uint16_t)1) : (uint16_t)0;
+    }
+    __syncthreads();
+    fin_sums(L, F, bx, by, bz, g);
+  }
+}
+
 // Site voxels cleared before level 0 of a full pass (brick-major cells).
 __global__ void k_sites_clear(const uint32_t *__restrict__ sites, uint32_t S, BFSArgs A) {
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < S && (int64_t)sites[s] < A.g.n) A.cell[brick_pos(A, sites[s]).bi] = kNone;
 }
+
+unsigned brick_grid(const VTGrid &bg) { return (unsigned)std::min<int64_t>(bg.nbricks, 65535); }
 
 unsigned finish_grid(const VTGrid &bg) {
   const int64_t g = (bg.nbricks * kRows + kVTThreads / BX - 1) / (kVTThreads / BX);
@@ -1718,7 +1883,7 @@ int32_t run_levels(const Geom &g, const BFSArgs &A, CvtWork &W, VTState &st, hip
 // One restricted Voronoi pass over every voxel: level 0 at the sites, then
 // the level launches until the device reports an empty level.
 int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
-               hipStream_t s) {
+               hipStream_t s, const Fuse *fz = nullptr) {
   VTGrid bg = vt_grid(g);
   int32_t rc;
   if ((rc = clear_pass(bg, W, s))) return rc;
@@ -1730,8 +1895,12 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     bool redo = false;
     if ((rc = run_levels<false>(g, A, W, st, s, &redo))) return rc;
   }
-  hipLaunchKernelGGL(k_vt_finish<false>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, W.cellb,
-                     cell);
+  if (fz)
+    hipLaunchKernelGGL(k_vt_finish_sums<false>, dim3(brick_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg,
+                       W.cellb, cell, *fz);
+  else
+    hipLaunchKernelGGL(k_vt_finish<false>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg,
+                       W.cellb, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
@@ -1746,8 +1915,8 @@ int32_t run_vt(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
 // pass's keys and W.moved flags the sites that moved.  The result is that of
 // a full pass with the new sites (see the incremental-pass notes above).
 int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
-                   hipStream_t s) {
-  if (!W.inv || S == 0) return run_vt(g, sites, S, cell, W, st, s);
+                   hipStream_t s, const Fuse *fz = nullptr) {
+  if (!W.inv || S == 0) return run_vt(g, sites, S, cell, W, st, s, fz);
   VTGrid bg = vt_grid(g);
   int32_t rc;
   if ((rc = clear_pass(bg, W, s))) return rc;
@@ -1763,10 +1932,14 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
   if ((rc = run_levels<true>(g, A, W, st, s, &redo))) return rc;
   if (redo) {
     if ((rc = fill<uint32_t>(W.err, 1, 0u, s))) return rc;
-    return run_vt(g, sites, S, cell, W, st, s);
+    return run_vt(g, sites, S, cell, W, st, s, fz);
   }
-  hipLaunchKernelGGL(k_vt_finish<true>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg, W.cellb,
-                     cell);
+  if (fz)
+    hipLaunchKernelGGL(k_vt_finish_sums<true>, dim3(brick_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg,
+                       W.cellb, cell, *fz);
+  else
+    hipLaunchKernelGGL(k_vt_finish<true>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, W.vis, W.inv, g, bg,
+                       W.cellb, cell);
   LSRVT_LAUNCHED();
   static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
   if (debug_levels) {  // sizes of the pass: moved sites, invalid and changed voxels, listed kept voxels
@@ -1823,7 +1996,7 @@ BRArgs br_args(const Geom &g, CvtWork &W) {
 // W.moved.  Rounds are enqueued in batches (the first sized by the previous
 // pass); after each batch the host reads whether any brick is marked.
 int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st, bool inc,
-               hipStream_t s) {
+               hipStream_t s, const Fuse *fz = nullptr) {
   const VTGrid bg = vt_grid(g);
   BRArgs A = br_args(g, W);
   int32_t rc;
@@ -1887,7 +2060,10 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     for (uint32_t i = 1; i < nl; ++i) fprintf(stderr, " %u", h[i]);
     fprintf(stderr, "\n");
   }
-  hipLaunchKernelGGL(k_br_finish, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, A.key, g, bg, cell);
+  if (fz)
+    hipLaunchKernelGGL(k_br_finish_sums, dim3(brick_grid(bg)), dim3(kVTThreads), 0, s, A.key, g, bg, cell, *fz);
+  else
+    hipLaunchKernelGGL(k_br_finish, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, A.key, g, bg, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
@@ -1898,11 +2074,12 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   return LSRVT_OK;
 }
 
-// A Voronoi pass with the selected schedule.
+// A Voronoi pass with the selected schedule; with fz, its last kernel also
+// takes the centroid sums of the update that follows.
 int32_t vt_pass(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st, bool inc,
-                hipStream_t s) {
-  if (vt_engine(g, S) == VTEngine::Bricks) return run_br(g, sites, S, cell, W, st, inc, s);
-  return inc ? run_vt_inc(g, sites, S, cell, W, st, s) : run_vt(g, sites, S, cell, W, st, s);
+                hipStream_t s, const Fuse *fz = nullptr) {
+  if (vt_engine(g, S) == VTEngine::Bricks) return run_br(g, sites, S, cell, W, st, inc, s, fz);
+  return inc ? run_vt_inc(g, sites, S, cell, W, st, s, fz) : run_vt(g, sites, S, cell, W, st, s, fz);
 }
 
 // Errors a run reported on the device (synchronises).
@@ -1915,15 +2092,20 @@ int32_t vt_errors(CvtWork &W, hipStream_t s) {
   return LSRVT_OK;
 }
 
+// The site update; with `summed` the centroid sums are already in W.sums
+// (taken by the pass that produced the cells).
 int32_t run_update(const uint32_t *cell, const Geom &g, const uint16_t *w, uint32_t *sites, uint32_t S, double *ds,
-                   CvtWork &W, hipStream_t s) {
+                   CvtWork &W, hipStream_t s, bool summed = false) {
   if (S == 0) return LSRVT_OK;
   int32_t rc;
-  if ((rc = fill<unsigned long long>(W.sums, 4 * (int64_t)S, 0ull, s))) return rc;
   if ((rc = fill<uint32_t>(W.fb_cnt, 1, 0u, s))) return rc;
   Sums sm{W.sums, W.sums + S, W.sums + 2 * (size_t)S, W.sums + 3 * (size_t)S};
-  const int64_t ntiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
-  hipLaunchKernelGGL(k_centroid, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(256), 0, s, cell, w, g, S, sm);
+  if (!summed) {
+    if ((rc = fill<unsigned long long>(W.sums, 4 * (int64_t)S, 0ull, s))) return rc;
+    const int64_t ntiles = (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) * ((g.nz + TZ - 1) / TZ);
+    hipLaunchKernelGGL(k_centroid, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(256), 0, s, cell, w, g, S,
+                       sm);
+  }
   hipLaunchKernelGGL(k_snap, dim3((S + 255) / 256), dim3(256), 0, s, cell, g, S, sm, sites, ds, W.moved, W.fb_list,
                      W.fb_cnt);
   hipLaunchKernelGGL(k_snap_fallback, dim3(S < 1024 ? S : 1024), dim3(256), 0, s, cell, g, sm, sites, ds, W.moved,
@@ -2258,11 +2440,16 @@ extern "C" int32_t lsrvt_cvt(const uint8_t *d_band, const uint32_t *d_comp, lsrv
   }
   if ((rc = vt_prepare(d_band, g, W, s))) return rc;
   VTState st;
+  const Fuse fz{d_weights, n_sites,
+                Sums{W.sums, W.sums + n_sites, W.sums + 2 * (size_t)n_sites, W.sums + 3 * (size_t)n_sites}};
   for (int32_t t = 0; t <= iters; ++t) {
-    // the first pass covers every voxel; later ones only what the moved sites change
-    if ((rc = vt_pass(g, d_sites, n_sites, d_cell, W, st, t > 0, s))) return rc;
+    // the first pass covers every voxel; later ones only what the moved sites change.  A pass
+    // followed by an update also takes the update's centroid sums.
+    const bool upd = t < iters && n_sites > 0;
+    if (upd && (rc = fill<unsigned long long>(W.sums, 4 * (int64_t)n_sites, 0ull, s))) return rc;
+    if ((rc = vt_pass(g, d_sites, n_sites, d_cell, W, st, t > 0, s, upd ? &fz : nullptr))) return rc;
     if (t == iters) break;
-    if ((rc = run_update(d_cell, g, d_weights, d_sites, n_sites, W.ds, W, s))) return rc;
+    if ((rc = run_update(d_cell, g, d_weights, d_sites, n_sites, W.ds, W, s, true))) return rc;
     hipLaunchKernelGGL(k_mean_ds_part, dim3(kMeanParts), dim3(256), 0, s, W.ds, n_sites, W.mean_part);
     hipLaunchKernelGGL(k_mean_ds, dim3(1), dim3(256), 0, s, W.mean_part, n_sites, W.mean + t);
     LSRVT_LAUNCHED();

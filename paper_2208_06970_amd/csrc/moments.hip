@@ -1,31 +1,21 @@
 // Joint moments up to fourth order of every cell, component and band: the
 // centred sums M2 (covariance), M3 (coskewness) and M4 (cokurtosis) that the
 // joint plots compare between the raw data and the fitted distribution
-// models (Sec. 4.4), merged up the hierarchy of Sec. 3.2.4 / Fig. 5.
+// models (Sec. 4.4), merged up the hierarchy of Sec. 3.2.4 / Fig. 5.  Up to
+// 18 variables: 7314 sums of orders 1 to 4 per unit.
 //
-// Cells: the voxels of a cell are one range of the structured layout; one
-// workgroup per cell stages 256 voxels at a time in LDS as float64 offsets
-// d = x - x(site) and each thread accumulates the raw sums of one or two
-// "units" (S1_i, S2_ij, S3_ijk, S4_ijkl over index tuples in lexicographic
-// order).  The raw sums about the site value become centred sums with the
-// mean offset a = S1 / n:
-//   M2_ij   = S2_ij - n a_i a_j
-//   M3_ijk  = S3_ijk - (a_i S2_jk + a_j S2_ik + a_k S2_ij) + 2 n a_i a_j a_k
-//   M4_ijkl = S4_ijkl - sum over the 4 indices of a_x S3_(other three)
-//             + sum over the 6 index pairs of a_x a_y S2_(other two)
-//             - 3 n a_i a_j a_k a_l.
+// Cells: the voxels of a cell are one range of the structured layout.  The
+// raw sums about the site value (S1_i, S2_ij, S3_ijk, S4_ijkl over index
+// tuples in lexicographic order, the "units") are taken in passes of 1024
+// units: one workgroup per (cell, pass) stages 256 voxels at a time in LDS
+// as float64 offsets d = x - x(site) and each thread sums four units.  The
+// raw sums, written to the cell's output rows, then become centred sums in
+// place with the mean offset a = S1 / n (k_mom_center).
 // Components and bands: pairwise merges (Pebay, "Formulas for robust,
 // one-pass parallel computation of covariances and arbitrary-order
-// statistical moments", 2008): for parts A, B with n = nA + nB and
-// delta = mean_B - mean_A,
-//   M2_ab   = M2A + M2B + nA nB / n d_a d_b
-//   M3_abc  = M3A + M3B + nA nB (nA - nB) / n^2 d_a d_b d_c
-//             + 1/n sum over the 3 indices x of d_x (nA M2B - nB M2A)_(other two)
-//   M4_abcd = M4A + M4B + nA nB (nA^2 - nA nB + nB^2) / n^3 d_a d_b d_c d_d
-//             + 1/n^2 sum over the 6 index pairs {x,y} of d_x d_y (nA^2 M2B + nB^2 M2A)_(other two)
-//             + 1/n sum over the 4 indices x of d_x (nA M3B - nB M3A)_(other three)
-// in a fixed order (cells of a component by site id, components of a band by
-// id), in chunks of kMergeChunk members merged one wave each and then the
+// statistical moments", 2008; the formulas at k_mom_merge) in a fixed order
+// (cells of a component by site id, components of a band by id), in chunks
+// of kMergeChunk members merged in place by one workgroup each and then the
 // chunk results in order.  Everything is float64.
 #include <algorithm>
 
@@ -34,9 +24,10 @@
 namespace lsrvt {
 namespace {
 
-constexpr int kMomMaxVars = 8;
+constexpr int kMomMaxVars = 18;  // 7314 moments of orders 1..4 per unit at m = 18
 constexpr int kMomThreads = 256;
-constexpr int kMaxUnits = 512;  // m + P2 + P3 + P4 <= 494 for m = 8
+constexpr int kMomUPT = 4;                            // raw-sum units per thread and cell pass
+constexpr int kMomChunk = kMomThreads * kMomUPT;      // units per cell pass
 constexpr int kMergeChunk = 128;
 
 struct MomShape {
@@ -53,8 +44,8 @@ MomShape mom_shape(int m) {
   return s;
 }
 
-// Tables built on the device by one thread: code[u] = order | i << 4 | j << 8
-// | k << 12 | l << 16 of raw unit u (units of order 1, then 2, 3, 4, each in
+// Tables built on the device by one thread: code[u] = order | i << 4 | j << 9
+// | k << 14 | l << 19 of raw unit u (units of order 1, then 2, 3, 4, each in
 // lexicographic order of i <= j <= k <= l), and the packed position of every
 // sorted pair and triple.
 struct MomTables {
@@ -72,20 +63,20 @@ __global__ void k_mom_tables(MomShape S, MomTables T) {
   for (int i = 0; i < m; ++i)
     for (int j = i; j < m; ++j) {
       T.idx2[i * m + j] = (uint16_t)p++;
-      T.code[u++] = 2u | (uint32_t)i << 4 | (uint32_t)j << 8;
+      T.code[u++] = 2u | (uint32_t)i << 4 | (uint32_t)j << 9;
     }
   p = 0;
   for (int i = 0; i < m; ++i)
     for (int j = i; j < m; ++j)
       for (int k = j; k < m; ++k) {
         T.idx3[(i * m + j) * m + k] = (uint16_t)p++;
-        T.code[u++] = 3u | (uint32_t)i << 4 | (uint32_t)j << 8 | (uint32_t)k << 12;
+        T.code[u++] = 3u | (uint32_t)i << 4 | (uint32_t)j << 9 | (uint32_t)k << 14;
       }
   for (int i = 0; i < m; ++i)
     for (int j = i; j < m; ++j)
       for (int k = j; k < m; ++k)
         for (int l = k; l < m; ++l)
-          T.code[u++] = 4u | (uint32_t)i << 4 | (uint32_t)j << 8 | (uint32_t)k << 12 | (uint32_t)l << 16;
+          T.code[u++] = 4u | (uint32_t)i << 4 | (uint32_t)j << 9 | (uint32_t)k << 14 | (uint32_t)l << 19;
 }
 
 struct MomOut {
@@ -93,7 +84,7 @@ struct MomOut {
   double *mean, *m2, *m3, *m4;
 };
 
-__device__ __forceinline__ int cidx(uint32_t code, int q) { return (int)((code >> (4 + 4 * q)) & 15u); }
+__device__ __forceinline__ int cidx(uint32_t code, int q) { return (int)((code >> (4 + 5 * q)) & 31u); }
 
 // sorted-tuple lookups (a <= b <= c)
 __device__ __forceinline__ int p2(const uint16_t *idx2, int m, int a, int b) { return idx2[a * m + b]; }
@@ -101,8 +92,12 @@ __device__ __forceinline__ int p3(const uint16_t *idx3, int m, int a, int b, int
   return idx3[(a * m + b) * m + c];
 }
 
-// One workgroup per cell (rank r of the layout): raw sums about the site
-// value, then the centred sums, written at the cell's site id.
+// Raw sums about the site value of every cell (rank r of the layout), units
+// [blockIdx.y * kMomChunk, + kMomChunk): the cell's voxels are staged 256 at a
+// time in LDS as float64 offsets d = x - x(site); thread t sums the products
+// of units u0 + t, u0 + t + 256, ... over the voxels in layout order.  The
+// sums go to the cell's rows of the outputs (order 1 to mean, 2 to m2, ...),
+// where k_mom_center turns them into centred sums.
 __global__ __launch_bounds__(kMomThreads) void k_mom_cells(const uint32_t *__restrict__ perm,
                                                            const uint32_t *__restrict__ cell_off,
                                                            const uint32_t *__restrict__ order,
@@ -110,152 +105,120 @@ __global__ __launch_bounds__(kMomThreads) void k_mom_cells(const uint32_t *__res
                                                            const float *__restrict__ vars, int64_t N, MomShape sh,
                                                            MomTables T, MomOut out) {
   __shared__ double dch[kMomThreads * kMomMaxVars];
-  __shared__ double raw[kMaxUnits];
-  __shared__ uint16_t i2[kMomMaxVars * kMomMaxVars], i3[kMomMaxVars * kMomMaxVars * kMomMaxVars];
   const int t = threadIdx.x;
   const int m = sh.m;
-  for (int i = t; i < m * m; i += kMomThreads) i2[i] = T.idx2[i];
-  for (int i = t; i < m * m * m; i += kMomThreads) i3[i] = T.idx3[i];
-  const uint32_t c0 = t < sh.U ? T.code[t] : 0u;
-  const uint32_t c1 = t + kMomThreads < sh.U ? T.code[t + kMomThreads] : 0u;
+  const int u0 = (int)blockIdx.y * kMomChunk;
+  uint32_t cd[kMomUPT];
+#pragma unroll
+  for (int q = 0; q < kMomUPT; ++q) {
+    const int u = u0 + q * kMomThreads + t;
+    cd[q] = u < sh.U ? T.code[u] : 0u;
+  }
   for (uint32_t r = blockIdx.x; r < S; r += gridDim.x) {
     const uint32_t lo = cell_off[r], hi = cell_off[r + 1];
     const uint32_t site = order[r];
     const uint32_t sv = sites[site];
-    double acc0 = 0.0, acc1 = 0.0;
+    double acc[kMomUPT];
+#pragma unroll
+    for (int q = 0; q < kMomUPT; ++q) acc[q] = 0.0;
     for (uint32_t base = lo; base < hi; base += kMomThreads) {
       const uint32_t cnt = min((uint32_t)kMomThreads, hi - base);
       __syncthreads();
       if ((uint32_t)t < cnt) {
         const uint32_t v = perm[base + t];
         for (int j = 0; j < m; ++j)
-          dch[t * kMomMaxVars + j] = (double)vars[(int64_t)j * N + v] - (double)vars[(int64_t)j * N + sv];
+          dch[t * m + j] = (double)vars[(int64_t)j * N + v] - (double)vars[(int64_t)j * N + sv];
       }
       __syncthreads();
       for (uint32_t i = 0; i < cnt; ++i) {
-        const double *d = dch + i * kMomMaxVars;
-        if (c0) {
-          double p = d[cidx(c0, 0)];
-          const int o = (int)(c0 & 15u);
-          if (o > 1) p *= d[cidx(c0, 1)];
-          if (o > 2) p *= d[cidx(c0, 2)];
-          if (o > 3) p *= d[cidx(c0, 3)];
-          acc0 += p;
-        }
-        if (c1) {
-          double p = d[cidx(c1, 0)];
-          const int o = (int)(c1 & 15u);
-          if (o > 1) p *= d[cidx(c1, 1)];
-          if (o > 2) p *= d[cidx(c1, 2)];
-          if (o > 3) p *= d[cidx(c1, 3)];
-          acc1 += p;
+        const double *d = dch + i * m;
+#pragma unroll
+        for (int q = 0; q < kMomUPT; ++q) {
+          const uint32_t c = cd[q];
+          if (!c) continue;
+          double p = d[cidx(c, 0)];
+          const int o = (int)(c & 15u);
+          if (o > 1) p *= d[cidx(c, 1)];
+          if (o > 2) p *= d[cidx(c, 2)];
+          if (o > 3) p *= d[cidx(c, 3)];
+          acc[q] += p;
         }
       }
     }
-    if (t < sh.U) raw[t] = acc0;
-    if (t + kMomThreads < sh.U) raw[t + kMomThreads] = acc1;
-    __syncthreads();
-    const double n = (double)(hi - lo);
-    const double *S1 = raw, *S2 = raw + m, *S3 = raw + m + sh.P2, *S4 = raw + m + sh.P2 + sh.P3;
-    // mean offsets a_j = S1_j / n (0 for an empty cell)
-    auto a = [&](int j) { return hi > lo ? S1[j] / n : 0.0; };
-    for (int u = t; u < sh.U; u += kMomThreads) {
-      const uint32_t code = T.code[u];
-      const int o = (int)(code & 15u);
-      const int i = cidx(code, 0), j = cidx(code, 1), k = cidx(code, 2), l = cidx(code, 3);
-      if (o == 1) {
-        out.mean[(int64_t)site * m + i] = (double)vars[(int64_t)i * N + sv] + a(i);
-      } else if (o == 2) {
-        const int q = u - m;
-        out.m2[(int64_t)site * sh.P2 + q] = S2[q] - n * a(i) * a(j);
-      } else if (o == 3) {
-        const int q = u - m - sh.P2;
-        const double v = S3[q] - (a(i) * S2[p2(i2, m, j, k)] + a(j) * S2[p2(i2, m, i, k)] + a(k) * S2[p2(i2, m, i, j)]) +
-                         2.0 * n * a(i) * a(j) * a(k);
-        out.m3[(int64_t)site * sh.P3 + q] = v;
-      } else {
-        const int q = u - m - sh.P2 - sh.P3;
-        double v = S4[q];
-        v -= a(i) * S3[p3(i3, m, j, k, l)] + a(j) * S3[p3(i3, m, i, k, l)] + a(k) * S3[p3(i3, m, i, j, l)] +
-             a(l) * S3[p3(i3, m, i, j, k)];
-        v += a(i) * a(j) * S2[p2(i2, m, k, l)] + a(i) * a(k) * S2[p2(i2, m, j, l)] + a(i) * a(l) * S2[p2(i2, m, j, k)] +
-             a(j) * a(k) * S2[p2(i2, m, i, l)] + a(j) * a(l) * S2[p2(i2, m, i, k)] + a(k) * a(l) * S2[p2(i2, m, i, j)];
-        v -= 3.0 * n * a(i) * a(j) * a(k) * a(l);
-        out.m4[(int64_t)site * sh.P4 + q] = v;
-      }
+#pragma unroll
+    for (int q = 0; q < kMomUPT; ++q) {
+      const int u = u0 + q * kMomThreads + t;
+      if (u >= sh.U) continue;
+      if (u < m)
+        out.mean[(int64_t)site * m + u] = acc[q];
+      else if (u < m + sh.P2)
+        out.m2[(int64_t)site * sh.P2 + (u - m)] = acc[q];
+      else if (u < m + sh.P2 + sh.P3)
+        out.m3[(int64_t)site * sh.P3 + (u - m - sh.P2)] = acc[q];
+      else
+        out.m4[(int64_t)site * sh.P4 + (u - m - sh.P2 - sh.P3)] = acc[q];
     }
-    if (t == 0) out.n[site] = (uint64_t)(hi - lo);
-    if (hi == lo)
-      for (int j = t; j < m; j += kMomThreads) out.mean[(int64_t)site * m + j] = 0.0;
-    __syncthreads();
   }
 }
 
-// Moments of one part, held in LDS by one wave: n, mean[m], M2[P2], M3[P3], M4[P4].
-struct PartView {
-  double *n, *mean, *m2, *m3, *m4;
-};
-
-__device__ __forceinline__ PartView part_at(double *base, const MomShape &sh) {
-  PartView p;
-  p.n = base;
-  p.mean = base + 1;
-  p.m2 = p.mean + sh.m;
-  p.m3 = p.m2 + sh.P2;
-  p.m4 = p.m3 + sh.P3;
-  return p;
-}
-
-// C = merge(A, B) over the lanes of one wave (C distinct from A and B).
-__device__ void merge_parts(const PartView &A, const PartView &B, const PartView &C, const MomShape &sh,
-                            const uint32_t *code, const uint16_t *i2, const uint16_t *i3) {
-  const int lane = lane_id();
+// The raw sums of every cell about its site value become centred sums with
+// the mean offset a = S1 / n, in place, highest order first (each order reads
+// only lower orders' raw sums, which are rewritten later):
+//   M4_ijkl = S4_ijkl - sum over the 4 indices of a_x S3_(other three)
+//             + sum over the 6 index pairs of a_x a_y S2_(other two)
+//             - 3 n a_i a_j a_k a_l
+//   M3_ijk  = S3_ijk - (a_i S2_jk + a_j S2_ik + a_k S2_ij) + 2 n a_i a_j a_k
+//   M2_ij   = S2_ij - n a_i a_j
+//   mean_i  = x_i(site) + a_i
+// One workgroup per cell.
+__global__ __launch_bounds__(kMomThreads) void k_mom_center(const uint32_t *__restrict__ cell_off,
+                                                            const uint32_t *__restrict__ order,
+                                                            const uint32_t *__restrict__ sites, uint32_t S,
+                                                            const float *__restrict__ vars, int64_t N, MomShape sh,
+                                                            MomTables T, MomOut out) {
+  __shared__ uint16_t i2[kMomMaxVars * kMomMaxVars], i3[kMomMaxVars * kMomMaxVars * kMomMaxVars];
+  __shared__ double a_s[kMomMaxVars];
+  const int t = threadIdx.x;
   const int m = sh.m;
-  const double nA = *A.n, nB = *B.n;
-  if (nB == 0.0 || nA == 0.0) {
-    const PartView &X = nB == 0.0 ? A : B;
-    const int len = 1 + sh.U;
-    for (int q = lane; q < len; q += kWave) C.n[q] = X.n[q];
-    return;
-  }
-  const double n = nA + nB;
-  auto d = [&](int x) { return B.mean[x] - A.mean[x]; };
-  for (int u = lane; u < sh.U; u += kWave) {
-    const uint32_t cd = code[u];
-    const int o = (int)(cd & 15u);
-    const int a = cidx(cd, 0), b = cidx(cd, 1), c = cidx(cd, 2), e = cidx(cd, 3);
-    if (o == 1) {
-      C.mean[a] = A.mean[a] + d(a) * (nB / n);
-    } else if (o == 2) {
-      const int q = u - m;
-      C.m2[q] = A.m2[q] + B.m2[q] + nA * nB / n * d(a) * d(b);
-    } else if (o == 3) {
-      const int q = u - m - sh.P2;
-      auto w2 = [&](int x, int y) {
-        const int k = p2(i2, m, x, y);
-        return nA * B.m2[k] - nB * A.m2[k];
-      };
-      C.m3[q] = A.m3[q] + B.m3[q] + nA * nB * (nA - nB) / (n * n) * d(a) * d(b) * d(c) +
-                (d(a) * w2(b, c) + d(b) * w2(a, c) + d(c) * w2(a, b)) / n;
-    } else {
-      const int q = u - m - sh.P2 - sh.P3;
-      auto v2 = [&](int x, int y) {
-        const int k = p2(i2, m, x, y);
-        return nA * nA * B.m2[k] + nB * nB * A.m2[k];
-      };
-      auto v3 = [&](int x, int y, int z) {
-        const int k = p3(i3, m, x, y, z);
-        return nA * B.m3[k] - nB * A.m3[k];
-      };
-      const double t4 = nA * nB * (nA * nA - nA * nB + nB * nB) / (n * n * n) * d(a) * d(b) * d(c) * d(e);
-      const double t2 = (d(a) * d(b) * v2(c, e) + d(a) * d(c) * v2(b, e) + d(a) * d(e) * v2(b, c) +
-                         d(b) * d(c) * v2(a, e) + d(b) * d(e) * v2(a, c) + d(c) * d(e) * v2(a, b)) /
-                        (n * n);
-      const double t3 = (d(a) * v3(b, c, e) + d(b) * v3(a, c, e) + d(c) * v3(a, b, e) + d(e) * v3(a, b, c)) / n;
-      C.m4[q] = A.m4[q] + B.m4[q] + t4 + t2 + t3;
+  for (int i = t; i < m * m; i += kMomThreads) i2[i] = T.idx2[i];
+  for (int i = t; i < m * m * m; i += kMomThreads) i3[i] = T.idx3[i];
+  for (uint32_t r = blockIdx.x; r < S; r += gridDim.x) {
+    const uint32_t lo = cell_off[r], hi = cell_off[r + 1];
+    const uint32_t site = order[r];
+    const double n = (double)(hi - lo);
+    double *mean = out.mean + (int64_t)site * m, *m2 = out.m2 + (int64_t)site * sh.P2,
+           *m3 = out.m3 + (int64_t)site * sh.P3, *m4 = out.m4 + (int64_t)site * sh.P4;
+    __syncthreads();
+    if (t < m) a_s[t] = hi > lo ? mean[t] / n : 0.0;
+    __syncthreads();
+    auto a = [&](int j) { return a_s[j]; };
+    for (int q = t; q < sh.P4; q += kMomThreads) {
+      const uint32_t code = T.code[m + sh.P2 + sh.P3 + q];
+      const int i = cidx(code, 0), j = cidx(code, 1), k = cidx(code, 2), l = cidx(code, 3);
+      double v = m4[q];
+      v -= a(i) * m3[p3(i3, m, j, k, l)] + a(j) * m3[p3(i3, m, i, k, l)] + a(k) * m3[p3(i3, m, i, j, l)] +
+           a(l) * m3[p3(i3, m, i, j, k)];
+      v += a(i) * a(j) * m2[p2(i2, m, k, l)] + a(i) * a(k) * m2[p2(i2, m, j, l)] + a(i) * a(l) * m2[p2(i2, m, j, k)] +
+           a(j) * a(k) * m2[p2(i2, m, i, l)] + a(j) * a(l) * m2[p2(i2, m, i, k)] + a(k) * a(l) * m2[p2(i2, m, i, j)];
+      v -= 3.0 * n * a(i) * a(j) * a(k) * a(l);
+      m4[q] = v;
     }
+    __syncthreads();
+    for (int q = t; q < sh.P3; q += kMomThreads) {
+      const uint32_t code = T.code[m + sh.P2 + q];
+      const int i = cidx(code, 0), j = cidx(code, 1), k = cidx(code, 2);
+      m3[q] = m3[q] - (a(i) * m2[p2(i2, m, j, k)] + a(j) * m2[p2(i2, m, i, k)] + a(k) * m2[p2(i2, m, i, j)]) +
+              2.0 * n * a(i) * a(j) * a(k);
+    }
+    __syncthreads();
+    for (int q = t; q < sh.P2; q += kMomThreads) {
+      const uint32_t code = T.code[m + q];
+      const int i = cidx(code, 0), j = cidx(code, 1);
+      m2[q] = m2[q] - n * a(i) * a(j);
+    }
+    if (t < m) mean[t] = hi > lo ? (double)vars[(int64_t)t * N + sites[site]] + a(t) : 0.0;
+    if (t == 0) out.n[site] = (uint64_t)(hi - lo);
   }
-  if (lane == 0) *C.n = n;
 }
 
 // Group inputs: members of group g are member_id(lo + k) for k < hi - lo.
@@ -265,63 +228,119 @@ struct MergeIn {
   const uint32_t *map;  // member index -> row (null: identity)
 };
 
-__device__ void load_part(const MergeIn &in, uint32_t row, const PartView &P, const MomShape &sh) {
-  const int lane = lane_id();
-  if (lane == 0) *P.n = (double)in.n[row];
-  for (int q = lane; q < sh.m; q += kWave) P.mean[q] = in.mean[(int64_t)row * sh.m + q];
-  for (int q = lane; q < sh.P2; q += kWave) P.m2[q] = in.m2[(int64_t)row * sh.P2 + q];
-  for (int q = lane; q < sh.P3; q += kWave) P.m3[q] = in.m3[(int64_t)row * sh.P3 + q];
-  for (int q = lane; q < sh.P4; q += kWave) P.m4[q] = in.m4[(int64_t)row * sh.P4 + q];
-}
-
-__device__ void store_part(const MomOut &out, uint32_t row, const PartView &P, const MomShape &sh) {
-  const int lane = lane_id();
-  if (lane == 0) out.n[row] = (uint64_t)*P.n;
-  for (int q = lane; q < sh.m; q += kWave) out.mean[(int64_t)row * sh.m + q] = P.mean[q];
-  for (int q = lane; q < sh.P2; q += kWave) out.m2[(int64_t)row * sh.P2 + q] = P.m2[q];
-  for (int q = lane; q < sh.P3; q += kWave) out.m3[(int64_t)row * sh.P3 + q] = P.m3[q];
-  for (int q = lane; q < sh.P4; q += kWave) out.m4[(int64_t)row * sh.P4 + q] = P.m4[q];
-}
-
-constexpr int kPartDoubles = 1 + kMaxUnits;
-
-// One wave per job: merges members [lo, hi) of the job in order into row
-// `dst` of `out`.  Job j: group = job_group[j], members
-// [job_lo[j], job_hi[j]).
+// One workgroup per job: members [job_lo[j], job_hi[j]) merged in order into
+// row j of `out`, in place (Pebay's pairwise formulas; A the running result,
+// B the next member, n = nA + nB, d = mean_B - mean_A):
+//   M4_abcd += M4B + nA nB (nA^2 - nA nB + nB^2) / n^3 d_a d_b d_c d_d
+//              + 1/n^2 sum over the 6 index pairs {x,y} of d_x d_y (nA^2 M2B + nB^2 M2A)_(other two)
+//              + 1/n sum over the 4 indices x of d_x (nA M3B - nB M3A)_(other three)
+//   M3_abc  += M3B + nA nB (nA - nB) / n^2 d_a d_b d_c
+//              + 1/n sum over the 3 indices x of d_x (nA M2B - nB M2A)_(other two)
+//   M2_ab   += M2B + nA nB / n d_a d_b
+//   mean_a  += d_a nB / n
+// highest order first, so every order still reads the lower orders of A
+// before the merge.
 __global__ __launch_bounds__(kMomThreads) void k_mom_merge(uint32_t n_jobs, const uint32_t *job_lo,
                                                            const uint32_t *job_hi, MergeIn in, MomOut out,
                                                            MomShape sh, MomTables T) {
-  __shared__ double buf[kMomThreads / kWave][3][kPartDoubles];
   __shared__ uint16_t i2[kMomMaxVars * kMomMaxVars], i3[kMomMaxVars * kMomMaxVars * kMomMaxVars];
-  __shared__ uint32_t code[kMaxUnits];
-  const int t = threadIdx.x, w = t / kWave, lane = lane_id();
+  __shared__ double d_s[kMomMaxVars];
+  const int t = threadIdx.x;
   const int m = sh.m;
   for (int i = t; i < m * m; i += kMomThreads) i2[i] = T.idx2[i];
   for (int i = t; i < m * m * m; i += kMomThreads) i3[i] = T.idx3[i];
-  for (int i = t; i < sh.U; i += kMomThreads) code[i] = T.code[i];
-  __syncthreads();
-  const uint32_t waves = gridDim.x * (kMomThreads / kWave);
-  for (uint32_t j = blockIdx.x * (kMomThreads / kWave) + w; j < n_jobs; j += waves) {
-    PartView acc = part_at(buf[w][0], sh), nxt = part_at(buf[w][1], sh), inc = part_at(buf[w][2], sh);
-    if (lane == 0) *acc.n = 0.0;
-    for (int q = lane; q < sh.U; q += kWave) acc.mean[q] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    for (uint32_t k = job_lo[j]; k < job_hi[j]; ++k) {
-      const uint32_t row = in.map ? in.map[k] : k;
-      load_part(in, row, inc, sh);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      merge_parts(acc, inc, nxt, sh, code, i2, i3);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const PartView tmp = acc;
-      acc = nxt;
-      nxt = tmp;
+  const int len = sh.U;  // mean, m2, m3, m4 of a row, as one index space
+  for (uint32_t j = blockIdx.x; j < n_jobs; j += gridDim.x) {
+    double *A1 = out.mean + (int64_t)j * m, *A2 = out.m2 + (int64_t)j * sh.P2, *A3 = out.m3 + (int64_t)j * sh.P3,
+           *A4 = out.m4 + (int64_t)j * sh.P4;
+    auto copy_in = [&](uint32_t row) {
+      for (int q = t; q < len; q += kMomThreads) {
+        if (q < m)
+          A1[q] = in.mean[(int64_t)row * m + q];
+        else if (q < m + sh.P2)
+          A2[q - m] = in.m2[(int64_t)row * sh.P2 + q - m];
+        else if (q < m + sh.P2 + sh.P3)
+          A3[q - m - sh.P2] = in.m3[(int64_t)row * sh.P3 + q - m - sh.P2];
+        else
+          A4[q - m - sh.P2 - sh.P3] = in.m4[(int64_t)row * sh.P4 + q - m - sh.P2 - sh.P3];
+      }
+    };
+    const uint32_t lo = job_lo[j], hi = job_hi[j];
+    __syncthreads();
+    uint64_t nAi = 0;
+    if (hi > lo) {
+      const uint32_t row = in.map ? in.map[lo] : lo;
+      copy_in(row);
+      nAi = in.n[row];
+    } else {
+      for (int q = t; q < len; q += kMomThreads) {
+        if (q < m)
+          A1[q] = 0.0;
+        else if (q < m + sh.P2)
+          A2[q - m] = 0.0;
+        else if (q < m + sh.P2 + sh.P3)
+          A3[q - m - sh.P2] = 0.0;
+        else
+          A4[q - m - sh.P2 - sh.P3] = 0.0;
+      }
     }
-    store_part(out, j, acc, sh);
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    for (uint32_t k = lo + 1; k < hi; ++k) {
+      const uint32_t row = in.map ? in.map[k] : k;
+      const uint64_t nBi = in.n[row];
+      if (nBi == 0) continue;  // uniform
+      if (nAi == 0) {
+        copy_in(row);
+        nAi = nBi;
+        __syncthreads();
+        continue;
+      }
+      const double nA = (double)nAi, nB = (double)nBi, n = nA + nB;
+      const double *B1 = in.mean + (int64_t)row * m, *B2 = in.m2 + (int64_t)row * sh.P2,
+                   *B3 = in.m3 + (int64_t)row * sh.P3, *B4 = in.m4 + (int64_t)row * sh.P4;
+      if (t < m) d_s[t] = B1[t] - A1[t];
+      __syncthreads();
+      auto d = [&](int x) { return d_s[x]; };
+      for (int q = t; q < sh.P4; q += kMomThreads) {
+        const uint32_t cd = T.code[m + sh.P2 + sh.P3 + q];
+        const int a = cidx(cd, 0), b = cidx(cd, 1), c = cidx(cd, 2), e = cidx(cd, 3);
+        auto v2 = [&](int x, int y) {
+          const int kk = p2(i2, m, x, y);
+          return nA * nA * B2[kk] + nB * nB * A2[kk];
+        };
+        auto v3 = [&](int x, int y, int z) {
+          const int kk = p3(i3, m, x, y, z);
+          return nA * B3[kk] - nB * A3[kk];
+        };
+        const double t4 = nA * nB * (nA * nA - nA * nB + nB * nB) / (n * n * n) * d(a) * d(b) * d(c) * d(e);
+        const double t2 = (d(a) * d(b) * v2(c, e) + d(a) * d(c) * v2(b, e) + d(a) * d(e) * v2(b, c) +
+                           d(b) * d(c) * v2(a, e) + d(b) * d(e) * v2(a, c) + d(c) * d(e) * v2(a, b)) /
+                          (n * n);
+        const double t3 = (d(a) * v3(b, c, e) + d(b) * v3(a, c, e) + d(c) * v3(a, b, e) + d(e) * v3(a, b, c)) / n;
+        A4[q] = A4[q] + B4[q] + t4 + t2 + t3;
+      }
+      __syncthreads();
+      for (int q = t; q < sh.P3; q += kMomThreads) {
+        const uint32_t cd = T.code[m + sh.P2 + q];
+        const int a = cidx(cd, 0), b = cidx(cd, 1), c = cidx(cd, 2);
+        auto w2 = [&](int x, int y) {
+          const int kk = p2(i2, m, x, y);
+          return nA * B2[kk] - nB * A2[kk];
+        };
+        A3[q] = A3[q] + B3[q] + nA * nB * (nA - nB) / (n * n) * d(a) * d(b) * d(c) +
+                (d(a) * w2(b, c) + d(b) * w2(a, c) + d(c) * w2(a, b)) / n;
+      }
+      __syncthreads();
+      for (int q = t; q < sh.P2; q += kMomThreads) {
+        const uint32_t cd = T.code[m + q];
+        const int a = cidx(cd, 0), b = cidx(cd, 1);
+        A2[q] = A2[q] + B2[q] + nA * nB / n * d(a) * d(b);
+      }
+      if (t < m) A1[t] = A1[t] + d(t) * (nB / n);
+      nAi += nBi;
+      __syncthreads();
+    }
+    if (t == 0) out.n[j] = nAi;
   }
 }
 
@@ -378,9 +397,9 @@ void mom_layout(A &a, const Geom &g, uint32_t S, uint32_t C, int32_t nb, const M
   const int64_t J = chunk_cap((int64_t)S + C, G);
   layout_take(a, g, S, C, W ? &W->lay : nullptr);
   auto perm = a.template take<uint32_t>(g.n);
-  auto code = a.template take<uint32_t>(kMaxUnits);
-  auto idx2 = a.template take<uint16_t>(kMomMaxVars * kMomMaxVars);
-  auto idx3 = a.template take<uint16_t>(kMomMaxVars * kMomMaxVars * kMomMaxVars);
+  auto code = a.template take<uint32_t>(sh.U);
+  auto idx2 = a.template take<uint16_t>((size_t)sh.m * sh.m);
+  auto idx3 = a.template take<uint16_t>((size_t)sh.m * sh.m * sh.m);
   auto boff = a.template take<uint32_t>((size_t)nb + 1);
   auto nch = a.template take<uint32_t>(G + 1);
   auto cho = a.template take<uint32_t>(G + 1);
@@ -429,10 +448,10 @@ int32_t merge_groups(const uint32_t *goff, uint32_t G, const MergeIn &in, const 
     if (rc_) return rc_;
   }
   hipLaunchKernelGGL(k_mom_jobs, dim3((G + 255) / 256), dim3(256), 0, s, goff, G, W.choff, W.job_lo, W.job_hi);
-  const unsigned grid1 = (unsigned)std::min<int64_t>(((int64_t)J + 3) / 4, 65535);
+  const unsigned grid1 = (unsigned)std::min<int64_t>((int64_t)J, 65535);
   if (J)
-    hipLaunchKernelGGL(k_mom_merge, dim3(grid1 ? grid1 : 1), dim3(kMomThreads), 0, s, J, W.job_lo, W.job_hi, in,
-                       W.part, sh, W.tab);
+    hipLaunchKernelGGL(k_mom_merge, dim3(grid1), dim3(kMomThreads), 0, s, J, W.job_lo, W.job_hi, in, W.part, sh,
+                       W.tab);
   // second level: the chunk results of every group, in order
   MergeIn in2;
   in2.n = W.part.n;
@@ -441,7 +460,7 @@ int32_t merge_groups(const uint32_t *goff, uint32_t G, const MergeIn &in, const 
   in2.m3 = W.part.m3;
   in2.m4 = W.part.m4;
   in2.map = nullptr;
-  const unsigned grid2 = (unsigned)std::min<int64_t>(((int64_t)G + 3) / 4, 65535);
+  const unsigned grid2 = (unsigned)std::min<int64_t>((int64_t)G, 65535);
   hipLaunchKernelGGL(k_mom_merge, dim3(grid2), dim3(kMomThreads), 0, s, G, W.choff, W.choff + 1, in2, out, sh,
                      W.tab);
   LSRVT_LAUNCHED();
@@ -497,7 +516,10 @@ extern "C" int32_t lsrvt_comoments(const uint32_t *d_cell, lsrvt_dims dims, cons
   if ((rc = layout_voxels(d_cell, g, S, W.lay, W.perm, s))) return rc;
   const MomOut co{cell->n, cell->mean, cell->m2, cell->m3, cell->m4};
   if (S) {
-    hipLaunchKernelGGL(k_mom_cells, dim3((unsigned)std::min<uint32_t>(S, 65535)), dim3(kMomThreads), 0, s, W.perm,
+    const unsigned passes = (unsigned)((sh.U + kMomChunk - 1) / kMomChunk);
+    hipLaunchKernelGGL(k_mom_cells, dim3((unsigned)std::min<uint32_t>(S, 65535), passes), dim3(kMomThreads), 0, s,
+                       W.perm, W.lay.cell_off, W.lay.order, d_sites, S, d_vars, g.n, sh, W.tab, co);
+    hipLaunchKernelGGL(k_mom_center, dim3((unsigned)std::min<uint32_t>(S, 65535)), dim3(kMomThreads), 0, s,
                        W.lay.cell_off, W.lay.order, d_sites, S, d_vars, g.n, sh, W.tab, co);
     LSRVT_LAUNCHED();
   }

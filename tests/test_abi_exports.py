@@ -88,15 +88,15 @@ def test_comoments_host_validation_without_gpu(lib):
     nul = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(4096)
     d = L.Dims(32, 32, 32)
-    assert lib.lsrvt_comoments_workspace(d, 100, 10, 3, 8) > 0
-    assert lib.lsrvt_comoments_workspace(d, 100, 10, 3, 9) == 0   # at most 8 variables
+    assert lib.lsrvt_comoments_workspace(d, 100, 10, 3, 18) > 0
+    assert lib.lsrvt_comoments_workspace(d, 100, 10, 3, 19) == 0   # at most 18 variables
     mo = L.MomentsC(fake, fake, fake, fake, fake)
     bad = L.MomentsC(fake, nul, fake, fake, fake)
     call = lambda m, a, b, c, wb=16: lib.lsrvt_comoments(fake, d, fake, fake, 100, fake, 10, 3, fake, m,
                                                         ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), fake, wb,
                                                         nul)
     assert call(0, mo, mo, mo) == L.EINVAL
-    assert call(9, mo, mo, mo) == L.EINVAL
+    assert call(19, mo, mo, mo) == L.EINVAL
     assert call(4, mo, bad, mo) == L.EINVAL
     assert call(4, mo, mo, mo) == L.EWORKSPACE
 

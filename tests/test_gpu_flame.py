@@ -187,3 +187,47 @@ def test_flame_fullsize_sampled():
         xs = np.ascontiguousarray(x[(slice(None),) + bx])
         want = oracle.stats(unit, 1, xs, wl.edges, cov=True)
         _check_level(f"component {c}", _sub(gs, [c]), want, 18)
+
+
+def test_flame_fullsize_against_oracle():
+    """The whole 2^28-voxel Lloyd loop (30 updates) bit for bit against the
+    oracle's run of Algorithm 1 on the same inputs, through the digests
+    ``tests/golden/make_golden.py`` stored (cells, sites, site components, and
+    the cells of every component to name the first one that differs), and
+    the statistics of components and bands against the oracle's stored ones:
+    exact digests of counts, extrema and histograms, moments and covariance
+    within the tolerances of the statistics tests."""
+    from tests import golden_util as G
+    doc, arrays = G.load("flame_t30")
+    banner("flame golden: generating 1024x512x512")
+    wl = synth.flame_workload()
+    b, _ = L.lsrvt_isobands(dev(wl.field), wl.iso)
+    g = L.lsrvt_components(b, wl.n_bands)
+    assert g.n_comp == doc["n_comp"]
+    comp = host(g.comp, np.uint32)
+    seeds = synth.flame_sites(comp, g.n_comp, wl.weights, wl.rho, wl.seed)
+    assert G.sha(seeds) == doc["seeds_sha256"], "inputs differ from the ones the oracle ran on"
+    banner(f"flame golden: Lloyd loop, {wl.iters} updates, S={len(seeds)}")
+    r = L.lsrvt_cvt(b, g.comp, dev(seeds), dev(wl.weights), wl.iters)
+    cell = host(r.cell, np.uint32)
+    if G.sha(cell) != doc["cell_sha256"]:
+        kflat, cflat = comp.ravel(), cell.ravel()
+        order = np.argsort(kflat, kind="stable")
+        bounds = np.searchsorted(kflat[order], np.arange(g.n_comp + 1))
+        for c in range(g.n_comp):
+            if G.sha(cflat[order[bounds[c]:bounds[c + 1]]]) != doc["comp_cell_sha256"][c]:
+                raise AssertionError(f"flame T=30 cells differ from the oracle's, first in component {c}")
+        G.check_labels(cell, doc, "flame T=30")
+    assert G.sha(host(r.sites, np.uint32)) == doc["sites_sha256"]
+    assert G.sha(host(r.site_comp, np.uint32)) == doc["site_comp_sha256"]
+    np.testing.assert_allclose(r.mean_ds, doc["mean_ds"], rtol=1e-12, atol=0)
+    del cell
+    banner("flame golden: statistics of components and bands, 18 variables, covariance")
+    x = dev(np.ascontiguousarray(wl.variables))
+    cs, gs, bs = L.lsrvt_aggregate(r.cell, r.sites, r.site_comp, g.comp_band, g.n_comp, wl.n_bands, x,
+                                   dev(wl.edges), cov=True)
+    G.exact_digests_match(gs, doc["comp_exact_sha256"], "component")
+    G.exact_digests_match(bs, doc["band_exact_sha256"], "band")
+    rows = arrays["comp_rows"]
+    _check_level("component", _sub(gs, rows), G.level_stats(arrays, "comp"), 18)
+    _check_level("band", bs, G.level_stats(arrays, "band"), 18)

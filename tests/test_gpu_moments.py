@@ -81,6 +81,8 @@ def _units(cell, site_comp, comp_band):
     ((40, 36, 44), 1, 3, 4, 2, 200.0),
     ((33, 48, 29), 2, 5, 8, 1, 120.0),
     ((20, 64, 24), 3, 2, 1, 3, 400.0),
+    ((28, 20, 36), 5, 4, 13, 2, 150.0),   # 13 variables: two passes of the cell sums
+    ((24, 30, 20), 6, 3, 18, 1, 300.0),   # 18 variables (the combustion workload's count)
 ])
 def test_comoments_match_oracle(shape, seed, n_iso, m, iters, rho):
     x, cc, g, r, nb = _case(shape, seed, n_iso, m, iters, rho)
