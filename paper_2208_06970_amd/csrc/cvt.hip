@@ -790,6 +790,7 @@ struct BRArgs {
   uint32_t *mark;                  // [2][nbricks]: mark[r & 1][b] == r when brick b works in round r
   uint32_t *list;                  // [nbricks] bricks of the current round
   uint32_t *ctl;                   // [0] list length, [3] error bits
+  uint32_t *rnd;                   // the current round (advanced on the device, so rounds replay from a graph)
   uint32_t *alive;                 // [3] round alive flags (by r % 3); shared by the jobs of a batch
   uint32_t *hist;                  // [kHistLen] bricks that worked in each round
   unsigned long long *dbg;         // diagnostics (LSRVT_DEBUG_LEVELS only): processings, sweep rounds
@@ -895,7 +896,14 @@ __device__ __forceinline__ void d_br_list(BRArgs A, uint32_t r) {
     __syncthreads();
   }
 }
-__global__ __launch_bounds__(256) void k_br_list(BRArgs A, uint32_t r) { d_br_list(A, r); }
+// Start of a round: the list is emptied and the round number advanced.
+__global__ void k_br_next(BRArgs A) {
+  if (threadIdx.x == 0) {
+    A.ctl[0] = 0u;
+    *A.rnd += 1u;
+  }
+}
+__global__ __launch_bounds__(256) void k_br_list(BRArgs A) { d_br_list(A, *A.rnd); }
 
 
 __device__ __forceinline__ int br_at(int lx, int row) { return row * kBRRow + lx; }
@@ -1084,7 +1092,7 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     __syncthreads();
   }
 }
-__global__ __launch_bounds__(kBRThreads, 4) void k_br_round(BRArgs A, uint32_t r) { d_br_round(A, r); }
+__global__ __launch_bounds__(kBRThreads, 4) void k_br_round(BRArgs A) { d_br_round(A, *A.rnd); }
 
 
 // End of a pass: keys to the caller's C-order cells (NONE where unreached),
@@ -1596,10 +1604,50 @@ int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t
 
 // Driver state of one Lloyd run: the number of levels of the previous pass,
 // which sizes the first batch of level launches of the next one.
+// Rounds per graph of relaxation rounds.
+constexpr int kGraphRounds = 8;
+
+// Captures kGraphRounds calls of launch_round(stream) into an executable
+// graph (kernel nodes only: nothing is cleared by memset).  The capture runs
+// on a stream of its own (the caller's may be the null stream, which cannot
+// be captured); the graph is then launched on the caller's stream.
+template <class F>
+int32_t capture_rounds(hipGraphExec_t *exec, F launch_round) {
+  hipStream_t cs = nullptr;
+  LSRVT_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph = nullptr;
+  int32_t rc = LSRVT_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    hipStreamDestroy(cs);
+    return LSRVT_EDEVICE;
+  }
+  for (int i = 0; i < kGraphRounds && rc == LSRVT_OK; ++i) rc = launch_round(cs);
+  const hipError_t e = hipStreamEndCapture(cs, &graph);
+  hipStreamDestroy(cs);
+  if (rc != LSRVT_OK || e != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    return rc ? rc : LSRVT_EDEVICE;
+  }
+  const hipError_t ei = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    *exec = nullptr;
+    return LSRVT_EDEVICE;
+  }
+  return LSRVT_OK;
+}
+
 struct VTState {
   uint32_t levels = 0;      // levels of the last full pass
   uint32_t inc_levels = 0;  // levels of the first run of the last incremental pass
   uint32_t br_rounds = 0;   // rounds of the last brick relaxation pass
+  hipGraphExec_t br_graph = nullptr;  // kGraphRounds relaxation rounds of this call's workspace
+  VTState() = default;
+  VTState(const VTState &) = delete;
+  VTState &operator=(const VTState &) = delete;
+  ~VTState() {
+    if (br_graph) hipGraphExecDestroy(br_graph);
+  }
 };
 
 // Which schedule computes the Voronoi passes: the level-synchronous search
@@ -1983,6 +2031,7 @@ BRArgs br_args(const Geom &g, CvtWork &W) {
   A.xface = W.xface;
   A.mark = W.act;
   A.list = W.brlist;
+  A.rnd = W.ctl + 7;
   A.ctl = W.ctl;
   A.alive = W.ctl + 4;
   A.hist = W.hist;
@@ -2003,7 +2052,7 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   const int64_t nkeys = bg.nbricks * kRows * BX;
   if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.ctl, 3, 0u, s))) return rc;
-  if ((rc = fill<uint32_t>(W.ctl + 4, 3, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.ctl + 4, 4, 0u, s))) return rc;  // alive flags and the round counter
   if (!inc) {
     if ((rc = fill<unsigned long long>(A.key, nkeys, kInfKey, s))) return rc;
     if ((rc = fill<unsigned long long>(A.xface, bg.nbricks * 512, kInfKey, s))) return rc;
@@ -2018,28 +2067,36 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   }
   const unsigned lgrid = (unsigned)std::min<int64_t>((bg.nbricks + 255) / 256, 4096);
   const unsigned rgrid = (unsigned)std::min<int64_t>(bg.nbricks, 2048);
+  // kGraphRounds rounds (three launches each) captured once per call and
+  // replayed as one graph launch
+  if (!st.br_graph) {
+    rc = capture_rounds(&st.br_graph, [&](hipStream_t cs) -> int32_t {
+      hipLaunchKernelGGL(k_br_next, dim3(1), dim3(64), 0, cs, A);
+      hipLaunchKernelGGL(k_br_list, dim3(lgrid), dim3(256), 0, cs, A);
+      hipLaunchKernelGGL(k_br_round, dim3(rgrid), dim3(kBRThreads), 0, cs, A);
+      LSRVT_LAUNCHED();
+      return LSRVT_OK;
+    });
+    if (rc) return rc;
+  }
   uint32_t r = 0;
-  int batch = st.br_rounds ? (int)st.br_rounds : 8;
+  int batch = st.br_rounds ? (int)st.br_rounds : kGraphRounds;
   uint32_t c[8];
   const int64_t max_rounds = 4 * g.n + 8;
   while (true) {
     const bool timed = timer().on;
     std::pair<hipEvent_t, hipEvent_t> ev;
+    const int graphs = (batch + kGraphRounds - 1) / kGraphRounds;
     if (timed && (rc = timed_begin(s, ev))) return rc;
-    for (int i = 0; i < batch; ++i) {
-      ++r;
-      if ((rc = fill<uint32_t>(W.ctl, 1, 0u, s))) return rc;
-      hipLaunchKernelGGL(k_br_list, dim3(lgrid), dim3(256), 0, s, A, r);
-      hipLaunchKernelGGL(k_br_round, dim3(rgrid), dim3(kBRThreads), 0, s, A, r);
-      LSRVT_LAUNCHED();
-    }
-    if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
+    for (int i = 0; i < graphs; ++i) LSRVT_HIP(hipGraphLaunch(st.br_graph, s));
+    r += (uint32_t)(graphs * kGraphRounds);
+    if (timed && (rc = timed_end(s, ev, (uint64_t)graphs * kGraphRounds))) return rc;
     if ((rc = read_words(W.ctl, 8, c, s))) return rc;
     if (c[3] & 1u) return LSRVT_EINVAL;
     if (c[3]) return LSRVT_EDEVICE;
     if (c[4 + (r + 1) % 3] == 0) break;
     if ((int64_t)r > max_rounds) return LSRVT_EDEVICE;
-    batch = 8;
+    batch = kGraphRounds;
   }
   // the rounds that had work size the first batch of the next pass
   const uint32_t nl = std::min<uint32_t>(r + 1, kHistLen);
@@ -2159,10 +2216,12 @@ __global__ void kb_init_sites(const JobDev *J) {
 
 // Start of pass t: marks and list counters cleared, and for a full pass
 // (t = 0) every key and packed face unreached.  Block (0, 0) clears the
-// shared round flags.
+// shared round flags and round counter and records the pass (the shared
+// words after the flags: [3] round, [4] pass, read by the graph-replayed
+// round kernels).
 __global__ __launch_bounds__(256) void kb_pass_clear(const JobDev *J, int32_t t) {
   const JobDev &j = J[blockIdx.y];
-  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 3) j.A.alive[threadIdx.x] = 0u;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 5) j.A.alive[threadIdx.x] = threadIdx.x == 4 ? (uint32_t)t : 0u;
   if (t > j.iters) return;
   const int64_t nb = j.A.bg.nbricks, stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2186,20 +2245,25 @@ __global__ void kb_sites(const JobDev *J, int32_t t) {
   d_br_sites(j.sites, j.S, j.A);
 }
 
+// Start of a round: every job's list emptied, the shared round advanced.
 __global__ void kb_round_prep(const JobDev *J) {
-  if (threadIdx.x == 0) J[blockIdx.y].A.ctl[0] = 0u;
+  if (threadIdx.x == 0) {
+    const JobDev &j = J[blockIdx.y];
+    j.A.ctl[0] = 0u;
+    if (blockIdx.y == 0) j.A.alive[3] += 1u;
+  }
 }
 
-__global__ __launch_bounds__(256) void kb_list(const JobDev *J, int32_t t, uint32_t r) {
+__global__ __launch_bounds__(256) void kb_list(const JobDev *J) {
   const JobDev &j = J[blockIdx.y];
-  if (t > j.iters) return;
-  d_br_list(j.A, r);
+  if ((int32_t)j.A.alive[4] > j.iters) return;
+  d_br_list(j.A, j.A.alive[3]);
 }
 
-__global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J, int32_t t, uint32_t r) {
+__global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J) {
   const JobDev &j = J[blockIdx.y];
-  if (t > j.iters) return;
-  d_br_round(j.A, r);
+  if ((int32_t)j.A.alive[4] > j.iters) return;
+  d_br_round(j.A, j.A.alive[3]);
 }
 
 __global__ __launch_bounds__(kVTThreads) void kb_finish(const JobDev *J, int32_t t) {
@@ -2321,30 +2385,36 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
   const unsigned g_tiles = cap(max_tiles, 65535);
   const unsigned g_fb = cap(max_sites, 1024);
   uint32_t rounds_hint = 0;
+  // kGraphRounds rounds of every job captured once and replayed as one graph launch
+  VTState gs;
+  int32_t rc0 = capture_rounds(&gs.br_graph, [&](hipStream_t cs) -> int32_t {
+    hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, cs, dj);
+    hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, cs, dj);
+    hipLaunchKernelGGL(kb_round, dim3(g_round, N), dim3(kBRThreads), 0, cs, dj);
+    LSRVT_LAUNCHED();
+    return LSRVT_OK;
+  });
+  if (rc0) return rc0;
   for (int32_t t = 0; t <= tmax; ++t) {
     hipLaunchKernelGGL(kb_pass_clear, dim3(g_clear, N), dim3(256), 0, s, dj, t);
     if (t > 0) hipLaunchKernelGGL(kb_reset, dim3(g_clear, N), dim3(256), 0, s, dj, t);
     hipLaunchKernelGGL(kb_sites, dim3(g_sites, N), dim3(256), 0, s, dj, t);
     LSRVT_LAUNCHED();
     uint32_t r = 0;
-    int batch = rounds_hint ? (int)rounds_hint : 8;
+    int batch = rounds_hint ? (int)rounds_hint : kGraphRounds;
     uint32_t c[3];
     const bool timed = timer().on;
     while (true) {
       std::pair<hipEvent_t, hipEvent_t> ev;
+      const int graphs = (batch + kGraphRounds - 1) / kGraphRounds;
       if (timed && (rc = timed_begin(s, ev))) return rc;
-      for (int k = 0; k < batch; ++k) {
-        ++r;
-        hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, s, dj);
-        hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, s, dj, t, r);
-        hipLaunchKernelGGL(kb_round, dim3(g_round, N), dim3(kBRThreads), 0, s, dj, t, r);
-        LSRVT_LAUNCHED();
-      }
-      if (timed && (rc = timed_end(s, ev, (uint64_t)batch))) return rc;
+      for (int k = 0; k < graphs; ++k) LSRVT_HIP(hipGraphLaunch(gs.br_graph, s));
+      r += (uint32_t)(graphs * kGraphRounds);
+      if (timed && (rc = timed_end(s, ev, (uint64_t)graphs * kGraphRounds))) return rc;
       if ((rc = read_words(alive, 3, c, s))) return rc;
       if (c[(r + 1) % 3] == 0) break;
       if (r > (uint32_t)(1u << 30)) return LSRVT_EDEVICE;
-      batch = 8;
+      batch = kGraphRounds;
     }
     rounds_hint = r;
     hipLaunchKernelGGL(kb_finish, dim3(g_fin, N), dim3(kVTThreads), 0, s, dj, t);
