@@ -96,19 +96,42 @@ __global__ __launch_bounds__(kCCThreads) void k_cc_local(const uint8_t *__restri
   const int b = blockIdx.x;
   const int bx = b % bg.nbx, by = (b / bg.nbx) % bg.nby, bz = b / (bg.nbx * bg.nby);
   const int x0 = bx * CX, y0 = by * CY, z0 = bz * CZ;
+  bool mixed = false;  // the brick holds more than one band (or voxels beyond the volume)
+  uint8_t first = 0;
   for (int li = threadIdx.x; li < kBrick; li += kCCThreads) {
     int lx = li % CX, ly = (li / CX) % CY, lz = li / (CX * CY);
     int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
     bool valid = gx < g.nx && gy < g.ny && gz < g.nz;
-    sb[li] = valid ? band[gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz)] : kOutside;
-    sp[li] = li;
+    const uint8_t bv = valid ? band[gx + (int64_t)g.nx * (gy + (int64_t)g.ny * gz)] : kOutside;
+    sb[li] = bv;
+    if (li == (int)threadIdx.x) first = bv;
+    mixed |= bv != first || bv == kOutside;
+  }
+  __syncthreads();
+  // one band over the whole brick: every voxel's root is the brick's first voxel
+  mixed |= first != sb[0];
+  if (!__syncthreads_or(mixed)) {
+    const int64_t gr = x0 + (int64_t)g.nx * (y0 + (int64_t)g.ny * z0);
+    for (int li = threadIdx.x; li < kBrick; li += kCCThreads) {
+      int lx = li % CX, ly = (li / CX) % CY, lz = li / (CX * CY);
+      label[(x0 + lx) + (int64_t)g.nx * ((y0 + ly) + (int64_t)g.ny * (z0 + lz))] = (uint32_t)gr;
+    }
+    return;
+  }
+  // every voxel starts linked to the first voxel of its run of equal band
+  // along x (a valid forest: parents never exceed their children), so only
+  // the y and z neighbours need unions
+  for (int li = threadIdx.x; li < kBrick; li += kCCThreads) {
+    const uint8_t bv = sb[li];
+    int st = li;
+    while ((st % CX) > 0 && sb[st - 1] == bv) --st;
+    sp[li] = (uint32_t)st;
   }
   __syncthreads();
   for (int li = threadIdx.x; li < kBrick; li += kCCThreads) {
     uint8_t bv = sb[li];
     if (bv == kOutside) continue;
-    int lx = li % CX, ly = (li / CX) % CY, lz = li / (CX * CY);
-    if (lx > 0 && sb[li - 1] == bv) unite_lds(sp, li, li - 1);
+    int ly = (li / CX) % CY, lz = li / (CX * CY);
     if (ly > 0 && sb[li - CX] == bv) unite_lds(sp, li, li - CX);
     if (lz > 0 && sb[li - CX * CY] == bv) unite_lds(sp, li, li - CX * CY);
   }

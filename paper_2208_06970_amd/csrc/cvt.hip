@@ -987,7 +987,12 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     raw[0][t] = e1;
     raw[1][t] = e2;
     chg[t] = 0u;
-    dx[t] = dy[t] = dz[t] = 1;
+    // In round 1 every line starts dirty (sites were set, keys reset or the
+    // pass starts from nothing).  Later a brick's keys are a fixed point of
+    // its own relaxation (its last processing ended at one, or the previous
+    // pass's result is one), so only the lines through voxels that a
+    // neighbour's offer lowered can change.
+    dx[t] = dy[t] = dz[t] = r == 1 ? 1 : 0;
     if (t < 8) flags[t] = 0u;
     __syncthreads();
     // line masks of this thread's y line (lx, lz) and z line (lx, ly), in
@@ -1002,8 +1007,12 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     // offers of the six face neighbours: their keys plus one hop
     {
       auto offer = [&](bool has, bool edge, unsigned long long h, int lx, int row) {
-        if (has && edge && h != kInfKey && atomicMin(&K[br_at(lx, row)], h + kOneHop) > h + kOneHop)
+        if (has && edge && h != kInfKey && atomicMin(&K[br_at(lx, row)], h + kOneHop) > h + kOneHop) {
           atomicOr(&chg[row], 1u << lx);
+          dx[row] = 1;
+          dy[lx + 16 * (row >> 4)] = 1;
+          dz[lx + 16 * (row & 15)] = 1;
+        }
       };
       offer(hxm, mx & 1u, fxm, 0, t);
       offer(hxp, (mx >> 31) & 1u, fxp, 15, t);
@@ -1014,8 +1023,8 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     }
     __syncthreads();
     // the brick's own fixed point: line sweeps along x, y and z.  A line is
-    // swept again along its axis only after a voxel on it changed (every
-    // line starts dirty); the loop ends when no line is dirty.
+    // swept (again) along its axis only after a voxel on it changed; the
+    // loop ends when no line is dirty.
     uint32_t sweeps = 0;
     for (;;) {
       ++sweeps;
