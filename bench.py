@@ -240,7 +240,18 @@ def bench_flame(args):
     sd = torch.from_numpy(seeds.view(np.int32)).cuda()
     _log(f"flame: comps={cc.n_comp} sites={len(seeds)}")
     step = Step(f, wl.iso, wl.n_bands, sd, w, wl.iters, x, e)
-    ms, timing = timed_steps(step, args.steps, args.warmup, "flame")
+    # launch shapes for this job class, tuned before timing (cached on disk)
+    from paper_2208_06970_amd import autotune
+    _log("flame: tuning launch shapes")
+    grid = autotune.br_grid(band, sd, wl.n_bands)
+    r1 = L.lsrvt_cvt(band, cc.comp, sd, w, 1, want_mean_ds=False)
+    tile = autotune.stats_tile(tuple(band.shape), len(seeds), wl.n_bands, int(x.shape[0]),
+                               lambda: L.lsrvt_aggregate(r1.cell, r1.sites, r1.site_comp, cc.comp_band, cc.n_comp,
+                                                         wl.n_bands, x, e, cov=True))
+    del r1
+    _log(f"flame: relaxation grid {grid}, statistics tile {tile} voxels per thread")
+    with autotune.shapes(br_grid=grid, stats_tile=tile):
+        ms, timing = timed_steps(step, args.steps, args.warmup, "flame")
     ph = step.phases()
     out = {
         "metric": "Gvoxels/s per Lloyd iteration (whole step incl. isobands, components, final pass, stats)",
@@ -257,6 +268,8 @@ def bench_flame(args):
         "stats_gvox_s": round(n / (ph["aggregate"] / 1e3) / 1e9, 4) if ph["aggregate"] else None,
         "end_to_end_gvox_s": round(n / (ms / 1e3) / 1e9, 4),
         "stats_dtype": "f32 compensated per cell, f64 merges",
+        "tuning": {"vt_schedule": "bricks" if timing[4] == 2 else "levels" if timing[4] == 1 else "both",
+                   "br_grid": grid, "stats_tile": tile},
         "roofline": roofline(timing, "flame"),
     }
     if not args.no_extras:

@@ -521,6 +521,24 @@ int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d
 int32_t lsrvt_set_vt_engine(int32_t engine);
 
 /* ------------------------------------------------------------------------
+ * Launch shapes of the calling host thread's later calls (none of them
+ * changes what is computed; the autotuner of the Python package picks them
+ * per job class by measurement):
+ *   LSRVT_TUNE_BR_GRID      workgroups of each brick-relaxation round
+ *                           (each walks the round's bricks with that stride):
+ *                           256 .. 16384, 0 = the library's choice (2048)
+ *   LSRVT_TUNE_STATS_TILE   voxels staged in LDS per thread and round by the
+ *                           statistics' cell kernel (its tile is this times
+ *                           its workgroup size): 1, 2 or 4, 0 = the largest
+ *                           that keeps a workgroup within 40 KiB of LDS
+ * Returns the previous value, or -1 (and changes nothing) for an unknown
+ * knob or a value outside its range.
+ */
+#define LSRVT_TUNE_BR_GRID 1
+#define LSRVT_TUNE_STATS_TILE 2
+int32_t lsrvt_set_tuning(int32_t knob, int32_t value);
+
+/* ------------------------------------------------------------------------
  * Benchmark instrumentation of the Voronoi passes' dominant kernel: the
  * level kernel (one launch per breadth-first level) under LSRVT_VT_LEVELS,
  * the relaxation round (one brick-list launch and one round launch per

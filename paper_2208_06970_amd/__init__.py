@@ -37,7 +37,7 @@ EXPORTS = (
     "lsrvt_aggregate_workspace", "lsrvt_aggregate", "lsrvt_batch_workspace", "lsrvt_batch_run",
     "lsrvt_layout_workspace", "lsrvt_layout", "lsrvt_extract", "lsrvt_seed_workspace", "lsrvt_seed",
     "lsrvt_comoments_workspace", "lsrvt_comoments", "lsrvt_los_workspace", "lsrvt_los_vt", "lsrvt_los_update",
-    "lsrvt_los_cvt", "lsrvt_set_vt_engine", "lsrvt_timing_enable", "lsrvt_timing_read",
+    "lsrvt_los_cvt", "lsrvt_set_vt_engine", "lsrvt_set_tuning", "lsrvt_timing_enable", "lsrvt_timing_read",
 )
 
 
@@ -137,6 +137,8 @@ def _lib():
         lib.lsrvt_los_cvt.argtypes = [P, Dims, P, u32, P, i32, P, P, P, P, P, P, P, P, S, P]
         lib.lsrvt_set_vt_engine.argtypes = [i32]
         lib.lsrvt_set_vt_engine.restype = i32
+        lib.lsrvt_set_tuning.argtypes = [i32, i32]
+        lib.lsrvt_set_tuning.restype = i32
         lib.lsrvt_timing_enable.argtypes = [i32]
         lib.lsrvt_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64),
                                           ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int64),
@@ -627,6 +629,20 @@ def lsrvt_set_vt_engine(engine: int) -> int:
     prev = int(_lib().lsrvt_set_vt_engine(int(engine)))
     if prev < 0:
         raise LsrvtError(EINVAL, "lsrvt_set_vt_engine", f"unknown engine {engine}")
+    return prev
+
+
+TUNE_BR_GRID, TUNE_STATS_TILE = 1, 2
+
+
+def lsrvt_set_tuning(knob: int, value: int) -> int:
+    """Launch shape of this host thread's later calls (TUNE_BR_GRID:
+    workgroups per relaxation round, 256..16384; TUNE_STATS_TILE: voxels per
+    thread and staging round of the statistics, 1, 2 or 4; 0 = the library's
+    choice); returns the previous value."""
+    prev = int(_lib().lsrvt_set_tuning(int(knob), int(value)))
+    if prev < 0:
+        raise LsrvtError(EINVAL, "lsrvt_set_tuning", f"knob {knob} value {value}")
     return prev
 
 

@@ -1,6 +1,7 @@
 """Autotuner for the schedule choices of the hot path, with an on-disk cache.
 
-Two choices are tuned by measurement on the GPU at hand:
+Four choices are tuned by measurement on the GPU at hand (none of them
+changes what is computed):
 
 * the schedule of the Voronoi passes (``lsrvt_set_vt_engine``): the
   level-synchronous search or the brick relaxation.  Both give the same
@@ -8,7 +9,11 @@ Two choices are tuned by measurement on the GPU at hand:
   each site holds (wide cells mean many levels per pass but few relaxation
   rounds).  Tuned per job class by timing one Voronoi pass with each.
 * the number of streams of ``lsrvt_batch_run``'s per-job phases (labels and
-  statistics), tuned per batch by timing the whole batch.
+  statistics), tuned per batch by timing the whole batch;
+* the launch shapes (``lsrvt_set_tuning``): the workgroups of a relaxation
+  round (each walks the round's 16^3 bricks with that stride) and the tile
+  the statistics stage in LDS per round (1, 2 or 4 voxels per thread), each
+  tuned per job class by timing one Voronoi pass or one statistics call.
 
 A job class is (GPU name, log2 of the voxel count, log2 of voxels per site,
 band count bucket).  Results are kept in a JSON file (``LSRVT_AUTOTUNE_CACHE``,
@@ -28,7 +33,8 @@ import time
 
 import numpy as np
 
-from . import (VT_BRICKS, VT_LEVELS, lsrvt_set_vt_engine, lsrvt_vt)
+from . import (TUNE_BR_GRID, TUNE_STATS_TILE, VT_BRICKS, VT_LEVELS, lsrvt_set_tuning, lsrvt_set_vt_engine,
+               lsrvt_vt)
 
 _LOCK = threading.Lock()
 _CACHE = None
@@ -168,3 +174,89 @@ def batch_streams(make_jobs, candidates=(2, 4, 8), key: str | None = None, ws=No
             _store(f"batch:{_device_name()}:{key}", {"streams": best,
                                                      "ms": {str(k): round(v * 1e3, 3) for k, v in times.items()}})
     return best
+
+
+def _cached(key):
+    with _LOCK:
+        return _load().get(key)
+
+
+def _time(fn, reps: int = 2) -> float:
+    import torch
+    fn()  # warm-up (and workspace sizing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def br_grid(band, sites, n_bands: int, candidates=(1024, 2048, 4096, 8192), tune: bool = True) -> int | None:
+    """Workgroups per relaxation round for this job class: cached, or
+    measured now (one Voronoi pass by brick relaxation with each)."""
+    key = "brgrid:" + job_class(tuple(band.shape), int(sites.numel()), n_bands)
+    hit = _cached(key)
+    if hit is not None:
+        return int(hit["grid"])
+    if not tune:
+        return None
+    prev_e = lsrvt_set_vt_engine(VT_BRICKS)
+    times = {}
+    try:
+        for gsz in candidates:
+            prev = lsrvt_set_tuning(TUNE_BR_GRID, gsz)
+            try:
+                times[gsz] = _time(lambda: lsrvt_vt(band, sites))
+            finally:
+                lsrvt_set_tuning(TUNE_BR_GRID, prev)
+    finally:
+        lsrvt_set_vt_engine(prev_e)
+    best = min(times, key=times.get)
+    with _LOCK:
+        _store(key, {"grid": best, "ms": {str(k): round(v * 1e3, 4) for k, v in times.items()}})
+    return best
+
+
+def stats_tile(shape, n_sites: int, n_bands: int, n_vars: int, run, candidates=(1, 2, 4),
+               tune: bool = True) -> int | None:
+    """Voxels per thread and staging round of the statistics for this job
+    class (shape, sites, bands, variable count): cached, or measured now by
+    timing run() (one lsrvt_aggregate call) with each."""
+    key = f"statstile:m{int(n_vars)}:" + job_class(tuple(shape), int(n_sites), n_bands)
+    hit = _cached(key)
+    if hit is not None:
+        return int(hit["tile"])
+    if not tune:
+        return None
+    times = {}
+    for v in candidates:
+        prev = lsrvt_set_tuning(TUNE_STATS_TILE, v)
+        try:
+            times[v] = _time(run)
+        finally:
+            lsrvt_set_tuning(TUNE_STATS_TILE, prev)
+    best = min(times, key=times.get)
+    with _LOCK:
+        _store(key, {"tile": best, "ms": {str(k): round(v * 1e3, 4) for k, v in times.items()}})
+    return best
+
+
+class shapes:
+    """Context manager: run the enclosed calls of this thread with the given
+    launch shapes (None leaves a knob at the library's choice)."""
+
+    def __init__(self, br_grid: int | None = None, stats_tile: int | None = None):
+        self.want = {TUNE_BR_GRID: br_grid, TUNE_STATS_TILE: stats_tile}
+        self.prev = {}
+
+    def __enter__(self):
+        for k, v in self.want.items():
+            if v is not None:
+                self.prev[k] = lsrvt_set_tuning(k, v)
+        return self
+
+    def __exit__(self, *exc):
+        for k, v in self.prev.items():
+            lsrvt_set_tuning(k, v)
+        return False

@@ -1083,6 +1083,15 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
       lds = fixed + sizeof(float) * (size_t)m * (A.tile + 4);
       if (lds <= 40960 || vpt == 1) break;
     }
+    const int32_t tv = tuning(LSRVT_TUNE_STATS_TILE);  // a tuned round size, if it fits in 64 KiB
+    if (tv) {
+      const size_t l2 = fixed + sizeof(float) * (size_t)m * ((size_t)tv * NT + 4);
+      if (l2 <= 65536) {
+        vpt = tv;
+        A.tile = vpt * NT;
+        lds = l2;
+      }
+    }
     if (lds > 65536 || R > 3 || NT > kAggMaxThreads) return LSRVT_EINVAL;
     const unsigned grid = n_items < 16384 ? n_items : 16384;
     auto launch = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, s, A); };

@@ -174,6 +174,10 @@ struct CvtBatchJob {
   int32_t iters;
   uint32_t *cell, *sites, *site_comp;
 };
+// Launch-shape settings of the calling host thread (lsrvt_set_tuning); 0 =
+// the library's choice.
+int32_t tuning(int32_t knob);
+
 size_t cvt_batch_header(int32_t n);
 size_t cvt_batch_job_workspace(lsrvt_dims dims, uint32_t n_sites, int32_t iters);
 int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, int32_t *status, hipStream_t s);

@@ -1136,11 +1136,13 @@ struct Sums {
 // position of every cell, exact uint64 integers, so their order does not
 // matter) taken at the end of the Voronoi pass that produces the cells: the
 // pass's last kernel holds every voxel's cell id once anyway, so the sums
-// cost no second read of the cell array.  One workgroup per 16^3 brick
-// stages the brick's cells and weights in LDS; thread t then walks row t
-// (16 voxels along x) and adds every run of equal cell id into an LDS table
-// keyed by cell id (global atomics when the table is full); the table is
-// flushed with one set of global atomics per distinct cell of the brick.
+// cost no second read of the cell array.  One workgroup per 16^3 brick;
+// thread t takes voxel t, t + 256, ... of the brick, so the 16 lanes of each
+// quarter wave hold one row along x.  A segmented scan over those 16 lanes
+// (DPP row shifts) sums (w, w * (x - x0)) over every run of equal cell id,
+// the last lane of a run adds it into an LDS table keyed by cell id (global
+// atomics when the table is full), and the table is flushed with one set of
+// global atomics per distinct cell of the brick.
 struct Fuse {
   const uint16_t *w;  // weights (C order) or null for unit weights
   uint32_t S;
@@ -1148,68 +1150,78 @@ struct Fuse {
 };
 
 constexpr int kFinTab = 256;
-constexpr int kFinRow = BX + 1;  // LDS row stride: the row walks read without bank conflicts
-struct FinLds {
-  uint32_t c[kRows * kFinRow];
-  uint16_t w[kRows * kFinRow];
+struct FinTab {
   uint32_t tkey[kFinTab];
   unsigned long long tM[kFinTab], tX[kFinTab], tY[kFinTab], tZ[kFinTab];
 };
 
-__device__ __forceinline__ void fin_clear(FinLds &L) {
+__device__ __forceinline__ void fin_clear(FinTab &T) {
   for (int i = threadIdx.x; i < kFinTab; i += blockDim.x) {
-    L.tkey[i] = kNone;
-    L.tM[i] = L.tX[i] = L.tY[i] = L.tZ[i] = 0ull;
+    T.tkey[i] = kNone;
+    T.tM[i] = T.tX[i] = T.tY[i] = T.tZ[i] = 0ull;
   }
 }
 
-// After the brick's cells and weights are staged (and a barrier): the row
-// walks and the flush.  Ends with a barrier.
-__device__ __forceinline__ void fin_sums(FinLds &L, const Fuse &F, int bx, int by, int bz, const Geom &g) {
-  const int t = threadIdx.x;
-  const int y = by * BY + (t & 15), z = bz * BZ + (t >> 4);
-  const uint32_t x0 = (uint32_t)(bx * BX);
-  if (y < g.ny && z < g.nz) {
-    uint32_t cur = kNone, m = 0, sx = 0;  // run mass and sum of w * (x - x0): below 2^24
-    auto flush = [&]() {
-      if (cur < F.S && m) {
-        const unsigned long long M = m, X = (unsigned long long)m * x0 + sx, Y = (unsigned long long)m * (uint32_t)y,
-                                 Z = (unsigned long long)m * (uint32_t)z;
-        const int sl = lds_slot<kFinTab>(L.tkey, cur);
-        if (sl >= 0) {
-          atomicAdd(&L.tM[sl], M);
-          atomicAdd(&L.tX[sl], X);
-          atomicAdd(&L.tY[sl], Y);
-          atomicAdd(&L.tZ[sl], Z);
-        } else {
-          atomicAdd(&F.sums.M[cur], M);
-          atomicAdd(&F.sums.Sx[cur], X);
-          atomicAdd(&F.sums.Sy[cur], Y);
-          atomicAdd(&F.sums.Sz[cur], Z);
-        }
-      }
-    };
-#pragma unroll
-    for (int i = 0; i < BX; ++i) {
-      const uint32_t c = L.c[t * kFinRow + i], wv = L.w[t * kFinRow + i];
-      if (c != cur) {
-        flush();
-        cur = c;
-        m = sx = 0;
-      }
-      m += wv;
-      sx += wv * (uint32_t)i;
-    }
-    flush();
+// v moved right by CTRL's shift within each row of 16 lanes; 0 where the
+// source lane lies outside the row.
+template <int CTRL>
+__device__ __forceinline__ uint32_t row_shift(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// One voxel per lane, 16 lanes per row (lane & 15 = x - x0, every lane of
+// the wave active): adds the runs of equal cell id of the wave's four rows
+// into the table.  c = kNone for voxels outside the volume (weight 0).
+__device__ __forceinline__ void fin_row_runs(FinTab &T, const Fuse &F, uint32_t c, uint32_t wv, uint32_t x0,
+                                             uint32_t y, uint32_t z) {
+  const uint32_t lx = threadIdx.x & 15;
+  const uint32_t cl = (uint32_t)__builtin_amdgcn_update_dpp((int)kNone, (int)c, 0x111, 0xF, 0xF, false);  // row_shr:1
+  const uint32_t cr = (uint32_t)__builtin_amdgcn_update_dpp((int)kNone, (int)c, 0x101, 0xF, 0xF, false);  // row_shl:1
+  uint32_t m = wv, sx = wv * lx;  // sum of w * (x - x0) over a run: below 2^24
+  uint32_t f = (lx == 0 || cl != c) ? 1u : 0u;  // a run starts within the lanes summed so far
+#define LSRVT_SEG_STEP(CTRL)                                        \
+  {                                                                 \
+    const uint32_t mo = row_shift<CTRL>(m), so = row_shift<CTRL>(sx), fo = row_shift<CTRL>(f); \
+    if (!f) {                                                       \
+      m += mo;                                                      \
+      sx += so;                                                     \
+      f = fo;                                                       \
+    }                                                               \
   }
-  __syncthreads();
-  for (int i = t; i < kFinTab; i += blockDim.x) {
-    const uint32_t c = L.tkey[i];
-    if (c != kNone && L.tM[i]) {
-      atomicAdd(&F.sums.M[c], L.tM[i]);
-      atomicAdd(&F.sums.Sx[c], L.tX[i]);
-      atomicAdd(&F.sums.Sy[c], L.tY[i]);
-      atomicAdd(&F.sums.Sz[c], L.tZ[i]);
+  LSRVT_SEG_STEP(0x111)  // row_shr:1
+  LSRVT_SEG_STEP(0x112)  // row_shr:2
+  LSRVT_SEG_STEP(0x114)  // row_shr:4
+  LSRVT_SEG_STEP(0x118)  // row_shr:8
+#undef LSRVT_SEG_STEP
+  const bool tail = lx == 15 || cr != c;
+  if (tail && c < F.S && m) {
+    const unsigned long long M = m, X = (unsigned long long)m * x0 + sx, Y = (unsigned long long)m * y,
+                             Z = (unsigned long long)m * z;
+    const int sl = lds_slot<kFinTab>(T.tkey, c);
+    if (sl >= 0) {
+      atomicAdd(&T.tM[sl], M);
+      atomicAdd(&T.tX[sl], X);
+      atomicAdd(&T.tY[sl], Y);
+      atomicAdd(&T.tZ[sl], Z);
+    } else {
+      atomicAdd(&F.sums.M[c], M);
+      atomicAdd(&F.sums.Sx[c], X);
+      atomicAdd(&F.sums.Sy[c], Y);
+      atomicAdd(&F.sums.Sz[c], Z);
+    }
+  }
+}
+
+// After the brick's rows (and a barrier): the table to global memory.  Ends
+// with a barrier.
+__device__ __forceinline__ void fin_flush(FinTab &T, const Fuse &F) {
+  for (int i = threadIdx.x; i < kFinTab; i += blockDim.x) {
+    const uint32_t c = T.tkey[i];
+    if (c != kNone && T.tM[i]) {
+      atomicAdd(&F.sums.M[c], T.tM[i]);
+      atomicAdd(&F.sums.Sx[c], T.tX[i]);
+      atomicAdd(&F.sums.Sy[c], T.tY[i]);
+      atomicAdd(&F.sums.Sz[c], T.tZ[i]);
     }
   }
   __syncthreads();
@@ -1219,11 +1231,12 @@ __device__ __forceinline__ void fin_sums(FinLds &L, const Fuse &F, int bx, int b
 // (as k_br_finish) and the centroid sums, one workgroup per brick.
 __global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const unsigned long long *__restrict__ key, Geom g,
                                                                VTGrid bg, uint32_t *__restrict__ cell, Fuse F) {
-  __shared__ FinLds L;
+  __shared__ FinTab T;
   const int t = threadIdx.x;
   for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
     const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-    fin_clear(L);
+    fin_clear(T);
+    __syncthreads();
 #pragma unroll 4
     for (int i = 0; i < BX; ++i) {
       const int loc = i * kVTThreads + t;
@@ -1233,12 +1246,11 @@ __global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const unsigned lo
       const uint32_t c = k == kInfKey ? kNone : (uint32_t)(k & 0xFFFFFFFFull);
       const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
       if (in) cell[v] = c;
-      const int li = (loc >> 4) * kFinRow + (loc & 15);
-      L.c[li] = in ? c : kNone;
-      L.w[li] = in ? (F.w ? F.w[v] : (uint16_t)1) : (uint16_t)0;
+      const uint32_t wv = in ? (F.w ? (uint32_t)F.w[v] : 1u) : 0u;
+      fin_row_runs(T, F, in ? c : kNone, wv, (uint32_t)(bx * BX), (uint32_t)y, (uint32_t)z);
     }
     __syncthreads();
-    fin_sums(L, F, bx, by, bz, g);
+    fin_flush(T, F);
   }
 }
 
@@ -1760,11 +1772,12 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_finish_sums(const uint16_t *_
                                                                const uint16_t *__restrict__ inv, Geom g, VTGrid bg,
                                                                uint32_t *__restrict__ cellb,
                                                                uint32_t *__restrict__ cell, Fuse F) {
-  __shared__ FinLds L;
+  __shared__ FinTab T;
   const int t = threadIdx.x;
   for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
     const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-    fin_clear(L);
+    fin_clear(T);
+    __syncthreads();
 #pragma unroll 4
     for (int i = 0; i < BX; ++i) {
       const int loc = i * kVTThreads + t;
@@ -1785,12 +1798,11 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_finish_sums(const uint16_t *_
       }
       const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
       if (in) cell[v] = c;
-      const int li = (loc >> 4) * kFinRow + lx;
-      L.c[li] = c;
-      L.w[li] = in ? (F.w ? F.w[v] : (uint16_t)1) : (uint16_t)0;
+      const uint32_t wv = in ? (F.w ? (uint32_t)F.w[v] : 1u) : 0u;
+      fin_row_runs(T, F, c, wv, (uint32_t)(bx * BX), (uint32_t)y, (uint32_t)z);
     }
     __syncthreads();
-    fin_sums(L, F, bx, by, bz, g);
+    fin_flush(T, F);
   }
 }
 
@@ -2075,7 +2087,8 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     LSRVT_LAUNCHED();
   }
   const unsigned lgrid = (unsigned)std::min<int64_t>((bg.nbricks + 255) / 256, 4096);
-  const unsigned rgrid = (unsigned)std::min<int64_t>(bg.nbricks, 2048);
+  const int32_t tg = tuning(LSRVT_TUNE_BR_GRID);
+  const unsigned rgrid = (unsigned)std::min<int64_t>(bg.nbricks, tg ? tg : 2048);
   // kGraphRounds rounds (three launches each) captured once per call and
   // replayed as one graph launch
   if (!st.br_graph) {
@@ -2633,6 +2646,26 @@ extern "C" int32_t lsrvt_update_noalloc(const uint32_t *d_cell, lsrvt_dims dims,
   W.fb_cnt = reinterpret_cast<uint32_t *>(base + kNoAllocSums + kNoAllocList);
   W.moved = base + kNoAllocSums + kNoAllocList + 256;
   return run_update(d_cell, g, d_weights, d_sites, n_sites, d_ds, W, as_stream(stream));
+}
+
+namespace lsrvt {
+namespace {
+thread_local int32_t t_tuning[3] = {0, 0, 0};
+}  // namespace
+int32_t tuning(int32_t knob) { return knob > 0 && knob < 3 ? t_tuning[knob] : 0; }
+}  // namespace lsrvt
+
+extern "C" int32_t lsrvt_set_tuning(int32_t knob, int32_t value) {
+  if (knob == LSRVT_TUNE_BR_GRID) {
+    if (value != 0 && (value < 256 || value > 16384)) return -1;
+  } else if (knob == LSRVT_TUNE_STATS_TILE) {
+    if (value != 0 && value != 1 && value != 2 && value != 4) return -1;
+  } else {
+    return -1;
+  }
+  const int32_t prev = t_tuning[knob];
+  t_tuning[knob] = value;
+  return prev;
 }
 
 extern "C" int32_t lsrvt_set_vt_engine(int32_t engine) {

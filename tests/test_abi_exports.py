@@ -120,3 +120,17 @@ def test_los_host_validation_without_gpu(lib):
                                                  nul, fake, wb, nul)
     assert cvt(-1) == L.EINVAL
     assert cvt(2) == L.EWORKSPACE
+
+
+def test_set_tuning_validation_without_gpu(lib):
+    """Launch-shape knobs: unknown knobs and out-of-range values are refused
+    and change nothing; a valid value returns the previous one."""
+    assert lib.lsrvt_set_tuning(0, 1) == -1
+    assert lib.lsrvt_set_tuning(99, 1) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_BR_GRID, 100) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_BR_GRID, 1 << 20) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_STATS_TILE, 3) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_BR_GRID, 4096) == 0
+    assert lib.lsrvt_set_tuning(L.TUNE_BR_GRID, 0) == 4096
+    assert lib.lsrvt_set_tuning(L.TUNE_STATS_TILE, 2) == 0
+    assert lib.lsrvt_set_tuning(L.TUNE_STATS_TILE, 0) == 2

@@ -221,3 +221,19 @@ def test_cvt_errors_and_determinism(engine):
     a = L.lsrvt_cvt(band_d, cc.comp, dev(seeds), None, 4)
     b = L.lsrvt_cvt(band_d, cc.comp, dev(seeds), None, 4)
     assert np.array_equal(host(a.cell), host(b.cell)) and np.array_equal(host(a.sites), host(b.sites))
+
+
+@pytest.mark.parametrize("grid", [256, 1024, 16384])
+def test_cvt_every_relaxation_grid(grid):
+    """Each relaxation-round grid the autotuner may choose gives the oracle's
+    Lloyd loop bit for bit (the rounds' workgroups only walk the bricks with
+    another stride)."""
+    prev_e = L.lsrvt_set_vt_engine(L.VT_BRICKS)
+    prev = L.lsrvt_set_tuning(L.TUNE_BR_GRID, grid)
+    try:
+        f = _field((40, 36, 90), 11)
+        iso = synth.quantile_isovalues(f, [0.3, 0.6])
+        _cvt_case(f, iso, synth.gradient_weight(f), 300.0, 11, 4)
+    finally:
+        L.lsrvt_set_tuning(L.TUNE_BR_GRID, prev)
+        L.lsrvt_set_vt_engine(prev_e)

@@ -167,3 +167,15 @@ def test_stats_without_hist_and_determinism():
         for k in ("n", "mean", "m2", "vmin", "vmax", "cov"):
             assert np.array_equal(host(getattr(la, k)), host(getattr(lb, k))), k
     _check_level("cell", a[0], oracle.stats(r.cell, len(seeds), x, None, True), 2)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4])
+def test_stats_every_staging_tile(tile):
+    """Each statistics tile the autotuner may choose (voxels per thread and
+    staging round) stays within the tolerances; giant cells so that every
+    item spans several rounds."""
+    prev = L.lsrvt_set_tuning(L.TUNE_STATS_TILE, tile)
+    try:
+        _run((40, 44, 52), 6, 18, 32, True, rho=6000.0)
+    finally:
+        L.lsrvt_set_tuning(L.TUNE_STATS_TILE, prev)
