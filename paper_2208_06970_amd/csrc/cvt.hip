@@ -1066,33 +1066,49 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
       __syncthreads();  // every dirty mark of the z stage is visible before the test
       if (!__syncthreads_or(dx[t] | dy[t] | dz[t])) break;
     }
-    // store what changed; note which faces changed.  The thread index is
-    // passed through an empty asm statement so that the store addresses are
-    // recomputed here instead of being kept live (in registers) from the
-    // loads at the top across the sweeps.
+    // Which neighbours work in round r + 1: a face voxel that changed, has a
+    // same-band edge across the face and whose key plus one hop beats the
+    // neighbour's voxel across it as read at the top.  Keys only decrease
+    // within a pass, so a neighbour whose key already was no larger can never
+    // take the offer.  Thread t checks the face voxels it offered to above.
+    uint32_t fc = 0;
+    {
+      auto gain = [&](bool has, bool edge, int lx, int row, unsigned long long nbk) {
+        if (!has || !edge || !((chg[row] >> lx) & 1u)) return false;
+        const unsigned long long k = K[br_at(lx, row)];
+        return k != kInfKey && k + kOneHop < nbk;
+      };
+      fc |= gain(hxm, mx & 1u, 0, t, fxm) ? 2u : 0u;
+      fc |= gain(hxp, (mx >> 31) & 1u, 15, t, fxp) ? 4u : 0u;
+      fc |= gain(hym, my & 1u, lo4, 16 * hi4, fym) ? 8u : 0u;
+      fc |= gain(hyp, (my >> 31) & 1u, lo4, 15 + 16 * hi4, fyp) ? 16u : 0u;
+      fc |= gain(hzm, mz & 1u, lo4, hi4, fzm) ? 32u : 0u;
+      fc |= gain(hzp, (mz >> 31) & 1u, lo4, hi4 + 16 * 15, fzp) ? 64u : 0u;
+    }
+    if (fc) atomicOr(&flags[0], fc);
+    // store what changed.  The thread index is passed through an empty asm
+    // statement so that the store addresses are recomputed here instead of
+    // being kept live (in registers) from the loads at the top across the
+    // sweeps.
     int tt = t;
     asm volatile("" : "+v"(tt));
-    uint32_t fc = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int loc = i * kBRThreads + tt;
-      const int lx = loc & 15, row = loc >> 4, ly = row & 15, lz = row >> 4;
+      const int lx = loc & 15, row = loc >> 4;
       if ((chg[row] >> lx) & 1u) {
         const unsigned long long k = K[br_at(lx, row)];
         A.key[(size_t)b * kB + loc] = k;
         if (lx == 0) A.xface[(size_t)b * 512 + row] = k;
         if (lx == BX - 1) A.xface[(size_t)b * 512 + 256 + row] = k;
-        fc |= (lx == 0 ? 2u : 0u) | (lx == BX - 1 ? 4u : 0u) | (ly == 0 ? 8u : 0u) | (ly == BY - 1 ? 16u : 0u) |
-              (lz == 0 ? 32u : 0u) | (lz == BZ - 1 ? 64u : 0u);
       }
     }
-    if (fc) atomicOr(&flags[0], fc);
     if (A.dbg && t == 0) {
       atomicAdd(&A.dbg[0], 1ull);
       atomicAdd(&A.dbg[1], (unsigned long long)sweeps);
     }
     __syncthreads();
-    // a changed face: the neighbour across it (if any) works in round r + 1
+    // the neighbours that can gain work in round r + 1
     const uint32_t nb_exists = (hxm ? 2u : 0u) | (hxp ? 4u : 0u) | (hym ? 8u : 0u) | (hyp ? 16u : 0u) |
                                (hzm ? 32u : 0u) | (hzp ? 64u : 0u);
     const uint32_t f = flags[0] & nb_exists;
