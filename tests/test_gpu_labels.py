@@ -237,3 +237,34 @@ def test_cvt_every_relaxation_grid(grid):
     finally:
         L.lsrvt_set_tuning(L.TUNE_BR_GRID, prev)
         L.lsrvt_set_vt_engine(prev_e)
+
+
+def test_update_and_loop_with_every_voxel_a_site():
+    """More distinct cells than the LDS tables of the centroid sums hold
+    (512 per 64x8x8 tile in lsrvt_update, 256 per 16^3 brick in the sums a
+    Voronoi pass takes for the update that follows): every voxel a site, so
+    the global-atomic fallbacks run; bit-exact against the oracle."""
+    shape = (16, 24, 80)
+    rng = np.random.default_rng(21)
+    band = brute.random_bands(shape, 2, rng, smooth=True)
+    comp = oracle.components(band, 2).comp
+    sites = rng.permutation(band.size).astype(np.uint32)
+    w = rng.integers(0, 65536, size=shape).astype(np.uint16)
+    banner("update and loop, every voxel a site")
+    cell = oracle.vt(comp, sites)
+    want, want_ds = oracle.update(cell, sites, w)
+    s_d = dev(sites)
+    _, ds = L.lsrvt_update(dev(cell), s_d, dev(w))
+    np.testing.assert_array_equal(host(s_d, np.uint32), want)
+    np.testing.assert_allclose(host(ds), want_ds, rtol=1e-15, atol=0)
+    for eng in (L.VT_LEVELS, L.VT_BRICKS):
+        prev = L.lsrvt_set_vt_engine(eng)
+        try:
+            b = dev(band)
+            g = L.lsrvt_components(b, 2)
+            r = L.lsrvt_cvt(b, g.comp, dev(sites), dev(w), 2)
+        finally:
+            L.lsrvt_set_vt_engine(prev)
+        ref = oracle.cvt(comp, sites, w, 2)
+        np.testing.assert_array_equal(host(r.sites, np.uint32), ref.sites)
+        np.testing.assert_array_equal(host(r.cell, np.uint32), ref.cell)

@@ -255,3 +255,26 @@ def test_los_degenerate_shapes(shape):
     np.testing.assert_array_equal(host(got.vt.dist), want.dist)
     np.testing.assert_array_equal(host(got.vt.src, np.uint32), want.src)
     np.testing.assert_array_equal(host(got.vt.cell, np.uint32), want.cell)
+
+
+def test_los_update_every_voxel_a_site():
+    """More distinct cells per 64x8x8 tile than the Eq. 2 sums' LDS table
+    holds (512): every voxel a site, so the global-atomic fallback runs;
+    bit-exact against the oracle."""
+    shape = (12, 20, 70)
+    comp = np.zeros(shape, dtype=np.uint32)
+    comp[:, :, 35:] = 1
+    rng = np.random.default_rng(17)
+    seeds = rng.permutation(comp.size).astype(np.uint32)
+    w = rng.integers(1, 65536, size=shape).astype(np.uint16)
+    q = _q8(seeds, shape, 17)
+    banner("los_update: every voxel a site")
+    want = oracle.los_vt(comp, q, seeds)
+    d_comp, d_q, d_a = dev(comp), dev(q), dev(seeds)
+    got = L.lsrvt_los_vt(d_comp, d_q, d_a)
+    _cmp_vt(got, want)
+    wq, wa, wt = oracle.los_update(comp, want.cell, want.phi, q, seeds, w)
+    tg = L.lsrvt_los_update(d_comp, got.cell, got.phi, d_q, d_a, dev(w))
+    np.testing.assert_array_equal(host(tg), wt)
+    np.testing.assert_array_equal(host(d_q), wq)
+    np.testing.assert_array_equal(host(d_a, np.uint32), wa)
