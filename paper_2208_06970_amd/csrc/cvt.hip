@@ -947,20 +947,29 @@ __device__ __forceinline__ uint32_t br_sweep(unsigned long long *K, int base, in
 // (t & 15, t >> 4); their edge masks stay in registers.  LDS holds the
 // keys (rows padded against bank conflicts), a changed bit per voxel and a
 // dirty flag per line.
-__device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
-  __shared__ unsigned long long K[kRows * kBRRow];
-  __shared__ uint32_t raw[2][kRows];  // y and z edge masks by row, for the transposition into line masks
-  __shared__ uint32_t chg[kRows];     // bit lx of row: the voxel's key changed in this processing
-  __shared__ uint8_t dx[kRows], dy[kRows], dz[kRows];  // lines to sweep along x (by row), y (lx, lz), z (lx, ly)
-  __shared__ uint32_t flags[8];
+// LDS of one brick processing: the keys (rows padded against bank
+// conflicts), the y and z edge masks by row (transposed into line masks),
+// a changed bit per voxel, a dirty flag per line, the face flags.
+struct BRLds {
+  unsigned long long K[kRows * kBRRow];
+  uint32_t raw[2][kRows];
+  uint32_t chg[kRows];                      // bit lx of row: the voxel's key changed in this processing
+  uint8_t dx[kRows], dy[kRows], dz[kRows];  // lines to sweep along x (by row), y (lx, lz), z (lx, ly)
+  uint32_t flags[8];
+};
+
+// One processing of brick b in round r (all threads of the workgroup).
+__device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t r, BRLds &L) {
+  unsigned long long *K = L.K;
+  uint32_t(*raw)[kRows] = L.raw;
+  uint32_t *chg = L.chg;
+  uint8_t *dx = L.dx, *dy = L.dy, *dz = L.dz;
+  uint32_t *flags = L.flags;
   const int t = threadIdx.x;
   const int lo4 = t & 15, hi4 = t >> 4;
   const size_t kB = (size_t)kRows * BX;
   const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
-  const uint32_t count = A.ctl[0];
-  if (blockIdx.x == 0 && t == 0) A.hist[r % kHistLen] = count;  // bricks that work in round r
-  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-    const int64_t b = A.list[item];
+  {
     const int bx = (int)(b % A.bg.nbx), by = (int)((b / A.bg.nbx) % A.bg.nby),
               bz = (int)(b / ((int64_t)A.bg.nbx * A.bg.nby));
     const bool hxm = bx > 0, hxp = bx < A.bg.nbx - 1, hym = by > 0, hyp = by < A.bg.nby - 1, hzm = bz > 0,
@@ -1116,6 +1125,13 @@ __device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
     if (t == 0 && f) A.alive[(r + 1) % 3] = 1u;
     __syncthreads();
   }
+}
+
+__device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
+  __shared__ BRLds L;
+  const uint32_t count = A.ctl[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.hist[r % kHistLen] = count;  // bricks that work in round r
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) br_process(A, A.list[item], r, L);
 }
 __global__ __launch_bounds__(kBRThreads, 4) void k_br_round(BRArgs A) { d_br_round(A, *A.rnd); }
 
@@ -2298,10 +2314,54 @@ __global__ __launch_bounds__(256) void kb_list(const JobDev *J) {
   d_br_list(j.A, j.A.alive[3]);
 }
 
-__global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J) {
-  const JobDev &j = J[blockIdx.y];
-  if ((int32_t)j.A.alive[4] > j.iters) return;
-  d_br_round(j.A, j.A.alive[3]);
+// The round's work list of the whole batch: the jobs' lists back to back,
+// job j's at off[j] .. off[j + 1] (an exclusive prefix sum of the list
+// counts, by one workgroup).  A job that has stopped taking part has an empty
+// list.
+__global__ __launch_bounds__(1024) void kb_offsets(const JobDev *J, int32_t n, uint32_t *off) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int32_t per = (n + 1023) / 1024, a = t * per, e = a + per < n ? a + per : n;
+  const uint32_t r = J[0].A.alive[3];
+  uint32_t sum = 0;
+  for (int32_t i = a; i < e; ++i) {
+    const uint32_t c = J[i].A.ctl[0];
+    J[i].A.hist[r % kHistLen] = c;
+    sum += c;
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive scan of the threads' sums
+    const uint32_t v = t >= d ? part[t - d] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+  for (int32_t i = a; i < e; ++i) {
+    off[i] = run;
+    run += J[i].A.ctl[0];
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+// One relaxation round of the whole batch: the workgroups stride over the
+// concatenated list, each item being a (job, brick) pair found by a binary
+// search of the offsets.
+__global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J, int32_t n, const uint32_t *off) {
+  __shared__ BRLds L;
+  const uint32_t total = off[n];
+  const uint32_t r = J[0].A.alive[3];
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    int32_t lo = 0, hi = n - 1;  // the last job whose list starts at or before item
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= item) lo = mid;
+      else hi = mid - 1;
+    }
+    const BRArgs &A = J[lo].A;
+    br_process(A, A.list[item - off[lo]], r, L);
+  }
 }
 
 __global__ __launch_bounds__(kVTThreads) void kb_finish(const JobDev *J, int32_t t) {
@@ -2340,7 +2400,11 @@ __global__ __launch_bounds__(256) void kb_snap_fallback(const JobDev *J, int32_t
 }  // namespace
 
 // Bytes of the descriptor block that precedes the jobs' workspaces.
-size_t cvt_batch_header(int32_t n) { return ((size_t)n * sizeof(JobDev) + 256 + 255) & ~size_t(255); }
+// (the job descriptors, 256 bytes of shared round words, then the n + 1
+// offsets of the batch's round list)
+size_t cvt_batch_header(int32_t n) {
+  return ((size_t)n * sizeof(JobDev) + 256 + 4 * ((size_t)n + 1) + 255) & ~size_t(255);
+}
 
 size_t cvt_batch_job_workspace(lsrvt_dims dims, uint32_t n_sites, int32_t iters) {
   Geom g;
@@ -2359,6 +2423,7 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
   if (bytes < head) return LSRVT_EWORKSPACE;
   JobDev *dj = reinterpret_cast<JobDev *>(base);
   uint32_t *alive = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev));
+  uint32_t *offs = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev) + 256);
   size_t off = head;
   int32_t tmax = 0;
   int64_t max_keys = 0, max_sites = 0, max_tiles = 0, max_nb = 0, max_slots = 0;
@@ -2418,7 +2483,9 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
   LSRVT_LAUNCHED();
   const unsigned g_clear = cap((max_keys + 255) / 256, 8192);
   const unsigned g_list = cap((max_nb + 255) / 256, 4096);
-  const unsigned g_round = cap(max_nb, 2048);
+  int64_t sum_nb = 0;
+  for (int32_t i = 0; i < n; ++i) sum_nb += hj[(size_t)i].A.bg.nbricks;
+  const unsigned g_round = cap(sum_nb, tuning(LSRVT_TUNE_BR_GRID) > 0 ? tuning(LSRVT_TUNE_BR_GRID) : 2048);
   const unsigned g_fin = cap((max_slots + kVTThreads / BX - 1) / (kVTThreads / BX), 65535);
   const unsigned g_tiles = cap(max_tiles, 65535);
   const unsigned g_fb = cap(max_sites, 1024);
@@ -2428,7 +2495,8 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
   int32_t rc0 = capture_rounds(&gs.br_graph, [&](hipStream_t cs) -> int32_t {
     hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, cs, dj);
     hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, cs, dj);
-    hipLaunchKernelGGL(kb_round, dim3(g_round, N), dim3(kBRThreads), 0, cs, dj);
+    hipLaunchKernelGGL(kb_offsets, dim3(1), dim3(1024), 0, cs, dj, n, offs);
+    hipLaunchKernelGGL(kb_round, dim3(g_round), dim3(kBRThreads), 0, cs, dj, n, (const uint32_t *)offs);
     LSRVT_LAUNCHED();
     return LSRVT_OK;
   });
