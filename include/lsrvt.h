@@ -531,11 +531,21 @@ int32_t lsrvt_set_vt_engine(int32_t engine);
  *                           statistics' cell kernel (its tile is this times
  *                           its workgroup size): 1, 2 or 4, 0 = the largest
  *                           that keeps a workgroup within 40 KiB of LDS
+ *   LSRVT_TUNE_KEY_BITS     key width of the brick relaxation: 0 = narrow
+ *                           32-bit keys (distance and site id) when the site
+ *                           ids fit in 24 bits, wide 64-bit keys otherwise;
+ *                           64 = always wide; 1 .. 30 = narrow with an id
+ *                           field of at least that many bits (fewer distance
+ *                           bits).  A pass whose distances outgrow the
+ *                           narrow field is repeated with wide keys, which
+ *                           the rest of the call keeps, so every value gives
+ *                           the same results.
  * Returns the previous value, or -1 (and changes nothing) for an unknown
  * knob or a value outside its range.
  */
 #define LSRVT_TUNE_BR_GRID 1
 #define LSRVT_TUNE_STATS_TILE 2
+#define LSRVT_TUNE_KEY_BITS 3
 int32_t lsrvt_set_tuning(int32_t knob, int32_t value);
 
 /* ------------------------------------------------------------------------

@@ -632,14 +632,16 @@ def lsrvt_set_vt_engine(engine: int) -> int:
     return prev
 
 
-TUNE_BR_GRID, TUNE_STATS_TILE = 1, 2
+TUNE_BR_GRID, TUNE_STATS_TILE, TUNE_KEY_BITS = 1, 2, 3
 
 
 def lsrvt_set_tuning(knob: int, value: int) -> int:
     """Launch shape of this host thread's later calls (TUNE_BR_GRID:
     workgroups per relaxation round, 256..16384; TUNE_STATS_TILE: voxels per
-    thread and staging round of the statistics, 1, 2 or 4; 0 = the library's
-    choice); returns the previous value."""
+    thread and staging round of the statistics, 1, 2 or 4; TUNE_KEY_BITS: key
+    width of the brick relaxation, 64 = wide keys, 1..30 = narrow keys with at
+    least that many id bits; 0 = the library's choice); returns the previous
+    value."""
     prev = int(_lib().lsrvt_set_tuning(int(knob), int(value)))
     if prev < 0:
         raise LsrvtError(EINVAL, "lsrvt_set_tuning", f"knob {knob} value {value}")

@@ -777,16 +777,30 @@ __global__ __launch_bounds__(256) void k_wake_min(const uint32_t *__restrict__ w
 // the rounds end exactly at the fixed point.  An incremental pass starts from
 // the previous keys with the voxels of moved sites set to unreached, and
 // marks the bricks that hold such voxels or a changed site.
+//
+// Keys come in two widths.  Wide keys are 64 bits, distance << 32 | id.
+// Narrow keys are 32 bits, distance << b | id with b the bits the site ids
+// need (at most 24 by default); one hop adds 1 << b with unsigned
+// saturation, so a key that would pass 2^32 - 1 stays "unreached" (all
+// ones), which is never an offer.  Every key of a voxel whose true
+// distance is below D = 2^(32 - b) - 2 is then exact (its shortest path
+// never saturates), and a voxel farther away has a voxel at distance
+// exactly D on its shortest path.  So a round that stores a key of
+// distance D or more flags the pass, and the host repeats the pass (and
+// runs the rest of the call) with wide keys; a pass that ends unflagged
+// has every distance below D and is exact.
 constexpr int kBRThreads = 256;
-constexpr int kBRRow = BX + 1;  // LDS row stride (u64): padding against bank conflicts
-constexpr unsigned long long kOneHop = 1ull << 32;
+constexpr int kBRRow = BX + 1;  // LDS row stride (keys): padding against bank conflicts
 
 struct BRArgs {
   Geom g;
   VTGrid bg;
   const uint32_t *eq;              // [nbricks][256][3] same-band edge masks (as the level search)
-  unsigned long long *key;         // [nbricks][4096] brick-major keys, kInfKey = unreached
-  unsigned long long *xface;       // [nbricks][2][256] keys of the x = 0 and x = 15 voxels of every row
+  void *key;                       // [nbricks][4096] brick-major keys (narrow or wide), all ones = unreached
+  void *xface;                     // [nbricks][2][256] keys of the x = 0 and x = 15 voxels of every row
+  uint32_t hop32;                  // narrow keys: one hop (1 << b)
+  uint32_t idmask;                 // the id bits of a key (0xFFFFFFFF for wide keys)
+  uint32_t lim32;                  // narrow keys: the smallest key whose distance is D (flagged when stored)
   uint32_t *mark;                  // [2][nbricks]: mark[r & 1][b] == r when brick b works in round r
   uint32_t *list;                  // [nbricks] bricks of the current round
   uint32_t *ctl;                   // [0] list length, [3] error bits
@@ -794,6 +808,26 @@ struct BRArgs {
   uint32_t *alive;                 // [3] round alive flags (by r % 3); shared by the jobs of a batch
   uint32_t *hist;                  // [kHistLen] bricks that worked in each round
   unsigned long long *dbg;         // diagnostics (LSRVT_DEBUG_LEVELS only): processings, sweep rounds
+};
+
+// The two key widths: unreached value, one hop, and key + hop, which stays
+// unreached from unreached (a wide key tests for it, a narrow one
+// saturates).
+template <class KT>
+struct BRKey;
+template <>
+struct BRKey<unsigned long long> {
+  static constexpr unsigned long long inf = ~0ull;
+  __device__ static unsigned long long hop(const BRArgs &) { return 1ull << 32; }
+  __device__ static unsigned long long add(unsigned long long k, unsigned long long h) {
+    return k == inf ? inf : k + h;
+  }
+};
+template <>
+struct BRKey<uint32_t> {
+  static constexpr uint32_t inf = ~0u;
+  __device__ static uint32_t hop(const BRArgs &A) { return A.hop32; }
+  __device__ static uint32_t add(uint32_t k, uint32_t h) { return __builtin_elementwise_add_sat(k, h); }
 };
 
 __device__ __forceinline__ void br_mark(const BRArgs &A, int bx, int by, int bz, int k, uint32_t r) {
@@ -808,7 +842,9 @@ __device__ __forceinline__ void br_mark(const BRArgs &A, int bx, int by, int bz,
 // (every voxel of a full pass is unreached); a site voxel that changes
 // marks its brick, and the face neighbours whose face it lies on, for round
 // 1 (its packed x-face copy follows).
+template <class KT>
 __device__ __forceinline__ void d_br_sites(const uint32_t *__restrict__ sites, uint32_t S, BRArgs A) {
+  KT *key = static_cast<KT *>(A.key), *xface = static_cast<KT *>(A.xface);
   uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= S) return;
   const uint32_t v = sites[s];
@@ -822,53 +858,60 @@ __device__ __forceinline__ void d_br_sites(const uint32_t *__restrict__ sites, u
   const size_t b = (size_t)bx + (size_t)A.bg.nbx * ((size_t)by + (size_t)A.bg.nby * (size_t)bz);
   const uint32_t lx = x % BX, ly = y % BY, lz = z % BZ;
   const uint32_t row = ly + BY * lz;
-  const unsigned long long k = (unsigned long long)s;
-  const unsigned long long old = atomicMin(&A.key[b * (kRows * BX) + lx + BX * row], k);
+  const KT k = (KT)s;
+  const KT old = atomicMin(&key[b * (kRows * BX) + lx + BX * row], k);
   if (k >= old) return;
-  if (lx == 0) atomicMin(&A.xface[b * 512 + row], k);
-  if (lx == BX - 1) atomicMin(&A.xface[b * 512 + 256 + row], k);
+  if (lx == 0) atomicMin(&xface[b * 512 + row], k);
+  if (lx == BX - 1) atomicMin(&xface[b * 512 + 256 + row], k);
   const bool on[7] = {true, lx == 0, lx == BX - 1, ly == 0, ly == BY - 1, lz == 0, lz == BZ - 1};
 #pragma unroll
   for (int q = 0; q < 7; ++q)
     if (on[q]) br_mark(A, bx, by, bz, q, 1u);
   A.alive[1] = 1u;
 }
-__global__ void k_br_sites(const uint32_t *__restrict__ sites, uint32_t S, BRArgs A) { d_br_sites(sites, S, A); }
+template <class KT>
+__global__ void k_br_sites(const uint32_t *__restrict__ sites, uint32_t S, BRArgs A) { d_br_sites<KT>(sites, S, A); }
 
 
 // Incremental pass set-up: voxels whose site moved become unreached (keys
 // and packed faces), and their bricks are marked for round 1.  One thread
 // per voxel slot (the slot index is the brick-major index).
+template <class KT>
 __device__ __forceinline__ void d_br_reset(const uint8_t *__restrict__ moved, BRArgs A) {
+  constexpr KT kInf = BRKey<KT>::inf;
+  KT *key = static_cast<KT *>(A.key), *xface = static_cast<KT *>(A.xface);
   const int64_t slots = A.bg.nbricks * kRows * BX;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   constexpr int kU = 4;  // slots per thread and step: their loads are issued together
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < slots; i0 += kU * stride) {
-    unsigned long long k[kU];
+    KT k[kU];
     uint8_t mv[kU];
 #pragma unroll
     for (int j = 0; j < kU; ++j) {
       const int64_t i = i0 + j * stride;
-      k[j] = i < slots ? A.key[i] : kInfKey;
+      k[j] = i < slots ? key[i] : kInf;
     }
 #pragma unroll
-    for (int j = 0; j < kU; ++j) mv[j] = k[j] != kInfKey ? moved[(uint32_t)(k[j] & 0xFFFFFFFFull)] : (uint8_t)0;
+    for (int j = 0; j < kU; ++j) mv[j] = k[j] != kInf ? moved[(uint32_t)k[j] & A.idmask] : (uint8_t)0;
 #pragma unroll
     for (int j = 0; j < kU; ++j) {
       if (!mv[j]) continue;
       const int64_t i = i0 + j * stride;
-      A.key[i] = kInfKey;
+      key[i] = kInf;
       const int64_t b = i / (kRows * BX);
       const int loc = (int)(i % (kRows * BX));
       const int lx = loc & 15, row = loc >> 4;
-      if (lx == 0) A.xface[b * 512 + row] = kInfKey;
-      if (lx == BX - 1) A.xface[b * 512 + 256 + row] = kInfKey;
+      if (lx == 0) xface[b * 512 + row] = kInf;
+      if (lx == BX - 1) xface[b * 512 + 256 + row] = kInf;
       A.mark[(size_t)1 * A.bg.nbricks + b] = 1u;  // round 1 has parity 1
       A.alive[1] = 1u;
     }
   }
 }
-__global__ __launch_bounds__(256) void k_br_reset(const uint8_t *__restrict__ moved, BRArgs A) { d_br_reset(moved, A); }
+template <class KT>
+__global__ __launch_bounds__(256) void k_br_reset(const uint8_t *__restrict__ moved, BRArgs A) {
+  d_br_reset<KT>(moved, A);
+}
 
 
 // The bricks marked for round r, listed (one counter atomic per block).
@@ -912,28 +955,40 @@ __device__ __forceinline__ int br_at(int lx, int row) { return row * kBRRow + lx
 // along its same-band edges (mask bit i: edge from voxel i to i - 1, bit
 // 16 + i: edge to i + 1).  Returns the bits of the voxels whose key dropped;
 // the line is written back only then.  The calling thread owns the line for
-// the whole stage.
-__device__ __forceinline__ uint32_t br_sweep(unsigned long long *K, int base, int st, uint32_t mask) {
-  unsigned long long k[16];
+// the whole stage.  Branch-free: a missing edge turns the offer into all
+// ones (never smaller).  The mask passes through an empty asm statement so
+// that the per-voxel edge tests are made here, from one register, rather
+// than hoisted out of the caller's sweep loop as lane masks (two scalar
+// registers each, 90 for a thread's three lines).
+template <class KT>
+__device__ __forceinline__ uint32_t br_sweep(KT *K, int base, int st, uint32_t mask, KT hop) {
+  using KO = BRKey<KT>;
+  uint32_t nm = ~mask;
+  asm volatile("" : "+v"(nm));
+  // all ones when bit j of the mask is clear, else zero
+  auto cut = [&](int j) { return (KT)(int64_t)((int32_t)(nm << (31 - j)) >> 31); };
+  KT k[16];
 #pragma unroll
   for (int i = 0; i < 16; ++i) k[i] = K[base + i * st];
-  uint32_t c = 0;
+  // the changed bits are shifted in one at a time (no per-bit constants):
+  // forward voxel i lands at bit 15 - i (reversed below), backward voxel i
+  // at bit i
+  uint32_t cf = 0, cb = 0;
 #pragma unroll
   for (int i = 1; i < 16; ++i) {
-    const unsigned long long o = k[i - 1] + kOneHop;
-    if (((mask >> i) & 1u) && k[i - 1] != kInfKey && o < k[i]) {
-      k[i] = o;
-      c |= 1u << i;
-    }
+    const KT o = KO::add(k[i - 1], hop) | cut(i);
+    const bool lt = o < k[i];
+    k[i] = lt ? o : k[i];
+    cf = cf + cf + (uint32_t)lt;
   }
 #pragma unroll
   for (int i = 14; i >= 0; --i) {
-    const unsigned long long o = k[i + 1] + kOneHop;
-    if (((mask >> (16 + i)) & 1u) && k[i + 1] != kInfKey && o < k[i]) {
-      k[i] = o;
-      c |= 1u << i;
-    }
+    const KT o = KO::add(k[i + 1], hop) | cut(16 + i);
+    const bool lt = o < k[i];
+    k[i] = lt ? o : k[i];
+    cb = cb + cb + (uint32_t)lt;
   }
+  const uint32_t c = (__builtin_bitreverse32(cf) >> 16) | cb;
   if (c) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) K[base + i * st] = k[i];
@@ -950,8 +1005,9 @@ __device__ __forceinline__ uint32_t br_sweep(unsigned long long *K, int base, in
 // LDS of one brick processing: the keys (rows padded against bank
 // conflicts), the y and z edge masks by row (transposed into line masks),
 // a changed bit per voxel, a dirty flag per line, the face flags.
+template <class KT>
 struct BRLds {
-  unsigned long long K[kRows * kBRRow];
+  KT K[kRows * kBRRow];
   uint32_t raw[2][kRows];
   uint32_t chg[kRows];                      // bit lx of row: the voxel's key changed in this processing
   uint8_t dx[kRows], dy[kRows], dz[kRows];  // lines to sweep along x (by row), y (lx, lz), z (lx, ly)
@@ -959,13 +1015,22 @@ struct BRLds {
 };
 
 // One processing of brick b in round r (all threads of the workgroup).
-__device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t r, BRLds &L) {
-  unsigned long long *K = L.K;
+template <class KT>
+__device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t r, BRLds<KT> &L) {
+  using KO = BRKey<KT>;
+  constexpr KT kInf = KO::inf;
+  const KT hop = KO::hop(A);
+  KT *key = static_cast<KT *>(A.key), *xface = static_cast<KT *>(A.xface);
+  KT *K = L.K;
   uint32_t(*raw)[kRows] = L.raw;
   uint32_t *chg = L.chg;
   uint8_t *dx = L.dx, *dy = L.dy, *dz = L.dz;
   uint32_t *flags = L.flags;
-  const int t = threadIdx.x;
+  // the thread index passes through an empty asm statement so that what is
+  // derived from it (LDS and global offsets) is recomputed per processing
+  // instead of being kept live across a round's processings
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
   const int lo4 = t & 15, hi4 = t >> 4;
   const size_t kB = (size_t)kRows * BX;
   const int64_t bsy = A.bg.nbx, bsz = (int64_t)A.bg.nbx * A.bg.nby;
@@ -977,17 +1042,17 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     // every global read of the processing, issued together: the brick's keys
     // (16 per thread, coalesced), its edge masks and the six faces of the
     // neighbours (a missing neighbour reads the brick itself, unused)
-    unsigned long long kv[16];
+    KT kv[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) kv[i] = A.key[(size_t)b * kB + i * kBRThreads + t];
+    for (int i = 0; i < 16; ++i) kv[i] = key[(size_t)b * kB + i * kBRThreads + t];
     const uint32_t *eq = A.eq + ((size_t)b * kRows + t) * 3;
     const uint32_t mx = eq[0], e1 = eq[1], e2 = eq[2];
-    const unsigned long long fxm = A.xface[(size_t)(hxm ? b - 1 : b) * 512 + 256 + t];
-    const unsigned long long fxp = A.xface[(size_t)(hxp ? b + 1 : b) * 512 + t];
-    const unsigned long long fym = A.key[(size_t)(hym ? b - bsy : b) * kB + lo4 + 16 * 15 + 256 * hi4];
-    const unsigned long long fyp = A.key[(size_t)(hyp ? b + bsy : b) * kB + lo4 + 256 * hi4];
-    const unsigned long long fzm = A.key[(size_t)(hzm ? b - bsz : b) * kB + lo4 + 16 * hi4 + 256 * 15];
-    const unsigned long long fzp = A.key[(size_t)(hzp ? b + bsz : b) * kB + lo4 + 16 * hi4];
+    const KT fxm = xface[(size_t)(hxm ? b - 1 : b) * 512 + 256 + t];
+    const KT fxp = xface[(size_t)(hxp ? b + 1 : b) * 512 + t];
+    const KT fym = key[(size_t)(hym ? b - bsy : b) * kB + lo4 + 16 * 15 + 256 * hi4];
+    const KT fyp = key[(size_t)(hyp ? b + bsy : b) * kB + lo4 + 256 * hi4];
+    const KT fzm = key[(size_t)(hzm ? b - bsz : b) * kB + lo4 + 16 * hi4 + 256 * 15];
+    const KT fzp = key[(size_t)(hzp ? b + bsz : b) * kB + lo4 + 16 * hi4];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int loc = i * kBRThreads + t;
@@ -1007,7 +1072,7 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     // line masks of this thread's y line (lx, lz) and z line (lx, ly), in
     // the x rows' format (bit i: edge to i - 1, bit 16 + i: edge to i + 1)
     uint32_t my = 0, mz = 0;
-#pragma unroll
+#pragma unroll 2
     for (int i = 0; i < 16; ++i) {
       const uint32_t wy = raw[0][i + 16 * hi4], wz = raw[1][hi4 + 16 * i];
       my |= ((wy >> lo4) & 1u) << i | ((wy >> (16 + lo4)) & 1u) << (16 + i);
@@ -1015,8 +1080,9 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     }
     // offers of the six face neighbours: their keys plus one hop
     {
-      auto offer = [&](bool has, bool edge, unsigned long long h, int lx, int row) {
-        if (has && edge && h != kInfKey && atomicMin(&K[br_at(lx, row)], h + kOneHop) > h + kOneHop) {
+      auto offer = [&](bool has, bool edge, KT h, int lx, int row) {
+        const KT o = KO::add(h, hop);
+        if (has && edge && h != kInf && atomicMin(&K[br_at(lx, row)], o) > o) {
           atomicOr(&chg[row], 1u << lx);
           dx[row] = 1;
           dy[lx + 16 * (row >> 4)] = 1;
@@ -1039,7 +1105,7 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
       ++sweeps;
       if (dx[t]) {  // row t = (ly, lz)
         dx[t] = 0;
-        uint32_t c = br_sweep(K, t * kBRRow, 1, mx);
+        uint32_t c = br_sweep<KT>(K, t * kBRRow, 1, mx, hop);
         chg[t] |= c;  // only this thread touches row t's word in this stage
         while (c) {
           const int x = __builtin_ctz(c);
@@ -1051,7 +1117,7 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
       __syncthreads();
       if (dy[t]) {  // y line (lx, lz) = (lo4, hi4)
         dy[t] = 0;
-        uint32_t c = br_sweep(K, 16 * kBRRow * hi4 + lo4, kBRRow, my);
+        uint32_t c = br_sweep<KT>(K, 16 * kBRRow * hi4 + lo4, kBRRow, my, hop);
         while (c) {
           const int y = __builtin_ctz(c);
           c &= c - 1;
@@ -1063,7 +1129,7 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
       __syncthreads();
       if (dz[t]) {  // z line (lx, ly) = (lo4, hi4)
         dz[t] = 0;
-        uint32_t c = br_sweep(K, hi4 * kBRRow + lo4, 16 * kBRRow, mz);
+        uint32_t c = br_sweep<KT>(K, hi4 * kBRRow + lo4, 16 * kBRRow, mz, hop);
         while (c) {
           const int z = __builtin_ctz(c);
           c &= c - 1;
@@ -1082,10 +1148,10 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     // take the offer.  Thread t checks the face voxels it offered to above.
     uint32_t fc = 0;
     {
-      auto gain = [&](bool has, bool edge, int lx, int row, unsigned long long nbk) {
+      auto gain = [&](bool has, bool edge, int lx, int row, KT nbk) {
         if (!has || !edge || !((chg[row] >> lx) & 1u)) return false;
-        const unsigned long long k = K[br_at(lx, row)];
-        return k != kInfKey && k + kOneHop < nbk;
+        const KT k = K[br_at(lx, row)];
+        return KO::add(k, hop) < nbk;
       };
       fc |= gain(hxm, mx & 1u, 0, t, fxm) ? 2u : 0u;
       fc |= gain(hxp, (mx >> 31) & 1u, 15, t, fxp) ? 4u : 0u;
@@ -1099,19 +1165,24 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     // statement so that the store addresses are recomputed here instead of
     // being kept live (in registers) from the loads at the top across the
     // sweeps.
+    // A narrow key of distance D or more flags the pass (changed keys are
+    // reached, so never all ones).
     int tt = t;
     asm volatile("" : "+v"(tt));
+    bool far = false;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int loc = i * kBRThreads + tt;
       const int lx = loc & 15, row = loc >> 4;
       if ((chg[row] >> lx) & 1u) {
-        const unsigned long long k = K[br_at(lx, row)];
-        A.key[(size_t)b * kB + loc] = k;
-        if (lx == 0) A.xface[(size_t)b * 512 + row] = k;
-        if (lx == BX - 1) A.xface[(size_t)b * 512 + 256 + row] = k;
+        const KT k = K[br_at(lx, row)];
+        if (sizeof(KT) == 4) far |= (uint32_t)k >= A.lim32;
+        key[(size_t)b * kB + loc] = k;
+        if (lx == 0) xface[(size_t)b * 512 + row] = k;
+        if (lx == BX - 1) xface[(size_t)b * 512 + 256 + row] = k;
       }
     }
+    if (sizeof(KT) == 4 && far) atomicOr(&A.ctl[3], 4u);
     if (A.dbg && t == 0) {
       atomicAdd(&A.dbg[0], 1ull);
       atomicAdd(&A.dbg[1], (unsigned long long)sweeps);
@@ -1127,19 +1198,21 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
   }
 }
 
-__device__ __forceinline__ void d_br_round(BRArgs A, uint32_t r) {
-  __shared__ BRLds L;
+template <class KT>
+__global__ __launch_bounds__(kBRThreads, sizeof(KT) == 4 ? 5 : 4) void k_br_round(BRArgs A) {
+  __shared__ BRLds<KT> L;
+  const uint32_t r = *A.rnd;
   const uint32_t count = A.ctl[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) A.hist[r % kHistLen] = count;  // bricks that work in round r
-  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) br_process(A, A.list[item], r, L);
+  for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) br_process<KT>(A, A.list[item], r, L);
 }
-__global__ __launch_bounds__(kBRThreads, 4) void k_br_round(BRArgs A) { d_br_round(A, *A.rnd); }
 
 
 // End of a pass: keys to the caller's C-order cells (NONE where unreached),
 // 16 contiguous voxels per row.
-__device__ __forceinline__ void d_br_finish(const unsigned long long *__restrict__ key, Geom g,
-                                                          VTGrid bg, uint32_t *__restrict__ cell) {
+template <class KT>
+__device__ __forceinline__ void d_br_finish(const KT *__restrict__ key, Geom g, VTGrid bg, uint32_t idmask,
+                                            uint32_t *__restrict__ cell) {
   const int t = threadIdx.x;
   const int lx = t & 15;
   for (int64_t rr = (int64_t)blockIdx.x * (kVTThreads / BX) + (t >> 4); rr < bg.nbricks * kRows;
@@ -1149,12 +1222,15 @@ __device__ __forceinline__ void d_br_finish(const unsigned long long *__restrict
     const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
     const int x = bx * BX + lx, y = by * BY + (row & 15), z = bz * BZ + (row >> 4);
     if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
-    const unsigned long long k = key[(size_t)rr * BX + lx];
-    cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = k == kInfKey ? kNone : (uint32_t)(k & 0xFFFFFFFFull);
+    const KT k = key[(size_t)rr * BX + lx];
+    cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = k == BRKey<KT>::inf ? kNone : (uint32_t)k & idmask;
   }
 }
-__global__ __launch_bounds__(kVTThreads) void k_br_finish(const unsigned long long *__restrict__ key, Geom g,
-                                                          VTGrid bg, uint32_t *__restrict__ cell) { d_br_finish(key, g, bg, cell); }
+template <class KT>
+__global__ __launch_bounds__(kVTThreads) void k_br_finish(const KT *__restrict__ key, Geom g, VTGrid bg,
+                                                          uint32_t idmask, uint32_t *__restrict__ cell) {
+  d_br_finish<KT>(key, g, bg, idmask, cell);
+}
 
 
 // ----------------------------------------------------------------------------
@@ -1261,8 +1337,9 @@ __device__ __forceinline__ void fin_flush(FinTab &T, const Fuse &F) {
 
 // End of a relaxation pass followed by an update: the keys to C-order cells
 // (as k_br_finish) and the centroid sums, one workgroup per brick.
-__global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const unsigned long long *__restrict__ key, Geom g,
-                                                               VTGrid bg, uint32_t *__restrict__ cell, Fuse F) {
+template <class KT>
+__global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const KT *__restrict__ key, Geom g, VTGrid bg,
+                                                               uint32_t idmask, uint32_t *__restrict__ cell, Fuse F) {
   __shared__ FinTab T;
   const int t = threadIdx.x;
   for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
@@ -1274,8 +1351,8 @@ __global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const unsigned lo
       const int loc = i * kVTThreads + t;
       const int x = bx * BX + (loc & 15), y = by * BY + ((loc >> 4) & 15), z = bz * BZ + (loc >> 8);
       const bool in = x < g.nx && y < g.ny && z < g.nz;
-      const unsigned long long k = key[(size_t)b * (kRows * BX) + loc];
-      const uint32_t c = k == kInfKey ? kNone : (uint32_t)(k & 0xFFFFFFFFull);
+      const KT k = key[(size_t)b * (kRows * BX) + loc];
+      const uint32_t c = k == BRKey<KT>::inf ? kNone : (uint32_t)k & idmask;
       const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
       if (in) cell[v] = c;
       const uint32_t wv = in ? (F.w ? (uint32_t)F.w[v] : 1u) : 0u;
@@ -1694,12 +1771,16 @@ struct VTState {
   uint32_t levels = 0;      // levels of the last full pass
   uint32_t inc_levels = 0;  // levels of the first run of the last incremental pass
   uint32_t br_rounds = 0;   // rounds of the last brick relaxation pass
-  hipGraphExec_t br_graph = nullptr;  // kGraphRounds relaxation rounds of this call's workspace
+  hipGraphExec_t br_graph = nullptr;  // kGraphRounds relaxation rounds of this call's workspace (narrow keys)
+  hipGraphExec_t br_graph_w = nullptr;  // the same with wide keys
+  bool keys_set = false;    // the key width of the brick relaxation is chosen at its first pass
+  uint32_t id_bits = 0;     // narrow keys: the id field's bits; 0: wide keys
   VTState() = default;
   VTState(const VTState &) = delete;
   VTState &operator=(const VTState &) = delete;
   ~VTState() {
     if (br_graph) hipGraphExecDestroy(br_graph);
+    if (br_graph_w) hipGraphExecDestroy(br_graph_w);
   }
 };
 
@@ -2075,12 +2156,30 @@ int32_t run_vt_inc(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *c
   return LSRVT_OK;
 }
 
-BRArgs br_args(const Geom &g, CvtWork &W) {
+// The id bits of narrow relaxation keys for S sites, or 0 for wide keys.
+// Narrow keys need the ids 0 .. S - 1 in b bits and, by default, keep at
+// least 8 distance bits (b <= 24).  LSRVT_TUNE_KEY_BITS = 64 asks for wide
+// keys; 1 .. 30 for narrow keys with an id field of at least that many bits.
+uint32_t narrow_id_bits(uint32_t S) {
+  const int32_t kb = tuning(LSRVT_TUNE_KEY_BITS);
+  if (kb == 64) return 0;
+  uint32_t b = 1;
+  while (b < 32 && ((uint64_t)1 << b) < (uint64_t)S) ++b;
+  if (kb > 0 && (uint32_t)kb > b) b = (uint32_t)kb;
+  return b <= (kb > 0 ? 30u : 24u) ? b : 0u;
+}
+
+// Relaxation arguments over the workspace; id_bits: narrow keys with that
+// id field, 0: wide keys.
+BRArgs br_args(const Geom &g, CvtWork &W, uint32_t id_bits) {
   BRArgs A;
+  A.hop32 = id_bits ? 1u << id_bits : 0u;
+  A.idmask = id_bits ? (1u << id_bits) - 1u : 0xFFFFFFFFu;
+  A.lim32 = id_bits ? (uint32_t)(((uint64_t)1 << 32) - ((uint64_t)2 << id_bits)) : 0u;
   A.g = g;
   A.bg = vt_grid(g);
   A.eq = W.eq;
-  A.key = reinterpret_cast<unsigned long long *>(W.cellb);  // spans the cell and distance arrays
+  A.key = W.cellb;  // spans the cell and distance arrays (room for wide keys)
   A.xface = W.xface;
   A.mark = W.act;
   A.list = W.brlist;
@@ -2093,29 +2192,33 @@ BRArgs br_args(const Geom &g, CvtWork &W) {
   return A;
 }
 
-// One Voronoi pass by brick relaxation: a full pass from the sites, or (inc)
-// an incremental one from the previous keys after the update that set
-// W.moved.  Rounds are enqueued in batches (the first sized by the previous
-// pass); after each batch the host reads whether any brick is marked.
-int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st, bool inc,
-               hipStream_t s, const Fuse *fz = nullptr) {
+// One Voronoi pass by brick relaxation with keys KT: a full pass from the
+// sites, or (inc) an incremental one from the previous keys after the
+// update that set W.moved.  Rounds are enqueued in batches (the first sized
+// by the previous pass); after each batch the host reads whether any brick
+// is marked.  With narrow keys, a round that stored a key of the largest
+// exact distance sets *far and the pass stops unfinished.
+template <class KT>
+int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st,
+                 bool inc, hipStream_t s, const Fuse *fz, bool *far) {
   const VTGrid bg = vt_grid(g);
-  BRArgs A = br_args(g, W);
+  BRArgs A = br_args(g, W, sizeof(KT) == 4 ? st.id_bits : 0u);
+  constexpr KT kInf = BRKey<KT>::inf;
   int32_t rc;
   const int64_t nkeys = bg.nbricks * kRows * BX;
   if ((rc = fill<uint32_t>(W.act, 2 * bg.nbricks, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.ctl, 3, 0u, s))) return rc;
   if ((rc = fill<uint32_t>(W.ctl + 4, 4, 0u, s))) return rc;  // alive flags and the round counter
   if (!inc) {
-    if ((rc = fill<unsigned long long>(A.key, nkeys, kInfKey, s))) return rc;
-    if ((rc = fill<unsigned long long>(A.xface, bg.nbricks * 512, kInfKey, s))) return rc;
+    if ((rc = fill<KT>(static_cast<KT *>(A.key), nkeys, kInf, s))) return rc;
+    if ((rc = fill<KT>(static_cast<KT *>(A.xface), bg.nbricks * 512, kInf, s))) return rc;
   } else {
-    hipLaunchKernelGGL(k_br_reset, dim3((unsigned)std::min<int64_t>((nkeys + 255) / 256, 65535)), dim3(256), 0, s,
-                       W.moved, A);
+    hipLaunchKernelGGL(k_br_reset<KT>, dim3((unsigned)std::min<int64_t>((nkeys + 255) / 256, 65535)), dim3(256), 0,
+                       s, W.moved, A);
     LSRVT_LAUNCHED();
   }
   if (S) {
-    hipLaunchKernelGGL(k_br_sites, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
+    hipLaunchKernelGGL(k_br_sites<KT>, dim3((S + 255) / 256), dim3(256), 0, s, sites, S, A);
     LSRVT_LAUNCHED();
   }
   const unsigned lgrid = (unsigned)std::min<int64_t>((bg.nbricks + 255) / 256, 4096);
@@ -2123,11 +2226,12 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
   const unsigned rgrid = (unsigned)std::min<int64_t>(bg.nbricks, tg ? tg : 2048);
   // kGraphRounds rounds (three launches each) captured once per call and
   // replayed as one graph launch
-  if (!st.br_graph) {
-    rc = capture_rounds(&st.br_graph, [&](hipStream_t cs) -> int32_t {
+  hipGraphExec_t &graph = sizeof(KT) == 4 ? st.br_graph : st.br_graph_w;
+  if (!graph) {
+    rc = capture_rounds(&graph, [&](hipStream_t cs) -> int32_t {
       hipLaunchKernelGGL(k_br_next, dim3(1), dim3(64), 0, cs, A);
       hipLaunchKernelGGL(k_br_list, dim3(lgrid), dim3(256), 0, cs, A);
-      hipLaunchKernelGGL(k_br_round, dim3(rgrid), dim3(kBRThreads), 0, cs, A);
+      hipLaunchKernelGGL(k_br_round<KT>, dim3(rgrid), dim3(kBRThreads), 0, cs, A);
       LSRVT_LAUNCHED();
       return LSRVT_OK;
     });
@@ -2142,12 +2246,16 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     std::pair<hipEvent_t, hipEvent_t> ev;
     const int graphs = (batch + kGraphRounds - 1) / kGraphRounds;
     if (timed && (rc = timed_begin(s, ev))) return rc;
-    for (int i = 0; i < graphs; ++i) LSRVT_HIP(hipGraphLaunch(st.br_graph, s));
+    for (int i = 0; i < graphs; ++i) LSRVT_HIP(hipGraphLaunch(graph, s));
     r += (uint32_t)(graphs * kGraphRounds);
     if (timed && (rc = timed_end(s, ev, (uint64_t)graphs * kGraphRounds))) return rc;
     if ((rc = read_words(W.ctl, 8, c, s))) return rc;
     if (c[3] & 1u) return LSRVT_EINVAL;
-    if (c[3]) return LSRVT_EDEVICE;
+    if (c[3] & ~4u) return LSRVT_EDEVICE;
+    if (c[3] & 4u) {  // a narrow key reached the largest exact distance
+      *far = true;
+      return LSRVT_OK;
+    }
     if (c[4 + (r + 1) % 3] == 0) break;
     if ((int64_t)r > max_rounds) return LSRVT_EDEVICE;
     batch = kGraphRounds;
@@ -2171,10 +2279,12 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     for (uint32_t i = 1; i < nl; ++i) fprintf(stderr, " %u", h[i]);
     fprintf(stderr, "\n");
   }
+  const KT *keys = static_cast<const KT *>(A.key);
   if (fz)
-    hipLaunchKernelGGL(k_br_finish_sums, dim3(brick_grid(bg)), dim3(kVTThreads), 0, s, A.key, g, bg, cell, *fz);
+    hipLaunchKernelGGL(k_br_finish_sums<KT>, dim3(brick_grid(bg)), dim3(kVTThreads), 0, s, keys, g, bg, A.idmask,
+                       cell, *fz);
   else
-    hipLaunchKernelGGL(k_br_finish, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, A.key, g, bg, cell);
+    hipLaunchKernelGGL(k_br_finish<KT>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, keys, g, bg, A.idmask, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
@@ -2183,6 +2293,26 @@ int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell,
     timer().engines |= 2;
   }
   return LSRVT_OK;
+}
+
+// One Voronoi pass by brick relaxation, with narrow keys when the sites
+// allow and until a pass outgrows them: that pass is repeated from the sites
+// with wide keys, which the rest of the call keeps.
+int32_t run_br(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cell, CvtWork &W, VTState &st, bool inc,
+               hipStream_t s, const Fuse *fz = nullptr) {
+  if (!st.keys_set) {
+    st.id_bits = narrow_id_bits(S);
+    st.keys_set = true;
+  }
+  if (st.id_bits) {
+    bool far = false;
+    int32_t rc = run_br_k<uint32_t>(g, sites, S, cell, W, st, inc, s, fz, &far);
+    if (rc || !far) return rc;
+    st.id_bits = 0;
+    if ((rc = fill<uint32_t>(W.ctl + 3, 1, 0u, s))) return rc;
+    inc = false;
+  }
+  return run_br_k<unsigned long long>(g, sites, S, cell, W, st, inc, s, fz, nullptr);
 }
 
 // A Voronoi pass with the selected schedule; with fz, its last kernel also
@@ -2273,6 +2403,7 @@ __global__ void kb_init_sites(const JobDev *J) {
 // shared round flags and round counter and records the pass (the shared
 // words after the flags: [3] round, [4] pass, read by the graph-replayed
 // round kernels).
+template <class KT>
 __global__ __launch_bounds__(256) void kb_pass_clear(const JobDev *J, int32_t t) {
   const JobDev &j = J[blockIdx.y];
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 5) j.A.alive[threadIdx.x] = threadIdx.x == 4 ? (uint32_t)t : 0u;
@@ -2282,21 +2413,24 @@ __global__ __launch_bounds__(256) void kb_pass_clear(const JobDev *J, int32_t t)
   for (int64_t i = i0; i < 2 * nb; i += stride) j.A.mark[i] = 0u;
   if (i0 == 0) j.A.ctl[0] = 0u;
   if (t == 0) {
-    for (int64_t i = i0; i < nb * kRows * BX; i += stride) j.A.key[i] = kInfKey;
-    for (int64_t i = i0; i < nb * 512; i += stride) j.A.xface[i] = kInfKey;
+    KT *key = static_cast<KT *>(j.A.key), *xface = static_cast<KT *>(j.A.xface);
+    for (int64_t i = i0; i < nb * kRows * BX; i += stride) key[i] = BRKey<KT>::inf;
+    for (int64_t i = i0; i < nb * 512; i += stride) xface[i] = BRKey<KT>::inf;
   }
 }
 
+template <class KT>
 __global__ __launch_bounds__(256) void kb_reset(const JobDev *J, int32_t t) {
   const JobDev &j = J[blockIdx.y];
   if (t > j.iters || t == 0) return;
-  d_br_reset(j.moved, j.A);
+  d_br_reset<KT>(j.moved, j.A);
 }
 
+template <class KT>
 __global__ void kb_sites(const JobDev *J, int32_t t) {
   const JobDev &j = J[blockIdx.y];
   if (t > j.iters) return;
-  d_br_sites(j.sites, j.S, j.A);
+  d_br_sites<KT>(j.sites, j.S, j.A);
 }
 
 // Start of a round: every job's list emptied, the shared round advanced.
@@ -2348,8 +2482,9 @@ __global__ __launch_bounds__(1024) void kb_offsets(const JobDev *J, int32_t n, u
 // One relaxation round of the whole batch: the workgroups stride over the
 // concatenated list, each item being a (job, brick) pair found by a binary
 // search of the offsets.
-__global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J, int32_t n, const uint32_t *off) {
-  __shared__ BRLds L;
+template <class KT>
+__global__ __launch_bounds__(kBRThreads, sizeof(KT) == 4 ? 5 : 4) void kb_round(const JobDev *J, int32_t n, const uint32_t *off) {
+  __shared__ BRLds<KT> L;
   const uint32_t total = off[n];
   const uint32_t r = J[0].A.alive[3];
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
@@ -2360,14 +2495,15 @@ __global__ __launch_bounds__(kBRThreads, 4) void kb_round(const JobDev *J, int32
       else hi = mid - 1;
     }
     const BRArgs &A = J[lo].A;
-    br_process(A, A.list[item - off[lo]], r, L);
+    br_process<KT>(A, A.list[item - off[lo]], r, L);
   }
 }
 
+template <class KT>
 __global__ __launch_bounds__(kVTThreads) void kb_finish(const JobDev *J, int32_t t) {
   const JobDev &j = J[blockIdx.y];
   if (t > j.iters) return;
-  d_br_finish(j.A.key, j.g, j.A.bg, j.cell);
+  d_br_finish<KT>(static_cast<const KT *>(j.A.key), j.g, j.A.bg, j.A.idmask, j.cell);
 }
 
 __global__ __launch_bounds__(256) void kb_update_clear(const JobDev *J, int32_t t) {
@@ -2412,22 +2548,131 @@ size_t cvt_batch_job_workspace(lsrvt_dims dims, uint32_t n_sites, int32_t iters)
   return (cvt_workspace(g, n_sites, iters < 0 ? 0 : iters) + 255) & ~size_t(255);
 }
 
+namespace {
+
+// What the lockstep loop needs besides the descriptors.
+struct BatchCtx {
+  int32_t n;
+  JobDev *dj;           // device copy of the descriptors
+  uint32_t *alive;      // shared round words
+  uint32_t *offs;       // offsets of the batch's round list
+  std::vector<JobDev> *hj;
+  std::vector<CvtWork> *Ws;
+  int32_t tmax;
+  int64_t max_keys, max_sites, max_tiles, max_nb, max_slots, sum_nb;
+};
+
+// The Lloyd loops of the batch with keys KT, from the seeds.  status[i]
+// receives each job's status; *far is set when a job's narrow keys reached
+// their largest exact distance (its results are then not to be used).
+template <class KT>
+int32_t batch_loop(const BatchCtx &c, int32_t *status, bool *far, hipStream_t s) {
+  const int32_t n = c.n;
+  JobDev *dj = c.dj;
+  std::vector<JobDev> &hj = *c.hj;
+  int32_t rc;
+  LSRVT_HIP(hipMemcpyAsync(dj, hj.data(), sizeof(JobDev) * (size_t)n, hipMemcpyHostToDevice, s));
+  for (int32_t i = 0; i < n; ++i)
+    if ((rc = fill<uint32_t>((*c.Ws)[(size_t)i].ctl, 8 + 2 * 8, 0u, s))) return rc;
+  const unsigned N = (unsigned)n;
+  auto cap = [](int64_t v, int64_t m) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(v, m)); };
+  const unsigned g_sites = cap((c.max_sites + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(kb_init_sites, dim3(g_sites, N), dim3(256), 0, s, dj);
+  hipLaunchKernelGGL(kb_vt_eq, dim3(cap((c.max_keys + kVTThreads - 1) / kVTThreads, 65535), N), dim3(kVTThreads), 0,
+                     s, dj);
+  LSRVT_LAUNCHED();
+  const unsigned g_clear = cap((c.max_keys + 255) / 256, 8192);
+  const unsigned g_list = cap((c.max_nb + 255) / 256, 4096);
+  const unsigned g_round = cap(c.sum_nb, tuning(LSRVT_TUNE_BR_GRID) > 0 ? tuning(LSRVT_TUNE_BR_GRID) : 2048);
+  const unsigned g_fin = cap((c.max_slots + kVTThreads / BX - 1) / (kVTThreads / BX), 65535);
+  const unsigned g_tiles = cap(c.max_tiles, 65535);
+  const unsigned g_fb = cap(c.max_sites, 1024);
+  uint32_t rounds_hint = 0;
+  // kGraphRounds rounds of every job captured once and replayed as one graph launch
+  VTState gs;
+  uint32_t *offs = c.offs;
+  rc = capture_rounds(&gs.br_graph, [&](hipStream_t cs) -> int32_t {
+    hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, cs, dj);
+    hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, cs, dj);
+    hipLaunchKernelGGL(kb_offsets, dim3(1), dim3(1024), 0, cs, dj, n, offs);
+    hipLaunchKernelGGL(kb_round<KT>, dim3(g_round), dim3(kBRThreads), 0, cs, dj, n, (const uint32_t *)offs);
+    LSRVT_LAUNCHED();
+    return LSRVT_OK;
+  });
+  if (rc) return rc;
+  for (int32_t t = 0; t <= c.tmax; ++t) {
+    hipLaunchKernelGGL(kb_pass_clear<KT>, dim3(g_clear, N), dim3(256), 0, s, dj, t);
+    if (t > 0) hipLaunchKernelGGL(kb_reset<KT>, dim3(g_clear, N), dim3(256), 0, s, dj, t);
+    hipLaunchKernelGGL(kb_sites<KT>, dim3(g_sites, N), dim3(256), 0, s, dj, t);
+    LSRVT_LAUNCHED();
+    uint32_t r = 0;
+    int batch = rounds_hint ? (int)rounds_hint : kGraphRounds;
+    uint32_t w[3];
+    const bool timed = timer().on;
+    while (true) {
+      std::pair<hipEvent_t, hipEvent_t> ev;
+      const int graphs = (batch + kGraphRounds - 1) / kGraphRounds;
+      if (timed && (rc = timed_begin(s, ev))) return rc;
+      for (int k = 0; k < graphs; ++k) LSRVT_HIP(hipGraphLaunch(gs.br_graph, s));
+      r += (uint32_t)(graphs * kGraphRounds);
+      if (timed && (rc = timed_end(s, ev, (uint64_t)graphs * kGraphRounds))) return rc;
+      if ((rc = read_words(c.alive, 3, w, s))) return rc;
+      if (w[(r + 1) % 3] == 0) break;
+      if (r > (uint32_t)(1u << 30)) return LSRVT_EDEVICE;
+      batch = kGraphRounds;
+    }
+    rounds_hint = r;
+    hipLaunchKernelGGL(kb_finish<KT>, dim3(g_fin, N), dim3(kVTThreads), 0, s, dj, t);
+    if (t < c.tmax) {
+      hipLaunchKernelGGL(kb_update_clear, dim3(g_sites, N), dim3(256), 0, s, dj, t);
+      hipLaunchKernelGGL(kb_centroid, dim3(g_tiles, N), dim3(256), 0, s, dj, t);
+      hipLaunchKernelGGL(kb_snap, dim3(g_sites, N), dim3(256), 0, s, dj, t);
+      hipLaunchKernelGGL(kb_snap_fallback, dim3(g_fb, N), dim3(256), 0, s, dj, t);
+    }
+    LSRVT_LAUNCHED();
+    if (timed) {
+      std::lock_guard<std::mutex> lk(timer().mu);
+      timer().engines |= 2;
+      for (int32_t i = 0; i < n; ++i)
+        if (t <= hj[(size_t)i].iters) {
+          timer().passes += 1;
+          timer().voxels_per_pass = hj[(size_t)i].g.n;
+        }
+    }
+  }
+  // each job's error bits (a seed outside its volume; a narrow key that
+  // reached the largest exact distance)
+  for (int32_t i = 0; i < n; ++i) {
+    uint32_t e = 0;
+    if ((rc = read_words((*c.Ws)[(size_t)i].ctl + 3, 1, &e, s))) return rc;
+    if (e & 4u) *far = true;
+    status[i] = (e & 1u) ? LSRVT_EINVAL : (e & ~4u) ? LSRVT_EDEVICE : LSRVT_OK;
+  }
+  return LSRVT_OK;
+}
+
+}  // namespace
+
 // The Lloyd loops of n jobs in lockstep (see above).  work: the descriptor
 // block, then one cvt workspace per job (cvt_batch_job_workspace each, in
-// order).  status[i] receives each job's status.
+// order).  status[i] receives each job's status.  Narrow relaxation keys
+// are used when every job's sites allow them; if a job outgrows them, the
+// batch is run again with wide keys.
 int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, int32_t *status, hipStream_t s) {
   if (n <= 0) return LSRVT_OK;
   std::vector<JobDev> hj((size_t)n);
   uint8_t *base = static_cast<uint8_t *>(work);
   const size_t head = cvt_batch_header(n);
   if (bytes < head) return LSRVT_EWORKSPACE;
-  JobDev *dj = reinterpret_cast<JobDev *>(base);
-  uint32_t *alive = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev));
-  uint32_t *offs = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev) + 256);
+  BatchCtx c{};
+  c.n = n;
+  c.dj = reinterpret_cast<JobDev *>(base);
+  c.alive = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev));
+  c.offs = reinterpret_cast<uint32_t *>(base + (size_t)n * sizeof(JobDev) + 256);
   size_t off = head;
-  int32_t tmax = 0;
-  int64_t max_keys = 0, max_sites = 0, max_tiles = 0, max_nb = 0, max_slots = 0;
   std::vector<CvtWork> Ws((size_t)n);
+  std::vector<uint32_t> bits((size_t)n);
+  bool narrow = true;
   for (int32_t i = 0; i < n; ++i) {
     const CvtBatchJob &b = jobs[i];
     JobDev &j = hj[(size_t)i];
@@ -2441,8 +2686,10 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
     CvtWork &W = Ws[(size_t)i];
     if ((rc = carve_cvt(base + off, need, g, b.n_sites, b.iters, W))) return rc;
     off += need;
-    j.A = br_args(g, W);
-    j.A.alive = alive;
+    bits[(size_t)i] = narrow_id_bits(b.n_sites);
+    narrow = narrow && bits[(size_t)i] != 0;
+    j.A = br_args(g, W, 0u);
+    j.A.alive = c.alive;
     j.A.dbg = nullptr;
     j.g = g;
     j.band = b.band;
@@ -2461,96 +2708,37 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
     j.moved = W.moved;
     j.fb_list = W.fb_list;
     j.fb_cnt = W.fb_cnt;
-    tmax = std::max(tmax, b.iters);
+    c.tmax = std::max(c.tmax, b.iters);
     const VTGrid bg = vt_grid(g);
-    max_nb = std::max<int64_t>(max_nb, bg.nbricks);
-    max_keys = std::max<int64_t>(max_keys, bg.nbricks * kRows * BX);
-    max_slots = std::max<int64_t>(max_slots, bg.nbricks * kRows);
-    max_sites = std::max<int64_t>(max_sites, (int64_t)S);
-    max_tiles = std::max<int64_t>(max_tiles, (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) *
-                                                 ((g.nz + TZ - 1) / TZ));
+    c.max_nb = std::max<int64_t>(c.max_nb, bg.nbricks);
+    c.sum_nb += bg.nbricks;
+    c.max_keys = std::max<int64_t>(c.max_keys, bg.nbricks * kRows * BX);
+    c.max_slots = std::max<int64_t>(c.max_slots, bg.nbricks * kRows);
+    c.max_sites = std::max<int64_t>(c.max_sites, (int64_t)S);
+    c.max_tiles = std::max<int64_t>(c.max_tiles, (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) *
+                                                     ((g.nz + TZ - 1) / TZ));
   }
-  int32_t rc;
-  LSRVT_HIP(hipMemcpyAsync(dj, hj.data(), sizeof(JobDev) * (size_t)n, hipMemcpyHostToDevice, s));
-  for (int32_t i = 0; i < n; ++i)
-    if ((rc = fill<uint32_t>(Ws[(size_t)i].ctl, 8 + 2 * 8, 0u, s))) return rc;
-  const unsigned N = (unsigned)n;
-  auto cap = [](int64_t v, int64_t c) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(v, c)); };
-  const unsigned g_sites = cap((max_sites + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(kb_init_sites, dim3(g_sites, N), dim3(256), 0, s, dj);
-  hipLaunchKernelGGL(kb_vt_eq, dim3(cap((max_keys + kVTThreads - 1) / kVTThreads, 65535), N), dim3(kVTThreads), 0, s,
-                     dj);
-  LSRVT_LAUNCHED();
-  const unsigned g_clear = cap((max_keys + 255) / 256, 8192);
-  const unsigned g_list = cap((max_nb + 255) / 256, 4096);
-  int64_t sum_nb = 0;
-  for (int32_t i = 0; i < n; ++i) sum_nb += hj[(size_t)i].A.bg.nbricks;
-  const unsigned g_round = cap(sum_nb, tuning(LSRVT_TUNE_BR_GRID) > 0 ? tuning(LSRVT_TUNE_BR_GRID) : 2048);
-  const unsigned g_fin = cap((max_slots + kVTThreads / BX - 1) / (kVTThreads / BX), 65535);
-  const unsigned g_tiles = cap(max_tiles, 65535);
-  const unsigned g_fb = cap(max_sites, 1024);
-  uint32_t rounds_hint = 0;
-  // kGraphRounds rounds of every job captured once and replayed as one graph launch
-  VTState gs;
-  int32_t rc0 = capture_rounds(&gs.br_graph, [&](hipStream_t cs) -> int32_t {
-    hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, cs, dj);
-    hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, cs, dj);
-    hipLaunchKernelGGL(kb_offsets, dim3(1), dim3(1024), 0, cs, dj, n, offs);
-    hipLaunchKernelGGL(kb_round, dim3(g_round), dim3(kBRThreads), 0, cs, dj, n, (const uint32_t *)offs);
-    LSRVT_LAUNCHED();
-    return LSRVT_OK;
-  });
-  if (rc0) return rc0;
-  for (int32_t t = 0; t <= tmax; ++t) {
-    hipLaunchKernelGGL(kb_pass_clear, dim3(g_clear, N), dim3(256), 0, s, dj, t);
-    if (t > 0) hipLaunchKernelGGL(kb_reset, dim3(g_clear, N), dim3(256), 0, s, dj, t);
-    hipLaunchKernelGGL(kb_sites, dim3(g_sites, N), dim3(256), 0, s, dj, t);
-    LSRVT_LAUNCHED();
-    uint32_t r = 0;
-    int batch = rounds_hint ? (int)rounds_hint : kGraphRounds;
-    uint32_t c[3];
-    const bool timed = timer().on;
-    while (true) {
-      std::pair<hipEvent_t, hipEvent_t> ev;
-      const int graphs = (batch + kGraphRounds - 1) / kGraphRounds;
-      if (timed && (rc = timed_begin(s, ev))) return rc;
-      for (int k = 0; k < graphs; ++k) LSRVT_HIP(hipGraphLaunch(gs.br_graph, s));
-      r += (uint32_t)(graphs * kGraphRounds);
-      if (timed && (rc = timed_end(s, ev, (uint64_t)graphs * kGraphRounds))) return rc;
-      if ((rc = read_words(alive, 3, c, s))) return rc;
-      if (c[(r + 1) % 3] == 0) break;
-      if (r > (uint32_t)(1u << 30)) return LSRVT_EDEVICE;
-      batch = kGraphRounds;
+  c.hj = &hj;
+  c.Ws = &Ws;
+  if (narrow) {
+    for (int32_t i = 0; i < n; ++i) {
+      const BRArgs a = br_args(hj[(size_t)i].g, Ws[(size_t)i], bits[(size_t)i]);
+      hj[(size_t)i].A.hop32 = a.hop32;
+      hj[(size_t)i].A.idmask = a.idmask;
+      hj[(size_t)i].A.lim32 = a.lim32;
     }
-    rounds_hint = r;
-    hipLaunchKernelGGL(kb_finish, dim3(g_fin, N), dim3(kVTThreads), 0, s, dj, t);
-    if (t < tmax) {
-      hipLaunchKernelGGL(kb_update_clear, dim3(g_sites, N), dim3(256), 0, s, dj, t);
-      hipLaunchKernelGGL(kb_centroid, dim3(g_tiles, N), dim3(256), 0, s, dj, t);
-      hipLaunchKernelGGL(kb_snap, dim3(g_sites, N), dim3(256), 0, s, dj, t);
-      hipLaunchKernelGGL(kb_snap_fallback, dim3(g_fb, N), dim3(256), 0, s, dj, t);
-    }
-    LSRVT_LAUNCHED();
-    if (timed) {
-      std::lock_guard<std::mutex> lk(timer().mu);
-      timer().engines |= 2;
-      for (int32_t i = 0; i < n; ++i)
-        if (t <= hj[(size_t)i].iters) {
-          timer().passes += 1;
-          timer().voxels_per_pass = hj[(size_t)i].g.n;
-        }
+    bool far = false;
+    const int32_t rc = batch_loop<uint32_t>(c, status, &far, s);
+    if (rc || !far) return rc;
+    for (int32_t i = 0; i < n; ++i) {
+      const BRArgs a = br_args(hj[(size_t)i].g, Ws[(size_t)i], 0u);
+      hj[(size_t)i].A.hop32 = a.hop32;
+      hj[(size_t)i].A.idmask = a.idmask;
+      hj[(size_t)i].A.lim32 = a.lim32;
     }
   }
-  // each job's error bits (a seed outside its volume)
-  for (int32_t i0 = 0; i0 < n; i0 += 64) {
-    uint32_t e[64];
-    const int m = std::min<int32_t>(64, n - i0);
-    for (int k = 0; k < m; ++k) {
-      if ((rc = read_words(Ws[(size_t)(i0 + k)].ctl + 3, 1, &e[k], s))) return rc;
-      status[i0 + k] = (e[k] & 1u) ? LSRVT_EINVAL : e[k] ? LSRVT_EDEVICE : LSRVT_OK;
-    }
-  }
-  return LSRVT_OK;
+  bool far = false;
+  return batch_loop<unsigned long long>(c, status, &far, s);
 }
 
 namespace {
@@ -2734,9 +2922,9 @@ extern "C" int32_t lsrvt_update_noalloc(const uint32_t *d_cell, lsrvt_dims dims,
 
 namespace lsrvt {
 namespace {
-thread_local int32_t t_tuning[3] = {0, 0, 0};
+thread_local int32_t t_tuning[4] = {0, 0, 0, 0};
 }  // namespace
-int32_t tuning(int32_t knob) { return knob > 0 && knob < 3 ? t_tuning[knob] : 0; }
+int32_t tuning(int32_t knob) { return knob > 0 && knob < 4 ? t_tuning[knob] : 0; }
 }  // namespace lsrvt
 
 extern "C" int32_t lsrvt_set_tuning(int32_t knob, int32_t value) {
@@ -2744,6 +2932,8 @@ extern "C" int32_t lsrvt_set_tuning(int32_t knob, int32_t value) {
     if (value != 0 && (value < 256 || value > 16384)) return -1;
   } else if (knob == LSRVT_TUNE_STATS_TILE) {
     if (value != 0 && value != 1 && value != 2 && value != 4) return -1;
+  } else if (knob == LSRVT_TUNE_KEY_BITS) {
+    if (value != 64 && (value < 0 || value > 30)) return -1;
   } else {
     return -1;
   }

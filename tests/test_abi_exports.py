@@ -134,3 +134,10 @@ def test_set_tuning_validation_without_gpu(lib):
     assert lib.lsrvt_set_tuning(L.TUNE_BR_GRID, 0) == 4096
     assert lib.lsrvt_set_tuning(L.TUNE_STATS_TILE, 2) == 0
     assert lib.lsrvt_set_tuning(L.TUNE_STATS_TILE, 0) == 2
+    assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 31) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 32) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, -1) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 64) == 0
+    assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 30) == 64
+    assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 0) == 30
+    assert lib.lsrvt_set_tuning(4, 0) == -1

@@ -84,6 +84,30 @@ def test_batch_matches_alone_and_oracle():
         np.testing.assert_array_equal(host(j.sites, np.uint32)[:S], want.sites)
 
 
+@pytest.mark.parametrize("bits", [64, 30])
+def test_batch_key_widths(bits):
+    """The lockstep Lloyd loops with wide keys, and with narrow keys whose
+    distance field every job outgrows (the batch is then run again with wide
+    keys): cells and sites as the oracle's."""
+    data = [_job(*sp) for sp in SPECS[:4]]
+    jobs = [L.BatchJob(field=dev(d["f"]), iso=d["iso"], seeds=dev(d["seeds"]), weights=dev(d["w"]), iters=d["iters"],
+                       variables=dev(np.ascontiguousarray(d["x"])),
+                       edges=None if d["edges"] is None else dev(d["edges"]), cov=d["cov"],
+                       cap_comp=int(d["cc"].n_comp) + 5)
+            for d in data]
+    banner(f"batch: {len(jobs)} jobs, key bits {bits}")
+    prev = L.lsrvt_set_tuning(L.TUNE_KEY_BITS, bits)
+    try:
+        L.lsrvt_batch_run(jobs, n_streams=2)
+    finally:
+        L.lsrvt_set_tuning(L.TUNE_KEY_BITS, prev)
+    for i, (d, j) in enumerate(zip(data, jobs)):
+        assert j.status == 0, i
+        want = oracle.cvt(d["cc"].comp, d["seeds"], d["w"], d["iters"])
+        np.testing.assert_array_equal(host(j.cell, np.uint32), want.cell)
+        np.testing.assert_array_equal(host(j.sites, np.uint32)[:len(d["seeds"])], want.sites)
+
+
 def test_batch_capacity_and_validation():
     d = _job((20, 20, 20), 9, 4, 1, 1, 0, False, 64.0)
     banner("batch: capacity")

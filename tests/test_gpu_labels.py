@@ -239,6 +239,23 @@ def test_cvt_every_relaxation_grid(grid):
         L.lsrvt_set_vt_engine(prev_e)
 
 
+@pytest.mark.parametrize("bits", [0, 64, 20, 30])
+def test_cvt_every_key_width(bits):
+    """Narrow keys (the default here), wide keys, and narrow keys with so
+    wide an id field that distances outgrow the rest (30 id bits leave
+    distances below 2: every pass of this volume outgrows them and is
+    repeated with wide keys) all give the oracle's Lloyd loop bit for bit."""
+    prev_e = L.lsrvt_set_vt_engine(L.VT_BRICKS)
+    prev = L.lsrvt_set_tuning(L.TUNE_KEY_BITS, bits)
+    try:
+        f = _field((40, 36, 90), 12)
+        iso = synth.quantile_isovalues(f, [0.3, 0.6])
+        _cvt_case(f, iso, synth.gradient_weight(f), 300.0, 12, 4)
+    finally:
+        L.lsrvt_set_tuning(L.TUNE_KEY_BITS, prev)
+        L.lsrvt_set_vt_engine(prev_e)
+
+
 def test_update_and_loop_with_every_voxel_a_site():
     """More distinct cells than the LDS tables of the centroid sums hold
     (512 per 64x8x8 tile in lsrvt_update, 256 per 16^3 brick in the sums a
