@@ -882,7 +882,11 @@ __device__ __forceinline__ void d_br_reset(const uint8_t *__restrict__ moved, BR
   KT *key = static_cast<KT *>(A.key), *xface = static_cast<KT *>(A.xface);
   const int64_t slots = A.bg.nbricks * kRows * BX;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  constexpr int kU = 4;  // slots per thread and step: their loads are issued together
+  const int lane = lane_id();
+  constexpr int kU = 8;  // slots per thread and step: their loads are issued together
+  // A wave's 64 slots of a step lie in one brick (bricks are 4096 slots,
+  // waves and the stride multiples of 64), so the loop bounds are the same
+  // for the whole wave and one lane marks the brick.
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < slots; i0 += kU * stride) {
     KT k[kU];
     uint8_t mv[kU];
@@ -895,16 +899,20 @@ __device__ __forceinline__ void d_br_reset(const uint8_t *__restrict__ moved, BR
     for (int j = 0; j < kU; ++j) mv[j] = k[j] != kInf ? moved[(uint32_t)k[j] & A.idmask] : (uint8_t)0;
 #pragma unroll
     for (int j = 0; j < kU; ++j) {
-      if (!mv[j]) continue;
       const int64_t i = i0 + j * stride;
-      key[i] = kInf;
-      const int64_t b = i / (kRows * BX);
-      const int loc = (int)(i % (kRows * BX));
-      const int lx = loc & 15, row = loc >> 4;
-      if (lx == 0) xface[b * 512 + row] = kInf;
-      if (lx == BX - 1) xface[b * 512 + 256 + row] = kInf;
-      A.mark[(size_t)1 * A.bg.nbricks + b] = 1u;  // round 1 has parity 1
-      A.alive[1] = 1u;
+      if (mv[j]) {
+        key[i] = kInf;
+        const int64_t b = i / (kRows * BX);
+        const int loc = (int)(i % (kRows * BX));
+        const int lx = loc & 15, row = loc >> 4;
+        if (lx == 0) xface[b * 512 + row] = kInf;
+        if (lx == BX - 1) xface[b * 512 + 256 + row] = kInf;
+      }
+      const uint64_t any = __ballot(mv[j] != 0);
+      if (any && lane == __builtin_ctzll(any)) {
+        A.mark[(size_t)1 * A.bg.nbricks + i / (kRows * BX)] = 1u;  // round 1 has parity 1
+        A.alive[1] = 1u;
+      }
     }
   }
 }
@@ -1208,31 +1216,6 @@ __global__ __launch_bounds__(kBRThreads, sizeof(KT) == 4 ? 5 : 4) void k_br_roun
 }
 
 
-// End of a pass: keys to the caller's C-order cells (NONE where unreached),
-// 16 contiguous voxels per row.
-template <class KT>
-__device__ __forceinline__ void d_br_finish(const KT *__restrict__ key, Geom g, VTGrid bg, uint32_t idmask,
-                                            uint32_t *__restrict__ cell) {
-  const int t = threadIdx.x;
-  const int lx = t & 15;
-  for (int64_t rr = (int64_t)blockIdx.x * (kVTThreads / BX) + (t >> 4); rr < bg.nbricks * kRows;
-       rr += (int64_t)gridDim.x * (kVTThreads / BX)) {
-    const int64_t b = rr / kRows;
-    const int row = (int)(rr % kRows);
-    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-    const int x = bx * BX + lx, y = by * BY + (row & 15), z = bz * BZ + (row >> 4);
-    if (x >= g.nx || y >= g.ny || z >= g.nz) continue;
-    const KT k = key[(size_t)rr * BX + lx];
-    cell[x + (int64_t)g.nx * (y + (int64_t)g.ny * z)] = k == BRKey<KT>::inf ? kNone : (uint32_t)k & idmask;
-  }
-}
-template <class KT>
-__global__ __launch_bounds__(kVTThreads) void k_br_finish(const KT *__restrict__ key, Geom g, VTGrid bg,
-                                                          uint32_t idmask, uint32_t *__restrict__ cell) {
-  d_br_finish<KT>(key, g, bg, idmask, cell);
-}
-
-
 // ----------------------------------------------------------------------------
 // update
 
@@ -1244,13 +1227,15 @@ struct Sums {
 // position of every cell, exact uint64 integers, so their order does not
 // matter) taken at the end of the Voronoi pass that produces the cells: the
 // pass's last kernel holds every voxel's cell id once anyway, so the sums
-// cost no second read of the cell array.  One workgroup per 16^3 brick;
-// thread t takes voxel t, t + 256, ... of the brick, so the 16 lanes of each
-// quarter wave hold one row along x.  A segmented scan over those 16 lanes
-// (DPP row shifts) sums (w, w * (x - x0)) over every run of equal cell id,
-// the last lane of a run adds it into an LDS table keyed by cell id (global
-// atomics when the table is full), and the table is flushed with one set of
-// global atomics per distinct cell of the brick.
+// cost no second read of the cell array.  Partial sums go into an LDS
+// table keyed by cell id (global atomics when the table is full), flushed
+// with one set of global atomics per distinct cell of the workgroup's part.
+// The level search's finish takes one workgroup per 16^3 brick: thread t
+// takes voxel t, t + 256, ... of the brick, so the 16 lanes of each quarter
+// wave hold one row along x, and a segmented scan over those 16 lanes (DPP
+// row shifts) sums (w, w * (x - x0)) over every run of equal cell id, whose
+// last lane adds it into the table.  The relaxation's finish keeps running
+// sums per lane instead (d_br_finish_slabs).
 struct Fuse {
   const uint16_t *w;  // weights (C order) or null for unit weights
   uint32_t S;
@@ -1335,32 +1320,108 @@ __device__ __forceinline__ void fin_flush(FinTab &T, const Fuse &F) {
   __syncthreads();
 }
 
-// End of a relaxation pass followed by an update: the keys to C-order cells
-// (as k_br_finish) and the centroid sums, one workgroup per brick.
+// End of a relaxation pass: the keys to C-order cells (kNone where
+// unreached) and, with SUMS, the centroid sums of the update that follows.
+// One workgroup per slab of four x-adjacent bricks (64 x 16 x 16 voxels);
+// lane l of every wave owns x = 64 sx + l, so a row's cells (256 B) and
+// weights (128 B) are contiguous and each brick's 16 keys of the row are
+// one 64 B run.  Wave w takes the slab's rows with z - z0 in [4w, 4w + 4),
+// y fastest, eight rows per step with their loads issued together.  For
+// the sums a lane keeps running totals (w, w (y - y0), w (z - z0)) of the
+// cell it is in and adds them into the LDS table when its cell changes
+// (w x = x times the mass, x being fixed per lane); the table goes to global
+// memory once per slab.
+constexpr int kFinRows = 8;
+template <class KT, bool SUMS>
+__device__ __forceinline__ void d_br_finish_slabs(const KT *__restrict__ key, Geom g, VTGrid bg, uint32_t idmask,
+                                                  uint32_t *__restrict__ cell, const Fuse &F, FinTab *T) {
+  const int t = threadIdx.x, lane = t & (kWave - 1), wv_id = t / kWave;
+  const int nsx = (bg.nbx + 3) / 4;
+  const int64_t nslabs = (int64_t)nsx * bg.nby * bg.nbz;
+  for (int64_t sl = blockIdx.x; sl < nslabs; sl += gridDim.x) {
+    const int sx = (int)(sl % nsx), by = (int)((sl / nsx) % bg.nby), bz = (int)(sl / ((int64_t)nsx * bg.nby));
+    if constexpr (SUMS) {
+      fin_clear(*T);
+      __syncthreads();
+    }
+    const int bx = sx * 4 + (lane >> 4);
+    const int x = bx * BX + (lane & 15);
+    const bool has = bx < bg.nbx;  // the lane's brick exists
+    const bool xin = x < g.nx;
+    const int64_t b = (int64_t)(has ? bx : bg.nbx - 1) + (int64_t)bg.nbx * (by + (int64_t)bg.nby * bz);
+    const KT *kb = key + (size_t)b * (kRows * BX) + (lane & 15);
+    const int y0 = by * BY, z0 = bz * BZ;
+    uint32_t cur = kNone, m = 0, sy = 0, sz = 0;  // the lane's running sums (below 2^26 over 64 rows)
+    auto flush = [&]() {
+      if (cur < F.S && m) {
+        const unsigned long long M = m, X = (unsigned long long)m * (uint32_t)x,
+                                 Y = (unsigned long long)m * (uint32_t)y0 + sy,
+                                 Z = (unsigned long long)m * (uint32_t)z0 + sz;
+        const int slot = lds_slot<kFinTab>(T->tkey, cur);
+        if (slot >= 0) {
+          atomicAdd(&T->tM[slot], M);
+          atomicAdd(&T->tX[slot], X);
+          atomicAdd(&T->tY[slot], Y);
+          atomicAdd(&T->tZ[slot], Z);
+        } else {
+          atomicAdd(&F.sums.M[cur], M);
+          atomicAdd(&F.sums.Sx[cur], X);
+          atomicAdd(&F.sums.Sy[cur], Y);
+          atomicAdd(&F.sums.Sz[cur], Z);
+        }
+      }
+    };
+    for (int j0 = 0; j0 < kRows / (kVTThreads / kWave); j0 += kFinRows) {
+      KT k[kFinRows];
+      uint32_t wt[kFinRows];
+#pragma unroll
+      for (int u = 0; u < kFinRows; ++u) {
+        const int r = (kRows / (kVTThreads / kWave)) * wv_id + j0 + u;  // (ly, lz) = (r & 15, r >> 4)
+        const bool rin = y0 + (r & 15) < g.ny && z0 + (r >> 4) < g.nz;
+        k[u] = has && rin ? kb[r * BX] : BRKey<KT>::inf;
+        if constexpr (SUMS) {
+          const int64_t v = (int64_t)g.nx * ((y0 + (r & 15)) + (int64_t)g.ny * (z0 + (r >> 4))) + x;
+          wt[u] = xin && rin ? (F.w ? (uint32_t)F.w[v] : 1u) : 0u;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kFinRows; ++u) {
+        const int r = (kRows / (kVTThreads / kWave)) * wv_id + j0 + u;
+        const int ly = r & 15, lz = r >> 4;
+        const bool in = xin && y0 + ly < g.ny && z0 + lz < g.nz;
+        const uint32_t c = k[u] == BRKey<KT>::inf ? kNone : (uint32_t)k[u] & idmask;
+        if (in) cell[(int64_t)g.nx * ((y0 + ly) + (int64_t)g.ny * (z0 + lz)) + x] = c;
+        if constexpr (SUMS) {
+          const uint32_t cc = in ? c : kNone;
+          if (cc != cur) {
+            flush();
+            cur = cc;
+            m = sy = sz = 0;
+          }
+          m += wt[u];
+          sy += wt[u] * (uint32_t)ly;
+          sz += wt[u] * (uint32_t)lz;
+        }
+      }
+    }
+    if constexpr (SUMS) {
+      flush();
+      __syncthreads();
+      fin_flush(*T, F);
+    }
+  }
+}
+
 template <class KT>
 __global__ __launch_bounds__(kVTThreads) void k_br_finish_sums(const KT *__restrict__ key, Geom g, VTGrid bg,
                                                                uint32_t idmask, uint32_t *__restrict__ cell, Fuse F) {
   __shared__ FinTab T;
-  const int t = threadIdx.x;
-  for (int64_t b = blockIdx.x; b < bg.nbricks; b += gridDim.x) {
-    const int bx = (int)(b % bg.nbx), by = (int)((b / bg.nbx) % bg.nby), bz = (int)(b / ((int64_t)bg.nbx * bg.nby));
-    fin_clear(T);
-    __syncthreads();
-#pragma unroll 4
-    for (int i = 0; i < BX; ++i) {
-      const int loc = i * kVTThreads + t;
-      const int x = bx * BX + (loc & 15), y = by * BY + ((loc >> 4) & 15), z = bz * BZ + (loc >> 8);
-      const bool in = x < g.nx && y < g.ny && z < g.nz;
-      const KT k = key[(size_t)b * (kRows * BX) + loc];
-      const uint32_t c = k == BRKey<KT>::inf ? kNone : (uint32_t)k & idmask;
-      const int64_t v = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
-      if (in) cell[v] = c;
-      const uint32_t wv = in ? (F.w ? (uint32_t)F.w[v] : 1u) : 0u;
-      fin_row_runs(T, F, in ? c : kNone, wv, (uint32_t)(bx * BX), (uint32_t)y, (uint32_t)z);
-    }
-    __syncthreads();
-    fin_flush(T, F);
-  }
+  d_br_finish_slabs<KT, true>(key, g, bg, idmask, cell, F, &T);
+}
+template <class KT>
+__global__ __launch_bounds__(kVTThreads) void k_br_finish(const KT *__restrict__ key, Geom g, VTGrid bg,
+                                                          uint32_t idmask, uint32_t *__restrict__ cell) {
+  d_br_finish_slabs<KT, false>(key, g, bg, idmask, cell, Fuse{}, nullptr);
 }
 
 // One workgroup per 64x8x8 tile; each wave takes rows of the tile with one
@@ -1879,7 +1940,7 @@ __global__ __launch_bounds__(kVTThreads) void k_vt_finish(const uint16_t *__rest
 }
 
 // The same end of a level-search pass with the centroid sums of the update
-// that follows (see k_br_finish_sums), one workgroup per brick.
+// that follows, one workgroup per brick (segmented row scans, see Fuse).
 template <bool INC>
 __global__ __launch_bounds__(kVTThreads) void k_vt_finish_sums(const uint16_t *__restrict__ vis,
                                                                const uint16_t *__restrict__ inv, Geom g, VTGrid bg,
@@ -1926,6 +1987,10 @@ __global__ void k_sites_clear(const uint32_t *__restrict__ sites, uint32_t S, BF
 }
 
 unsigned brick_grid(const VTGrid &bg) { return (unsigned)std::min<int64_t>(bg.nbricks, 65535); }
+
+// Workgroups of the relaxation's finish: one per slab of four x-adjacent bricks.
+int64_t br_slabs(const VTGrid &bg) { return (int64_t)((bg.nbx + 3) / 4) * bg.nby * bg.nbz; }
+unsigned slab_grid(const VTGrid &bg) { return (unsigned)std::min<int64_t>(br_slabs(bg), 65535); }
 
 unsigned finish_grid(const VTGrid &bg) {
   const int64_t g = (bg.nbricks * kRows + kVTThreads / BX - 1) / (kVTThreads / BX);
@@ -2281,10 +2346,10 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
   }
   const KT *keys = static_cast<const KT *>(A.key);
   if (fz)
-    hipLaunchKernelGGL(k_br_finish_sums<KT>, dim3(brick_grid(bg)), dim3(kVTThreads), 0, s, keys, g, bg, A.idmask,
+    hipLaunchKernelGGL(k_br_finish_sums<KT>, dim3(slab_grid(bg)), dim3(kVTThreads), 0, s, keys, g, bg, A.idmask,
                        cell, *fz);
   else
-    hipLaunchKernelGGL(k_br_finish<KT>, dim3(finish_grid(bg)), dim3(kVTThreads), 0, s, keys, g, bg, A.idmask, cell);
+    hipLaunchKernelGGL(k_br_finish<KT>, dim3(slab_grid(bg)), dim3(kVTThreads), 0, s, keys, g, bg, A.idmask, cell);
   LSRVT_LAUNCHED();
   if (timer().on) {
     std::lock_guard<std::mutex> lk(timer().mu);
@@ -2503,7 +2568,7 @@ template <class KT>
 __global__ __launch_bounds__(kVTThreads) void kb_finish(const JobDev *J, int32_t t) {
   const JobDev &j = J[blockIdx.y];
   if (t > j.iters) return;
-  d_br_finish<KT>(static_cast<const KT *>(j.A.key), j.g, j.A.bg, j.A.idmask, j.cell);
+  d_br_finish_slabs<KT, false>(static_cast<const KT *>(j.A.key), j.g, j.A.bg, j.A.idmask, j.cell, Fuse{}, nullptr);
 }
 
 __global__ __launch_bounds__(256) void kb_update_clear(const JobDev *J, int32_t t) {
@@ -2559,7 +2624,7 @@ struct BatchCtx {
   std::vector<JobDev> *hj;
   std::vector<CvtWork> *Ws;
   int32_t tmax;
-  int64_t max_keys, max_sites, max_tiles, max_nb, max_slots, sum_nb;
+  int64_t max_keys, max_sites, max_tiles, max_nb, max_slabs, sum_nb;
 };
 
 // The Lloyd loops of the batch with keys KT, from the seeds.  status[i]
@@ -2584,7 +2649,7 @@ int32_t batch_loop(const BatchCtx &c, int32_t *status, bool *far, hipStream_t s)
   const unsigned g_clear = cap((c.max_keys + 255) / 256, 8192);
   const unsigned g_list = cap((c.max_nb + 255) / 256, 4096);
   const unsigned g_round = cap(c.sum_nb, tuning(LSRVT_TUNE_BR_GRID) > 0 ? tuning(LSRVT_TUNE_BR_GRID) : 2048);
-  const unsigned g_fin = cap((c.max_slots + kVTThreads / BX - 1) / (kVTThreads / BX), 65535);
+  const unsigned g_fin = cap(c.max_slabs, 65535);
   const unsigned g_tiles = cap(c.max_tiles, 65535);
   const unsigned g_fb = cap(c.max_sites, 1024);
   uint32_t rounds_hint = 0;
@@ -2713,7 +2778,7 @@ int32_t cvt_batch(const CvtBatchJob *jobs, int32_t n, void *work, size_t bytes, 
     c.max_nb = std::max<int64_t>(c.max_nb, bg.nbricks);
     c.sum_nb += bg.nbricks;
     c.max_keys = std::max<int64_t>(c.max_keys, bg.nbricks * kRows * BX);
-    c.max_slots = std::max<int64_t>(c.max_slots, bg.nbricks * kRows);
+    c.max_slabs = std::max<int64_t>(c.max_slabs, br_slabs(bg));
     c.max_sites = std::max<int64_t>(c.max_sites, (int64_t)S);
     c.max_tiles = std::max<int64_t>(c.max_tiles, (int64_t)((g.nx + TX - 1) / TX) * ((g.ny + TY - 1) / TY) *
                                                      ((g.nz + TZ - 1) / TZ));
