@@ -540,12 +540,21 @@ int32_t lsrvt_set_vt_engine(int32_t engine);
  *                           narrow field is repeated with wide keys, which
  *                           the rest of the call keeps, so every value gives
  *                           the same results.
+ *   LSRVT_TUNE_RESET        how an incremental relaxation pass of lsrvt_cvt
+ *                           starts: 0 = the reset of moved sites' voxels is
+ *                           fused into the first round (which then works on
+ *                           every brick) when the moved sites' cells cover
+ *                           most bricks, else done by its own kernel (which
+ *                           reads every key but lets the first round work
+ *                           only on bricks with reset voxels); 1 = always
+ *                           its own kernel; 2 = always fused.
  * Returns the previous value, or -1 (and changes nothing) for an unknown
  * knob or a value outside its range.
  */
 #define LSRVT_TUNE_BR_GRID 1
 #define LSRVT_TUNE_STATS_TILE 2
 #define LSRVT_TUNE_KEY_BITS 3
+#define LSRVT_TUNE_RESET 4
 int32_t lsrvt_set_tuning(int32_t knob, int32_t value);
 
 /* ------------------------------------------------------------------------

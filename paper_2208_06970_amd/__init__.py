@@ -632,7 +632,7 @@ def lsrvt_set_vt_engine(engine: int) -> int:
     return prev
 
 
-TUNE_BR_GRID, TUNE_STATS_TILE, TUNE_KEY_BITS = 1, 2, 3
+TUNE_BR_GRID, TUNE_STATS_TILE, TUNE_KEY_BITS, TUNE_RESET = 1, 2, 3, 4
 
 
 def lsrvt_set_tuning(knob: int, value: int) -> int:
@@ -640,8 +640,9 @@ def lsrvt_set_tuning(knob: int, value: int) -> int:
     workgroups per relaxation round, 256..16384; TUNE_STATS_TILE: voxels per
     thread and staging round of the statistics, 1, 2 or 4; TUNE_KEY_BITS: key
     width of the brick relaxation, 64 = wide keys, 1..30 = narrow keys with at
-    least that many id bits; 0 = the library's choice); returns the previous
-    value."""
+    least that many id bits; TUNE_RESET: 1 = the reset of an incremental
+    relaxation pass by its own kernel, 2 = fused into the first round; 0 = the
+    library's choice); returns the previous value."""
     prev = int(_lib().lsrvt_set_tuning(int(knob), int(value)))
     if prev < 0:
         raise LsrvtError(EINVAL, "lsrvt_set_tuning", f"knob {knob} value {value}")

@@ -39,6 +39,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -775,8 +776,13 @@ __global__ __launch_bounds__(256) void k_wake_min(const uint32_t *__restrict__ w
 // written in the same round: every value it can see is a real path length,
 // and a neighbour that lowers a face key after the read marks it again, so
 // the rounds end exactly at the fixed point.  An incremental pass starts from
-// the previous keys with the voxels of moved sites set to unreached, and
-// marks the bricks that hold such voxels or a changed site.
+// the previous keys with the voxels of moved sites set to unreached.  That
+// reset is done either by its own kernel (which marks the bricks that hold
+// such voxels), or fused into the first round, which then works on every
+// brick: each key it reads (the brick's own and the neighbours' faces) is
+// taken as unreached when its site moved, unless it is the site's own new
+// voxel, and it stores the whole brick.  Keys seen in the first round are
+// thus always the reset ones, whichever bricks have been stored already.
 //
 // Keys come in two widths.  Wide keys are 64 bits, distance << 32 | id.
 // Narrow keys are 32 bits, distance << b | id with b the bits the site ids
@@ -803,7 +809,9 @@ struct BRArgs {
   uint32_t lim32;                  // narrow keys: the smallest key whose distance is D (flagged when stored)
   uint32_t *mark;                  // [2][nbricks]: mark[r & 1][b] == r when brick b works in round r
   uint32_t *list;                  // [nbricks] bricks of the current round
-  uint32_t *ctl;                   // [0] list length, [3] error bits
+  uint32_t *ctl;                   // [0] list length, [2] reset fused into round 1, [3] error bits
+  const uint8_t *moved;            // the sites the last update moved (fused reset)
+  const uint32_t *fsites;          // the sites' voxels (fused reset)
   uint32_t *rnd;                   // the current round (advanced on the device, so rounds replay from a graph)
   uint32_t *alive;                 // [3] round alive flags (by r % 3); shared by the jobs of a batch
   uint32_t *hist;                  // [kHistLen] bricks that worked in each round
@@ -829,6 +837,30 @@ struct BRKey<uint32_t> {
   __device__ static uint32_t hop(const BRArgs &A) { return A.hop32; }
   __device__ static uint32_t add(uint32_t k, uint32_t h) { return __builtin_elementwise_add_sat(k, h); }
 };
+
+// A key of the previous pass as the fused reset sees it at voxel v:
+// unreached when its site moved, unless it is that site's new voxel
+// (distance 0 at the site's voxel).
+template <class KT>
+__device__ __forceinline__ KT br_filter(const BRArgs &A, KT k, KT hop, uint32_t v) {
+  if (k == BRKey<KT>::inf) return k;
+  const uint32_t id = (uint32_t)k & A.idmask;
+  if (!A.moved[id] || (k < hop && A.fsites[id] == v)) return k;
+  return BRKey<KT>::inf;
+}
+
+// *p = min(*p, k) with the stored value taken through the fused reset's
+// filter; returns whether k was stored.
+template <class KT>
+__device__ __forceinline__ bool br_cas_min(const BRArgs &A, KT *p, KT k, KT hop, uint32_t v) {
+  KT old = __atomic_load_n(p, __ATOMIC_RELAXED);
+  for (;;) {
+    if (k >= br_filter<KT>(A, old, hop, v)) return false;
+    const KT prev = atomicCAS(p, old, k);
+    if (prev == old) return true;
+    old = prev;
+  }
+}
 
 __device__ __forceinline__ void br_mark(const BRArgs &A, int bx, int by, int bz, int k, uint32_t r) {
   const int qx = bx + (k == 1 ? -1 : k == 2 ? 1 : 0);
@@ -859,10 +891,17 @@ __device__ __forceinline__ void d_br_sites(const uint32_t *__restrict__ sites, u
   const uint32_t lx = x % BX, ly = y % BY, lz = z % BZ;
   const uint32_t row = ly + BY * lz;
   const KT k = (KT)s;
-  const KT old = atomicMin(&key[b * (kRows * BX) + lx + BX * row], k);
-  if (k >= old) return;
-  if (lx == 0) atomicMin(&xface[b * 512 + row], k);
-  if (lx == BX - 1) atomicMin(&xface[b * 512 + 256 + row], k);
+  if (A.ctl[2] == 0u) {
+    const KT old = atomicMin(&key[b * (kRows * BX) + lx + BX * row], k);
+    if (k >= old) return;
+    if (lx == 0) atomicMin(&xface[b * 512 + row], k);
+    if (lx == BX - 1) atomicMin(&xface[b * 512 + 256 + row], k);
+  } else {  // previous keys, seen through the fused reset's filter
+    const KT hop = BRKey<KT>::hop(A);
+    if (!br_cas_min<KT>(A, &key[b * (kRows * BX) + lx + BX * row], k, hop, v)) return;
+    if (lx == 0) br_cas_min<KT>(A, &xface[b * 512 + row], k, hop, v);
+    if (lx == BX - 1) br_cas_min<KT>(A, &xface[b * 512 + 256 + row], k, hop, v);
+  }
   const bool on[7] = {true, lx == 0, lx == BX - 1, ly == 0, ly == BY - 1, lz == 0, lz == BZ - 1};
 #pragma unroll
   for (int q = 0; q < 7; ++q)
@@ -916,8 +955,30 @@ __device__ __forceinline__ void d_br_reset(const uint8_t *__restrict__ moved, BR
     }
   }
 }
+// Sites the last update moved, counted into *out (zeroed before).
+__global__ __launch_bounds__(256) void k_count_moved(const uint8_t *__restrict__ moved, uint32_t S, uint32_t *out) {
+  uint32_t c = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < S; i += gridDim.x * blockDim.x) c += moved[i] != 0;
+  for (int o = kWave / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, kWave);
+  if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
+// Set-up of an incremental pass of lsrvt_cvt: with more than fuse_min
+// sites moved (the count in ctl[1]; mode 0), or always (mode 2), the reset
+// is fused into round 1 (ctl[2] set, every brick marked for round 1);
+// otherwise (or always, mode 1) the voxels of moved sites are reset here.
 template <class KT>
-__global__ __launch_bounds__(256) void k_br_reset(const uint8_t *__restrict__ moved, BRArgs A) {
+__global__ __launch_bounds__(256) void k_br_reset_or_fuse(const uint8_t *__restrict__ moved, BRArgs A,
+                                                          uint32_t fuse_min, int32_t mode) {
+  if (mode == 2 || (mode == 0 && A.ctl[1] > fuse_min)) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) {
+      A.ctl[2] = 1u;
+      A.alive[1] = 1u;
+    }
+    for (int64_t b = i0; b < A.bg.nbricks; b += (int64_t)gridDim.x * blockDim.x) A.mark[A.bg.nbricks + b] = 1u;
+    return;
+  }
   d_br_reset<KT>(moved, A);
 }
 
@@ -1055,12 +1116,29 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     for (int i = 0; i < 16; ++i) kv[i] = key[(size_t)b * kB + i * kBRThreads + t];
     const uint32_t *eq = A.eq + ((size_t)b * kRows + t) * 3;
     const uint32_t mx = eq[0], e1 = eq[1], e2 = eq[2];
-    const KT fxm = xface[(size_t)(hxm ? b - 1 : b) * 512 + 256 + t];
-    const KT fxp = xface[(size_t)(hxp ? b + 1 : b) * 512 + t];
-    const KT fym = key[(size_t)(hym ? b - bsy : b) * kB + lo4 + 16 * 15 + 256 * hi4];
-    const KT fyp = key[(size_t)(hyp ? b + bsy : b) * kB + lo4 + 256 * hi4];
-    const KT fzm = key[(size_t)(hzm ? b - bsz : b) * kB + lo4 + 16 * hi4 + 256 * 15];
-    const KT fzp = key[(size_t)(hzp ? b + bsz : b) * kB + lo4 + 16 * hi4];
+    KT fxm = xface[(size_t)(hxm ? b - 1 : b) * 512 + 256 + t];
+    KT fxp = xface[(size_t)(hxp ? b + 1 : b) * 512 + t];
+    KT fym = key[(size_t)(hym ? b - bsy : b) * kB + lo4 + 16 * 15 + 256 * hi4];
+    KT fyp = key[(size_t)(hyp ? b + bsy : b) * kB + lo4 + 256 * hi4];
+    KT fzm = key[(size_t)(hzm ? b - bsz : b) * kB + lo4 + 16 * hi4 + 256 * 15];
+    KT fzp = key[(size_t)(hzp ? b + bsz : b) * kB + lo4 + 16 * hi4];
+    // first round of an incremental pass with the reset fused in
+    const bool fuse = r == 1 && A.ctl[2] != 0u;
+    if (fuse) {
+      const uint32_t nx = (uint32_t)A.g.nx, nxy = (uint32_t)A.g.nx * (uint32_t)A.g.ny;
+      const uint32_t x0 = (uint32_t)bx * BX, y0 = (uint32_t)by * BY, z0 = (uint32_t)bz * BZ;
+      // thread t's voxel i is (x0 + lo4, y0 + hi4, z0 + i)
+      const uint32_t v0 = x0 + lo4 + nx * (y0 + hi4) + nxy * z0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) kv[i] = br_filter<KT>(A, kv[i], hop, v0 + nxy * (uint32_t)i);
+      // the face voxels' own coordinates (unused where the neighbour is missing)
+      fxm = br_filter<KT>(A, fxm, hop, x0 - 1 + nx * (y0 + lo4) + nxy * (z0 + hi4));
+      fxp = br_filter<KT>(A, fxp, hop, x0 + BX + nx * (y0 + lo4) + nxy * (z0 + hi4));
+      fym = br_filter<KT>(A, fym, hop, x0 + lo4 + nx * (y0 - 1) + nxy * (z0 + hi4));
+      fyp = br_filter<KT>(A, fyp, hop, x0 + lo4 + nx * (y0 + BY) + nxy * (z0 + hi4));
+      fzm = br_filter<KT>(A, fzm, hop, x0 + lo4 + nx * (y0 + hi4) + nxy * (z0 - 1));
+      fzp = br_filter<KT>(A, fzp, hop, x0 + lo4 + nx * (y0 + hi4) + nxy * (z0 + BZ));
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int loc = i * kBRThreads + t;
@@ -1173,8 +1251,8 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     // statement so that the store addresses are recomputed here instead of
     // being kept live (in registers) from the loads at the top across the
     // sweeps.
-    // A narrow key of distance D or more flags the pass (changed keys are
-    // reached, so never all ones).
+    // A narrow key of distance D or more flags the pass (all ones is
+    // unreached: stored by the fused reset, it flags nothing).
     int tt = t;
     asm volatile("" : "+v"(tt));
     bool far = false;
@@ -1182,9 +1260,9 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
     for (int i = 0; i < 16; ++i) {
       const int loc = i * kBRThreads + tt;
       const int lx = loc & 15, row = loc >> 4;
-      if ((chg[row] >> lx) & 1u) {
+      if (fuse || ((chg[row] >> lx) & 1u)) {
         const KT k = K[br_at(lx, row)];
-        if (sizeof(KT) == 4) far |= (uint32_t)k >= A.lim32;
+        if (sizeof(KT) == 4) far |= (uint32_t)k >= A.lim32 && k != kInf;
         key[(size_t)b * kB + loc] = k;
         if (lx == 0) xface[(size_t)b * 512 + row] = k;
         if (lx == BX - 1) xface[(size_t)b * 512 + 256 + row] = k;
@@ -1831,7 +1909,8 @@ int32_t capture_rounds(hipGraphExec_t *exec, F launch_round) {
 struct VTState {
   uint32_t levels = 0;      // levels of the last full pass
   uint32_t inc_levels = 0;  // levels of the first run of the last incremental pass
-  uint32_t br_rounds = 0;   // rounds of the last brick relaxation pass
+  uint32_t br_rounds = 0;   // rounds of the last full brick relaxation pass
+  uint32_t br_rounds_inc = 0;  // rounds of the last incremental one
   hipGraphExec_t br_graph = nullptr;  // kGraphRounds relaxation rounds of this call's workspace (narrow keys)
   hipGraphExec_t br_graph_w = nullptr;  // the same with wide keys
   bool keys_set = false;    // the key width of the brick relaxation is chosen at its first pass
@@ -2238,6 +2317,8 @@ uint32_t narrow_id_bits(uint32_t S) {
 // id field, 0: wide keys.
 BRArgs br_args(const Geom &g, CvtWork &W, uint32_t id_bits) {
   BRArgs A;
+  A.moved = nullptr;
+  A.fsites = nullptr;
   A.hop32 = id_bits ? 1u << id_bits : 0u;
   A.idmask = id_bits ? (1u << id_bits) - 1u : 0xFFFFFFFFu;
   A.lim32 = id_bits ? (uint32_t)(((uint64_t)1 << 32) - ((uint64_t)2 << id_bits)) : 0u;
@@ -2268,6 +2349,8 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
                  bool inc, hipStream_t s, const Fuse *fz, bool *far) {
   const VTGrid bg = vt_grid(g);
   BRArgs A = br_args(g, W, sizeof(KT) == 4 ? st.id_bits : 0u);
+  A.moved = W.moved;
+  A.fsites = sites;
   constexpr KT kInf = BRKey<KT>::inf;
   int32_t rc;
   const int64_t nkeys = bg.nbricks * kRows * BX;
@@ -2278,8 +2361,21 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
     if ((rc = fill<KT>(static_cast<KT *>(A.key), nkeys, kInf, s))) return rc;
     if ((rc = fill<KT>(static_cast<KT *>(A.xface), bg.nbricks * 512, kInf, s))) return rc;
   } else {
-    hipLaunchKernelGGL(k_br_reset<KT>, dim3((unsigned)std::min<int64_t>((nkeys + 255) / 256, 65535)), dim3(256), 0,
-                       s, W.moved, A);
+    hipLaunchKernelGGL(k_count_moved, dim3(std::min<uint32_t>((S + 255) / 256, 256) + (S == 0)), dim3(256), 0, s,
+                       W.moved, S, W.ctl + 1);
+    // The separate reset reads every key and lets round 1 work on the bricks
+    // that hold reset voxels; the fused one costs about 1.5 rounds over
+    // every brick.  A cube of the mean cell volume n / S overlaps about
+    // (edge / 16 + 1)^3 bricks; the moved sites' voxels were measured to
+    // touch about three times that many (on the flame workload a separate
+    // reset's first round still worked on nearly every brick with 5-10 % of
+    // the sites moved), so the fused reset is taken once the moved sites
+    // would cover about 80 % of the bricks by that estimate.
+    const double edge = std::cbrt((double)g.n / std::max<uint32_t>(S, 1u));
+    const double overlap = 3.0 * std::pow(edge / BX + 1.0, 3.0);
+    const uint32_t fuse_min = (uint32_t)std::min(0.8 * (double)bg.nbricks / overlap, 4294967295.0);
+    hipLaunchKernelGGL(k_br_reset_or_fuse<KT>, dim3((unsigned)std::min<int64_t>((nkeys + 255) / 256, 65535)),
+                       dim3(256), 0, s, W.moved, A, fuse_min, tuning(LSRVT_TUNE_RESET));
     LSRVT_LAUNCHED();
   }
   if (S) {
@@ -2303,7 +2399,8 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
     if (rc) return rc;
   }
   uint32_t r = 0;
-  int batch = st.br_rounds ? (int)st.br_rounds : kGraphRounds;
+  uint32_t &hint = inc ? st.br_rounds_inc : st.br_rounds;
+  int batch = hint ? (int)hint : inc ? 2 * kGraphRounds : kGraphRounds;
   uint32_t c[8];
   const int64_t max_rounds = 4 * g.n + 8;
   while (true) {
@@ -2332,7 +2429,7 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
   LSRVT_HIP(hipStreamSynchronize(s));
   uint32_t worked = 0;
   while (worked + 1 < nl && h[worked + 1]) ++worked;
-  st.br_rounds = worked;
+  hint = worked;
   static const bool debug_levels = getenv("LSRVT_DEBUG_LEVELS") != nullptr;
   if (debug_levels) {
     unsigned long long d[2];
@@ -2987,9 +3084,9 @@ extern "C" int32_t lsrvt_update_noalloc(const uint32_t *d_cell, lsrvt_dims dims,
 
 namespace lsrvt {
 namespace {
-thread_local int32_t t_tuning[4] = {0, 0, 0, 0};
+thread_local int32_t t_tuning[5] = {0, 0, 0, 0, 0};
 }  // namespace
-int32_t tuning(int32_t knob) { return knob > 0 && knob < 4 ? t_tuning[knob] : 0; }
+int32_t tuning(int32_t knob) { return knob > 0 && knob < 5 ? t_tuning[knob] : 0; }
 }  // namespace lsrvt
 
 extern "C" int32_t lsrvt_set_tuning(int32_t knob, int32_t value) {
@@ -2999,6 +3096,8 @@ extern "C" int32_t lsrvt_set_tuning(int32_t knob, int32_t value) {
     if (value != 0 && value != 1 && value != 2 && value != 4) return -1;
   } else if (knob == LSRVT_TUNE_KEY_BITS) {
     if (value != 64 && (value < 0 || value > 30)) return -1;
+  } else if (knob == LSRVT_TUNE_RESET) {
+    if (value < 0 || value > 2) return -1;
   } else {
     return -1;
   }

@@ -140,4 +140,7 @@ def test_set_tuning_validation_without_gpu(lib):
     assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 64) == 0
     assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 30) == 64
     assert lib.lsrvt_set_tuning(L.TUNE_KEY_BITS, 0) == 30
-    assert lib.lsrvt_set_tuning(4, 0) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_RESET, 3) == -1
+    assert lib.lsrvt_set_tuning(L.TUNE_RESET, 2) == 0
+    assert lib.lsrvt_set_tuning(L.TUNE_RESET, 0) == 2
+    assert lib.lsrvt_set_tuning(5, 0) == -1

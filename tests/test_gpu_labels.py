@@ -256,6 +256,30 @@ def test_cvt_every_key_width(bits):
         L.lsrvt_set_vt_engine(prev_e)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("bits", [0, 64])
+def test_cvt_every_reset_mode(mode, bits):
+    """Incremental relaxation passes that reset the moved sites' voxels by
+    their own kernel, or in the first round as it reads them, with narrow
+    and wide keys: the oracle's Lloyd loop bit for bit.  Two volumes: a
+    weighted one with three isovalues (about 200 voxels per site) and an
+    unweighted one with one isovalue and wider cells (about 900)."""
+    prev_e = L.lsrvt_set_vt_engine(L.VT_BRICKS)
+    prev = L.lsrvt_set_tuning(L.TUNE_RESET, mode)
+    prev_b = L.lsrvt_set_tuning(L.TUNE_KEY_BITS, bits)
+    try:
+        f = _field((48, 40, 70), 13)
+        iso = synth.quantile_isovalues(f, [0.25, 0.5, 0.75])
+        _cvt_case(f, iso, synth.gradient_weight(f), 200.0, 13, 5)
+        f = _field((33, 47, 29), 14)
+        iso = synth.quantile_isovalues(f, [0.5])
+        _cvt_case(f, iso, None, 900.0, 14, 4)
+    finally:
+        L.lsrvt_set_tuning(L.TUNE_KEY_BITS, prev_b)
+        L.lsrvt_set_tuning(L.TUNE_RESET, prev)
+        L.lsrvt_set_vt_engine(prev_e)
+
+
 def test_update_and_loop_with_every_voxel_a_site():
     """More distinct cells than the LDS tables of the centroid sums hold
     (512 per 64x8x8 tile in lsrvt_update, 256 per 16^3 brick in the sums a
