@@ -13,7 +13,8 @@ changes what is computed):
 * the launch shapes (``lsrvt_set_tuning``): the workgroups of a relaxation
   round (each walks the round's 16^3 bricks with that stride) and the tile
   the statistics stage in LDS per round (1, 2 or 4 voxels per thread), each
-  tuned per job class by timing one Voronoi pass or one statistics call.
+  tuned per job class by timing a short Lloyd loop (or one Voronoi pass)
+  or one statistics call.
 
 A job class is (GPU name, log2 of the voxel count, log2 of voxels per site,
 band count bucket).  Results are kept in a JSON file (``LSRVT_AUTOTUNE_CACHE``,
@@ -192,22 +193,33 @@ def _time(fn, reps: int = 2) -> float:
     return (time.perf_counter() - t0) / reps
 
 
-def br_grid(band, sites, n_bands: int, candidates=(1024, 2048, 4096, 8192), tune: bool = True) -> int | None:
+def br_grid(band, sites, n_bands: int, candidates=(1024, 2048, 4096, 8192), tune: bool = True, comp=None,
+            weights=None, iters: int = 2) -> int | None:
     """Workgroups per relaxation round for this job class: cached, or
-    measured now (one Voronoi pass by brick relaxation with each)."""
+    measured now with each candidate by brick relaxation — a short Lloyd
+    loop (`iters` updates: one full pass, then incremental ones, which
+    dominate a long loop) when the components `comp` are given, else one
+    Voronoi pass."""
     key = "brgrid:" + job_class(tuple(band.shape), int(sites.numel()), n_bands)
     hit = _cached(key)
     if hit is not None:
         return int(hit["grid"])
     if not tune:
         return None
+    from . import lsrvt_cvt
+    if comp is not None:
+        def run():
+            lsrvt_cvt(band, comp, sites, weights, iters, want_mean_ds=False)
+    else:
+        def run():
+            lsrvt_vt(band, sites)
     prev_e = lsrvt_set_vt_engine(VT_BRICKS)
     times = {}
     try:
         for gsz in candidates:
             prev = lsrvt_set_tuning(TUNE_BR_GRID, gsz)
             try:
-                times[gsz] = _time(lambda: lsrvt_vt(band, sites))
+                times[gsz] = _time(run)
             finally:
                 lsrvt_set_tuning(TUNE_BR_GRID, prev)
     finally:

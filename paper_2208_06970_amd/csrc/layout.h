@@ -25,9 +25,10 @@ struct LayoutWork {
   uint32_t *cell_off;       // [S + 1] start of every cell, by rank
   uint32_t *tile_nd;        // [T] distinct cells per tile
   uint32_t *pair_off;       // [T + 1] first (tile, cell) pair of every tile
-  uint8_t *tile_big;        // [T] walked by the whole-tile kernel
-  uint32_t *big_list;       // [T]
-  uint32_t *big_cnt;        // [4]
+  uint8_t *tile_big;        // [T] 0: small table, 1: medium table, 2: whole-tile table
+  uint32_t *big_list;       // [T] tiles deferred by the small table
+  uint32_t *huge_list;      // [T] tiles deferred by the medium table
+  uint32_t *big_cnt;        // [4] [0] big_list length, [1] huge_list length
   uint32_t *pair_cell;      // [Pcap] cell of every pair, then reused
   uint32_t *pair_cnt;       // [Pcap] voxels of every pair, then segment starts
   uint32_t *val_a, *val_b;  // [Pcap + 1] pair sort ping-pong / scan output
@@ -68,6 +69,7 @@ void layout_take(A &a, const Geom &g, uint32_t S, uint32_t C, LayoutWork *W) {
   auto pair_off = a.template take<uint32_t>(T + 1);
   auto tile_big = a.template take<uint8_t>(T);
   auto big_list = a.template take<uint32_t>(T);
+  auto huge_list = a.template take<uint32_t>(T);
   auto big_cnt = a.template take<uint32_t>(4);
   auto pair_cell = a.template take<uint32_t>(P);
   auto pair_cnt = a.template take<uint32_t>(P);
@@ -90,6 +92,7 @@ void layout_take(A &a, const Geom &g, uint32_t S, uint32_t C, LayoutWork *W) {
     W->pair_off = pair_off;
     W->tile_big = tile_big;
     W->big_list = big_list;
+    W->huge_list = huge_list;
     W->big_cnt = big_cnt;
     W->pair_cell = pair_cell;
     W->pair_cnt = pair_cnt;

@@ -17,16 +17,22 @@
 // sizes gives every segment's start.  A last walk writes each voxel to its
 // segment start plus the number of earlier voxels of its cell in the tile.
 // Tiles with more distinct cells than the common kernel's table holds are
-// listed and walked by a kernel whose table covers a whole tile.
+// listed and walked with a medium table, and those that overflow it by a
+// kernel whose table covers a whole tile.
 #include "layout.h"
 
 namespace lsrvt {
 
 namespace {
 
-constexpr int kLayHalf = 2048;  // voxels staged in LDS at a time
+// Three table sizes: tiles with at most 256 distinct cells (almost all) are
+// walked with a small table, so many waves fit a CU; a tile with more is
+// deferred to a medium table (640), and from there to one that covers a
+// whole tile.
 constexpr int kSmallCap = 512, kSmallMax = 256;
+constexpr int kMidCap = 1024, kMidMax = 640;
 constexpr int kBigCap = kLayTile, kBigMax = kLayTile;
+constexpr int kLayAhead = 4;  // 64-voxel groups whose cells are loaded ahead of the walk
 
 enum { kPassCount = 0, kPassPairs = 1, kPassPlace = 2 };
 
@@ -35,7 +41,6 @@ struct TileTab {
   uint32_t key[Cap];    // cell id, kNone = empty
   uint32_t slot[Cap];   // order of first appearance in the tile
   uint32_t val[MaxD];   // per slot: running voxel count or next output index
-  uint32_t stage[kLayHalf];
 };
 
 struct LayArgs {
@@ -45,16 +50,20 @@ struct LayArgs {
   int64_t n_tiles;
   unsigned long long *cnt;
   uint32_t *tile_nd;
-  uint8_t *tile_big;
-  uint32_t *big_list, *big_cnt;
+  uint8_t *tile_big;    // 0: small table, 1: medium, 2: whole-tile table
+  uint32_t *big_list;   // tiles deferred by the small table
+  uint32_t *huge_list;  // tiles deferred by the medium table
+  uint32_t *big_cnt;    // [0] big_list length, [1] huge_list length
   const uint32_t *pair_off;
   uint32_t *pair_cell, *pair_cnt;
   const uint32_t *seg_off;
   uint32_t *perm;
 };
 
-// One wave walks one tile.  Returns false (and has no side effects in the
-// count and pair passes) when the tile has more than MaxD distinct cells.
+// One wave walks one tile, 64 voxels at a time, with the cells of the next
+// kLayAhead groups loaded while the current ones are walked.  Returns false
+// (and has no side effects in the count and pair passes) when the tile has
+// more than MaxD distinct cells.
 template <int Cap, int MaxD, int Pass>
 __device__ bool lay_walk(const LayArgs &A, int64_t tile, TileTab<Cap, MaxD> &T, uint32_t &nd_out) {
   const int lane = threadIdx.x;
@@ -65,19 +74,25 @@ __device__ bool lay_walk(const LayArgs &A, int64_t tile, TileTab<Cap, MaxD> &T, 
     const uint32_t p0 = A.pair_off[tile], np = A.pair_off[tile + 1] - p0;
     for (uint32_t i = lane; i < np && i < (uint32_t)MaxD; i += kWave) T.val[i] = A.seg_off[p0 + i];
   }
+  __syncthreads();
+  auto load = [&](int g) {
+    const int64_t v = v0 + g + lane;
+    const uint32_t c = v < A.n ? A.cell[v] : kNone;
+    return c < A.S ? c : kNone;
+  };
+  uint32_t cur[kLayAhead], nxt[kLayAhead];
+#pragma unroll
+  for (int j = 0; j < kLayAhead; ++j) cur[j] = load(j * kWave);
   uint32_t nd = 0, last_c = kNone, last_s = 0;
-  for (int half = 0; half < kLayTile / kLayHalf; ++half) {
-    const int64_t h0 = v0 + (int64_t)half * kLayHalf;
-    __syncthreads();
-#pragma unroll 8
-    for (int i = lane; i < kLayHalf; i += kWave) {
-      const int64_t v = h0 + i;
-      const uint32_t c = v < A.n ? A.cell[v] : kNone;
-      T.stage[i] = c < A.S ? c : kNone;
+  for (int g0 = 0; g0 < kLayTile; g0 += kLayAhead * kWave) {
+    if (g0 + kLayAhead * kWave < kLayTile) {
+#pragma unroll
+      for (int j = 0; j < kLayAhead; ++j) nxt[j] = load(g0 + (kLayAhead + j) * kWave);
     }
-    __syncthreads();
-    for (int g = 0; g < kLayHalf; g += kWave) {
-      const uint32_t c = T.stage[g + lane];
+#pragma unroll
+    for (int j = 0; j < kLayAhead; ++j) {
+      const int g = g0 + j * kWave;
+      const uint32_t c = cur[j];
       uint64_t rem = __ballot(c != kNone);
       while (rem) {
         const int leader = __ffsll((unsigned long long)rem) - 1;
@@ -111,26 +126,31 @@ __device__ bool lay_walk(const LayArgs &A, int64_t tile, TileTab<Cap, MaxD> &T, 
         }
         const uint32_t base = T.val[sl];
         if (Pass == kPassPlace && ((mask >> lane) & 1ull))
-          A.perm[base + (uint32_t)__popcll(mask & lanemask_lt())] = (uint32_t)(h0 + g + lane);
+          A.perm[base + (uint32_t)__popcll(mask & lanemask_lt())] = (uint32_t)(v0 + g + lane);
         T.val[sl] = base + (uint32_t)__popcll(mask);
       }
     }
+#pragma unroll
+    for (int j = 0; j < kLayAhead; ++j) cur[j] = nxt[j];
   }
   nd_out = nd;
   return true;
 }
 
-template <int Cap, int MaxD, int Pass>
-__device__ void lay_tile(const LayArgs &A, int64_t tile, TileTab<Cap, MaxD> &T, bool can_defer) {
+// Level 0 (small table) defers a tile to big_list, level 1 (medium) to
+// huge_list; level 2 cannot fail.  Only the count pass defers; the later
+// passes skip deferred tiles up front.
+template <int Cap, int MaxD, int Pass, int Level>
+__device__ void lay_tile(const LayArgs &A, int64_t tile, TileTab<Cap, MaxD> &T) {
   uint32_t nd = 0;
   const bool ok = lay_walk<Cap, MaxD, Pass>(A, tile, T, nd);
   __syncthreads();
   if (!ok) {
-    // only the count pass defers; the later passes skip deferred tiles up front
-    if (Pass == kPassCount && can_defer && threadIdx.x == 0) {
-      A.tile_big[tile] = 1;
+    if (Pass == kPassCount && Level < 2 && threadIdx.x == 0) {
+      A.tile_big[tile] = (uint8_t)(Level + 1);
       A.tile_nd[tile] = 0;
-      A.big_list[atomicAdd(A.big_cnt, 1u)] = (uint32_t)tile;
+      if (Level == 0) A.big_list[atomicAdd(&A.big_cnt[0], 1u)] = (uint32_t)tile;
+      else A.huge_list[atomicAdd(&A.big_cnt[1], 1u)] = (uint32_t)tile;
     }
     return;
   }
@@ -141,7 +161,7 @@ __device__ void lay_tile(const LayArgs &A, int64_t tile, TileTab<Cap, MaxD> &T, 
     }
     if (threadIdx.x == 0) {
       A.tile_nd[tile] = nd;
-      if (can_defer) A.tile_big[tile] = 0;
+      A.tile_big[tile] = (uint8_t)Level;
     }
   } else if (Pass == kPassPairs) {
     const uint32_t p0 = A.pair_off[tile];
@@ -160,7 +180,19 @@ __global__ __launch_bounds__(kWave) void k_lay_small(LayArgs A) {
   __shared__ TileTab<kSmallCap, kSmallMax> T;
   for (int64_t tile = blockIdx.x; tile < A.n_tiles; tile += gridDim.x) {
     if (Pass != kPassCount && A.tile_big[tile]) continue;
-    lay_tile<kSmallCap, kSmallMax, Pass>(A, tile, T, true);
+    lay_tile<kSmallCap, kSmallMax, Pass, 0>(A, tile, T);
+    __syncthreads();
+  }
+}
+
+template <int Pass>
+__global__ __launch_bounds__(kWave) void k_lay_mid(LayArgs A) {
+  __shared__ TileTab<kMidCap, kMidMax> T;
+  const uint32_t nb = A.big_cnt[0];
+  for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    const uint32_t tile = A.big_list[i];
+    if (Pass != kPassCount && A.tile_big[tile] != 1) continue;
+    lay_tile<kMidCap, kMidMax, Pass, 1>(A, tile, T);
     __syncthreads();
   }
 }
@@ -168,9 +200,9 @@ __global__ __launch_bounds__(kWave) void k_lay_small(LayArgs A) {
 template <int Pass>
 __global__ __launch_bounds__(kWave) void k_lay_big(LayArgs A) {
   __shared__ TileTab<kBigCap, kBigMax> T;
-  const uint32_t nb = *A.big_cnt;
+  const uint32_t nb = A.big_cnt[1];
   for (uint32_t i = blockIdx.x; i < nb; i += gridDim.x) {
-    lay_tile<kBigCap, kBigMax, Pass>(A, A.big_list[i], T, false);
+    lay_tile<kBigCap, kBigMax, Pass, 2>(A, A.huge_list[i], T);
     __syncthreads();
   }
 }
@@ -267,7 +299,7 @@ int32_t layout_sites(const uint32_t *site_comp, uint32_t S, uint32_t C, LayoutWo
 int32_t layout_voxels(const uint32_t *cell, const Geom &g, uint32_t S, LayoutWork &W, uint32_t *perm, hipStream_t s) {
   int32_t rc;
   if ((rc = fill<unsigned long long>(W.cnt, S ? S : 1, 0ull, s))) return rc;
-  if ((rc = fill<uint32_t>(W.big_cnt, 1, 0u, s))) return rc;
+  if ((rc = fill<uint32_t>(W.big_cnt, 2, 0u, s))) return rc;
   if (S == 0) return fill<uint32_t>(W.cell_off, 1, 0u, s);
   const int64_t T = W.n_tiles;
   LayArgs A;
@@ -279,6 +311,7 @@ int32_t layout_voxels(const uint32_t *cell, const Geom &g, uint32_t S, LayoutWor
   A.tile_nd = W.tile_nd;
   A.tile_big = W.tile_big;
   A.big_list = W.big_list;
+  A.huge_list = W.huge_list;
   A.big_cnt = W.big_cnt;
   A.pair_off = W.pair_off;
   A.pair_cell = W.pair_cell;
@@ -286,9 +319,10 @@ int32_t layout_voxels(const uint32_t *cell, const Geom &g, uint32_t S, LayoutWor
   A.seg_off = W.pair_cnt;  // segment starts replace the counts before the place pass
   A.perm = perm;
   const unsigned grid = (unsigned)(T < 65535 ? T : 65535);
-  const unsigned grid_big = 256;
+  const unsigned grid_mid = 2048, grid_big = 256;
   // 1. distinct cells per tile and voxels per site
   hipLaunchKernelGGL(k_lay_small<kPassCount>, dim3(grid), dim3(kWave), 0, s, A);
+  hipLaunchKernelGGL(k_lay_mid<kPassCount>, dim3(grid_mid), dim3(kWave), 0, s, A);
   hipLaunchKernelGGL(k_lay_big<kPassCount>, dim3(grid_big), dim3(kWave), 0, s, A);
   LSRVT_LAUNCHED();
   if ((rc = ScanU32::run(W.tile_nd, T, W.pair_off, W.scratch, W.scratch_bytes, s))) return rc;
@@ -300,6 +334,7 @@ int32_t layout_voxels(const uint32_t *cell, const Geom &g, uint32_t S, LayoutWor
   if ((int64_t)P > W.pair_cap) return LSRVT_EDEVICE;  // cannot happen: the capacity is an upper bound
   // 2. the pairs, in tile order
   hipLaunchKernelGGL(k_lay_small<kPassPairs>, dim3(grid), dim3(kWave), 0, s, A);
+  hipLaunchKernelGGL(k_lay_mid<kPassPairs>, dim3(grid_mid), dim3(kWave), 0, s, A);
   hipLaunchKernelGGL(k_lay_big<kPassPairs>, dim3(grid_big), dim3(kWave), 0, s, A);
   LSRVT_LAUNCHED();
   // 3. stable sort of the pairs by cell rank
@@ -327,6 +362,7 @@ int32_t layout_voxels(const uint32_t *cell, const Geom &g, uint32_t S, LayoutWor
     LSRVT_LAUNCHED();
     // 5. place every voxel
     hipLaunchKernelGGL(k_lay_small<kPassPlace>, dim3(grid), dim3(kWave), 0, s, A);
+    hipLaunchKernelGGL(k_lay_mid<kPassPlace>, dim3(grid_mid), dim3(kWave), 0, s, A);
     hipLaunchKernelGGL(k_lay_big<kPassPlace>, dim3(grid_big), dim3(kWave), 0, s, A);
     LSRVT_LAUNCHED();
   }

@@ -47,7 +47,7 @@ def test_layout_pipeline_fourier():
 
 def test_layout_many_cells_per_tile_ragged():
     # random labels: far more distinct cells per 4096-voxel tile than the
-    # common kernel's table holds, so every tile takes the whole-tile path
+    # small and medium tables hold, so every tile takes the whole-tile path
     rng = np.random.default_rng(5)
     shape = (3, 37, 113)  # 12543 voxels: three full tiles and a ragged one
     n = int(np.prod(shape))
@@ -74,6 +74,28 @@ def test_layout_mixed_tiles():
     comp_band = np.array([0, 0, 1, 1, 1, 2, 3, 3, 3, 3], dtype=np.uint8)
     banner(f"layout mixed tiles {shape}")
     _check(cell, site_comp, comp_band, 10, 4, shape)
+
+
+def test_layout_every_table_size():
+    """Tiles of 4096 voxels with 1, 256, 257, 400, 640, 641, 2000 and 4096
+    distinct cells: the small table (up to 256), the medium one (up to 640)
+    and the whole-tile one, at and across both limits; cells shared between
+    tiles, voxels of a tile in random order for half of them."""
+    rng = np.random.default_rng(17)
+    shape = (8, 64, 64)  # one tile per z-plane
+    S = 5000
+    parts = []
+    for k, d in enumerate([1, 256, 257, 400, 640, 641, 2000, 4096]):
+        local = (np.arange(4096) * d) // 4096
+        if k % 2:
+            local = rng.permutation(local)
+        parts.append(((local + 613 * k) % S).astype(np.uint32))
+    cell = np.concatenate(parts)
+    cell[rng.random(cell.size) < 0.02] = NONE
+    site_comp = np.sort(rng.integers(0, 12, size=S)).astype(np.uint32)
+    comp_band = np.sort(rng.integers(0, 4, size=12)).astype(np.uint8)
+    banner(f"layout every table size {shape}")
+    _check(cell, site_comp, comp_band, 12, 4, shape)
 
 
 def test_layout_edge_cases():
