@@ -2366,13 +2366,14 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
     // The separate reset reads every key and lets round 1 work on the bricks
     // that hold reset voxels; the fused one costs about 1.5 rounds over
     // every brick.  A cube of the mean cell volume n / S overlaps about
-    // (edge / 16 + 1)^3 bricks; the moved sites' voxels were measured to
-    // touch about three times that many (on the flame workload a separate
-    // reset's first round still worked on nearly every brick with 5-10 % of
-    // the sites moved), so the fused reset is taken once the moved sites
-    // would cover about 80 % of the bricks by that estimate.
+    // (edge / 16 + 1)^3 bricks; the first round after a separate reset was
+    // measured to work on far more (on the flame workload on nearly every
+    // brick with 3 % of the sites moved: the reset bricks, the sites' bricks
+    // and their neighbours), so eight times that count is taken, and the
+    // fused reset once the moved sites would cover about 80 % of the bricks
+    // by that estimate.
     const double edge = std::cbrt((double)g.n / std::max<uint32_t>(S, 1u));
-    const double overlap = 3.0 * std::pow(edge / BX + 1.0, 3.0);
+    const double overlap = 8.0 * std::pow(edge / BX + 1.0, 3.0);
     const uint32_t fuse_min = (uint32_t)std::min(0.8 * (double)bg.nbricks / overlap, 4294967295.0);
     hipLaunchKernelGGL(k_br_reset_or_fuse<KT>, dim3((unsigned)std::min<int64_t>((nkeys + 255) / 256, 65535)),
                        dim3(256), 0, s, W.moved, A, fuse_min, tuning(LSRVT_TUNE_RESET));
