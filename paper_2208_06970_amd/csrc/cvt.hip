@@ -797,6 +797,7 @@ __global__ __launch_bounds__(256) void k_wake_min(const uint32_t *__restrict__ w
 // has every distance below D and is exact.
 constexpr int kBRThreads = 256;
 constexpr int kBRRow = BX + 1;  // LDS row stride (keys): padding against bank conflicts
+constexpr int kGraphRounds = 8;  // relaxation rounds per captured graph
 
 struct BRArgs {
   Geom g;
@@ -983,8 +984,9 @@ __global__ __launch_bounds__(256) void k_br_reset_or_fuse(const uint8_t *__restr
 }
 
 
-// The bricks marked for round r, listed (one counter atomic per block).
-__device__ __forceinline__ void d_br_list(BRArgs A, uint32_t r) {
+// The bricks marked for round r, listed (one counter atomic per block on
+// *cnt, zero before the launch).
+__device__ __forceinline__ void d_br_list(BRArgs A, uint32_t r, uint32_t *cnt) {
   __shared__ uint32_t base_s;
   __shared__ uint32_t wcount[256 / kWave];
   const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
@@ -999,7 +1001,7 @@ __device__ __forceinline__ void d_br_list(BRArgs A, uint32_t r) {
     if (t == 0) {
       uint32_t tot = 0;
       for (int q = 0; q < 256 / kWave; ++q) tot += wcount[q];
-      base_s = tot ? atomicAdd(&A.ctl[0], tot) : 0u;
+      base_s = tot ? atomicAdd(cnt, tot) : 0u;
     }
     __syncthreads();
     uint32_t off = base_s;
@@ -1008,14 +1010,21 @@ __device__ __forceinline__ void d_br_list(BRArgs A, uint32_t r) {
     __syncthreads();
   }
 }
-// Start of a round: the list is emptied and the round number advanced.
-__global__ void k_br_next(BRArgs A) {
-  if (threadIdx.x == 0) {
-    A.ctl[0] = 0u;
-    *A.rnd += 1u;
-  }
+// Rounds are replayed from a graph of kGraphRounds rounds: the round at
+// position i of a replay is *rnd + 1 + i, and the graph's last kernel
+// advances *rnd by kGraphRounds.  Round r's list length is counted in
+// ctl[0] (odd r) or ctl[12] (even r); round r empties the counter of round
+// r + 1 (nobody else touches it while round r runs).
+__device__ __forceinline__ uint32_t *br_count(const BRArgs &A, uint32_t r) {
+  return (r & 1u) ? &A.ctl[0] : &A.ctl[12];
 }
-__global__ __launch_bounds__(256) void k_br_list(BRArgs A) { d_br_list(A, *A.rnd); }
+__global__ void k_br_advance(BRArgs A) {
+  if (threadIdx.x == 0) *A.rnd += (uint32_t)kGraphRounds;
+}
+__global__ __launch_bounds__(256) void k_br_list(BRArgs A, int32_t i) {
+  const uint32_t r = *A.rnd + 1u + (uint32_t)i;
+  d_br_list(A, r, br_count(A, r));
+}
 
 
 __device__ __forceinline__ int br_at(int lx, int row) { return row * kBRRow + lx; }
@@ -1285,11 +1294,14 @@ __device__ __forceinline__ void br_process(const BRArgs &A, int64_t b, uint32_t 
 }
 
 template <class KT>
-__global__ __launch_bounds__(kBRThreads, sizeof(KT) == 4 ? 5 : 4) void k_br_round(BRArgs A) {
+__global__ __launch_bounds__(kBRThreads, sizeof(KT) == 4 ? 5 : 4) void k_br_round(BRArgs A, int32_t i) {
   __shared__ BRLds<KT> L;
-  const uint32_t r = *A.rnd;
-  const uint32_t count = A.ctl[0];
-  if (blockIdx.x == 0 && threadIdx.x == 0) A.hist[r % kHistLen] = count;  // bricks that work in round r
+  const uint32_t r = *A.rnd + 1u + (uint32_t)i;
+  const uint32_t count = *br_count(A, r);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    A.hist[r % kHistLen] = count;  // bricks that work in round r
+    *br_count(A, r + 1u) = 0u;
+  }
   for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) br_process<KT>(A, A.list[item], r, L);
 }
 
@@ -1871,12 +1883,7 @@ int32_t carve_cvt(void *d_work, size_t bytes, const Geom &g, uint32_t S, int32_t
   return cv.ok ? LSRVT_OK : LSRVT_EWORKSPACE;
 }
 
-// Driver state of one Lloyd run: the number of levels of the previous pass,
-// which sizes the first batch of level launches of the next one.
-// Rounds per graph of relaxation rounds.
-constexpr int kGraphRounds = 8;
-
-// Captures kGraphRounds calls of launch_round(stream) into an executable
+// Captures kGraphRounds calls of launch_round(stream, position) into an executable
 // graph (kernel nodes only: nothing is cleared by memset).  The capture runs
 // on a stream of its own (the caller's may be the null stream, which cannot
 // be captured); the graph is then launched on the caller's stream.
@@ -1890,7 +1897,7 @@ int32_t capture_rounds(hipGraphExec_t *exec, F launch_round) {
     hipStreamDestroy(cs);
     return LSRVT_EDEVICE;
   }
-  for (int i = 0; i < kGraphRounds && rc == LSRVT_OK; ++i) rc = launch_round(cs);
+  for (int i = 0; i < kGraphRounds && rc == LSRVT_OK; ++i) rc = launch_round(cs, i);
   const hipError_t e = hipStreamEndCapture(cs, &graph);
   hipStreamDestroy(cs);
   if (rc != LSRVT_OK || e != hipSuccess) {
@@ -1906,6 +1913,9 @@ int32_t capture_rounds(hipGraphExec_t *exec, F launch_round) {
   return LSRVT_OK;
 }
 
+// Driver state of one Lloyd run: the levels or rounds of the previous
+// passes, which size the first batch of launches of the next one, and the
+// captured graphs of relaxation rounds.
 struct VTState {
   uint32_t levels = 0;      // levels of the last full pass
   uint32_t inc_levels = 0;  // levels of the first run of the last incremental pass
@@ -2386,14 +2396,14 @@ int32_t run_br_k(const Geom &g, const uint32_t *sites, uint32_t S, uint32_t *cel
   const unsigned lgrid = (unsigned)std::min<int64_t>((bg.nbricks + 255) / 256, 4096);
   const int32_t tg = tuning(LSRVT_TUNE_BR_GRID);
   const unsigned rgrid = (unsigned)std::min<int64_t>(bg.nbricks, tg ? tg : 2048);
-  // kGraphRounds rounds (three launches each) captured once per call and
-  // replayed as one graph launch
+  // kGraphRounds rounds (two launches each, and one that advances the
+  // round base) captured once per call and replayed as one graph launch
   hipGraphExec_t &graph = sizeof(KT) == 4 ? st.br_graph : st.br_graph_w;
   if (!graph) {
-    rc = capture_rounds(&graph, [&](hipStream_t cs) -> int32_t {
-      hipLaunchKernelGGL(k_br_next, dim3(1), dim3(64), 0, cs, A);
-      hipLaunchKernelGGL(k_br_list, dim3(lgrid), dim3(256), 0, cs, A);
-      hipLaunchKernelGGL(k_br_round<KT>, dim3(rgrid), dim3(kBRThreads), 0, cs, A);
+    rc = capture_rounds(&graph, [&](hipStream_t cs, int i) -> int32_t {
+      hipLaunchKernelGGL(k_br_list, dim3(lgrid), dim3(256), 0, cs, A, (int32_t)i);
+      hipLaunchKernelGGL(k_br_round<KT>, dim3(rgrid), dim3(kBRThreads), 0, cs, A, (int32_t)i);
+      if (i == kGraphRounds - 1) hipLaunchKernelGGL(k_br_advance, dim3(1), dim3(64), 0, cs, A);
       LSRVT_LAUNCHED();
       return LSRVT_OK;
     });
@@ -2608,7 +2618,7 @@ __global__ void kb_round_prep(const JobDev *J) {
 __global__ __launch_bounds__(256) void kb_list(const JobDev *J) {
   const JobDev &j = J[blockIdx.y];
   if ((int32_t)j.A.alive[4] > j.iters) return;
-  d_br_list(j.A, j.A.alive[3]);
+  d_br_list(j.A, j.A.alive[3], &j.A.ctl[0]);
 }
 
 // The round's work list of the whole batch: the jobs' lists back to back,
@@ -2754,7 +2764,7 @@ int32_t batch_loop(const BatchCtx &c, int32_t *status, bool *far, hipStream_t s)
   // kGraphRounds rounds of every job captured once and replayed as one graph launch
   VTState gs;
   uint32_t *offs = c.offs;
-  rc = capture_rounds(&gs.br_graph, [&](hipStream_t cs) -> int32_t {
+  rc = capture_rounds(&gs.br_graph, [&](hipStream_t cs, int) -> int32_t {
     hipLaunchKernelGGL(kb_round_prep, dim3(1, N), dim3(64), 0, cs, dj);
     hipLaunchKernelGGL(kb_list, dim3(g_list, N), dim3(256), 0, cs, dj);
     hipLaunchKernelGGL(kb_offsets, dim3(1), dim3(1024), 0, cs, dj, n, offs);
