@@ -521,9 +521,10 @@ int32_t lsrvt_los_cvt(const uint32_t *d_comp, lsrvt_dims dims, const uint32_t *d
 int32_t lsrvt_set_vt_engine(int32_t engine);
 
 /* ------------------------------------------------------------------------
- * Launch shapes of the calling host thread's later calls (none of them
- * changes what is computed; the autotuner of the Python package picks them
- * per job class by measurement):
+ * Launch shapes and schedule choices of the calling host thread's later
+ * calls (none of them changes what is computed; the autotuner of the Python
+ * package picks the two launch shapes per job class by measurement, the
+ * other two are for tests and experiments):
  *   LSRVT_TUNE_BR_GRID      workgroups of each brick-relaxation round
  *                           (each walks the round's bricks with that stride):
  *                           256 .. 16384, 0 = the library's choice (2048)
