@@ -243,7 +243,7 @@ def bench_flame(args):
     # launch shapes for this job class, tuned before timing (cached on disk)
     from paper_2208_06970_amd import autotune
     _log("flame: tuning launch shapes")
-    grid = autotune.br_grid(band, sd, wl.n_bands)
+    grid = autotune.br_grid(band, sd, wl.n_bands, comp=cc.comp, weights=w)
     r1 = L.lsrvt_cvt(band, cc.comp, sd, w, 1, want_mean_ds=False)
     tile = autotune.stats_tile(tuple(band.shape), len(seeds), wl.n_bands, int(x.shape[0]),
                                lambda: L.lsrvt_aggregate(r1.cell, r1.sites, r1.site_comp, cc.comp_band, cc.n_comp,
