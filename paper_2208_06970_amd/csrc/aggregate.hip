@@ -184,7 +184,8 @@ __global__ __launch_bounds__(kAggMaxThreads) void k_agg_cell(CellArgs A) {
   const int m = A.m, B = A.B, U = A.U, G = A.G, TL = A.tile, ld = A.tile + 4;
   const int NT = blockDim.x;
   float *dv = reinterpret_cast<float *>(smem);                       // [m][TL + 4] values minus the site value
-  uint32_t *hist_l = reinterpret_cast<uint32_t *>(dv + m * ld);      // [m*B]
+  float *ones = dv + m * ld;                                         // [TL + 4] 1.0: the second factor of Σd
+  uint32_t *hist_l = reinterpret_cast<uint32_t *>(ones + ld);        // [m*B]
   uint32_t *kmin_l = hist_l + m * B;                                 // [m]
   uint32_t *kmax_l = kmin_l + m;                                     // [m]
   float *K = reinterpret_cast<float *>(kmax_l + m);                  // [m]
@@ -199,6 +200,7 @@ __global__ __launch_bounds__(kAggMaxThreads) void k_agg_cell(CellArgs A) {
     for (int i = t; i < m * (B + 1); i += NT) edg[i] = A.edges[i];
     for (int j = t; j < m; j += NT) scl[j] = (float)B / (A.edges[j * (B + 1) + B] - A.edges[j * (B + 1)]);
   }
+  for (int i = t; i < ld; i += NT) ones[i] = 1.0f;
 
   const uint32_t n_list = *A.list_cnt;
   for (uint32_t k = blockIdx.x; k < n_list; k += gridDim.x) {
@@ -271,38 +273,37 @@ __global__ __launch_bounds__(kAggMaxThreads) void k_agg_cell(CellArgs A) {
         const int u = R == 1 ? t % U : t + q * NT;
         const bool worker = R == 1 ? t < G * U : u < U;
         if (!worker) continue;
+        // every unit sums products: Σd_j d_k, and Σd_j as d_j times a row of
+        // ones (d·1 is d exactly and its product error 0, so the sum is the
+        // one of d itself; only a d of ±inf, |x - x_site| beyond the float
+        // range, would give NaN instead of ±inf), so the lanes of a wave
+        // take one path
+        const float *dj, *dk;
         if (u < m) {
-          const float *du = dv + u * ld;
-          int v = v0;
-          for (; v + 4 <= v1; v += 4) {
-            const float4 a = *reinterpret_cast<const float4 *>(du + v);
-            acc(hi[q], lo[q], a.x, 0.0f);
-            acc(hi[q], lo[q], a.y, 0.0f);
-            acc(hi[q], lo[q], a.z, 0.0f);
-            acc(hi[q], lo[q], a.w, 0.0f);
-          }
-          for (; v < v1; ++v) acc(hi[q], lo[q], du[v], 0.0f);
+          dj = dv + u * ld;
+          dk = ones;
         } else {
           const int p = u - m;
-          const float *dj = dv + A.pairs.j[p] * ld, *dk = dv + A.pairs.k[p] * ld;
-          int v = v0;
-          for (; v + 4 <= v1; v += 4) {
-            const float4 a = *reinterpret_cast<const float4 *>(dj + v);
-            const float4 b = *reinterpret_cast<const float4 *>(dk + v);
-            const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+          dj = dv + A.pairs.j[p] * ld;
+          dk = dv + A.pairs.k[p] * ld;
+        }
+        int v = v0;
+        for (; v + 4 <= v1; v += 4) {
+          const float4 a = *reinterpret_cast<const float4 *>(dj + v);
+          const float4 b = *reinterpret_cast<const float4 *>(dk + v);
+          const float av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const float pr = av[i] * bv[i];
-              const float pe = __builtin_fmaf(av[i], bv[i], -pr);  // exact error of the product
-              acc(hi[q], lo[q], pr, pe);
-            }
-          }
-          for (; v < v1; ++v) {
-            const float a0 = dj[v], b0 = dk[v];
-            const float pr = a0 * b0;
-            const float pe = __builtin_fmaf(a0, b0, -pr);
+          for (int i = 0; i < 4; ++i) {
+            const float pr = av[i] * bv[i];
+            const float pe = __builtin_fmaf(av[i], bv[i], -pr);  // exact error of the product
             acc(hi[q], lo[q], pr, pe);
           }
+        }
+        for (; v < v1; ++v) {
+          const float a0 = dj[v], b0 = dk[v];
+          const float pr = a0 * b0;
+          const float pe = __builtin_fmaf(a0, b0, -pr);
+          acc(hi[q], lo[q], pr, pe);
         }
       }
       __syncthreads();
@@ -1080,12 +1081,12 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     int vpt = kMaxVPT;
     for (; vpt >= 1; vpt /= 2) {
       A.tile = vpt * NT;
-      lds = fixed + sizeof(float) * (size_t)m * (A.tile + 4);
+      lds = fixed + sizeof(float) * (size_t)(m + 1) * (A.tile + 4);
       if (lds <= 40960 || vpt == 1) break;
     }
     const int32_t tv = tuning(LSRVT_TUNE_STATS_TILE);  // a tuned round size, if it fits in 64 KiB
     if (tv) {
-      const size_t l2 = fixed + sizeof(float) * (size_t)m * ((size_t)tv * NT + 4);
+      const size_t l2 = fixed + sizeof(float) * (size_t)(m + 1) * ((size_t)tv * NT + 4);
       if (l2 <= 65536) {
         vpt = tv;
         A.tile = vpt * NT;
