@@ -362,7 +362,8 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell_wave(CellArgs A) {
   const int m = A.m, B = A.B, U = A.U, G = A.G, ld = kSmallCell + 1;
   const int wid = threadIdx.x / kWave, lane = lane_id();
   float *edg = reinterpret_cast<float *>(smem);  // [m][B+1], shared by the waves
-  float *dv = edg + m * (B + 1) + (size_t)wid * wave_region_words(m, B, U, G);
+  float *ones = edg + m * (B + 1);               // [kSmallCell + 1] 1.0, shared: the second factor of Σd
+  float *dv = ones + (kSmallCell + 1) + (size_t)wid * wave_region_words(m, B, U, G);
   uint32_t *hist_l = reinterpret_cast<uint32_t *>(dv + m * ld);  // [m*B]
   uint32_t *kmin_l = hist_l + m * B;
   uint32_t *kmax_l = kmin_l + m;
@@ -372,6 +373,7 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell_wave(CellArgs A) {
   const int grp = R == 1 ? lane / U : 0;
   if (B > 0)
     for (int i = threadIdx.x; i < m * (B + 1); i += kAggThreads) edg[i] = A.edges[i];
+  for (int i = threadIdx.x; i < kSmallCell + 1; i += kAggThreads) ones[i] = 1.0f;
   __syncthreads();
   const uint32_t n_list = *A.list_cnt;
   for (uint32_t k = blockIdx.x * kWaves + wid; k < n_list; k += gridDim.x * kWaves) {
@@ -431,18 +433,21 @@ __global__ __launch_bounds__(kAggThreads) void k_agg_cell_wave(CellArgs A) {
       const int u = R == 1 ? lane % U : lane + q * kWave;
       const bool worker = R == 1 ? lane < G * U : u < U;
       if (!worker) continue;
+      // Σd_j as d_j times ones through the product path (see k_agg_cell)
+      const float *dj, *dk;
       if (u < m) {
-        const float *du = dv + u * ld;
-        for (int v = grp; v < nt; v += G) acc(hi[q], lo[q], du[v], 0.0f);
+        dj = dv + u * ld;
+        dk = ones;
       } else {
         const int p = u - m;
-        const float *dj = dv + A.pairs.j[p] * ld, *dk = dv + A.pairs.k[p] * ld;
-        for (int v = grp; v < nt; v += G) {
-          const float a = dj[v], b = dk[v];
-          const float pr = a * b;
-          const float pe = __builtin_fmaf(a, b, -pr);
-          acc(hi[q], lo[q], pr, pe);
-        }
+        dj = dv + A.pairs.j[p] * ld;
+        dk = dv + A.pairs.k[p] * ld;
+      }
+      for (int v = grp; v < nt; v += G) {
+        const float a = dj[v], b = dk[v];
+        const float pr = a * b;
+        const float pe = __builtin_fmaf(a, b, -pr);
+        acc(hi[q], lo[q], pr, pe);
       }
     }
 #pragma unroll
@@ -1040,7 +1045,7 @@ extern "C" int32_t lsrvt_aggregate(const uint32_t *d_cell, lsrvt_dims dims, cons
     const int Rw = (U + kWave - 1) / kWave;
     const int Gw = Rw == 1 ? kWave / U : 1;
     const size_t lds_w =
-        sizeof(float) * ((size_t)m * (B + 1) + (kAggThreads / kWave) * wave_region_words(m, B, U, Gw));
+        sizeof(float) * ((size_t)m * (B + 1) + kSmallCell + 1 + (kAggThreads / kWave) * wave_region_words(m, B, U, Gw));
     const bool small_ok = Rw <= 3 && lds_w <= 65536;
     if ((rc = fill<uint32_t>(W.big_cnt + 1, 2, 0u, s))) return rc;
     uint32_t *counts = W.big_cnt + 1;
