@@ -88,7 +88,7 @@ int32_t on_streams(lsrvt_job *jobs, int32_t n, int32_t slots, uint8_t *work, siz
         if (jobs[i].status == LSRVT_OK) jobs[i].status = fn(jobs[i], slice, per, s);
       }
       if (hipStreamSynchronize(s) != hipSuccess) failed.store(1);
-      hipStreamDestroy(s);
+      (void)hipStreamDestroy(s);
     });
   }
   for (auto &th : pool) th.join();
@@ -137,7 +137,7 @@ extern "C" int32_t lsrvt_batch_run(lsrvt_job *jobs, int32_t n_jobs, int32_t n_st
   hipEvent_t ready;
   LSRVT_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
   if (hipEventRecord(ready, caller) != hipSuccess) {
-    hipEventDestroy(ready);
+    (void)hipEventDestroy(ready);
     return LSRVT_EDEVICE;
   }
   // 1. labels of every job
@@ -161,7 +161,7 @@ extern "C" int32_t lsrvt_batch_run(lsrvt_job *jobs, int32_t n_jobs, int32_t n_st
     if (rc == LSRVT_OK) rc = on_streams(jobs, n_jobs, slots, work, per, ready, dev, statistics);
   }
   if (hipStreamSynchronize(caller) != hipSuccess && rc == LSRVT_OK) rc = LSRVT_EDEVICE;
-  hipEventDestroy(ready);
+  (void)hipEventDestroy(ready);
   if (rc) return rc;
   for (int32_t i = 0; i < n_jobs; ++i)
     if (jobs[i].status != LSRVT_OK) return jobs[i].status;
